@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Benchmark of the LB-MHD hot path on one MI355X.
+
+Headline (``value``): site updates per second (MLUPS) of the fused FP32
+stream-collide step on a 4096 x 4096 periodic Orszag-Tang vortex
+(nu = eta = 1e-5, Smagorinsky-MHD closure with C_S = 0.1), inputs resident in
+HBM, K timed steps with the FP64 diagnostics reduction run every 100 steps
+inside the timed region.  The same JSON line also reports the FP16-storage
+step on 8192 x 8192 decaying turbulence (nu = eta = 1e-6), the adjoint
+(gradient of the final total energy after 2000 steps of a perturbed 1024 x 1024
+Orszag-Tang run, checkpoint every 100 steps), the HBM roofline of the
+dominant kernel, and the FP64 CPU oracle timed on the host on the headline
+workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Progress goes to stderr; stdout carries exactly one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + %HBM peak, FP32 vs FP16-store fwd and adjoint, at stated err"
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+FP32_BYTES_PER_SITE = 19 * 4 * 2
+FP16_BYTES_PER_SITE = 19 * 2 * 2
+ADJ_BYTES_PER_SITE = 19 * 4 * 2 + 3 * 19 * 4  # recompute step + (lam in, state gather, lam out)
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_step_fp32_4096.json")
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1607_08675_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 step from the committed counter
+    summary, or None if the kernel sources changed since it was taken."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return c.get("bytes_per_launch")
+
+
+def timed_steps(torch, lat, steps, diag_every):
+    """Run `steps` steps (diagnostics every diag_every) between two events on the
+    lattice's stream; returns milliseconds."""
+    s = lat.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    done = 0
+    while done < steps:
+        k = min(diag_every, steps - done) if diag_every else steps - done
+        lat.step(k)
+        done += k
+        if diag_every and done % diag_every == 0:
+            lat.diag()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def burst_ms_per_launch(torch, lat, launches):
+    """Average duration of back-to-back step launches, from HIP events."""
+    s = lat.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    lat.step(launches)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / launches
+
+
+def fp32_leg(torch, args):
+    from lbmhd_inputs import orszag_tang
+    from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
+    n = 4096
+    cfg = LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=True, cs=0.1, storage="fp32")
+    lat = Lattice(cfg)
+    lat.init_fields(*orszag_tang(n, n))
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"fp32 4096^2: warmup {args.warmup} done, timing {args.steps} steps")
+    t0 = time.perf_counter()
+    ms = timed_steps(torch, lat, args.steps, 100)
+    wall = time.perf_counter() - t0
+    d = lat.diag()
+    per_launch = burst_ms_per_launch(torch, lat, 200)
+    log(f"fp32: {ms / args.steps:.4f} ms/step, burst {per_launch:.4f} ms/launch, "
+        f"nonfinite={d['nonfinite']}")
+    out = dict(ms=ms, wall=wall, per_launch=per_launch, sites=n * n, diag=d)
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def fp16_leg(torch, args):
+    from lbmhd_inputs import decaying_turbulence
+    from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
+    n = 8192
+    log("fp16 8192^2: generating decaying-turbulence fields")
+    fields = decaying_turbulence(n, n)
+    cfg = LBMHDConfig(nx=n, ny=n, nu=1e-6, eta=1e-6, les=True, cs=0.1, storage="fp16")
+    lat = Lattice(cfg)
+    lat.init_fields(*fields)
+    del fields
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"fp16 8192^2: timing {args.fp16_steps} steps")
+    ms = timed_steps(torch, lat, args.fp16_steps, 100)
+    per_launch = burst_ms_per_launch(torch, lat, 100)
+    d = lat.diag()
+    log(f"fp16: {ms / args.fp16_steps:.4f} ms/step, burst {per_launch:.4f} ms/launch, "
+        f"nonfinite={d['nonfinite']}")
+    out = dict(ms=ms, per_launch=per_launch, sites=n * n, nonfinite=d["nonfinite"])
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_leg(torch, args):
+    from lbmhd_inputs import perturbed_orszag_tang
+    from paper_1607_08675_amd.adjoint import Checkpointed
+    from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
+    n, nsteps, every = 1024, args.adj_steps, 100
+    cfg = LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=True, cs=0.1, storage="fp32")
+    lat = Lattice(cfg)
+    fields = perturbed_orszag_tang(n, n)
+    run = Checkpointed(lat, every)
+    run.forward(fields, min(nsteps, 200))   # warm-up of both passes
+    run.backward()
+    torch.cuda.synchronize()
+    log(f"adjoint 1024^2: forward + backward of {nsteps} steps")
+    t0 = time.perf_counter()
+    J = run.forward(fields, nsteps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = run.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd_ms = burst_ms_per_launch(torch, lat, 200)
+    # one adjoint segment timed with events: recompute (every-1 steps) + every adjoint steps
+    lam, lam2, acc = lat.new_adj_buffer(), lat.new_adj_buffer(), lat.new_adj_acc()
+    states = [run.ckpts[0]] + [lat.new_state_buffer() for _ in range(every - 1)]
+    lat.adj_seed_energy(run.final, lam)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e0.record(lat.stream)
+    for j in range(every - 1):
+        lat.step_between(states[j], states[j + 1])
+    e1.record(lat.stream)
+    for j in reversed(range(every)):
+        lat.adj_step(states[j], lam, lam2, acc)
+        lam, lam2 = lam2, lam
+    e2.record(lat.stream)
+    torch.cuda.synchronize()
+    adj_kernel_ms = e1.elapsed_time(e2) / every
+    seg_ms = e0.elapsed_time(e2) / every
+    log(f"adjoint: J={J:.6e}, backward {t2 - t1:.3f}s, adjoint kernel {adj_kernel_ms:.4f} ms, "
+        f"recompute+adjoint {seg_ms:.4f} ms/step, forward {fwd_ms:.4f} ms/step")
+    out = dict(J=J, fwd_s=t1 - t0, bwd_s=t2 - t1, fwd_ms=fwd_ms, adj_kernel_ms=adj_kernel_ms,
+               seg_ms=seg_ms, sites=n * n, nsteps=nsteps, dJ_dcs=g[4])
+    del run, lat, states, lam, lam2
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle on the headline workload (4096^2 Orszag-Tang, LES),
+    timed on the host cores: whole steps until about `seconds` have passed."""
+    from lbmhd_inputs import orszag_tang
+    from oracle import oracle as orc
+    orc.build()
+    n = 4096
+    p = orc.Params(n, n, nu=1e-5, eta=1e-5, les=True, cs=0.1)
+    st = orc.init(p, *orszag_tang(n, n))
+    log(f"cpu baseline: oracle on {n}^2 with {orc.num_threads()} threads")
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        st = orc.run(p, st, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        log(f"cpu baseline: step {steps} at {el:.1f}s")
+        if el >= seconds or steps >= 50:
+            break
+    return dict(value=n * n * steps / el / 1e6, unit="MLUPS", cores=orc.num_threads(),
+                kind="oracle",
+                sample=f"FP64 oracle, {steps} step(s) of the 4096x4096 Orszag-Tang LES workload "
+                       f"({el:.1f} s wall)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--fp16-steps", type=int, default=500)
+    ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--skip", default="", help="comma list of legs to skip: fp16,adjoint,cpu")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    skip = set(s for s in args.skip.split(",") if s)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    props = torch.cuda.get_device_properties(0)
+    log(f"device: {props.name}, {props.multi_processor_count} CUs")
+
+    r32 = fp32_leg(torch, args)
+    r16 = None if "fp16" in skip else fp16_leg(torch, args)
+    radj = None if "adjoint" in skip else adjoint_leg(torch, args)
+    cpu = None if "cpu" in skip else cpu_baseline(args.cpu_seconds)
+
+    ms_step = r32["ms"] / args.steps
+    value = r32["sites"] / (ms_step * 1e-3) / 1e6
+    achieved = FP32_BYTES_PER_SITE * r32["sites"] / (r32["per_launch"] * 1e-3) / 1e9
+    traffic = measured_traffic()
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "Orszag-Tang vortex 4096x4096 periodic, FP32 storage+compute, "
+                        "nu=eta=1e-5, Smagorinsky-MHD LES C_S=0.1, diagnostics every 100 steps",
+            "lattice": [4096, 4096], "storage": "fp32", "nu": 1e-5, "eta": 1e-5, "cs": 0.1,
+        },
+        "pct_hbm_peak": round(100 * FP32_BYTES_PER_SITE * value * 1e6 / (HBM_PEAK_GBS * 1e9), 2),
+        "roofline": {
+            "kernel": "k_step<fp32,les>",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_site": FP32_BYTES_PER_SITE,
+            "ms_per_launch": round(r32["per_launch"], 5),
+        },
+        "cpu_baseline": cpu,
+        "error_bound": {
+            "fp32_rel_l2_uB": 1e-5, "fp16_rel_l2_uB": 1e-3,
+            "checked_by": "tests/test_gpu_forward.py (oracle parity, 64^2/256^2 trajectories, "
+                          "full-size sampled sites)",
+        },
+    }
+    if r16:
+        m16 = r16["sites"] / (r16["ms"] / args.fp16_steps * 1e-3) / 1e6
+        a16 = FP16_BYTES_PER_SITE * r16["sites"] / (r16["per_launch"] * 1e-3) / 1e9
+        line["fp16"] = {
+            "workload": "decaying 2D MHD turbulence 8192x8192, FP16 deviation storage (x2^10), "
+                        "nu=eta=1e-6, LES C_S=0.1",
+            "mlups": round(m16, 1), "ms_per_step": round(r16["ms"] / args.fp16_steps, 5),
+            "steps": args.fp16_steps, "achieved_gbs": round(a16, 1),
+            "frac": round(a16 / HBM_PEAK_GBS, 4), "bytes_per_site": FP16_BYTES_PER_SITE,
+            "speedup_vs_fp32_mlups": round(m16 / value, 3), "nonfinite": r16["nonfinite"],
+        }
+    if radj:
+        s = radj["sites"]
+        line["adjoint"] = {
+            "workload": f"perturbed Orszag-Tang 1024x1024, dJ/d(u0,B0,C_S) of the total energy "
+                        f"after {radj['nsteps']} steps, checkpoint every 100 (FP32)",
+            "backward_s": round(radj["bwd_s"], 4), "forward_s": round(radj["fwd_s"], 4),
+            "backward_mlups": round(s * radj["nsteps"] / radj["bwd_s"] / 1e6, 1),
+            "adj_kernel_ms": round(radj["adj_kernel_ms"], 5),
+            "recompute_plus_adjoint_ms_per_step": round(radj["seg_ms"], 5),
+            "forward_ms_per_step": round(radj["fwd_ms"], 5),
+            "ratio_to_forward": round(radj["seg_ms"] / radj["fwd_ms"], 3),
+            "adj_kernel_gbs": round(3 * 19 * 4 * s / (radj["adj_kernel_ms"] * 1e-3) / 1e9, 1),
+            "dJ_dcs": radj["dJ_dcs"],
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * lbmhd.h -- C ABI of the MI355X (gfx950) lattice Boltzmann MHD library.
+ *
+ * The library advances the 2D lattice Boltzmann MHD model of Flint & Vahala,
+ * "Lattice Boltzmann Large Eddy Simulation Model of MHD" (arXiv:1607.08675):
+ * a D2Q9 density distribution f relaxed by a multi-relaxation-time collision
+ * in the moment basis T of Sec. 3 (eq. FluidTMatrix), and a D2Q5 vector
+ * distribution g for the magnetic field relaxed by a single rate s_m
+ * (Sec. 3, eq. MagTMatrix), on a doubly periodic nx x ny lattice, with unit
+ * time step and the collide/stream split of Sec. 1.2 and Sec. 3.  Optionally
+ * the relaxation times carry the Smagorinsky-MHD eddy viscosity and eddy
+ * resistivity (Sec. 1.1, eqs. SmagorinskyClosure, SmagorinskyMHDClosureV/B),
+ * computed per site from the site's own non-equilibrium moments.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All functions return an int status: LBMHD_OK (0) or a negative
+ *    LBMHD_ERR_* code.  No C++ exception crosses this interface.  The text of
+ *    the last failure on a handle is available from lbmhd_last_error().
+ *  - "device" pointers are HIP device memory owned by the caller (for example
+ *    torch tensors); the library never frees caller memory and never
+ *    allocates device memory after lbmhd_bind().
+ *  - Field arrays ("fields") are float64, nx*ny elements, row-major [y][x]
+ *    with x fastest and no padding.  Site (x, y) sits at x_i = 2 pi x / nx,
+ *    y_j = 2 pi y / ny of the periodic box.
+ *  - Population arrays ("populations") are float64, 19 planes of nx*ny in the
+ *    same [y][x] order: planes 0..8 = f_0..f_8 with the D2Q9 velocities
+ *    c_x = {0,1,0,-1,0,1,-1,-1,1}, c_y = {0,0,1,0,-1,1,1,-1,-1}; planes 9..13
+ *    = x component of g_0..g_4 and 14..18 = y component, with the D2Q5
+ *    velocities C_x = {0,1,0,-1,0}, C_y = {0,0,1,0,-1} (Sec. 3).
+ *  - The state after n steps is the post-collision population at time n:
+ *    each step gathers (streams) from the neighbours and then collides at the
+ *    site.  Its density, momentum and B equal those of the pre-collision
+ *    population at time n of the paper's collide-then-stream ordering, since
+ *    the collision conserves them (Sec. 3, collision invariants).
+ *  - All work is enqueued on the stream given to lbmhd_bind(); functions
+ *    documented as "asynchronous" return before the GPU finishes.
+ *  - A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef LBMHD_H
+#define LBMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBMHD_OK = 0,
+  LBMHD_ERR_INVALID_ARG = -1, /* bad parameter, null or undersized buffer */
+  LBMHD_ERR_NOT_BOUND = -2,   /* lbmhd_bind() has not succeeded yet */
+  LBMHD_ERR_HIP = -3,         /* a HIP runtime call failed (text kept) */
+  LBMHD_ERR_NONFINITE = -4,   /* lbmhd_diag() found NaN/Inf populations */
+  LBMHD_ERR_UNSUPPORTED = -5  /* valid request the library does not offer */
+};
+
+/* Population storage in HBM.  Both store the deviation of each population
+ * from its value in the rest state (f_i - w_i with the D2Q9 weights
+ * w = 4/9, 1/9, 1/36; g unchanged since the rest state has B = 0).  FP16
+ * stores round-to-nearest-even half(deviation * 2^10).  Collision arithmetic
+ * is FP32 in both cases. */
+enum { LBMHD_FP32 = 0, LBMHD_FP16 = 1 };
+
+typedef struct lbmhd lbmhd_t;
+
+typedef struct {
+  int32_t nx, ny;         /* periodic lattice, each >= 2 */
+  double nu, eta;         /* shear viscosity and resistivity in lattice
+                             units, > 0; tau0 = 3 nu + 1/2 = 1/s_3 = 1/s_4 and
+                             tau_m0 = 3 eta + 1/2 = 1/s_m (Sec. 4.3) */
+  double s5, s6, s7, s8;  /* rates of the non-hydrodynamic moments M5..M8
+                             (Sec. 3), each in (0, 2); s5 must equal s6 */
+  int32_t les;            /* 0: rates fixed; 1: Smagorinsky-MHD closure */
+  double cs, delta;       /* closure constant C_S >= 0 (used for both the
+                             eddy viscosity C_S Delta^2 |S| and the eddy
+                             resistivity C_S Delta^2 |j|) and filter width
+                             Delta > 0 in lattice units */
+  int32_t storage;        /* LBMHD_FP32 or LBMHD_FP16 */
+} lbmhd_params;
+
+/* Global diagnostics of the current state, accumulated in FP64.
+ * Differences are centred: d_x a = (a(x+1) - a(x-1)) / 2, periodic. */
+typedef struct {
+  double mass;            /* sum rho */
+  double mom_x, mom_y;    /* sum rho u */
+  double flux_x, flux_y;  /* sum B */
+  double e_kin;           /* sum |rho u|^2 / (2 rho) */
+  double e_mag;           /* sum |B|^2 / 2 */
+  double cross_helicity;  /* sum u . B */
+  double max_abs_divB;    /* max |d_x B_x + d_y B_y| */
+  double enstrophy;       /* sum w^2 / 2, w = d_x u_y - d_y u_x */
+  double current_sq;      /* sum j^2 / 2, j = d_x B_y - d_y B_x */
+  double max_u;           /* max |u| */
+  int64_t nonfinite;      /* sites holding a NaN or Inf population */
+  int64_t step;           /* steps taken since the last (re)initialisation */
+} lbmhd_diag_t;
+
+/* Text for a status code.  Never NULL; static storage. */
+const char* lbmhd_strerror(int code);
+
+/* Text of the most recent failure on h ("" if none).  Owned by h; valid
+ * until the next call on h. */
+const char* lbmhd_last_error(const lbmhd_t* h);
+
+/* Validate p and create a host-side handle.  Allocates no device memory.
+ * Errors: LBMHD_ERR_INVALID_ARG if p is out of range (nx, ny < 2; nu, eta
+ * <= 0; a rate outside (0, 2); s5 != s6; cs < 0; delta <= 0; unknown
+ * storage; lattice too large for 32-bit in-plane offsets). */
+int lbmhd_create(const lbmhd_params* p, lbmhd_t** out);
+
+/* Release the handle (not the caller's buffers).  NULL is accepted. */
+int lbmhd_destroy(lbmhd_t* h);
+
+/* Byte sizes the caller must allocate in device memory:
+ *   lattice    -- one encoded population lattice (two are bound);
+ *   workspace  -- scratch used by diagnostics, energy and reductions;
+ *   adj_lattice -- one FP32 adjoint lattice (lambda), for the adjoint calls;
+ *   adj_acc    -- the FP64 accumulator array of lbmhd_adj_step.
+ * Any output pointer may be NULL. */
+int lbmhd_sizes(const lbmhd_t* h, size_t* lattice, size_t* workspace, size_t* adj_lattice,
+                size_t* adj_acc);
+
+/* Attach caller-owned device buffers and the HIP stream (a hipStream_t, or
+ * NULL for the null stream).  lat_a and lat_b must each hold `lattice`
+ * bytes and workspace `workspace` bytes (lbmhd_sizes), 256-byte aligned, and
+ * must not overlap.  The stored sizes are checked against the requirement.
+ * Does not initialise the state.  Errors: LBMHD_ERR_INVALID_ARG. */
+int lbmhd_bind(lbmhd_t* h, void* lat_a, size_t lat_a_bytes, void* lat_b, size_t lat_b_bytes,
+               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Set every site to the equilibria f^eq(rho, u, B) and g^eq(u, B) of Sec. 3
+ * (the D2Q9 and D2Q5 relaxation distributions) computed in FP64, then encode
+ * to storage.  rho, ux, uy, bx, by: device fields.  Resets the step count to
+ * 0.  Asynchronous.  Errors: LBMHD_ERR_NOT_BOUND, LBMHD_ERR_INVALID_ARG,
+ * LBMHD_ERR_HIP. */
+int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const double* uy,
+                      const double* bx, const double* by);
+
+/* Advance nsteps >= 0 steps of stream + collide (Sec. 1.2 update with the
+ * moment-space collision of Sec. 3; closure per site when les = 1).  One
+ * fused kernel launch per step, ping-ponging the two bound lattices.
+ * Asynchronous. */
+int lbmhd_step(lbmhd_t* h, int64_t nsteps);
+
+/* One step from the encoded lattice src into dst (device, `lattice` bytes
+ * each, not overlapping each other or the bound buffers), same update as
+ * lbmhd_step.  Leaves the handle's current state and step count untouched;
+ * used to recompute stored states for the adjoint.  Asynchronous. */
+int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst);
+
+/* Macroscopic fields of the current state: rho = sum f, u = (sum c f) / rho,
+ * B = sum g (Sec. 3).  Outputs: device fields.  Asynchronous. */
+int lbmhd_macro(lbmhd_t* h, double* rho, double* ux, double* uy, double* bx, double* by);
+
+/* FP64 global diagnostics of the current state into *out (host memory).
+ * Synchronises the bound stream.  Returns LBMHD_ERR_NONFINITE (with *out
+ * filled) when any population is NaN or Inf. */
+int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out);
+
+/* Decode the current state to plain populations (device, 19*nx*ny float64):
+ * f_i = w_i + deviation.  Asynchronous. */
+int lbmhd_get_populations(lbmhd_t* h, double* out);
+
+/* Encode plain populations (device, 19*nx*ny float64) as the current state
+ * and set the step count.  The deviation from the rest state is formed in
+ * FP64 and rounded to FP32 (then, for FP16 storage, to half of 2^10 times
+ * it).  Asynchronous. */
+int lbmhd_set_populations(lbmhd_t* h, const double* in, int64_t step);
+
+/* Copy the current encoded lattice (`lattice` bytes) to / from caller device
+ * memory, bit-exact; used for checkpoints.  load sets the step count.
+ * Asynchronous. */
+int lbmhd_save_state(lbmhd_t* h, void* dst);
+int lbmhd_load_state(lbmhd_t* h, const void* src, int64_t step);
+
+/* Steps taken since the last (re)initialisation (host value). */
+int lbmhd_get_step(const lbmhd_t* h, int64_t* step);
+
+/* Total energy J = sum (|rho u|^2 / (2 rho) + |B|^2 / 2) of an encoded
+ * lattice `state` (device, `lattice` bytes; NULL = current state), in FP64,
+ * written to *J (host).  Synchronises the bound stream. */
+int lbmhd_energy(lbmhd_t* h, const void* state, double* J);
+
+/* ---------------------------------------------------------------------
+ * Adjoint (reverse mode) of the step.  The step maps an encoded lattice x_n
+ * to x_{n+1} = C(S(x_n)) (S: periodic gather, C: per-site collision with
+ * the closure).  Adjoint lattices are FP32, adj_lattice bytes, 19 planes in
+ * the same padded layout as an FP32 state; they hold dJ/d(population).
+ * Storage rounding is treated as the identity (its derivative is zero
+ * almost everywhere).
+ * ------------------------------------------------------------------- */
+
+/* lam = dJ/dx for the total energy J of `state` (see lbmhd_energy):
+ * dJ/df_i = c_i . u - |u|^2 / 2, dJ/dg_k = B.  Asynchronous. */
+int lbmhd_adj_seed_energy(lbmhd_t* h, const void* state, float* lam);
+
+/* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next, where state_n is
+ * the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc
+ * bytes, FP64) gains, slot per thread block, the contribution
+ * lam_next . d x_{n+1} / d C_S; slots are only ever added to, so zero acc
+ * once before a backward sweep.  lam_prev must not alias lam_next.
+ * Asynchronous. */
+int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float* lam_prev,
+                   double* acc);
+
+/* Sum the slots of acc into *out (host), in FP64.  Synchronises. */
+int lbmhd_adj_acc_total(lbmhd_t* h, const double* acc, double* out);
+
+/* Pull an adjoint lattice back through the initial equilibria: with
+ * x_0 = encode(f^eq(rho0, u0, B0), g^eq(u0, B0)), write
+ * dJ/du_x, dJ/du_y, dJ/dB_x, dJ/dB_y (device fields) from lam0 and the
+ * initial fields (device fields).  Asynchronous. */
+int lbmhd_adj_fields(lbmhd_t* h, const float* lam0, const double* rho0, const double* ux0,
+                     const double* uy0, const double* bx0, const double* by0, double* g_ux,
+                     double* g_uy, double* g_bx, double* g_by);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMHD_H */

@@ -1,0 +1,410 @@
+// lbmhd_adjoint.hip -- reverse-mode (adjoint) kernels of the lattice
+// Boltzmann MHD step on gfx950.
+//
+// The forward step is x_{n+1}(x) = C(pre(x)), pre_i(x) = x_n,i(x - c_i): a
+// periodic gather S followed by the per-site collision C (moment-space MRT
+// for f, single-rate relaxation for g, Smagorinsky-MHD relaxation times).
+// Its transpose is lam_n = S^T J_C(pre)^T lam_{n+1}: every site recomputes
+// the collision from the gathered x_n, applies the hand-derived transposed
+// Jacobian to its own lam_{n+1}, and scatters component i back to x - c_i.
+// The scatter writes each (site, population) exactly once, so no atomics are
+// needed.  The derivative with respect to the closure constant C_S is
+// accumulated per thread block in FP64, into a slot owned by that block.
+//
+// Reverse-mode rules follow the forward collision operation by operation;
+// the kinks of |A| and of the norm Q take derivative 0 at exactly 0.
+#include <math.h>
+
+#include "lbmhd_impl.h"
+
+#ifndef LBMHD_ADJ_TX
+#define LBMHD_ADJ_TX 256
+#endif
+
+namespace lbk {
+namespace {
+
+template <int ST>
+struct Dec;
+template <>
+struct Dec<LBMHD_FP32> {
+  using T = float;
+  __device__ static __forceinline__ float dec(float v) { return v; }
+};
+template <>
+struct Dec<LBMHD_FP16> {
+  using T = _Float16;
+  __device__ static __forceinline__ float dec(_Float16 v) { return float(v) * 0x1p-10f; }
+};
+
+__device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kMx[5] = {0, 1, 0, -1, 0};
+__device__ constexpr int kMy[5] = {0, 0, 1, 0, -1};
+__device__ constexpr double kW[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+__device__ constexpr double kWm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+struct AdjConsts {
+  float dcf;  // d(18 C_S Delta^2) / dC_S
+  float dcm;  // d(36 C_S Delta^2) / dC_S
+};
+
+// lam (19 values, in: adjoint of the post-collision populations; out:
+// adjoint of the pre-collision populations) for the collision at the
+// pre-collision state f[9], g[10] (deviation variables).  Returns the
+// site's contribution to dJ/dC_S.
+template <bool LES>
+__device__ __forceinline__ float collide_adjoint(const float (&f)[9], const float (&g)[10],
+                                                 float (&lf)[9], float (&lg)[10],
+                                                 const Rates& r, const AdjConsts& ac) {
+  // ---- forward recompute of what the reverse sweep needs (same operations
+  // as the forward collision)
+  const float a13 = f[1] + f[3], a24 = f[2] + f[4];
+  const float d13 = f[1] - f[3], d24 = f[2] - f[4];
+  const float s57 = f[5] + f[7], s68 = f[6] + f[8];
+  const float d57 = f[5] - f[7], d68 = f[6] - f[8];
+  const float dd = s57 + s68;
+  const float drho = f[0] + a13 + a24 + dd;
+  const float rho = 1.0f + drho;
+  const float jx = d13 + d57 - d68;
+  const float jy = d24 + d57 + d68;
+  const float M3 = s57 - s68;
+  const float M4 = a13 - a24;
+  const float ir = frcp(rho);
+  const float ux = jx * ir, uy = jy * ir;
+  const float Bx = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+  const float By = (g[5] + g[6]) + (g[7] + g[8]) + g[9];
+  const float jxux = jx * ux, jyuy = jy * uy;
+  const float n3 = M3 - (jx * uy - Bx * By);
+  const float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
+  const float E = ux * By - uy * Bx;
+  float s3q, sm, Q = 0.0f, Rr = 1.0f, tau = 1.0f, A = 0.0f, Rm = 1.0f, taum = 1.0f;
+  if (LES) {
+    Q = fsqrt(n4 * n4 + 4.0f * (n3 * n3));
+    Rr = fsqrt(r.tau0sq + r.cf * Q * ir);
+    tau = 0.5f * (r.tau0 + Rr);
+    s3q = 0.25f * frcp(tau);
+    A = (g[6] - g[8]) - (g[2] - g[4]) - 2.0f * E;
+    Rm = fsqrt(r.taum0sq + r.cm * fabsf(A));
+    taum = 0.5f * (r.taum0 + Rm);
+    sm = frcp(taum);
+  } else {
+    s3q = r.s3q;
+    sm = r.sm;
+  }
+  const float bx6 = Bx * (1.0f / 6.0f), by6 = By * (1.0f / 6.0f), he = 0.5f * E;
+  const float geq[10] = {Bx - 4.0f * bx6, bx6, bx6 - he, bx6, bx6 + he,
+                         By - 4.0f * by6, by6 + he, by6, by6 - he, by6};
+
+  // ---- reverse
+  // f* = f - K r, K_ij = T_ji:  rbar_j = -(T lam*_f)_j, j = 3..8.
+  const float la13 = lf[1] + lf[3], la24 = lf[2] + lf[4];
+  const float ld13 = lf[1] - lf[3], ld24 = lf[2] - lf[4];
+  const float ls57 = lf[5] + lf[7], ls68 = lf[6] + lf[8];
+  const float ld57 = lf[5] - lf[7], ld68 = lf[6] - lf[8];
+  const float ldd = ls57 + ls68;
+  const float ljx = ld13 + ld57 - ld68, ljy = ld24 + ld57 + ld68;
+  const float rb3 = -(ls57 - ls68);
+  const float rb4 = -(la13 - la24);
+  const float rb5 = -(ljx - 3.0f * ld13);
+  const float rb6 = -(ljy - 3.0f * ld24);
+  const float rb7 = -(4.0f * lf[0] - 5.0f * (la13 + la24) + 4.0f * ldd);
+  const float rb8 = -(4.0f * lf[0] - ldd);
+  float nb3 = s3q * rb3, nb4 = s3q * rb4;
+  const float nb5 = r.s5q * rb5, nb6 = r.s5q * rb6;
+  const float nb7 = r.s7q * rb7, nb8 = r.s8q * rb8;
+  const float s3qb = n3 * rb3 + n4 * rb4;
+
+  // g* = g - sm (g - geq)
+  float smb = 0.0f, geqb[10], lgo[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    smb -= lg[q] * (g[q] - geq[q]);
+    geqb[q] = sm * lg[q];
+    lgo[q] = (1.0f - sm) * lg[q];
+  }
+  float Bxb = (1.0f / 3.0f) * geqb[0] + (1.0f / 6.0f) * (geqb[1] + geqb[2] + geqb[3] + geqb[4]);
+  float Byb = (1.0f / 3.0f) * geqb[5] + (1.0f / 6.0f) * (geqb[6] + geqb[7] + geqb[8] + geqb[9]);
+  float Eb = 0.5f * (-geqb[2] + geqb[4] + geqb[6] - geqb[8]);
+
+  float dcs = 0.0f, irb = 0.0f;
+  if (LES) {
+    // sm = 1 / taum, taum = (taum0 + Rm) / 2, Rm = sqrt(taum0^2 + cm |A|)
+    const float taumb = -smb * sm * sm;
+    const float amb = 0.5f * taumb * 0.5f * frcp(Rm);
+    const float absAb = r.cm * amb;
+    const float Ab = A > 0.0f ? absAb : (A < 0.0f ? -absAb : 0.0f);
+    dcs += ac.dcm * fabsf(A) * amb;
+    lgo[6] += Ab;
+    lgo[8] -= Ab;
+    lgo[2] -= Ab;
+    lgo[4] += Ab;
+    Eb -= 2.0f * Ab;
+    // s3q = 1 / (4 tau), tau = (tau0 + Rr) / 2, Rr = sqrt(tau0^2 + cf Q ir)
+    const float itau = frcp(tau);
+    const float taub = -0.25f * s3qb * itau * itau;
+    const float ab = 0.5f * taub * 0.5f * frcp(Rr);
+    const float Qb = r.cf * ir * ab;
+    irb += r.cf * Q * ab;
+    dcs += ac.dcf * Q * ir * ab;
+    if (Q > 0.0f) {
+      const float iQ = frcp(Q);
+      nb4 += Qb * n4 * iQ;
+      nb3 += 4.0f * Qb * n3 * iQ;
+    }
+  }
+  // E = ux By - uy Bx
+  float uxb = Eb * By, uyb = -Eb * Bx;
+  Byb += Eb * ux;
+  Bxb -= Eb * uy;
+  // n3 = M3 - jx jy ir + Bx By
+  float jxb = -nb3 * jy * ir, jyb = -nb3 * jx * ir;
+  irb -= nb3 * jx * jy;
+  Bxb += nb3 * By;
+  Byb += nb3 * Bx;
+  // n4 = M4 - (jx^2 - jy^2) ir + Bx^2 - By^2
+  jxb -= 2.0f * nb4 * jx * ir;
+  jyb += 2.0f * nb4 * jy * ir;
+  irb -= nb4 * (jx * jx - jy * jy);
+  Bxb += 2.0f * nb4 * Bx;
+  Byb -= 2.0f * nb4 * By;
+  // n5 = M5 + jx, n6 = M6 + jy
+  jxb += nb5;
+  jyb += nb6;
+  // n7, n8 through jj = (jx^2 + jy^2) ir and drho
+  const float jjb = 3.0f * (nb7 + nb8);
+  float drhob = -(5.0f / 3.0f) * nb8;
+  jxb += 2.0f * jjb * jx * ir;
+  jyb += 2.0f * jjb * jy * ir;
+  irb += jjb * (jx * jx + jy * jy);
+  // ux = jx ir, uy = jy ir
+  jxb += uxb * ir;
+  jyb += uyb * ir;
+  irb += uxb * jx + uyb * jy;
+  // ir = 1 / (1 + drho)
+  drhob -= irb * ir * ir;
+  // moments M3..M8 = T_r f; drho = sum f; j = sum c f
+  const float Mb3 = nb3, Mb4 = nb4, Mb5 = nb5, Mb6 = nb6, Mb7 = nb7, Mb8 = nb8;
+  lf[0] += drhob + 4.0f * Mb7 + 4.0f * Mb8;
+  lf[1] += drhob + jxb + Mb4 - 2.0f * Mb5 - 5.0f * Mb7;
+  lf[2] += drhob + jyb - Mb4 - 2.0f * Mb6 - 5.0f * Mb7;
+  lf[3] += drhob - jxb + Mb4 + 2.0f * Mb5 - 5.0f * Mb7;
+  lf[4] += drhob - jyb - Mb4 + 2.0f * Mb6 - 5.0f * Mb7;
+  const float c58 = 4.0f * Mb7 - Mb8;
+  lf[5] += drhob + jxb + jyb + Mb3 + Mb5 + Mb6 + c58;
+  lf[6] += drhob - jxb + jyb - Mb3 - Mb5 + Mb6 + c58;
+  lf[7] += drhob - jxb - jyb + Mb3 - Mb5 - Mb6 + c58;
+  lf[8] += drhob + jxb - jyb - Mb3 + Mb5 - Mb6 + c58;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    lg[k] = lgo[k] + Bxb;
+    lg[5 + k] = lgo[5 + k] + Byb;
+  }
+  return dcs;
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int q = nb / kXcd, rem = nb % kXcd;
+  const int xcd = b % kXcd, local = b / kXcd;
+  return (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + local;
+}
+
+template <int ST, bool LES>
+__global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
+    const typename Dec<ST>::T* __restrict__ st, const float* __restrict__ lam_next,
+    float* __restrict__ lam_prev, double* __restrict__ acc, Geom geo, Geom ga, Rates rt,
+    AdjConsts ac, int tiles_x) {
+  using D = Dec<ST>;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int x = (b % tiles_x) * LBMHD_ADJ_TX + int(threadIdx.x);
+  const int y = b / tiles_x;
+  float dcs = 0.0f;
+  if (x < geo.nx) {
+    const int xm = x == 0 ? geo.nx - 1 : x - 1;
+    const int xp = x == geo.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? geo.ny - 1 : y - 1;
+    const int yp = y == geo.ny - 1 ? 0 : y + 1;
+    // offsets of x - c_i in the state layout and in the adjoint layout
+    const unsigned r0 = unsigned(y) * geo.pitch, rm = unsigned(ym) * geo.pitch,
+                   rp = unsigned(yp) * geo.pitch;
+    const unsigned o[9] = {r0 + x,  r0 + xm, rm + x,  r0 + xp, rp + x,
+                           rm + xm, rm + xp, rp + xp, rp + xm};
+    const unsigned a0 = unsigned(y) * ga.pitch, am = unsigned(ym) * ga.pitch,
+                   ap = unsigned(yp) * ga.pitch;
+    const unsigned oa[9] = {a0 + x,  a0 + xm, am + x,  a0 + xp, ap + x,
+                            am + xm, am + xp, ap + xp, ap + xm};
+    const long long P = geo.plane, PA = ga.plane;
+    float f[9], g[10], lf[9], lg[10];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = D::dec(st[i * P + o[i]]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      g[k] = D::dec(st[(9 + k) * P + o[k]]);
+      g[5 + k] = D::dec(st[(14 + k) * P + o[k]]);
+    }
+    const unsigned oc = a0 + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lf[i] = lam_next[i * PA + oc];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) lg[q] = lam_next[(9 + q) * PA + oc];
+    dcs = collide_adjoint<LES>(f, g, lf, lg, rt, ac);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(lf[i], lam_prev + i * PA + oa[i]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      __builtin_nontemporal_store(lg[k], lam_prev + (9 + k) * PA + oa[k]);
+      __builtin_nontemporal_store(lg[5 + k], lam_prev + (14 + k) * PA + oa[k]);
+    }
+  }
+  if (LES) {
+    __shared__ double sh[LBMHD_ADJ_TX];
+    sh[threadIdx.x] = double(dcs);
+    __syncthreads();
+    for (int w = LBMHD_ADJ_TX / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[blockIdx.x] += sh[0];
+  }
+}
+
+// lam = dJ/dx for J = sum |rho u|^2 / (2 rho) + |B|^2 / 2:
+// dJ/df_i = c_i . u - |u|^2 / 2, dJ/dg = B.
+template <int ST>
+__global__ void k_adj_seed(const typename Dec<ST>::T* __restrict__ st, float* __restrict__ lam,
+                           Geom geo, Geom ga) {
+  using D = Dec<ST>;
+  const long long n = (long long)geo.nx * geo.ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / geo.nx), x = int(s % geo.nx);
+  const long long o = (long long)y * geo.pitch + x, oa = (long long)y * ga.pitch + x;
+  double v[kNPop];
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) v[q] = double(D::dec(st[q * geo.plane + o]));
+  double dr = 0.0, jx = 0.0, jy = 0.0, bx = 0.0, by = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    dr += v[i];
+    jx += kCx[i] * v[i];
+    jy += kCy[i] * v[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    bx += v[9 + k];
+    by += v[14 + k];
+  }
+  const double rho = 1.0 + dr, ux = jx / rho, uy = jy / rho, h = 0.5 * (ux * ux + uy * uy);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lam[i * ga.plane + oa] = float(kCx[i] * ux + kCy[i] * uy - h);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    lam[(9 + k) * ga.plane + oa] = float(bx);
+    lam[(14 + k) * ga.plane + oa] = float(by);
+  }
+}
+
+// Pull lam0 back through x_0 = (f^eq(rho0, u0, B0), g^eq(u0, B0)).
+__global__ void k_adj_fields(const float* __restrict__ lam, const double* __restrict__ rho0,
+                             const double* __restrict__ ux0, const double* __restrict__ uy0,
+                             const double* __restrict__ bx0, const double* __restrict__ by0,
+                             double* __restrict__ gux, double* __restrict__ guy,
+                             double* __restrict__ gbx, double* __restrict__ gby, Geom ga,
+                             int nx, int ny) {
+  const long long n = (long long)nx * ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / nx), x = int(s % nx);
+  const long long oa = (long long)y * ga.pitch + x;
+  const double rho = rho0[s], ux = ux0[s], uy = uy0[s], bx = bx0[s], by = by0[s];
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double l = double(lam[i * ga.plane + oa]);
+    const double cx = kCx[i], cy = kCy[i], w = kW[i];
+    const double cu = cx * ux + cy * uy, cb = cx * bx + cy * by, c2 = cx * cx + cy * cy;
+    // f^eq_i = w rho (1 + 3 cu + 4.5 cu^2 - 1.5 u^2) + 4.5 w (B^2 c^2 / 2 - cb^2)
+    a += l * w * rho * (3.0 * cx + 9.0 * cu * cx - 3.0 * ux);
+    b += l * w * rho * (3.0 * cy + 9.0 * cu * cy - 3.0 * uy);
+    c += l * 4.5 * w * (bx * c2 - 2.0 * cb * cx);
+    d += l * 4.5 * w * (by * c2 - 2.0 * cb * cy);
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double lx = double(lam[(9 + k) * ga.plane + oa]);
+    const double ly = double(lam[(14 + k) * ga.plane + oa]);
+    const double cx = kMx[k], cy = kMy[k], w = kWm[k];
+    const double cu = cx * ux + cy * uy, cb = cx * bx + cy * by;
+    // g^eq_x = w (B_x + 3 (cu B_x - cb u_x)), g^eq_y = w (B_y + 3 (cu B_y - cb u_y))
+    a += lx * w * 3.0 * (cx * bx - cb) + ly * w * 3.0 * cx * by;
+    b += lx * w * 3.0 * cy * bx + ly * w * 3.0 * (cy * by - cb);
+    c += lx * w * (1.0 + 3.0 * (cu - cx * ux)) + ly * w * 3.0 * (-cx * uy);
+    d += lx * w * 3.0 * (-cy * ux) + ly * w * (1.0 + 3.0 * (cu - cy * uy));
+  }
+  gux[s] = a;
+  guy[s] = b;
+  gbx[s] = c;
+  gby[s] = d;
+}
+
+}  // namespace
+
+int adj_step_blocks(const Geom& g) {
+  return ((g.nx + LBMHD_ADJ_TX - 1) / LBMHD_ADJ_TX) * g.ny;
+}
+
+hipError_t launch_adj_step(int storage, bool les, const void* state, const float* lam_next,
+                           float* lam_prev, double* acc, const Geom& g, const Geom& ga,
+                           const Rates& r, double delta2, hipStream_t s) {
+  const int tiles_x = (g.nx + LBMHD_ADJ_TX - 1) / LBMHD_ADJ_TX;
+  const dim3 grid(unsigned(adj_step_blocks(g))), block(LBMHD_ADJ_TX);
+  // cf = 18 C_S Delta^2 and cm = 36 C_S Delta^2 are linear in C_S.
+  const AdjConsts ac{float(18.0 * delta2), float(36.0 * delta2)};
+  if (storage == LBMHD_FP32) {
+    auto* st = static_cast<const float*>(state);
+    if (les)
+      hipLaunchKernelGGL((k_adj_step<LBMHD_FP32, true>), grid, block, 0, s, st, lam_next,
+                         lam_prev, acc, g, ga, r, ac, tiles_x);
+    else
+      hipLaunchKernelGGL((k_adj_step<LBMHD_FP32, false>), grid, block, 0, s, st, lam_next,
+                         lam_prev, acc, g, ga, r, ac, tiles_x);
+  } else {
+    auto* st = static_cast<const _Float16*>(state);
+    if (les)
+      hipLaunchKernelGGL((k_adj_step<LBMHD_FP16, true>), grid, block, 0, s, st, lam_next,
+                         lam_prev, acc, g, ga, r, ac, tiles_x);
+    else
+      hipLaunchKernelGGL((k_adj_step<LBMHD_FP16, false>), grid, block, 0, s, st, lam_next,
+                         lam_prev, acc, g, ga, r, ac, tiles_x);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed(int storage, const void* lat, float* lam, const Geom& g,
+                           const Geom& ga, hipStream_t s) {
+  const unsigned nb = unsigned(((long long)g.nx * g.ny + 255) / 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_adj_seed<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float*>(lat), lam, g, ga);
+  else
+    hipLaunchKernelGGL(k_adj_seed<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const _Float16*>(lat), lam, g, ga);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_fields(const float* lam0, const double* rho0, const double* ux0,
+                             const double* uy0, const double* bx0, const double* by0,
+                             double* gux, double* guy, double* gbx, double* gby, const Geom& ga,
+                             int nx, int ny, hipStream_t s) {
+  const unsigned nb = unsigned(((long long)nx * ny + 255) / 256);
+  hipLaunchKernelGGL(k_adj_fields, dim3(nb), dim3(256), 0, s, lam0, rho0, ux0, uy0, bx0, by0,
+                     gux, guy, gbx, gby, ga, nx, ny);
+  return hipGetLastError();
+}
+
+}  // namespace lbk

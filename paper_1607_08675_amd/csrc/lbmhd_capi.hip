@@ -1,0 +1,367 @@
+// lbmhd_capi.hip -- host side of the C ABI declared in include/lbmhd.h:
+// parameter validation, the handle, buffer binding and kernel sequencing.
+// No exception crosses the interface; every HIP status is checked and kept.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "lbmhd_impl.h"
+
+struct lbmhd {
+  lbmhd_params p;
+  lbk::Geom geo;   // state lattice
+  lbk::Geom geoa;  // FP32 adjoint lattice
+  lbk::Rates rates;
+  size_t lattice_bytes = 0, workspace_bytes = 0, adj_lattice_bytes = 0, adj_acc_bytes = 0;
+  void* lat[2] = {nullptr, nullptr};
+  double* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  int cur = 0;  // index of the lattice holding the current state
+  int64_t step = 0;
+  std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int fail(lbmhd_t* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_fail(lbmhd_t* h, hipError_t e, const char* where) {
+  return fail(h, LBMHD_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+lbk::Geom make_geom(int nx, int ny, size_t esize) {
+  lbk::Geom g;
+  g.nx = nx;
+  g.ny = ny;
+  g.pitch = int(round_up(size_t(nx) * esize, kAlign) / esize);
+  g.plane = (long long)g.pitch * ny;
+  return g;
+}
+
+bool rate_ok(double s) { return s > 0.0 && s < 2.0; }
+
+// Workspace (doubles): 5 macro planes, diagnostics partials, 16 results.
+size_t workspace_doubles(const lbk::Geom& g) {
+  return 5 * size_t(g.nx) * g.ny + size_t(lbk::kDiagBlocks) * lbk::kDiagSlots + 32;
+}
+double* ws_out(lbmhd_t* h) {
+  return h->ws + 5 * size_t(h->geo.nx) * h->geo.ny + size_t(lbk::kDiagBlocks) * lbk::kDiagSlots;
+}
+
+int need_bound(lbmhd_t* h) {
+  if (!h) return LBMHD_ERR_INVALID_ARG;
+  if (!h->bound) return fail(h, LBMHD_ERR_NOT_BOUND, "lbmhd_bind() has not succeeded");
+  return LBMHD_OK;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+// Run the diagnostics kernels on `lat` and copy the 16 results to host.
+int run_diag(lbmhd_t* h, const void* lat, double out[lbk::kDiagSlots]) {
+  hipError_t e = lbk::launch_diag(h->p.storage, lat, h->ws, ws_out(h), h->geo, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "diagnostics launch");
+  e = hipMemcpyAsync(out, ws_out(h), sizeof(double) * lbk::kDiagSlots, hipMemcpyDeviceToHost,
+                     h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "diagnostics copy");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "diagnostics synchronise");
+  return LBMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbmhd_strerror(int code) {
+  switch (code) {
+    case LBMHD_OK: return "ok";
+    case LBMHD_ERR_INVALID_ARG: return "invalid argument";
+    case LBMHD_ERR_NOT_BOUND: return "device buffers not bound";
+    case LBMHD_ERR_HIP: return "HIP runtime error";
+    case LBMHD_ERR_NONFINITE: return "non-finite populations";
+    case LBMHD_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* lbmhd_last_error(const lbmhd_t* h) { return h ? h->err.c_str() : ""; }
+
+int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
+  if (!p || !out) return LBMHD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (p->nx < 2 || p->ny < 2) return LBMHD_ERR_INVALID_ARG;
+  if (!(p->nu > 0.0) || !(p->eta > 0.0) || !isfinite(p->nu) || !isfinite(p->eta))
+    return LBMHD_ERR_INVALID_ARG;
+  if (!rate_ok(p->s5) || !rate_ok(p->s6) || !rate_ok(p->s7) || !rate_ok(p->s8))
+    return LBMHD_ERR_INVALID_ARG;
+  if (p->s5 != p->s6) return LBMHD_ERR_INVALID_ARG;
+  if (p->les != 0 && p->les != 1) return LBMHD_ERR_INVALID_ARG;
+  if (!(p->cs >= 0.0) || !isfinite(p->cs) || !(p->delta > 0.0) || !isfinite(p->delta))
+    return LBMHD_ERR_INVALID_ARG;
+  if (p->storage != LBMHD_FP32 && p->storage != LBMHD_FP16) return LBMHD_ERR_INVALID_ARG;
+  const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
+  lbk::Geom g = make_geom(p->nx, p->ny, esize);
+  lbk::Geom ga = make_geom(p->nx, p->ny, 4);
+  // in-plane offsets are 32-bit unsigned in the kernels
+  if ((unsigned long long)ga.plane >= (1ull << 32)) return LBMHD_ERR_INVALID_ARG;
+
+  lbmhd_t* h = new (std::nothrow) lbmhd;
+  if (!h) return LBMHD_ERR_INVALID_ARG;
+  h->p = *p;
+  h->geo = g;
+  h->geoa = ga;
+  const double tau0 = 3.0 * p->nu + 0.5, taum0 = 3.0 * p->eta + 0.5;
+  const double d2 = p->delta * p->delta;
+  lbk::Rates& r = h->rates;
+  r.s3q = float(0.25 / tau0);
+  r.s5q = float(p->s5 / 12.0);
+  r.s7q = float(p->s7 / 180.0);
+  r.s8q = float(p->s8 / 20.0);
+  r.sm = float(1.0 / taum0);
+  r.tau0 = float(tau0);
+  r.tau0sq = float(tau0 * tau0);
+  r.taum0 = float(taum0);
+  r.taum0sq = float(taum0 * taum0);
+  r.cf = float(18.0 * p->cs * d2);
+  r.cm = float(36.0 * p->cs * d2);
+  h->lattice_bytes = size_t(lbk::kNPop) * size_t(g.plane) * esize;
+  h->adj_lattice_bytes = size_t(lbk::kNPop) * size_t(ga.plane) * 4;
+  h->workspace_bytes = round_up(workspace_doubles(g) * sizeof(double), kAlign);
+  h->adj_acc_bytes = round_up(size_t(lbk::adj_step_blocks(g)) * sizeof(double), kAlign);
+  *out = h;
+  return LBMHD_OK;
+}
+
+int lbmhd_destroy(lbmhd_t* h) {
+  delete h;
+  return LBMHD_OK;
+}
+
+int lbmhd_sizes(const lbmhd_t* h, size_t* lattice, size_t* workspace, size_t* adj_lattice,
+                size_t* adj_acc) {
+  if (!h) return LBMHD_ERR_INVALID_ARG;
+  if (lattice) *lattice = h->lattice_bytes;
+  if (workspace) *workspace = h->workspace_bytes;
+  if (adj_lattice) *adj_lattice = h->adj_lattice_bytes;
+  if (adj_acc) *adj_acc = h->adj_acc_bytes;
+  return LBMHD_OK;
+}
+
+int lbmhd_bind(lbmhd_t* h, void* lat_a, size_t lat_a_bytes, void* lat_b, size_t lat_b_bytes,
+               void* workspace, size_t workspace_bytes, void* stream) {
+  if (!h) return LBMHD_ERR_INVALID_ARG;
+  h->bound = false;
+  if (!lat_a || !lat_b || !workspace)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null buffer passed to lbmhd_bind");
+  if (lat_a_bytes < h->lattice_bytes || lat_b_bytes < h->lattice_bytes ||
+      workspace_bytes < h->workspace_bytes)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "buffer smaller than lbmhd_sizes() requires");
+  if (!aligned(lat_a) || !aligned(lat_b) || !aligned(workspace))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+  if (overlap(lat_a, h->lattice_bytes, lat_b, h->lattice_bytes) ||
+      overlap(lat_a, h->lattice_bytes, workspace, h->workspace_bytes) ||
+      overlap(lat_b, h->lattice_bytes, workspace, h->workspace_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "bound buffers overlap");
+  h->lat[0] = lat_a;
+  h->lat[1] = lat_b;
+  h->ws = static_cast<double*>(workspace);
+  h->stream = static_cast<hipStream_t>(stream);
+  h->cur = 0;
+  h->step = 0;
+  h->bound = true;
+  return LBMHD_OK;
+}
+
+int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const double* uy,
+                      const double* bx, const double* by) {
+  if (int rc = need_bound(h)) return rc;
+  if (!rho || !ux || !uy || !bx || !by) return fail(h, LBMHD_ERR_INVALID_ARG, "null field");
+  hipError_t e = lbk::launch_init(h->p.storage, rho, ux, uy, bx, by, h->lat[0], h->geo,
+                                    h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "init launch");
+  h->cur = 0;
+  h->step = 0;
+  return LBMHD_OK;
+}
+
+int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
+  if (int rc = need_bound(h)) return rc;
+  if (nsteps < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
+  for (int64_t t = 0; t < nsteps; ++t) {
+    // C_S = 0 makes the closure the identity (tau = tau0): use the plain kernel.
+    hipError_t e = lbk::launch_step(h->p.storage, h->p.les != 0 && h->p.cs > 0.0, h->lat[h->cur],
+                                      h->lat[1 - h->cur], h->geo, h->rates, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "step launch");
+    h->cur = 1 - h->cur;
+    ++h->step;
+  }
+  return LBMHD_OK;
+}
+
+int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst) {
+  if (int rc = need_bound(h)) return rc;
+  if (!src || !dst || !aligned(src) || !aligned(dst))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null or unaligned lattice");
+  if (overlap(src, h->lattice_bytes, dst, h->lattice_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "src and dst overlap");
+  for (const void* b : {(const void*)h->lat[0], (const void*)h->lat[1]})
+    if (overlap(dst, h->lattice_bytes, b, h->lattice_bytes))
+      return fail(h, LBMHD_ERR_INVALID_ARG, "dst overlaps a bound lattice");
+  hipError_t e = lbk::launch_step(h->p.storage, h->p.les != 0 && h->p.cs > 0.0, src, dst,
+                                  h->geo, h->rates, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "step launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_macro(lbmhd_t* h, double* rho, double* ux, double* uy, double* bx, double* by) {
+  if (int rc = need_bound(h)) return rc;
+  if (!rho || !ux || !uy || !bx || !by) return fail(h, LBMHD_ERR_INVALID_ARG, "null field");
+  hipError_t e = lbk::launch_macro(h->p.storage, h->lat[h->cur], rho, ux, uy, bx, by, h->geo,
+                                     h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "macro launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out) {
+  if (int rc = need_bound(h)) return rc;
+  if (!out) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
+  double v[lbk::kDiagSlots];
+  if (int rc = run_diag(h, h->lat[h->cur], v)) return rc;
+  out->mass = v[0];
+  out->mom_x = v[1];
+  out->mom_y = v[2];
+  out->flux_x = v[3];
+  out->flux_y = v[4];
+  out->e_kin = v[5];
+  out->e_mag = v[6];
+  out->cross_helicity = v[7];
+  out->enstrophy = v[8];
+  out->current_sq = v[9];
+  out->nonfinite = int64_t(v[10]);
+  out->max_abs_divB = v[11];
+  out->max_u = v[12];
+  out->step = h->step;
+  if (out->nonfinite > 0)
+    return fail(h, LBMHD_ERR_NONFINITE,
+                std::to_string(out->nonfinite) + " sites hold non-finite populations");
+  return LBMHD_OK;
+}
+
+int lbmhd_get_populations(lbmhd_t* h, double* out) {
+  if (int rc = need_bound(h)) return rc;
+  if (!out) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
+  hipError_t e = lbk::launch_decode(h->p.storage, h->lat[h->cur], out, h->geo, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "decode launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_set_populations(lbmhd_t* h, const double* in, int64_t step) {
+  if (int rc = need_bound(h)) return rc;
+  if (!in || step < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "null input or negative step");
+  hipError_t e = lbk::launch_encode(h->p.storage, in, h->lat[0], h->geo, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "encode launch");
+  h->cur = 0;
+  h->step = step;
+  return LBMHD_OK;
+}
+
+int lbmhd_save_state(lbmhd_t* h, void* dst) {
+  if (int rc = need_bound(h)) return rc;
+  if (!dst || !aligned(dst)) return fail(h, LBMHD_ERR_INVALID_ARG, "null or unaligned dst");
+  hipError_t e = lbk::launch_copy(h->lat[h->cur], dst, h->lattice_bytes, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "copy launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_load_state(lbmhd_t* h, const void* src, int64_t step) {
+  if (int rc = need_bound(h)) return rc;
+  if (!src || !aligned(src) || step < 0)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null or unaligned src, or negative step");
+  hipError_t e = lbk::launch_copy(src, h->lat[0], h->lattice_bytes, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "copy launch");
+  h->cur = 0;
+  h->step = step;
+  return LBMHD_OK;
+}
+
+int lbmhd_get_step(const lbmhd_t* h, int64_t* step) {
+  if (!h || !step) return LBMHD_ERR_INVALID_ARG;
+  *step = h->step;
+  return LBMHD_OK;
+}
+
+int lbmhd_energy(lbmhd_t* h, const void* state, double* J) {
+  if (int rc = need_bound(h)) return rc;
+  if (!J) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
+  double v[lbk::kDiagSlots];
+  if (int rc = run_diag(h, state ? state : h->lat[h->cur], v)) return rc;
+  *J = v[5] + v[6];
+  return LBMHD_OK;
+}
+
+int lbmhd_adj_seed_energy(lbmhd_t* h, const void* state, float* lam) {
+  if (int rc = need_bound(h)) return rc;
+  if (!state || !lam) return fail(h, LBMHD_ERR_INVALID_ARG, "null state or lambda");
+  hipError_t e = lbk::launch_adj_seed(h->p.storage, state, lam, h->geo, h->geoa, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint seed launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float* lam_prev,
+                   double* acc) {
+  if (int rc = need_bound(h)) return rc;
+  if (!state_n || !lam_next || !lam_prev || !acc)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
+  if (overlap(lam_next, h->adj_lattice_bytes, lam_prev, h->adj_lattice_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "lam_prev overlaps lam_next");
+  hipError_t e = lbk::launch_adj_step(h->p.storage, h->p.les != 0, state_n, lam_next, lam_prev,
+                                        acc, h->geo, h->geoa, h->rates,
+                                        h->p.delta * h->p.delta, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_adj_acc_total(lbmhd_t* h, const double* acc, double* out) {
+  if (int rc = need_bound(h)) return rc;
+  if (!acc || !out) return fail(h, LBMHD_ERR_INVALID_ARG, "null argument");
+  double* dev = ws_out(h) + lbk::kDiagSlots;
+  hipError_t e = lbk::launch_sum(acc, (long long)(h->adj_acc_bytes / sizeof(double)), dev,
+                                   h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sum launch");
+  e = hipMemcpyAsync(out, dev, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sum copy");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sum synchronise");
+  return LBMHD_OK;
+}
+
+int lbmhd_adj_fields(lbmhd_t* h, const float* lam0, const double* rho0, const double* ux0,
+                     const double* uy0, const double* bx0, const double* by0, double* g_ux,
+                     double* g_uy, double* g_bx, double* g_by) {
+  if (int rc = need_bound(h)) return rc;
+  if (!lam0 || !rho0 || !ux0 || !uy0 || !bx0 || !by0 || !g_ux || !g_uy || !g_bx || !g_by)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
+  hipError_t e = lbk::launch_adj_fields(lam0, rho0, ux0, uy0, bx0, by0, g_ux, g_uy, g_bx, g_by,
+                                          h->geoa, h->p.nx, h->p.ny, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint fields launch");
+  return LBMHD_OK;
+}
+
+}  // extern "C"

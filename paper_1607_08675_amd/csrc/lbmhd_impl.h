@@ -1,0 +1,73 @@
+// lbmhd_impl.h -- internal declarations shared by the kernels and the C ABI
+// of the gfx950 lattice Boltzmann MHD library (not installed, not part of
+// the public interface in include/lbmhd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbmhd.h"
+
+namespace lbk {
+
+// Device layout of one lattice: 19 planes, each ny rows of `pitch` elements
+// (pitch >= nx, a multiple of 256 bytes), plane stride `plane` elements.
+struct Geom {
+  int nx, ny;
+  int pitch;
+  long long plane;
+};
+
+// Collision constants, precomputed on the host in FP64 and rounded once.
+struct Rates {
+  float s3q;      // s_3 / 4 with s_3 = s_4 = 1 / tau0 (fixed-rate case)
+  float s5q;      // s_5 / 12 (= s_6 / 12)
+  float s7q;      // s_7 / 180
+  float s8q;      // s_8 / 20
+  float sm;       // s_m = 1 / tau_m0 (fixed-rate case)
+  float tau0;     // 3 nu + 1/2
+  float tau0sq;   // tau0^2
+  float taum0;    // 3 eta + 1/2
+  float taum0sq;  // tau_m0^2
+  float cf;       // 18 C_S Delta^2
+  float cm;       // 36 C_S Delta^2
+};
+
+constexpr int kNPop = 19;
+constexpr int kDiagSlots = 16;   // doubles per diagnostics partial
+constexpr int kDiagBlocks = 1024;
+
+// Forward step: dst = C(S(src)).
+hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
+                       const Rates& r, hipStream_t s);
+// Equilibrium initialisation from FP64 fields.
+hipError_t launch_init(int storage, const double* rho, const double* ux, const double* uy,
+                       const double* bx, const double* by, void* lat, const Geom& g,
+                       hipStream_t s);
+// Plain populations <-> encoded lattice.
+hipError_t launch_decode(int storage, const void* lat, double* out, const Geom& g, hipStream_t s);
+hipError_t launch_encode(int storage, const double* in, void* lat, const Geom& g, hipStream_t s);
+// Macroscopic fields of an encoded lattice (no streaming).
+hipError_t launch_macro(int storage, const void* lat, double* rho, double* ux, double* uy,
+                        double* bx, double* by, const Geom& g, hipStream_t s);
+// Byte copy (vector loads/stores) for checkpoints.
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+// Diagnostics: macro planes (5 x nx*ny doubles at ws), partials, final 16
+// doubles at out_dev.
+hipError_t launch_diag(int storage, const void* lat, double* ws, double* out_dev, const Geom& g,
+                       hipStream_t s);
+
+// Adjoint.
+hipError_t launch_adj_seed(int storage, const void* lat, float* lam, const Geom& g,
+                           const Geom& ga, hipStream_t s);
+hipError_t launch_adj_step(int storage, bool les, const void* state, const float* lam_next,
+                           float* lam_prev, double* acc, const Geom& g, const Geom& ga,
+                           const Rates& r, double delta2, hipStream_t s);
+int adj_step_blocks(const Geom& g);
+hipError_t launch_sum(const double* in, long long n, double* out_dev, hipStream_t s);
+hipError_t launch_adj_fields(const float* lam0, const double* rho0, const double* ux0,
+                             const double* uy0, const double* bx0, const double* by0,
+                             double* gux, double* guy, double* gbx, double* gby, const Geom& ga,
+                             int nx, int ny, hipStream_t s);
+
+}  // namespace lbk

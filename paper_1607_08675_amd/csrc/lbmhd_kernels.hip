@@ -1,0 +1,552 @@
+// lbmhd_kernels.hip -- gfx950 kernels of the lattice Boltzmann MHD update
+// (Flint & Vahala, arXiv:1607.08675): fused pull-stream + moment-space
+// collision, equilibrium initialisation, encode/decode, macroscopic fields
+// and FP64 diagnostics.
+//
+// Data layout in HBM (one lattice): 19 planes [plane][y][pitch], x fastest.
+// Planes 0..8 = f_0..f_8 (D2Q9), 9..13 = g_x,0..4, 14..18 = g_y,0..4 (D2Q5),
+// velocities in the order of Sec. 3.  Every plane stores the deviation from
+// the rest state (f_i - w_i, g unchanged): this keeps the low-order bits of
+// rho u = sum c_i f_i that a plain f_i would spend on the large w_i.
+//
+// The step is HBM-bound: 19 loads + 19 stores per site against ~200 FP32
+// operations, so the kernel is laid out for bandwidth, not for matrix cores:
+// one site per thread, a wavefront covers 64 consecutive x of one row, all
+// 19 gathers are issued before any arithmetic, the +-1 x shifts of the pull
+// are absorbed by L2 (neighbouring tiles are scheduled on the same XCD by
+// the block remap below), and stores are aligned and non-temporal.
+#include <math.h>
+
+#include "lbmhd_impl.h"
+
+#ifndef LBMHD_TX
+#define LBMHD_TX 256
+#endif
+#ifndef LBMHD_TY
+#define LBMHD_TY 1
+#endif
+
+namespace lbk {
+namespace {
+
+// ------------------------------------------------------------ storage codec
+template <int ST>
+struct Codec;
+template <>
+struct Codec<LBMHD_FP32> {
+  using T = float;
+  __device__ static __forceinline__ float dec(float v) { return v; }
+  __device__ static __forceinline__ float enc(float v) { return v; }
+};
+template <>
+struct Codec<LBMHD_FP16> {
+  using T = _Float16;
+  // deviation = half * 2^-10; scaling by a power of two is exact, the only
+  // rounding is the RNE conversion to half.
+  __device__ static __forceinline__ float dec(_Float16 v) { return float(v) * 0x1p-10f; }
+  __device__ static __forceinline__ _Float16 enc(float v) { return _Float16(v * 0x1p10f); }
+};
+
+// D2Q9 / D2Q5 lattice (Sec. 3 velocity lists) and the weights under which the
+// equilibria reproduce the printed moment tables.
+__device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kMx[5] = {0, 1, 0, -1, 0};
+__device__ constexpr int kMy[5] = {0, 0, 1, 0, -1};
+__device__ constexpr double kW[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+__device__ constexpr double kWm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Renumber them so that
+// each XCD receives one contiguous range of tiles: tiles that share rows and
+// the +-1 halo columns then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int q = nb / kXcd, rem = nb % kXcd;
+  const int xcd = b % kXcd, local = b / kXcd;
+  return (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + local;
+}
+
+// ------------------------------------------------------------ the collision
+// One collision in deviation variables.  f[9] = f_i - w_i and g[10] (g_x,
+// then g_y) in, post-collision values out.
+//  M = T f with the rows of eq. FluidTMatrix; the equilibrium moments of
+//  eq. KinMomentEq (w carries rho = 1, so T(f - w) differs from T f only in
+//  M_0 and M_8, by 1 and 5/3); f* = f - T^-1 diag(s) (M - M^eq) with
+//  T^-1 = T^T diag(1/9, 1/6, 1/6, 1/4, 1/4, 1/12, 1/12, 1/180, 1/20)
+//  expanded by hand; g* = g - s_m (g - g^eq) with g^eq of Sec. 3.
+//  With LES the shear rate and the magnetic rate follow the Smagorinsky-MHD
+//  closure: tau = (tau0 + sqrt(tau0^2 + 18 C_S Delta^2 Q / rho)) / 2 with
+//  Q = sqrt((M4 - M4eq)^2 + 4 (M3 - M3eq)^2) (|S| = 3 Q / (2 rho tau)), and
+//  tau_m = (tau_m0 + sqrt(tau_m0^2 + 36 C_S Delta^2 |A|)) / 2 with A the
+//  antisymmetric non-equilibrium first moment of g (j = -3 A / tau_m).
+template <bool LES>
+__device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rates& r) {
+  const float a13 = f[1] + f[3], a24 = f[2] + f[4];
+  const float d13 = f[1] - f[3], d24 = f[2] - f[4];
+  const float s57 = f[5] + f[7], s68 = f[6] + f[8];
+  const float d57 = f[5] - f[7], d68 = f[6] - f[8];
+  const float dd = s57 + s68;
+  const float drho = f[0] + a13 + a24 + dd;
+  const float rho = 1.0f + drho;
+  const float jx = d13 + d57 - d68;
+  const float jy = d24 + d57 + d68;
+  const float M3 = s57 - s68;
+  const float M4 = a13 - a24;
+  const float M5 = jx - 3.0f * d13;
+  const float M6 = jy - 3.0f * d24;
+  const float M7 = 4.0f * f[0] - 5.0f * (a13 + a24) + 4.0f * dd;
+  const float M8 = 4.0f * f[0] - dd;
+
+  const float ir = frcp(rho);
+  const float ux = jx * ir, uy = jy * ir;
+  const float Bx = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+  const float By = (g[5] + g[6]) + (g[7] + g[8]) + g[9];
+  const float jxux = jx * ux, jyuy = jy * uy;
+  const float jj = jxux + jyuy;
+  const float n3 = M3 - (jx * uy - Bx * By);
+  const float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
+  const float n5 = M5 + jx;
+  const float n6 = M6 + jy;
+  const float n7 = M7 + 3.0f * jj;
+  const float n8 = M8 - (5.0f / 3.0f) * drho + 3.0f * jj;
+  const float E = ux * By - uy * Bx;
+
+  float s3q, sm;
+  if (LES) {
+    const float Q = fsqrt(n4 * n4 + 4.0f * (n3 * n3));
+    const float tau = 0.5f * (r.tau0 + fsqrt(r.tau0sq + r.cf * Q * ir));
+    s3q = 0.25f * frcp(tau);
+    const float A = (g[6] - g[8]) - (g[2] - g[4]) - 2.0f * E;
+    const float taum = 0.5f * (r.taum0 + fsqrt(r.taum0sq + r.cm * fabsf(A)));
+    sm = frcp(taum);
+  } else {
+    s3q = r.s3q;
+    sm = r.sm;
+  }
+  const float r3 = s3q * n3, r4 = s3q * n4;
+  const float r5 = r.s5q * n5, r6 = r.s5q * n6;
+  const float r7 = r.s7q * n7, r8 = r.s8q * n8;
+  const float c58 = 4.0f * r7 - r8;
+  const float c14 = 5.0f * r7;
+  f[0] -= 4.0f * (r7 + r8);
+  f[1] -= r4 - 2.0f * r5 - c14;
+  f[2] -= -r4 - 2.0f * r6 - c14;
+  f[3] -= r4 + 2.0f * r5 - c14;
+  f[4] -= -r4 + 2.0f * r6 - c14;
+  f[5] -= r3 + r5 + r6 + c58;
+  f[6] -= -r3 - r5 + r6 + c58;
+  f[7] -= r3 - r5 - r6 + c58;
+  f[8] -= -r3 + r5 - r6 + c58;
+
+  // g^eq of the four moving directions is B/6 +- E/2; the rest direction takes
+  // the remainder B - 4 (B/6) so that sum_k g^eq = B holds in FP32 as well
+  // (6 * fl(1/6) != 1 would otherwise feed a systematic drift into B).
+  const float bx6 = Bx * (1.0f / 6.0f), by6 = By * (1.0f / 6.0f), he = 0.5f * E;
+  g[0] -= sm * (g[0] - (Bx - 4.0f * bx6));
+  g[1] -= sm * (g[1] - bx6);
+  g[2] -= sm * (g[2] - (bx6 - he));
+  g[3] -= sm * (g[3] - bx6);
+  g[4] -= sm * (g[4] - (bx6 + he));
+  g[5] -= sm * (g[5] - (By - 4.0f * by6));
+  g[6] -= sm * (g[6] - (by6 + he));
+  g[7] -= sm * (g[7] - by6);
+  g[8] -= sm * (g[8] - (by6 - he));
+  g[9] -= sm * (g[9] - by6);
+}
+
+// --------------------------------------------------------------- the step
+// dst(x) = C(pre(x)),  pre_i(x) = src_i(x - c_i) (periodic pull; Sec. 1.2
+// streaming written as a gather).
+template <int ST, bool LES>
+__global__ __launch_bounds__(LBMHD_TX* LBMHD_TY) void k_step(
+    const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
+    Geom geo, Rates rt, int tiles_x) {
+  using C = Codec<ST>;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int x = (b % tiles_x) * LBMHD_TX + int(threadIdx.x % LBMHD_TX);
+  const int y = (b / tiles_x) * LBMHD_TY + int(threadIdx.x / LBMHD_TX);
+  if (x >= geo.nx || y >= geo.ny) return;
+  const int xm = x == 0 ? geo.nx - 1 : x - 1;
+  const int xp = x == geo.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? geo.ny - 1 : y - 1;
+  const int yp = y == geo.ny - 1 ? 0 : y + 1;
+  const unsigned r0 = unsigned(y) * geo.pitch, rm = unsigned(ym) * geo.pitch,
+                 rp = unsigned(yp) * geo.pitch;
+  const long long P = geo.plane;
+  // source offsets of the 9 + 5 pulls: x - c
+  const unsigned o[9] = {r0 + x,  r0 + xm, rm + x,  r0 + xp, rp + x,
+                         rm + xm, rm + xp, rp + xp, rp + xm};
+  float f[9], g[10];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = C::dec(src[i * P + o[i]]);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    g[k] = C::dec(src[(9 + k) * P + o[k]]);
+    g[5 + k] = C::dec(src[(14 + k) * P + o[k]]);
+  }
+  collide<LES>(f, g, rt);
+  const unsigned od = r0 + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(C::enc(f[i]), dst + i * P + od);
+#pragma unroll
+  for (int q = 0; q < 10; ++q) __builtin_nontemporal_store(C::enc(g[q]), dst + (9 + q) * P + od);
+}
+
+// ------------------------------------------------------- initialisation etc.
+// f^eq - w and g^eq of Sec. 3 in FP64 at one site.
+__device__ __forceinline__ void equilibrium_dev(double rho, double ux, double uy, double bx,
+                                                double by, double (&df)[9], double (&gq)[10]) {
+  const double u2 = ux * ux + uy * uy, b2 = bx * bx + by * by;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double cu = kCx[i] * ux + kCy[i] * uy;
+    const double cb = kCx[i] * bx + kCy[i] * by;
+    const double c2 = double(kCx[i] * kCx[i] + kCy[i] * kCy[i]);
+    df[i] = kW[i] * (rho - 1.0) + kW[i] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * u2) +
+            4.5 * kW[i] * (0.5 * b2 * c2 - cb * cb);
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double cu = kMx[k] * ux + kMy[k] * uy;
+    const double cb = kMx[k] * bx + kMy[k] * by;
+    gq[k] = kWm[k] * (bx + 3.0 * (cu * bx - cb * ux));
+    gq[5 + k] = kWm[k] * (by + 3.0 * (cu * by - cb * uy));
+  }
+}
+
+template <int ST>
+__global__ void k_init(const double* __restrict__ rho, const double* __restrict__ ux,
+                       const double* __restrict__ uy, const double* __restrict__ bx,
+                       const double* __restrict__ by, typename Codec<ST>::T* __restrict__ lat,
+                       Geom geo) {
+  using C = Codec<ST>;
+  const long long n = (long long)geo.nx * geo.ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / geo.nx), x = int(s % geo.nx);
+  double df[9], gq[10];
+  equilibrium_dev(rho[s], ux[s], uy[s], bx[s], by[s], df, gq);
+  const long long o = (long long)y * geo.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lat[i * geo.plane + o] = C::enc(float(df[i]));
+#pragma unroll
+  for (int q = 0; q < 10; ++q) lat[(9 + q) * geo.plane + o] = C::enc(float(gq[q]));
+}
+
+template <int ST>
+__global__ void k_decode(const typename Codec<ST>::T* __restrict__ lat, double* __restrict__ out,
+                         Geom geo) {
+  using C = Codec<ST>;
+  const long long n = (long long)geo.nx * geo.ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / geo.nx), x = int(s % geo.nx);
+  const long long o = (long long)y * geo.pitch + x;
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) {
+    const double w = q < 9 ? kW[q] : 0.0;
+    out[q * n + s] = w + double(C::dec(lat[q * geo.plane + o]));
+  }
+}
+
+template <int ST>
+__global__ void k_encode(const double* __restrict__ in, typename Codec<ST>::T* __restrict__ lat,
+                         Geom geo) {
+  using C = Codec<ST>;
+  const long long n = (long long)geo.nx * geo.ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / geo.nx), x = int(s % geo.nx);
+  const long long o = (long long)y * geo.pitch + x;
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) {
+    const double w = q < 9 ? kW[q] : 0.0;
+    lat[q * geo.plane + o] = C::enc(float(in[q * n + s] - w));
+  }
+}
+
+// Macroscopic fields (FP64) of the stored state at one site; returns false if
+// any population is not finite.
+template <int ST>
+__device__ __forceinline__ bool macro_site(const typename Codec<ST>::T* __restrict__ lat,
+                                           const Geom& geo, long long o, double& rho,
+                                           double& ux, double& uy, double& bx, double& by) {
+  using C = Codec<ST>;
+  float v[kNPop];
+  bool ok = true;
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) {
+    v[q] = C::dec(lat[q * geo.plane + o]);
+    ok = ok && isfinite(v[q]);
+  }
+  double dr = 0.0, jx = 0.0, jy = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    dr += double(v[i]);
+    jx += kCx[i] * double(v[i]);
+    jy += kCy[i] * double(v[i]);
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    b0 += double(v[9 + k]);
+    b1 += double(v[14 + k]);
+  }
+  rho = 1.0 + dr;
+  ux = jx / rho;
+  uy = jy / rho;
+  bx = b0;
+  by = b1;
+  return ok;
+}
+
+template <int ST>
+__global__ void k_macro(const typename Codec<ST>::T* __restrict__ lat, double* __restrict__ rho,
+                        double* __restrict__ ux, double* __restrict__ uy,
+                        double* __restrict__ bx, double* __restrict__ by, Geom geo) {
+  const long long n = (long long)geo.nx * geo.ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / geo.nx), x = int(s % geo.nx);
+  double r, a, b, c, d;
+  macro_site<ST>(lat, geo, (long long)y * geo.pitch + x, r, a, b, c, d);
+  rho[s] = r;
+  ux[s] = a;
+  uy[s] = b;
+  bx[s] = c;
+  by[s] = d;
+}
+
+__global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n16) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// ------------------------------------------------------------ diagnostics
+// Pass 1: FP64 macro planes (rho, ux, uy, bx, by) into ws; rho = NaN marks a
+// site with a non-finite population.
+template <int ST>
+__global__ void k_diag_macro(const typename Codec<ST>::T* __restrict__ lat, double* __restrict__ ws,
+                             Geom geo) {
+  const long long n = (long long)geo.nx * geo.ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / geo.nx), x = int(s % geo.nx);
+  double r, a, b, c, d;
+  const bool ok = macro_site<ST>(lat, geo, (long long)y * geo.pitch + x, r, a, b, c, d);
+  ws[s] = ok ? r : __builtin_nan("");
+  ws[n + s] = a;
+  ws[2 * n + s] = b;
+  ws[3 * n + s] = c;
+  ws[4 * n + s] = d;
+}
+
+enum {
+  kSumMass = 0, kSumMx, kSumMy, kSumBx, kSumBy, kSumEk, kSumEm, kSumHc, kSumOm, kSumJ2,
+  kSumBad, kNSum,          // slots 0..10 are sums
+  kMaxDiv = kNSum, kMaxU,  // slots 11, 12 are maxima
+  kNRed
+};
+
+template <int NT>
+__device__ void block_reduce(double (&v)[kNRed], double* __restrict__ out) {
+  __shared__ double sh[kNRed][NT];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kNRed; ++q) sh[q][t] = v[q];
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int q = 0; q < kNSum; ++q) sh[q][t] += sh[q][t + w];
+#pragma unroll
+      for (int q = kNSum; q < kNRed; ++q) sh[q][t] = fmax(sh[q][t], sh[q][t + w]);
+    }
+    __syncthreads();
+  }
+  if (t < kNRed) out[t] = sh[t][0];
+}
+
+// Pass 2: per-block partial sums / maxima over a grid-stride range of sites.
+__global__ __launch_bounds__(256) void k_diag_reduce(const double* __restrict__ ws,
+                                                     double* __restrict__ part, int nx, int ny) {
+  const long long n = (long long)nx * ny;
+  const double* rho = ws;
+  const double* ux = ws + n;
+  const double* uy = ws + 2 * n;
+  const double* bx = ws + 3 * n;
+  const double* by = ws + 4 * n;
+  double v[kNRed];
+#pragma unroll
+  for (int q = 0; q < kNRed; ++q) v[q] = 0.0;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int y = int(s / nx), x = int(s % nx);
+    const long long row = (long long)y * nx;
+    const long long e = row + (x == nx - 1 ? 0 : x + 1), w = row + (x == 0 ? nx - 1 : x - 1);
+    const long long nn = (long long)(y == ny - 1 ? 0 : y + 1) * nx + x;
+    const long long so = (long long)(y == 0 ? ny - 1 : y - 1) * nx + x;
+    const double r = rho[s], u = ux[s], vv = uy[s], b0 = bx[s], b1 = by[s];
+    const double jx = r * u, jy = r * vv;
+    v[kSumMass] += r;
+    v[kSumMx] += jx;
+    v[kSumMy] += jy;
+    v[kSumBx] += b0;
+    v[kSumBy] += b1;
+    v[kSumEk] += (jx * jx + jy * jy) / (2.0 * r);
+    v[kSumEm] += 0.5 * (b0 * b0 + b1 * b1);
+    v[kSumHc] += u * b0 + vv * b1;
+    const double div = 0.5 * (bx[e] - bx[w]) + 0.5 * (by[nn] - by[so]);
+    const double om = 0.5 * (uy[e] - uy[w]) - 0.5 * (ux[nn] - ux[so]);
+    const double jz = 0.5 * (by[e] - by[w]) - 0.5 * (bx[nn] - bx[so]);
+    v[kSumOm] += 0.5 * om * om;
+    v[kSumJ2] += 0.5 * jz * jz;
+    v[kSumBad] += isfinite(r) ? 0.0 : 1.0;
+    v[kMaxDiv] = fmax(v[kMaxDiv], fabs(div));
+    v[kMaxU] = fmax(v[kMaxU], sqrt(u * u + vv * vv));
+  }
+  block_reduce<256>(v, part + (long long)blockIdx.x * kDiagSlots);
+}
+
+// Pass 3: one block folds the partials.
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ part, int nparts,
+                                                    double* __restrict__ out) {
+  double v[kNRed];
+#pragma unroll
+  for (int q = 0; q < kNRed; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < kNSum; ++q) v[q] += part[(long long)b * kDiagSlots + q];
+#pragma unroll
+    for (int q = kNSum; q < kNRed; ++q) v[q] = fmax(v[q], part[(long long)b * kDiagSlots + q]);
+  }
+  block_reduce<256>(v, out);
+}
+
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ in, long long n,
+                                             double* __restrict__ out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) a += in[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+inline unsigned blocks_for(long long n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
+                       const Rates& r, hipStream_t s) {
+  const int tiles_x = (g.nx + LBMHD_TX - 1) / LBMHD_TX;
+  const int tiles_y = (g.ny + LBMHD_TY - 1) / LBMHD_TY;
+  const dim3 grid(unsigned(tiles_x * tiles_y)), block(LBMHD_TX * LBMHD_TY);
+  if (storage == LBMHD_FP32) {
+    auto* a = static_cast<const float*>(src);
+    auto* b = static_cast<float*>(dst);
+    if (les)
+      hipLaunchKernelGGL((k_step<LBMHD_FP32, true>), grid, block, 0, s, a, b, g, r, tiles_x);
+    else
+      hipLaunchKernelGGL((k_step<LBMHD_FP32, false>), grid, block, 0, s, a, b, g, r, tiles_x);
+  } else {
+    auto* a = static_cast<const _Float16*>(src);
+    auto* b = static_cast<_Float16*>(dst);
+    if (les)
+      hipLaunchKernelGGL((k_step<LBMHD_FP16, true>), grid, block, 0, s, a, b, g, r, tiles_x);
+    else
+      hipLaunchKernelGGL((k_step<LBMHD_FP16, false>), grid, block, 0, s, a, b, g, r, tiles_x);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, const double* rho, const double* ux, const double* uy,
+                       const double* bx, const double* by, void* lat, const Geom& g,
+                       hipStream_t s) {
+  const unsigned nb = blocks_for((long long)g.nx * g.ny, 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_init<LBMHD_FP32>, dim3(nb), dim3(256), 0, s, rho, ux, uy, bx, by,
+                       static_cast<float*>(lat), g);
+  else
+    hipLaunchKernelGGL(k_init<LBMHD_FP16>, dim3(nb), dim3(256), 0, s, rho, ux, uy, bx, by,
+                       static_cast<_Float16*>(lat), g);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(int storage, const void* lat, double* out, const Geom& g,
+                         hipStream_t s) {
+  const unsigned nb = blocks_for((long long)g.nx * g.ny, 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_decode<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float*>(lat), out, g);
+  else
+    hipLaunchKernelGGL(k_decode<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const _Float16*>(lat), out, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(int storage, const double* in, void* lat, const Geom& g,
+                         hipStream_t s) {
+  const unsigned nb = blocks_for((long long)g.nx * g.ny, 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_encode<LBMHD_FP32>, dim3(nb), dim3(256), 0, s, in,
+                       static_cast<float*>(lat), g);
+  else
+    hipLaunchKernelGGL(k_encode<LBMHD_FP16>, dim3(nb), dim3(256), 0, s, in,
+                       static_cast<_Float16*>(lat), g);
+  return hipGetLastError();
+}
+
+hipError_t launch_macro(int storage, const void* lat, double* rho, double* ux, double* uy,
+                        double* bx, double* by, const Geom& g, hipStream_t s) {
+  const unsigned nb = blocks_for((long long)g.nx * g.ny, 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_macro<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float*>(lat), rho, ux, uy, bx, by, g);
+  else
+    hipLaunchKernelGGL(k_macro<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const _Float16*>(lat), rho, ux, uy, bx, by, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const long long n16 = (long long)(bytes / 16);
+  const unsigned nb = unsigned(n16 < 256LL * 4096 ? blocks_for(n16, 256) : 4096u);
+  if (n16 > 0)
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, static_cast<const uint4*>(src),
+                       static_cast<uint4*>(dst), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(int storage, const void* lat, double* ws, double* out_dev, const Geom& g,
+                       hipStream_t s) {
+  const long long n = (long long)g.nx * g.ny;
+  const unsigned nb = blocks_for(n, 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_diag_macro<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float*>(lat), ws, g);
+  else
+    hipLaunchKernelGGL(k_diag_macro<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const _Float16*>(lat), ws, g);
+  double* part = ws + 5 * n;
+  const int nparts = int(std::min<long long>(kDiagBlocks, blocks_for(n, 256)));
+  hipLaunchKernelGGL(k_diag_reduce, dim3(nparts), dim3(256), 0, s, ws, part, g.nx, g.ny);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* in, long long n, double* out_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, in, n, out_dev);
+  return hipGetLastError();
+}
+
+}  // namespace lbk

@@ -1,0 +1,201 @@
+"""``Lattice``: a thin Python handle over the C ABI of ``liblbmhd.so``.
+
+PyTorch owns every device buffer (two encoded lattices and the workspace) and
+supplies the stream; the library runs every step of the update in its own HIP
+kernels.  Field arrays are float64 (ny, nx); population arrays are float64
+(19, ny, nx) with planes f_0..f_8, g_x,0..4, g_y,0..4 (Flint & Vahala,
+arXiv:1607.08675, Sec. 3 velocity order).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _capi as C
+
+FIELDS = ("rho", "ux", "uy", "bx", "by")
+
+
+@dataclass
+class LBMHDConfig:
+    """Lattice size and physical parameters (lattice units).
+
+    nu, eta: viscosity and resistivity (tau0 = 3 nu + 1/2, tau_m0 = 3 eta + 1/2).
+    s5 (= s6), s7, s8: rates of the non-hydrodynamic moments.
+    les, cs, delta: Smagorinsky-MHD closure switch, C_S and filter width.
+    storage: "fp32" or "fp16" (deviation from the rest state, FP16 scaled by 2^10).
+    """
+    nx: int
+    ny: int
+    nu: float = 0.01
+    eta: float = 0.01
+    s5: float = 1.0
+    s7: float = 1.0
+    s8: float = 1.0
+    les: bool = True
+    cs: float = 0.1
+    delta: float = 1.0
+    storage: str = "fp32"
+
+    def c_params(self) -> C.Params:
+        st = {"fp32": C.LBMHD_FP32, "fp16": C.LBMHD_FP16}[self.storage]
+        return C.Params(self.nx, self.ny, self.nu, self.eta, self.s5, self.s5, self.s7,
+                        self.s8, int(bool(self.les)), self.cs, self.delta, st)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """One periodic LB-MHD lattice on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, cfg: LBMHDConfig, device: str | torch.device = "cuda",
+                 stream: torch.cuda.Stream | None = None):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        L = C.lib()
+        self._L = L
+        h = ctypes.c_void_p()
+        C.check(L.lbmhd_create(ctypes.byref(cfg.c_params()), ctypes.byref(h)), "lbmhd_create")
+        self._h = h
+        sizes = [ctypes.c_size_t() for _ in range(4)]
+        C.check(L.lbmhd_sizes(h, *[ctypes.byref(s) for s in sizes]), "lbmhd_sizes", h)
+        (self.lattice_bytes, self.workspace_bytes,
+         self.adj_lattice_bytes, self.adj_acc_bytes) = (s.value for s in sizes)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._a = torch.empty(self.lattice_bytes, dtype=torch.uint8, device=self.device)
+        self._b = torch.empty(self.lattice_bytes, dtype=torch.uint8, device=self.device)
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        C.check(L.lbmhd_bind(h, _ptr(self._a), self.lattice_bytes, _ptr(self._b),
+                             self.lattice_bytes, _ptr(self._ws), self.workspace_bytes,
+                             ctypes.c_void_p(self.stream.cuda_stream)), "lbmhd_bind", h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._L.lbmhd_destroy(h)
+            self._h = None
+
+    # ----------------------------------------------------------- helpers
+    def _field(self, a) -> torch.Tensor:
+        t = torch.as_tensor(a, dtype=torch.float64)
+        t = t.expand(self.cfg.ny, self.cfg.nx) if t.dim() == 0 else t
+        if tuple(t.shape) != (self.cfg.ny, self.cfg.nx):
+            raise ValueError(f"field shape {tuple(t.shape)} != (ny, nx)")
+        return t.to(self.device).contiguous()
+
+    def _check(self, rc, what):
+        C.check(rc, what, self._h)
+
+    # ------------------------------------------------------------ the ABI
+    def init_fields(self, rho, ux, uy, bx, by) -> "Lattice":
+        fs = [self._field(a) for a in (rho, ux, uy, bx, by)]
+        self._check(self._L.lbmhd_init_fields(self._h, *[_ptr(f) for f in fs]),
+                    "lbmhd_init_fields")
+        self._keep = fs  # inputs stay alive until the stream has used them
+        return self
+
+    def step(self, n: int = 1) -> "Lattice":
+        self._check(self._L.lbmhd_step(self._h, int(n)), "lbmhd_step")
+        return self
+
+    def step_between(self, src: torch.Tensor, dst: torch.Tensor):
+        """One step from encoded lattice src into dst; the current state is untouched."""
+        if src.numel() < self.lattice_bytes or dst.numel() < self.lattice_bytes:
+            raise ValueError("state buffer too small")
+        self._check(self._L.lbmhd_step_between(self._h, _ptr(src), _ptr(dst)),
+                    "lbmhd_step_between")
+
+    def macro(self) -> dict:
+        out = [torch.empty(self.cfg.ny, self.cfg.nx, dtype=torch.float64, device=self.device)
+               for _ in FIELDS]
+        self._check(self._L.lbmhd_macro(self._h, *[_ptr(o) for o in out]), "lbmhd_macro")
+        return dict(zip(FIELDS, out))
+
+    def diag(self, raise_nonfinite: bool = False) -> dict:
+        d = C.Diag()
+        rc = self._L.lbmhd_diag(self._h, ctypes.byref(d))
+        if rc != C.LBMHD_ERR_NONFINITE or raise_nonfinite:
+            self._check(rc, "lbmhd_diag")
+        return d.as_dict()
+
+    def populations(self) -> torch.Tensor:
+        out = torch.empty(19, self.cfg.ny, self.cfg.nx, dtype=torch.float64, device=self.device)
+        self._check(self._L.lbmhd_get_populations(self._h, _ptr(out)), "lbmhd_get_populations")
+        return out
+
+    def set_populations(self, pops, step: int = 0) -> "Lattice":
+        t = torch.as_tensor(pops, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != (19, self.cfg.ny, self.cfg.nx):
+            raise ValueError("populations must have shape (19, ny, nx)")
+        self._check(self._L.lbmhd_set_populations(self._h, _ptr(t), int(step)),
+                    "lbmhd_set_populations")
+        self._keep = t
+        return self
+
+    def new_state_buffer(self) -> torch.Tensor:
+        return torch.empty(self.lattice_bytes, dtype=torch.uint8, device=self.device)
+
+    def save_state(self, dst: torch.Tensor | None = None) -> torch.Tensor:
+        dst = self.new_state_buffer() if dst is None else dst
+        if dst.numel() < self.lattice_bytes:
+            raise ValueError("state buffer too small")
+        self._check(self._L.lbmhd_save_state(self._h, _ptr(dst)), "lbmhd_save_state")
+        return dst
+
+    def load_state(self, src: torch.Tensor, step: int) -> "Lattice":
+        if src.numel() < self.lattice_bytes:
+            raise ValueError("state buffer too small")
+        self._check(self._L.lbmhd_load_state(self._h, _ptr(src), int(step)), "lbmhd_load_state")
+        return self
+
+    @property
+    def step_count(self) -> int:
+        v = ctypes.c_int64()
+        self._check(self._L.lbmhd_get_step(self._h, ctypes.byref(v)), "lbmhd_get_step")
+        return v.value
+
+    def energy(self, state: torch.Tensor | None = None) -> float:
+        J = ctypes.c_double()
+        p = _ptr(state) if state is not None else ctypes.c_void_p(0)
+        self._check(self._L.lbmhd_energy(self._h, p, ctypes.byref(J)), "lbmhd_energy")
+        return J.value
+
+    # -------------------------------------------------------------- adjoint
+    def new_adj_buffer(self) -> torch.Tensor:
+        return torch.empty(self.adj_lattice_bytes // 4, dtype=torch.float32, device=self.device)
+
+    def new_adj_acc(self) -> torch.Tensor:
+        return torch.zeros(self.adj_acc_bytes // 8, dtype=torch.float64, device=self.device)
+
+    def adj_seed_energy(self, state: torch.Tensor, lam: torch.Tensor):
+        self._check(self._L.lbmhd_adj_seed_energy(self._h, _ptr(state), _ptr(lam)),
+                    "lbmhd_adj_seed_energy")
+
+    def adj_step(self, state_n: torch.Tensor, lam_next: torch.Tensor, lam_prev: torch.Tensor,
+                 acc: torch.Tensor):
+        self._check(self._L.lbmhd_adj_step(self._h, _ptr(state_n), _ptr(lam_next),
+                                           _ptr(lam_prev), _ptr(acc)), "lbmhd_adj_step")
+
+    def adj_acc_total(self, acc: torch.Tensor) -> float:
+        out = ctypes.c_double()
+        self._check(self._L.lbmhd_adj_acc_total(self._h, _ptr(acc), ctypes.byref(out)),
+                    "lbmhd_adj_acc_total")
+        return out.value
+
+    def adj_fields(self, lam0: torch.Tensor, fields) -> tuple:
+        fs = [self._field(a) for a in fields]
+        outs = [torch.empty(self.cfg.ny, self.cfg.nx, dtype=torch.float64, device=self.device)
+                for _ in range(4)]
+        self._check(self._L.lbmhd_adj_fields(self._h, _ptr(lam0), *[_ptr(f) for f in fs],
+                                             *[_ptr(o) for o in outs]), "lbmhd_adj_fields")
+        return tuple(outs)
+
+    def adj_view(self, lam: torch.Tensor) -> torch.Tensor:
+        """(19, ny, nx) view of an adjoint buffer (drops the row padding)."""
+        pitch = (self.adj_lattice_bytes // 4) // (19 * self.cfg.ny)
+        return lam.view(19, self.cfg.ny, pitch)[:, :, : self.cfg.nx]

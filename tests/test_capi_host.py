@@ -1,0 +1,112 @@
+"""Host-only checks of the C ABI (no GPU work is launched).
+
+The library loads, exports every function include/lbmhd.h declares, validates
+parameters in lbmhd_create, reports sizes, and refuses device calls before
+lbmhd_bind.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_1607_08675_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_1607_08675_amd import build
+        build.build()
+    return _capi
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "lbmhd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbmhd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(capi):
+    declared = _header_functions()
+    assert len(declared) >= 20
+    assert set(declared) == set(capi.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], check=True,
+                         capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (lbmhd_\w+)", out))
+    missing = set(declared) - exported
+    assert not missing, missing
+    L = capi.lib()
+    for name in declared:
+        assert hasattr(L, name)
+
+
+def _params(capi, **kw):
+    base = dict(nx=64, ny=48, nu=0.01, eta=0.02, s5=1.0, s6=1.0, s7=1.1, s8=0.9, les=1,
+                cs=0.1, delta=1.0, storage=capi.LBMHD_FP32)
+    base.update(kw)
+    return capi.Params(*[base[n] for n, _ in capi.Params._fields_])
+
+
+def _create(capi, p):
+    h = ctypes.c_void_p()
+    rc = capi.lib().lbmhd_create(ctypes.byref(p), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=1), dict(ny=0), dict(nu=0.0), dict(eta=-1.0), dict(nu=float("nan")),
+    dict(s5=2.0), dict(s7=0.0), dict(s8=-0.5), dict(s5=1.1, s6=1.2), dict(les=2),
+    dict(cs=-0.1), dict(delta=0.0), dict(storage=7), dict(nx=70000, ny=70000),
+])
+def test_create_rejects_invalid_parameters(capi, bad):
+    rc, h = _create(capi, _params(capi, **bad))
+    assert rc == capi.LBMHD_ERR_INVALID_ARG
+    assert not h.value
+
+
+def test_sizes_and_layout(capi):
+    L = capi.lib()
+    for storage, esize in ((capi.LBMHD_FP32, 4), (capi.LBMHD_FP16, 2)):
+        rc, h = _create(capi, _params(capi, nx=100, ny=36, storage=storage))
+        assert rc == 0
+        s = [ctypes.c_size_t() for _ in range(4)]
+        assert L.lbmhd_sizes(h, *[ctypes.byref(x) for x in s]) == 0
+        lat, ws, adj, acc = (x.value for x in s)
+        pitch = -(-100 * esize // 256) * 256 // esize   # rows padded to 256 bytes
+        assert lat == 19 * 36 * pitch * esize
+        assert adj == 19 * 36 * 128 * 4
+        assert ws >= 5 * 100 * 36 * 8 and ws % 256 == 0
+        assert acc % 256 == 0 and acc >= 8
+        assert L.lbmhd_destroy(h) == 0
+
+
+def test_calls_before_bind_are_refused(capi):
+    L = capi.lib()
+    rc, h = _create(capi, _params(capi))
+    assert rc == 0
+    assert L.lbmhd_step(h, 1) == capi.LBMHD_ERR_NOT_BOUND
+    assert b"bind" in L.lbmhd_last_error(h)
+    d = capi.Diag()
+    assert L.lbmhd_diag(h, ctypes.byref(d)) == capi.LBMHD_ERR_NOT_BOUND
+    assert L.lbmhd_bind(h, None, 0, None, 0, None, 0, None) == capi.LBMHD_ERR_INVALID_ARG
+    step = ctypes.c_int64(-1)
+    assert L.lbmhd_get_step(h, ctypes.byref(step)) == 0 and step.value == 0
+    assert L.lbmhd_destroy(h) == 0
+    assert L.lbmhd_destroy(None) == 0
+
+
+def test_strerror_covers_codes(capi):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert capi.strerror(code) not in ("", "unknown status")
+    assert capi.strerror(-99) == "unknown status"
+
+
+def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1607_08675_amd import _capi
+    monkeypatch.setattr(_capi, "_lib", None)
+    monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no non-GPU fallback"):
+        _capi.lib()
