@@ -112,6 +112,10 @@ def fp32_leg(torch, args):
     wall = time.perf_counter() - t0
     d = lat.diag()
     per_launch = burst_ms_per_launch(torch, lat, 200)
+    # checkpoint of the final state: one plain copy kernel of lattice_bytes,
+    # the reference size for calibrating HBM byte counters
+    lat.save_state()
+    torch.cuda.synchronize()
     log(f"fp32: {ms / args.steps:.4f} ms/step, burst {per_launch:.4f} ms/launch, "
         f"nonfinite={d['nonfinite']}")
     out = dict(ms=ms, wall=wall, per_launch=per_launch, sites=n * n, diag=d)

@@ -207,20 +207,13 @@ __device__ __forceinline__ float collide_adjoint(const float (&f)[9], const floa
   return dcs;
 }
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  constexpr int kXcd = 8;
-  const int q = nb / kXcd, rem = nb % kXcd;
-  const int xcd = b % kXcd, local = b / kXcd;
-  return (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + local;
-}
-
 template <int ST, bool LES>
 __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
     const typename Dec<ST>::T* __restrict__ st, const float* __restrict__ lam_next,
     float* __restrict__ lam_prev, double* __restrict__ acc, Geom geo, Geom ga, Rates rt,
     AdjConsts ac, int tiles_x) {
   using D = Dec<ST>;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = int(blockIdx.x);
   const int x = (b % tiles_x) * LBMHD_ADJ_TX + int(threadIdx.x);
   const int y = b / tiles_x;
   float dcs = 0.0f;

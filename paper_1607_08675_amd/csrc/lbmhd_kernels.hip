@@ -10,21 +10,18 @@
 // rho u = sum c_i f_i that a plain f_i would spend on the large w_i.
 //
 // The step is HBM-bound: 19 loads + 19 stores per site against ~200 FP32
-// operations, so the kernel is laid out for bandwidth, not for matrix cores:
-// one site per thread, a wavefront covers 64 consecutive x of one row, all
-// 19 gathers are issued before any arithmetic, the +-1 x shifts of the pull
-// are absorbed by L2 (neighbouring tiles are scheduled on the same XCD by
-// the block remap below), and stores are aligned and non-temporal.
+// operations, so the kernel is laid out for bandwidth, not for matrix cores.
+// A thread owns V consecutive sites of one row (V = 1 for FP32 storage, V = 2
+// for FP16 so that every lane moves 4-byte words); a 256-thread block owns
+// 256 V consecutive sites.  All 19 gathers are issued before any arithmetic;
+// a plane that streams along x is read with the aligned vector of the
+// thread's own sites plus one edge element, the +-1 shifts being served by
+// the caches; stores are aligned and non-temporal.  Blocks run in plain row
+// order (a remap giving each XCD a contiguous band of tiles measured slower).
 #include <math.h>
 
 #include "lbmhd_impl.h"
 
-#ifndef LBMHD_TX
-#define LBMHD_TX 256
-#endif
-#ifndef LBMHD_TY
-#define LBMHD_TY 1
-#endif
 
 namespace lbk {
 namespace {
@@ -47,6 +44,22 @@ struct Codec<LBMHD_FP16> {
   __device__ static __forceinline__ _Float16 enc(float v) { return _Float16(v * 0x1p10f); }
 };
 
+// V consecutive stored elements moved as one vector access.
+template <typename T, int V>
+struct Vec;
+template <>
+struct Vec<float, 1> {
+  typedef float type;
+};
+template <>
+struct Vec<_Float16, 1> {
+  typedef _Float16 type;
+};
+template <>
+struct Vec<_Float16, 2> {
+  typedef _Float16 type __attribute__((ext_vector_type(2)));
+};
+
 // D2Q9 / D2Q5 lattice (Sec. 3 velocity lists) and the weights under which the
 // equilibria reproduce the printed moment tables.
 __device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -56,19 +69,15 @@ __device__ constexpr int kMy[5] = {0, 0, 1, 0, -1};
 __device__ constexpr double kW[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 __device__ constexpr double kWm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+// velocity (c_x, c_y) of the population held by each of the 19 planes
+__device__ constexpr int kPlaneCx[kNPop] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0,
+                                            1, 0, -1, 0, 0, 1,  0, -1, 0};
+__device__ constexpr int kPlaneCy[kNPop] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0,
+                                            0, 1, 0, -1, 0, 0, 1,  0, -1};
+constexpr int kStepThreads = 256;
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-// Blocks are dispatched round-robin over the 8 XCDs.  Renumber them so that
-// each XCD receives one contiguous range of tiles: tiles that share rows and
-// the +-1 halo columns then meet in the same L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  constexpr int kXcd = 8;
-  const int q = nb / kXcd, rem = nb % kXcd;
-  const int xcd = b % kXcd, local = b / kXcd;
-  return (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + local;
-}
 
 // ------------------------------------------------------------ the collision
 // One collision in deviation variables.  f[9] = f_i - w_i and g[10] (g_x,
@@ -160,40 +169,78 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
 
 // --------------------------------------------------------------- the step
 // dst(x) = C(pre(x)),  pre_i(x) = src_i(x - c_i) (periodic pull; Sec. 1.2
-// streaming written as a gather).
-template <int ST, bool LES>
-__global__ __launch_bounds__(LBMHD_TX* LBMHD_TY) void k_step(
+// streaming written as a gather).  Thread t of block b updates sites
+// x0 .. x0 + V - 1 of row y, x0 = (b mod tiles_x) * 256 V + t V, y = b / tiles_x.
+// V > 1 requires nx % V == 0.
+template <int ST, int V, bool LES>
+__global__ __launch_bounds__(kStepThreads) void k_step(
     const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
     Geom geo, Rates rt, int tiles_x) {
   using C = Codec<ST>;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int x = (b % tiles_x) * LBMHD_TX + int(threadIdx.x % LBMHD_TX);
-  const int y = (b / tiles_x) * LBMHD_TY + int(threadIdx.x / LBMHD_TX);
-  if (x >= geo.nx || y >= geo.ny) return;
-  const int xm = x == 0 ? geo.nx - 1 : x - 1;
-  const int xp = x == geo.nx - 1 ? 0 : x + 1;
+  using T = typename C::T;
+  using VT = typename Vec<T, V>::type;
+  const int x0 = ((int(blockIdx.x) % tiles_x) * kStepThreads + int(threadIdx.x)) * V;
+  const int y = int(blockIdx.x) / tiles_x;
+  if (x0 >= geo.nx) return;
+  const int xl = x0 == 0 ? geo.nx - 1 : x0 - 1;       // source of c_x = +1 planes
+  const int xr = x0 + V == geo.nx ? 0 : x0 + V;       // source of c_x = -1 planes
   const int ym = y == 0 ? geo.ny - 1 : y - 1;
   const int yp = y == geo.ny - 1 ? 0 : y + 1;
-  const unsigned r0 = unsigned(y) * geo.pitch, rm = unsigned(ym) * geo.pitch,
-                 rp = unsigned(yp) * geo.pitch;
+  // source row of a plane with velocity c_y: y - c_y, indexed by c_y + 1
+  const unsigned row[3] = {unsigned(yp) * geo.pitch, unsigned(y) * geo.pitch,
+                           unsigned(ym) * geo.pitch};
   const long long P = geo.plane;
-  // source offsets of the 9 + 5 pulls: x - c
-  const unsigned o[9] = {r0 + x,  r0 + xm, rm + x,  r0 + xp, rp + x,
-                         rm + xm, rm + xp, rp + xp, rp + xm};
-  float f[9], g[10];
+  float v[kNPop][V];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = C::dec(src[i * P + o[i]]);
+  for (int q = 0; q < kNPop; ++q) {
+    const T* __restrict__ pl = src + q * P + row[kPlaneCy[q] + 1];
+    if (V == 1 || kPlaneCx[q] == 0) {
+      const int xs = kPlaneCx[q] == 0 ? x0 : (kPlaneCx[q] == 1 ? xl : xr);
+      const VT a = *reinterpret_cast<const VT*>(pl + xs);
+      if constexpr (V == 1) {
+        v[q][0] = C::dec(a);
+      } else {
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    g[k] = C::dec(src[(9 + k) * P + o[k]]);
-    g[5 + k] = C::dec(src[(14 + k) * P + o[k]]);
+        for (int j = 0; j < V; ++j) v[q][j] = C::dec(a[j]);
+      }
+    } else if constexpr (V > 1) {
+      const VT a = *reinterpret_cast<const VT*>(pl + x0);
+      const float e = C::dec(pl[kPlaneCx[q] == 1 ? xl : xr]);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        if (kPlaneCx[q] == 1)
+          v[q][j] = j == 0 ? e : C::dec(a[j > 0 ? j - 1 : 0]);
+        else
+          v[q][j] = j == V - 1 ? e : C::dec(a[j < V - 1 ? j + 1 : 0]);
+      }
+    }
   }
-  collide<LES>(f, g, rt);
-  const unsigned od = r0 + x;
+  float out[kNPop][V];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(C::enc(f[i]), dst + i * P + od);
+  for (int j = 0; j < V; ++j) {
+    float f[9], g[10];
 #pragma unroll
-  for (int q = 0; q < 10; ++q) __builtin_nontemporal_store(C::enc(g[q]), dst + (9 + q) * P + od);
+    for (int i = 0; i < 9; ++i) f[i] = v[i][j];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) g[k] = v[9 + k][j];
+    collide<LES>(f, g, rt);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i][j] = f[i];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[9 + k][j] = g[k];
+  }
+  const unsigned od = row[1] + unsigned(x0);
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) {
+    VT w;
+    if constexpr (V == 1) {
+      w = C::enc(out[q][0]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j) w[j] = C::enc(out[q][j]);
+    }
+    __builtin_nontemporal_store(w, reinterpret_cast<VT*>(dst + q * P + od));
+  }
 }
 
 // ------------------------------------------------------- initialisation etc.
@@ -446,26 +493,28 @@ inline unsigned blocks_for(long long n, int bs) { return unsigned((n + bs - 1) /
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
+template <int ST, int V>
+void launch_step_v(bool les, const void* src, void* dst, const Geom& g, const Rates& r,
+                   hipStream_t s) {
+  using T = typename Codec<ST>::T;
+  const int tiles_x = (g.nx / V + kStepThreads - 1) / kStepThreads;
+  const dim3 grid(unsigned(tiles_x) * unsigned(g.ny)), block(kStepThreads);
+  auto* a = static_cast<const T*>(src);
+  auto* b = static_cast<T*>(dst);
+  if (les)
+    hipLaunchKernelGGL((k_step<ST, V, true>), grid, block, 0, s, a, b, g, r, tiles_x);
+  else
+    hipLaunchKernelGGL((k_step<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x);
+}
+
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
                        const Rates& r, hipStream_t s) {
-  const int tiles_x = (g.nx + LBMHD_TX - 1) / LBMHD_TX;
-  const int tiles_y = (g.ny + LBMHD_TY - 1) / LBMHD_TY;
-  const dim3 grid(unsigned(tiles_x * tiles_y)), block(LBMHD_TX * LBMHD_TY);
-  if (storage == LBMHD_FP32) {
-    auto* a = static_cast<const float*>(src);
-    auto* b = static_cast<float*>(dst);
-    if (les)
-      hipLaunchKernelGGL((k_step<LBMHD_FP32, true>), grid, block, 0, s, a, b, g, r, tiles_x);
-    else
-      hipLaunchKernelGGL((k_step<LBMHD_FP32, false>), grid, block, 0, s, a, b, g, r, tiles_x);
-  } else {
-    auto* a = static_cast<const _Float16*>(src);
-    auto* b = static_cast<_Float16*>(dst);
-    if (les)
-      hipLaunchKernelGGL((k_step<LBMHD_FP16, true>), grid, block, 0, s, a, b, g, r, tiles_x);
-    else
-      hipLaunchKernelGGL((k_step<LBMHD_FP16, false>), grid, block, 0, s, a, b, g, r, tiles_x);
-  }
+  if (storage == LBMHD_FP32)
+    launch_step_v<LBMHD_FP32, 1>(les, src, dst, g, r, s);
+  else if (g.nx % 2 == 0)
+    launch_step_v<LBMHD_FP16, 2>(les, src, dst, g, r, s);
+  else
+    launch_step_v<LBMHD_FP16, 1>(les, src, dst, g, r, s);
   return hipGetLastError();
 }
 

@@ -120,7 +120,7 @@ def _fp16_representable(x0):
 
 
 @pytest.mark.parametrize("les", [False, True])
-@pytest.mark.parametrize("nx,ny", [(8, 8), (100, 36), (300, 5)])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (100, 36), (300, 5), (257, 3), (2, 2), (1030, 4)])
 def test_one_step_fp16(lb, orc, nx, ny, les):
     L, op = make(lb, orc, nx, ny, "fp16", nu=0.01, eta=0.02, les=les, cs=0.15)
     x0 = _fp16_representable(random_state(nx, ny, seed=3 + nx))
