@@ -22,7 +22,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbmhd_oracle.cpp")
-LIB = os.path.join(HERE, "liblbmhd_oracle.so")
+# LBMHD_ORACLE_LIB selects another build of the same source (the mutation tests
+# point it at deliberately broken copies to show the pins catch them).
+LIB = os.environ.get("LBMHD_ORACLE_LIB") or os.path.join(HERE, "liblbmhd_oracle.so")
 
 NPOP = 19
 NDIAG = 14
@@ -35,13 +37,20 @@ DIAG_NAMES = (
 )
 
 
+def compile_source(src: str, out: str) -> str:
+    """g++ -O2 -fopenmp (no fast-math) of one oracle source into a shared library."""
+    cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", src, "-o", out + ".tmp"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with g++ (OpenMP over sites, no fast-math)."""
+    """Compile the oracle (unless LBMHD_ORACLE_LIB names a prebuilt variant)."""
+    if os.environ.get("LBMHD_ORACLE_LIB"):
+        return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", SRC,
-               "-o", LIB + ".tmp"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB + ".tmp", LIB)
+        compile_source(SRC, LIB)
     return LIB
 
 

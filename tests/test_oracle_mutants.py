@@ -1,0 +1,80 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of ``oracle/lbmhd_oracle.cpp`` (a
+wrong weight, a flipped sign, a dropped factor, a transposed inverse, the
+wrong streaming direction, a wrong closure constant, a wrong rate index, a
+broken dual-number rule), builds it with the same flags into a temporary
+library, and runs the pin suite (test_oracle_tables.py, test_oracle_physics.py)
+against it in a subprocess.  Every mutant must make at least one pin fail; the
+unmodified source must pass.  Everything runs on the CPU.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from conftest import ROOT
+
+SRC = os.path.join(ROOT, "oracle", "lbmhd_oracle.cpp")
+PINS = [os.path.join(ROOT, "tests", "test_oracle_tables.py"),
+        os.path.join(ROOT, "tests", "test_oracle_physics.py")]
+
+MUTANTS = {
+    "diagonal weight 1/36 -> 1/18": ("1.0 / 9.0 : 1.0 / 36.0)", "1.0 / 9.0 : 1.0 / 18.0)"),
+    "T row 7 drops a factor 2": ("4.0 - 9.0 * (cx2 + cy2 - 2.0 * cx2 * cy2)",
+                                 "4.0 - 9.0 * (cx2 + cy2 - cx2 * cy2)"),
+    "Maxwell stress sign": ("4.5 * w * (0.5 * b2 * c2 - cb * cb)",
+                            "4.5 * w * (0.5 * b2 * c2 + cb * cb)"),
+    "Maxwell stress half": ("4.5 * w * (0.5 * b2 * c2 - cb * cb)",
+                            "4.5 * w * (1.0 * b2 * c2 - cb * cb)"),
+    "g^eq u x B sign": ("geq[k] = w * (bx + 3.0 * (cu * bx - cb * ux));",
+                        "geq[k] = w * (bx + 3.0 * (cu * bx + cb * ux));"),
+    "M3^eq Lorentz sign": ("meq[3] = jx * jy / rho - bx * by;", "meq[3] = jx * jy / rho + bx * by;"),
+    "M8^eq coefficient": ("meq[8] = (5.0 / 3.0) * rho", "meq[8] = (4.0 / 3.0) * rho"),
+    "T inverse transposed": ("Tinv[i][r] = T[r][i] / n2;", "Tinv[r][i] = T[r][i] / n2;"),
+    "tau0 offset": ("r.tau0 = 3.0 * p.nu + 0.5;", "r.tau0 = 3.0 * p.nu + 1.0;"),
+    "eta mapping uses nu": ("r.taum0 = 3.0 * p.eta + 0.5;", "r.taum0 = 3.0 * p.nu + 0.5;"),
+    "closure factor 18 -> 9": ("18.0 * d2 * cs * Q / rho", "9.0 * d2 * cs * Q / rho"),
+    "closure Q drops factor 4": ("R Q = root(n4 * n4 + 4.0 * n3 * n3);", "R Q = root(n4 * n4 + n3 * n3);"),
+    "magnetic closure sign of A": ("R A = (N[5 + 1] - neq[5 + 1]) - (N[0 + 2] - neq[0 + 2]);",
+                                   "R A = (N[5 + 1] - neq[5 + 1]) + (N[0 + 2] - neq[0 + 2]);"),
+    "magnetic closure factor 36 -> 18": ("36.0 * d2 * cs * magnitude(A)", "18.0 * d2 * cs * magnitude(A)"),
+    "shear rate s4 takes s5": ("  s[4] = 1.0 / tau;\n", "  s[4] = R(rt.s[5]);\n"),
+    "relaxation sign": ("Mstar[r] = M[r] - s[r] * (M[r] - meq[r]);",
+                        "Mstar[r] = M[r] + s[r] * (M[r] - meq[r]);"),
+    "magnetic rate uses tau": ("R sm = 1.0 / taum;", "R sm = 1.0 / tau;"),
+    "streaming direction of f": ("int64_t xd = wrap(x + CX[i], nx), yd = wrap(y + CY[i], ny);",
+                                 "int64_t xd = wrap(x - CX[i], nx), yd = wrap(y - CY[i], ny);"),
+    "dual product rule": ("r.d[k] = a.d[k] * b.v + a.v * b.d[k];", "r.d[k] = a.d[k] * b.v;"),
+    "dual sqrt rule": ("double g = r.v > 0.0 ? 0.5 / r.v : 0.0;", "double g = r.v > 0.0 ? 1.0 / r.v : 0.0;"),
+}
+
+
+def _run_pins(lib_path):
+    env = dict(os.environ, LBMHD_ORACLE_LIB=lib_path, OMP_NUM_THREADS="4")
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def _build(tmp_path, text, name):
+    from oracle import oracle
+    src = tmp_path / f"{name}.cpp"
+    src.write_text(text)
+    return oracle.compile_source(str(src), str(tmp_path / f"lib{name}.so"))
+
+
+def test_unmodified_oracle_passes_pins(tmp_path):
+    lib = _build(tmp_path, open(SRC).read(), "orig")
+    r = _run_pins(lib)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) >= 1, f"mutation site not found: {old}"
+    lib = _build(tmp_path, text.replace(old, new, 1), "mut")
+    r = _run_pins(lib)
+    assert r.returncode != 0, f"mutant '{name}' passed every pin"
