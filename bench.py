@@ -8,8 +8,9 @@ HBM, K timed steps with the FP64 diagnostics reduction run every 100 steps
 inside the timed region.  The same JSON line also reports the FP16-storage
 step on 8192 x 8192 decaying turbulence (nu = eta = 1e-6), the adjoint
 (gradient of the final total energy after 2000 steps of a perturbed 1024 x 1024
-Orszag-Tang run, checkpoint every 100 steps), the HBM roofline of the
-dominant kernel, and the FP64 CPU oracle timed on the host on the headline
+Orszag-Tang run, checkpoint every 100 steps), the adjoint-driven fit of C_S
+(2048^2 FP16 LES against a box-filtered 8192^2 FP32 run), the HBM roofline of
+the dominant kernel, and the FP64 CPU oracle timed on the host on the headline
 workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -195,6 +196,28 @@ def adjoint_leg(torch, args):
     return out
 
 
+def fit_leg(torch, args):
+    """Adjoint-driven C_S fit: 8192^2 FP32 LES reference after 5000 steps,
+    box-filtered (width 4) onto 2048^2; the 2048^2 FP16 model from the same
+    realisation runs 1250 steps at nu = eta = 2.5e-7 (acoustic scaling)."""
+    from lbmhd_inputs import decaying_turbulence
+    from paper_1607_08675_amd.fit import fit_cs, reference
+    from paper_1607_08675_amd.lattice import LBMHDConfig
+    nf, w = 8192, 4
+    log("fit: 8192^2 FP32 reference, 5000 steps")
+    t0 = time.perf_counter()
+    ref_cfg = LBMHDConfig(nx=nf, ny=nf, nu=1e-6, eta=1e-6, les=True, cs=0.1, storage="fp32")
+    targets = reference(decaying_turbulence(nf, nf), ref_cfg, args.fit_ref_steps, w)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    nc = nf // w
+    cfg = LBMHDConfig(nx=nc, ny=nc, nu=1e-6 / w, eta=1e-6 / w, les=True, cs=0.1, storage="fp16")
+    res = fit_cs(decaying_turbulence(nc, nc), targets, cfg, args.fit_ref_steps // w,
+                 iters=args.fit_iters, every=100, log=log)
+    return dict(t_ref=t_ref, res=res, steps=args.fit_ref_steps // w)
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle on the headline workload (4096^2 Orszag-Tang, LES),
     timed on the host cores: whole steps until about `seconds` have passed."""
@@ -227,7 +250,10 @@ def main():
     ap.add_argument("--fp16-steps", type=int, default=500)
     ap.add_argument("--adj-steps", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--skip", default="", help="comma list of legs to skip: fp16,adjoint,cpu")
+    ap.add_argument("--fit-iters", type=int, default=20)
+    ap.add_argument("--fit-ref-steps", type=int, default=5000)
+    ap.add_argument("--skip", default="",
+                    help="comma list of legs to skip: fp16,adjoint,fit,cpu")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -244,6 +270,7 @@ def main():
     r32 = fp32_leg(torch, args)
     r16 = None if "fp16" in skip else fp16_leg(torch, args)
     radj = None if "adjoint" in skip else adjoint_leg(torch, args)
+    rfit = None if "fit" in skip else fit_leg(torch, args)
     cpu = None if "cpu" in skip else cpu_baseline(args.cpu_seconds)
 
     ms_step = r32["ms"] / args.steps
@@ -311,6 +338,17 @@ def main():
             "ratio_to_forward": round(radj["seg_ms"] / radj["fwd_ms"], 3),
             "adj_kernel_gbs": round(3 * 19 * 4 * s / (radj["adj_kernel_ms"] * 1e-3) / 1e9, 1),
             "dJ_dcs": radj["dJ_dcs"],
+        }
+    if rfit:
+        r = rfit["res"]
+        line["cs_fit"] = {
+            "workload": f"C_S fit: 2048x2048 FP16-storage LES ({rfit['steps']} steps, nu=eta=2.5e-7) "
+                        f"against the width-4 box filter of an 8192x8192 FP32 LES run "
+                        f"({args.fit_ref_steps} steps, nu=eta=1e-6), decaying turbulence",
+            "iterations": len(r.cs), "seconds": round(r.seconds, 3),
+            "reference_seconds": round(rfit["t_ref"], 3),
+            "cs": [round(c, 6) for c in r.cs], "loss": [float(f"{v:.6e}") for v in r.loss],
+            "best_cs": round(r.cs[min(range(len(r.loss)), key=r.loss.__getitem__)], 6),
         }
     print(json.dumps(line), flush=True)
 

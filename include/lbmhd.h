@@ -154,6 +154,20 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst);
  * B = sum g (Sec. 3).  Outputs: device fields.  Asynchronous. */
 int lbmhd_macro(lbmhd_t* h, double* rho, double* ux, double* uy, double* bx, double* by);
 
+/* Box-filtered macroscopic fields of the current state: rho, u, B of each
+ * site (as lbmhd_macro) averaged over w x w blocks of sites (a width-w box
+ * filter sampled on the coarse grid; w >= 1 must divide nx and ny).  Outputs:
+ * device fields of (nx / w) x (ny / w), row-major.  Asynchronous. */
+int lbmhd_macro_box(lbmhd_t* h, int32_t w, double* rho, double* ux, double* uy, double* bx,
+                    double* by);
+
+/* L2 mismatch L = sum_x |u - u_t|^2 + |B - B_t|^2 of the encoded lattice
+ * `state` (device, `lattice` bytes; NULL = current state) against target
+ * fields u_t, B_t (device fields, nx*ny), accumulated in FP64 and written to
+ * *L (host).  Synchronises the bound stream. */
+int lbmhd_mismatch(lbmhd_t* h, const void* state, const double* ux_t, const double* uy_t,
+                   const double* bx_t, const double* by_t, double* L);
+
 /* FP64 global diagnostics of the current state into *out (host memory).
  * Synchronises the bound stream.  Returns LBMHD_ERR_NONFINITE (with *out
  * filled) when any population is NaN or Inf. */
@@ -195,6 +209,13 @@ int lbmhd_energy(lbmhd_t* h, const void* state, double* J);
 /* lam = dJ/dx for the total energy J of `state` (see lbmhd_energy):
  * dJ/df_i = c_i . u - |u|^2 / 2, dJ/dg_k = B.  Asynchronous. */
 int lbmhd_adj_seed_energy(lbmhd_t* h, const void* state, float* lam);
+
+/* lam = scale * dL/dx for the mismatch L of lbmhd_mismatch evaluated on
+ * `state`: dL/df_i = 2 (u - u_t) . (c_i - u) / rho, dL/dg_k = 2 (B - B_t).
+ * Asynchronous. */
+int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
+                            const double* uy_t, const double* bx_t, const double* by_t,
+                            double scale, float* lam);
 
 /* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next, where state_n is
  * the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc

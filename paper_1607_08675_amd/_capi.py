@@ -26,9 +26,10 @@ LBMHD_FP16 = 1
 # Every function declared in include/lbmhd.h, in declaration order.
 EXPORTS = (
     "lbmhd_strerror", "lbmhd_last_error", "lbmhd_create", "lbmhd_destroy", "lbmhd_sizes",
-    "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_step_between", "lbmhd_macro", "lbmhd_diag",
-    "lbmhd_get_populations", "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state",
-    "lbmhd_get_step", "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_step",
+    "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_step_between", "lbmhd_macro",
+    "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_get_populations",
+    "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state", "lbmhd_get_step",
+    "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_seed_mismatch", "lbmhd_adj_step",
     "lbmhd_adj_acc_total", "lbmhd_adj_fields",
 )
 
@@ -88,6 +89,9 @@ def lib():
             "lbmhd_step": [vp, i64],
             "lbmhd_step_between": [vp, vp, vp],
             "lbmhd_macro": [vp] * 6,
+            "lbmhd_macro_box": [vp, ctypes.c_int32] + [vp] * 5,
+            "lbmhd_mismatch": [vp] * 6 + [P(ctypes.c_double)],
+            "lbmhd_adj_seed_mismatch": [vp] * 6 + [ctypes.c_double, vp],
             "lbmhd_diag": [vp, P(Diag)],
             "lbmhd_get_populations": [vp, vp],
             "lbmhd_set_populations": [vp, vp, i64],

@@ -28,8 +28,12 @@ class Checkpointed:
         self.every = every
         self.ckpts: list[torch.Tensor] = []
 
-    def forward(self, fields, nsteps: int) -> float:
+    def forward(self, fields, nsteps: int, targets=None) -> float:
+        """Run nsteps from equilibrium at `fields` (rho, ux, uy, bx, by) keeping
+        checkpoints.  Returns the final total energy, or with `targets`
+        (ux, uy, bx, by) the mismatch sum |u - u_t|^2 + |B - B_t|^2."""
         lat = self.lat
+        self.targets = targets
         lat.init_fields(*fields)
         self.fields = fields
         self.nsteps = nsteps
@@ -41,15 +45,21 @@ class Checkpointed:
             lat.step(k)
             done += k
         self.final = lat.save_state()
-        return lat.energy()
+        return lat.energy() if targets is None else lat.mismatch(targets)
 
-    def backward(self):
-        """Returns (dJ/du_x, dJ/du_y, dJ/dB_x, dJ/dB_y, dJ/dC_S)."""
+    def backward(self, scale: float = 1.0):
+        """Returns scale * (dJ/du_x, dJ/du_y, dJ/dB_x, dJ/dB_y, dJ/dC_S) for the
+        functional returned by forward()."""
         lat = self.lat
         lam = lat.new_adj_buffer()
         lam2 = lat.new_adj_buffer()
         acc = lat.new_adj_acc()
-        lat.adj_seed_energy(self.final, lam)
+        if self.targets is None:
+            if scale != 1.0:
+                raise ValueError("the energy seed takes no scale")
+            lat.adj_seed_energy(self.final, lam)
+        else:
+            lat.adj_seed_mismatch(self.final, self.targets, scale, lam)
         seg_states = [lat.new_state_buffer() for _ in range(self.every - 1)]
         for s in reversed(range(len(self.ckpts))):
             start = s * self.every

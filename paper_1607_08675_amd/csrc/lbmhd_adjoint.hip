@@ -302,6 +302,49 @@ __global__ void k_adj_seed(const typename Dec<ST>::T* __restrict__ st, float* __
   }
 }
 
+// lam = scale * dL/dx for L = sum |u - u_t|^2 + |B - B_t|^2:
+// dL/df_i = 2 (u - u_t) . (c_i - u) / rho, dL/dg = 2 (B - B_t).
+template <int ST>
+__global__ void k_adj_seed_mismatch(const typename Dec<ST>::T* __restrict__ st,
+                                    const double* __restrict__ ux_t,
+                                    const double* __restrict__ uy_t,
+                                    const double* __restrict__ bx_t,
+                                    const double* __restrict__ by_t, double scale,
+                                    float* __restrict__ lam, Geom geo, Geom ga) {
+  using D = Dec<ST>;
+  const long long n = (long long)geo.nx * geo.ny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int y = int(s / geo.nx), x = int(s % geo.nx);
+  const long long o = (long long)y * geo.pitch + x, oa = (long long)y * ga.pitch + x;
+  double v[kNPop];
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) v[q] = double(D::dec(st[q * geo.plane + o]));
+  double dr = 0.0, jx = 0.0, jy = 0.0, bx = 0.0, by = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    dr += v[i];
+    jx += kCx[i] * v[i];
+    jy += kCy[i] * v[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    bx += v[9 + k];
+    by += v[14 + k];
+  }
+  const double rho = 1.0 + dr, ux = jx / rho, uy = jy / rho;
+  const double eu = 2.0 * scale * (ux - ux_t[s]) / rho, ev = 2.0 * scale * (uy - uy_t[s]) / rho;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    lam[i * ga.plane + oa] = float(eu * (kCx[i] - ux) + ev * (kCy[i] - uy));
+  const double gx = 2.0 * scale * (bx - bx_t[s]), gy = 2.0 * scale * (by - by_t[s]);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    lam[(9 + k) * ga.plane + oa] = float(gx);
+    lam[(14 + k) * ga.plane + oa] = float(gy);
+  }
+}
+
 // Pull lam0 back through x_0 = (f^eq(rho0, u0, B0), g^eq(u0, B0)).
 __global__ void k_adj_fields(const float* __restrict__ lam, const double* __restrict__ rho0,
                              const double* __restrict__ ux0, const double* __restrict__ uy0,
@@ -387,6 +430,21 @@ hipError_t launch_adj_seed(int storage, const void* lat, float* lam, const Geom&
   else
     hipLaunchKernelGGL(k_adj_seed<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
                        static_cast<const _Float16*>(lat), lam, g, ga);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed_mismatch(int storage, const void* lat, const double* ux_t,
+                                    const double* uy_t, const double* bx_t, const double* by_t,
+                                    double scale, float* lam, const Geom& g, const Geom& ga,
+                                    hipStream_t s) {
+  const unsigned nb = unsigned(((long long)g.nx * g.ny + 255) / 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_adj_seed_mismatch<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float*>(lat), ux_t, uy_t, bx_t, by_t, scale, lam, g, ga);
+  else
+    hipLaunchKernelGGL(k_adj_seed_mismatch<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const _Float16*>(lat), ux_t, uy_t, bx_t, by_t, scale, lam, g,
+                       ga);
   return hipGetLastError();
 }
 

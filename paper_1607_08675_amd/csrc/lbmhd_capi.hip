@@ -239,6 +239,35 @@ int lbmhd_macro(lbmhd_t* h, double* rho, double* ux, double* uy, double* bx, dou
   return LBMHD_OK;
 }
 
+int lbmhd_macro_box(lbmhd_t* h, int32_t w, double* rho, double* ux, double* uy, double* bx,
+                    double* by) {
+  if (int rc = need_bound(h)) return rc;
+  if (!rho || !ux || !uy || !bx || !by) return fail(h, LBMHD_ERR_INVALID_ARG, "null field");
+  if (w < 1 || h->p.nx % w != 0 || h->p.ny % w != 0)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "box width must divide nx and ny");
+  hipError_t e = lbk::launch_macro_box(h->p.storage, h->lat[h->cur], w, rho, ux, uy, bx, by,
+                                       h->geo, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "box macro launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_mismatch(lbmhd_t* h, const void* state, const double* ux_t, const double* uy_t,
+                   const double* bx_t, const double* by_t, double* L) {
+  if (int rc = need_bound(h)) return rc;
+  if (!ux_t || !uy_t || !bx_t || !by_t || !L)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null target or output");
+  double* part = h->ws + 5 * size_t(h->geo.nx) * h->geo.ny;  // diagnostics partials area
+  double* dev = ws_out(h) + lbk::kDiagSlots + 1;
+  hipError_t e = lbk::launch_mismatch(h->p.storage, state ? state : h->lat[h->cur], ux_t, uy_t,
+                                      bx_t, by_t, part, dev, h->geo, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "mismatch launch");
+  e = hipMemcpyAsync(L, dev, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "mismatch copy");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "mismatch synchronise");
+  return LBMHD_OK;
+}
+
 int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out) {
   if (int rc = need_bound(h)) return rc;
   if (!out) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
@@ -321,6 +350,18 @@ int lbmhd_adj_seed_energy(lbmhd_t* h, const void* state, float* lam) {
   if (!state || !lam) return fail(h, LBMHD_ERR_INVALID_ARG, "null state or lambda");
   hipError_t e = lbk::launch_adj_seed(h->p.storage, state, lam, h->geo, h->geoa, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint seed launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
+                            const double* uy_t, const double* bx_t, const double* by_t,
+                            double scale, float* lam) {
+  if (int rc = need_bound(h)) return rc;
+  if (!state || !ux_t || !uy_t || !bx_t || !by_t || !lam)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
+  hipError_t e = lbk::launch_adj_seed_mismatch(h->p.storage, state, ux_t, uy_t, bx_t, by_t, scale,
+                                               lam, h->geo, h->geoa, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "mismatch seed launch");
   return LBMHD_OK;
 }
 

@@ -57,9 +57,22 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_diag(int storage, const void* lat, double* ws, double* out_dev, const Geom& g,
                        hipStream_t s);
 
+// Box-averaged macroscopic fields (w x w blocks).
+hipError_t launch_macro_box(int storage, const void* lat, int w, double* rho, double* ux,
+                            double* uy, double* bx, double* by, const Geom& g, hipStream_t s);
+// Mismatch to target fields: per-block partials (kDiagBlocks doubles at part)
+// folded into out_dev[0].
+hipError_t launch_mismatch(int storage, const void* lat, const double* ux_t, const double* uy_t,
+                           const double* bx_t, const double* by_t, double* part, double* out_dev,
+                           const Geom& g, hipStream_t s);
+
 // Adjoint.
 hipError_t launch_adj_seed(int storage, const void* lat, float* lam, const Geom& g,
                            const Geom& ga, hipStream_t s);
+hipError_t launch_adj_seed_mismatch(int storage, const void* lat, const double* ux_t,
+                                    const double* uy_t, const double* bx_t, const double* by_t,
+                                    double scale, float* lam, const Geom& g, const Geom& ga,
+                                    hipStream_t s);
 hipError_t launch_adj_step(int storage, bool les, const void* state, const float* lam_next,
                            float* lam_prev, double* acc, const Geom& g, const Geom& ga,
                            const Rates& r, double delta2, hipStream_t s);

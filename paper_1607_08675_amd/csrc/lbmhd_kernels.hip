@@ -367,6 +367,61 @@ __global__ void k_macro(const typename Codec<ST>::T* __restrict__ lat, double* _
   by[s] = d;
 }
 
+template <int ST>
+__global__ void k_macro_box(const typename Codec<ST>::T* __restrict__ lat, int w,
+                            double* __restrict__ rho, double* __restrict__ ux,
+                            double* __restrict__ uy, double* __restrict__ bx,
+                            double* __restrict__ by, Geom geo) {
+  const int cnx = geo.nx / w, cny = geo.ny / w;
+  const long long n = (long long)cnx * cny;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int cy = int(s / cnx), cx = int(s % cnx);
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int dy = 0; dy < w; ++dy)
+    for (int dx = 0; dx < w; ++dx) {
+      double v[5];
+      macro_site<ST>(lat, geo, (long long)(cy * w + dy) * geo.pitch + (cx * w + dx), v[0], v[1],
+                     v[2], v[3], v[4]);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) a[q] += v[q];
+    }
+  const double iw = 1.0 / (double(w) * w);
+  rho[s] = a[0] * iw;
+  ux[s] = a[1] * iw;
+  uy[s] = a[2] * iw;
+  bx[s] = a[3] * iw;
+  by[s] = a[4] * iw;
+}
+
+// Per-block partial sums of |u - u_t|^2 + |B - B_t|^2 (grid-stride over sites).
+template <int ST>
+__global__ __launch_bounds__(256) void k_mismatch(const typename Codec<ST>::T* __restrict__ lat,
+                                                  const double* __restrict__ ux_t,
+                                                  const double* __restrict__ uy_t,
+                                                  const double* __restrict__ bx_t,
+                                                  const double* __restrict__ by_t,
+                                                  double* __restrict__ part, Geom geo) {
+  __shared__ double sh[256];
+  const long long n = (long long)geo.nx * geo.ny;
+  double acc = 0.0;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int y = int(s / geo.nx), x = int(s % geo.nx);
+    double r, u, v, b0, b1;
+    macro_site<ST>(lat, geo, (long long)y * geo.pitch + x, r, u, v, b0, b1);
+    const double du = u - ux_t[s], dv = v - uy_t[s], d0 = b0 - bx_t[s], d1 = b1 - by_t[s];
+    acc += du * du + dv * dv + d0 * d0 + d1 * d1;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 __global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n16) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
        i += (long long)gridDim.x * blockDim.x)
@@ -590,6 +645,33 @@ hipError_t launch_diag(int storage, const void* lat, double* ws, double* out_dev
   const int nparts = int(std::min<long long>(kDiagBlocks, blocks_for(n, 256)));
   hipLaunchKernelGGL(k_diag_reduce, dim3(nparts), dim3(256), 0, s, ws, part, g.nx, g.ny);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_macro_box(int storage, const void* lat, int w, double* rho, double* ux,
+                            double* uy, double* bx, double* by, const Geom& g, hipStream_t s) {
+  const unsigned nb = blocks_for((long long)(g.nx / w) * (g.ny / w), 256);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_macro_box<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float*>(lat), w, rho, ux, uy, bx, by, g);
+  else
+    hipLaunchKernelGGL(k_macro_box<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const _Float16*>(lat), w, rho, ux, uy, bx, by, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_mismatch(int storage, const void* lat, const double* ux_t, const double* uy_t,
+                           const double* bx_t, const double* by_t, double* part, double* out_dev,
+                           const Geom& g, hipStream_t s) {
+  const long long n = (long long)g.nx * g.ny;
+  const int nparts = int(std::min<long long>(kDiagBlocks, blocks_for(n, 256)));
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_mismatch<LBMHD_FP32>, dim3(nparts), dim3(256), 0, s,
+                       static_cast<const float*>(lat), ux_t, uy_t, bx_t, by_t, part, g);
+  else
+    hipLaunchKernelGGL(k_mismatch<LBMHD_FP16>, dim3(nparts), dim3(256), 0, s,
+                       static_cast<const _Float16*>(lat), ux_t, uy_t, bx_t, by_t, part, g);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, (long long)nparts, out_dev);
   return hipGetLastError();
 }
 

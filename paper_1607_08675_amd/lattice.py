@@ -116,6 +116,23 @@ class Lattice:
         self._check(self._L.lbmhd_macro(self._h, *[_ptr(o) for o in out]), "lbmhd_macro")
         return dict(zip(FIELDS, out))
 
+    def macro_box(self, w: int) -> dict:
+        """rho, u, B averaged over w x w blocks: fields of (ny / w, nx / w)."""
+        out = [torch.empty(self.cfg.ny // w, self.cfg.nx // w, dtype=torch.float64,
+                           device=self.device) for _ in FIELDS]
+        self._check(self._L.lbmhd_macro_box(self._h, int(w), *[_ptr(o) for o in out]),
+                    "lbmhd_macro_box")
+        return dict(zip(FIELDS, out))
+
+    def mismatch(self, targets, state: torch.Tensor | None = None) -> float:
+        """sum |u - u_t|^2 + |B - B_t|^2 for targets (ux, uy, bx, by)."""
+        ts = [self._field(t) for t in targets]
+        L = ctypes.c_double()
+        p = _ptr(state) if state is not None else ctypes.c_void_p(0)
+        self._check(self._L.lbmhd_mismatch(self._h, p, *[_ptr(t) for t in ts], ctypes.byref(L)),
+                    "lbmhd_mismatch")
+        return L.value
+
     def diag(self, raise_nonfinite: bool = False) -> dict:
         d = C.Diag()
         rc = self._L.lbmhd_diag(self._h, ctypes.byref(d))
@@ -175,6 +192,13 @@ class Lattice:
     def adj_seed_energy(self, state: torch.Tensor, lam: torch.Tensor):
         self._check(self._L.lbmhd_adj_seed_energy(self._h, _ptr(state), _ptr(lam)),
                     "lbmhd_adj_seed_energy")
+
+    def adj_seed_mismatch(self, state: torch.Tensor, targets, scale: float, lam: torch.Tensor):
+        ts = [self._field(t) for t in targets]
+        self._check(self._L.lbmhd_adj_seed_mismatch(self._h, _ptr(state), *[_ptr(t) for t in ts],
+                                                     float(scale), _ptr(lam)),
+                    "lbmhd_adj_seed_mismatch")
+        self._keep = ts
 
     def adj_step(self, state_n: torch.Tensor, lam_next: torch.Tensor, lam_prev: torch.Tensor,
                  acc: torch.Tensor):
