@@ -193,6 +193,27 @@ def adjoint_leg(torch, args):
                seg_ms=seg_ms, sites=n * n, nsteps=nsteps, dJ_dcs=g[4])
     del run, lat, states, lam, lam2
     torch.cuda.empty_cache()
+    # the adjoint kernel where its working set (3 x 1.3 GB) is far above the caches
+    from lbmhd_inputs import orszag_tang
+    nb = 4096
+    lat = Lattice(LBMHDConfig(nx=nb, ny=nb, nu=1e-5, eta=1e-5, les=True, cs=0.1, storage="fp32"))
+    lat.init_fields(*orszag_tang(nb, nb)).step(10)
+    st = lat.save_state()
+    lam, lam2, acc = lat.new_adj_buffer(), lat.new_adj_buffer(), lat.new_adj_acc()
+    lat.adj_seed_energy(st, lam)
+    lat.adj_step(st, lam, lam2, acc)
+    e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    torch.cuda.synchronize()
+    e0.record(lat.stream)
+    for _ in range(20):
+        lat.adj_step(st, lam, lam2, acc)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    out["adj_ms_4096"] = e0.elapsed_time(e1) / 20
+    out["fwd_ms_4096"] = burst_ms_per_launch(torch, lat, 50)
+    log(f"adjoint kernel 4096^2: {out['adj_ms_4096']:.4f} ms, forward {out['fwd_ms_4096']:.4f} ms")
+    del lat, st, lam, lam2, acc
+    torch.cuda.empty_cache()
     return out
 
 
@@ -338,6 +359,10 @@ def main():
             "ratio_to_forward": round(radj["seg_ms"] / radj["fwd_ms"], 3),
             "adj_kernel_gbs": round(3 * 19 * 4 * s / (radj["adj_kernel_ms"] * 1e-3) / 1e9, 1),
             "dJ_dcs": radj["dJ_dcs"],
+            "adj_kernel_ms_4096": round(radj["adj_ms_4096"], 5),
+            "adj_kernel_gbs_4096": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9, 1),
+            "adj_kernel_frac_4096": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "ratio_to_forward_4096": round((radj["adj_ms_4096"] + radj["fwd_ms_4096"]) / radj["fwd_ms_4096"], 3),
         }
     if rfit:
         r = rfit["res"]

@@ -107,7 +107,8 @@ const char* lbmhd_last_error(const lbmhd_t* h);
 /* Validate p and create a host-side handle.  Allocates no device memory.
  * Errors: LBMHD_ERR_INVALID_ARG if p is out of range (nx, ny < 2; nu, eta
  * <= 0; a rate outside (0, 2); s5 != s6; cs < 0; delta <= 0; unknown
- * storage; lattice too large for 32-bit in-plane offsets). */
+ * storage; one FP32 plane of ny rows of padded nx reaching 4 GiB, since
+ * in-plane byte offsets are 32-bit). */
 int lbmhd_create(const lbmhd_params* p, lbmhd_t** out);
 
 /* Release the handle (not the caller's buffers).  NULL is accepted. */

@@ -48,6 +48,16 @@ __device__ constexpr double kWm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Plane element access with a uniform base and a 32-bit byte offset (the byte
+// size of a plane is below 2^32, checked at lbmhd_create).
+template <typename T>
+__device__ __forceinline__ T ld_plane(const T* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off * unsigned(sizeof(T)));
+}
+__device__ __forceinline__ void st_plane_nt(float* __restrict__ base, unsigned off, float v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off * 4u));
+}
+
 struct AdjConsts {
   float dcf;  // d(18 C_S Delta^2) / dC_S
   float dcm;  // d(36 C_S Delta^2) / dC_S
@@ -234,24 +244,24 @@ __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
     const long long P = geo.plane, PA = ga.plane;
     float f[9], g[10], lf[9], lg[10];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = D::dec(st[i * P + o[i]]);
+    for (int i = 0; i < 9; ++i) f[i] = D::dec(ld_plane(st + i * P, o[i]));
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      g[k] = D::dec(st[(9 + k) * P + o[k]]);
-      g[5 + k] = D::dec(st[(14 + k) * P + o[k]]);
+      g[k] = D::dec(ld_plane(st + (9 + k) * P, o[k]));
+      g[5 + k] = D::dec(ld_plane(st + (14 + k) * P, o[k]));
     }
     const unsigned oc = a0 + x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lf[i] = lam_next[i * PA + oc];
+    for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam_next + i * PA, oc);
 #pragma unroll
-    for (int q = 0; q < 10; ++q) lg[q] = lam_next[(9 + q) * PA + oc];
+    for (int q = 0; q < 10; ++q) lg[q] = ld_plane(lam_next + (9 + q) * PA, oc);
     dcs = collide_adjoint<LES>(f, g, lf, lg, rt, ac);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(lf[i], lam_prev + i * PA + oa[i]);
+    for (int i = 0; i < 9; ++i) st_plane_nt(lam_prev + i * PA, oa[i], lf[i]);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      __builtin_nontemporal_store(lg[k], lam_prev + (9 + k) * PA + oa[k]);
-      __builtin_nontemporal_store(lg[5 + k], lam_prev + (14 + k) * PA + oa[k]);
+      st_plane_nt(lam_prev + (9 + k) * PA, oa[k], lg[k]);
+      st_plane_nt(lam_prev + (14 + k) * PA, oa[k], lg[5 + k]);
     }
   }
   if (LES) {

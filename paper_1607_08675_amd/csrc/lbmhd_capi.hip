@@ -119,8 +119,9 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
   lbk::Geom g = make_geom(p->nx, p->ny, esize);
   lbk::Geom ga = make_geom(p->nx, p->ny, 4);
-  // in-plane offsets are 32-bit unsigned in the kernels
-  if ((unsigned long long)ga.plane >= (1ull << 32)) return LBMHD_ERR_INVALID_ARG;
+  // in-plane byte offsets are 32-bit unsigned in the kernels (FP32 adjoint
+  // planes are the largest)
+  if ((unsigned long long)ga.plane * 4ull >= (1ull << 32)) return LBMHD_ERR_INVALID_ARG;
 
   lbmhd_t* h = new (std::nothrow) lbmhd;
   if (!h) return LBMHD_ERR_INVALID_ARG;

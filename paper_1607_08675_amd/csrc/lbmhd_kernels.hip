@@ -69,6 +69,19 @@ __device__ constexpr int kMy[5] = {0, 0, 1, 0, -1};
 __device__ constexpr double kW[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 __device__ constexpr double kWm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+// Element `off` of a plane: the plane base is uniform across the wavefront and
+// the byte offset fits 32 bits (checked at lbmhd_create), so the compiler emits
+// scalar-base + 32-bit-offset global accesses instead of 64-bit lane addresses.
+template <typename VT, typename T>
+__device__ __forceinline__ VT ld_plane(const T* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const VT*>(reinterpret_cast<const char*>(base) + off * unsigned(sizeof(T)));
+}
+template <typename VT, typename T>
+__device__ __forceinline__ void st_plane_nt(T* __restrict__ base, unsigned off, VT v) {
+  __builtin_nontemporal_store(
+      v, reinterpret_cast<VT*>(reinterpret_cast<char*>(base) + off * unsigned(sizeof(T))));
+}
+
 // velocity (c_x, c_y) of the population held by each of the 19 planes
 __device__ constexpr int kPlaneCx[kNPop] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0,
                                             1, 0, -1, 0, 0, 1,  0, -1, 0};
@@ -193,10 +206,11 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
   float v[kNPop][V];
 #pragma unroll
   for (int q = 0; q < kNPop; ++q) {
-    const T* __restrict__ pl = src + q * P + row[kPlaneCy[q] + 1];
+    const T* __restrict__ base = src + q * P;
+    const unsigned r = row[kPlaneCy[q] + 1];
     if (V == 1 || kPlaneCx[q] == 0) {
       const int xs = kPlaneCx[q] == 0 ? x0 : (kPlaneCx[q] == 1 ? xl : xr);
-      const VT a = *reinterpret_cast<const VT*>(pl + xs);
+      const VT a = ld_plane<VT>(base, r + unsigned(xs));
       if constexpr (V == 1) {
         v[q][0] = C::dec(a);
       } else {
@@ -204,8 +218,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
         for (int j = 0; j < V; ++j) v[q][j] = C::dec(a[j]);
       }
     } else if constexpr (V > 1) {
-      const VT a = *reinterpret_cast<const VT*>(pl + x0);
-      const float e = C::dec(pl[kPlaneCx[q] == 1 ? xl : xr]);
+      const VT a = ld_plane<VT>(base, r + unsigned(x0));
+      const float e = C::dec(ld_plane<T>(base, r + unsigned(kPlaneCx[q] == 1 ? xl : xr)));
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         if (kPlaneCx[q] == 1)
@@ -239,7 +253,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
 #pragma unroll
       for (int j = 0; j < V; ++j) w[j] = C::enc(out[q][j]);
     }
-    __builtin_nontemporal_store(w, reinterpret_cast<VT*>(dst + q * P + od));
+    st_plane_nt<VT>(dst + q * P, od, w);
   }
 }
 

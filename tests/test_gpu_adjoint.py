@@ -145,3 +145,58 @@ def test_seed_is_energy_gradient(lb, orc):
         v = rng.standard_normal(x.shape)
         fd = (orc.energy(op, x + eps * v) - orc.energy(op, x - eps * v)) / (2 * eps)
         assert abs(fd - np.sum(got * v)) <= 1e-6 * abs(fd) + 1e-6
+
+
+def _stored16(x):
+    dev = (x - W19[:, None, None]).astype(np.float32)
+    dev = (dev * np.float32(1024)).astype(np.float16).astype(np.float64) / 1024.0
+    return W19[:, None, None] + dev
+
+
+@pytest.mark.parametrize("storage,n,nu,gen", [
+    ("fp32", 1024, 1e-5, "perturbed_ot"),    # energy-gradient workload
+    ("fp16", 2048, 2.5e-7, "turbulence"),     # C_S-fit model
+])
+def test_adjoint_step_full_size_patches(lb, orc, storage, n, nu, gen):
+    """Production sizes and launch configuration.  The adjoint step is local,
+    so the dot-product test runs on patches: b lives on a 7x7 window, a on the
+    9x9 window around it; the oracle evaluates J b and dC/dC_S on a 11x11
+    patch of the same initial equilibrium (pre-collision states there only
+    need sites inside the patch)."""
+    from lbmhd_inputs import decaying_turbulence
+    fields = perturbed_orszag_tang(n, n) if gen == "perturbed_ot" else decaying_turbulence(n, n)
+    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=nu, eta=nu, les=True, cs=0.1, storage=storage)
+    L = lb.Lattice(cfg)
+    L.init_fields(*fields)
+    state = L.save_state()
+    op = orc.Params(11, 11, nu=nu, eta=nu, les=True, cs=0.1)
+    rng = np.random.default_rng(n)
+    centres = [(0, 0), (n - 1, n - 1), (n // 2, 0)] + [tuple(int(v) for v in rng.integers(0, n, 2))
+                                                     for _ in range(7)]
+    rb, ra, R = 3, 4, 5
+    for (cx, cy) in centres:
+        ys = (np.arange(cy - R, cy + R + 1)) % n
+        xs = (np.arange(cx - R, cx + R + 1)) % n
+        d = np.maximum(np.abs(np.arange(-R, R + 1))[:, None], np.abs(np.arange(-R, R + 1))[None, :])
+        a = rng.standard_normal((19, 2 * R + 1, 2 * R + 1)) * (d <= ra)
+        b = rng.standard_normal((19, 2 * R + 1, 2 * R + 1)) * (d <= rb)
+        lam = L.new_adj_buffer().zero_()
+        view = L.adj_view(lam)
+        ti = torch.as_tensor
+        view[:, ti(ys).cuda()[:, None], ti(xs).cuda()[None, :]] = ti(a, dtype=torch.float32).cuda()
+        out = L.new_adj_buffer().zero_()
+        acc = L.new_adj_acc()
+        L.adj_step(state, lam, out, acc)
+        JTa = L.adj_view(out)[:, ti(ys).cuda()[:, None], ti(xs).cuda()[None, :]].double().cpu().numpy()
+        rhs = float(np.sum(JTa * b))
+        x = orc.init(op, *[f[np.ix_(ys, xs)] for f in fields])
+        x = _stored16(x) if storage == "fp16" else stored(x, "fp32")
+        sx = orc.stream(op, x)
+        _, Jb = orc.tl_collide(op, sx, orc.stream(op, b)[None], np.zeros(1))
+        lhs = float(np.sum(a * Jb[0]))
+        scale = np.sqrt(np.sum(a * a) * np.sum(b * b))
+        assert abs(lhs - rhs) <= 2e-5 * scale, ((cx, cy), lhs, rhs)
+        _, Jc = orc.tl_collide(op, sx, np.zeros((1, 19, 2 * R + 1, 2 * R + 1)), np.ones(1))
+        want = float(np.sum(a * Jc[0]))
+        got = L.adj_acc_total(acc)
+        assert abs(got - want) <= 2e-4 * abs(want) + 1e-5 * np.sqrt(np.sum(a * a)), ((cx, cy), got, want)
