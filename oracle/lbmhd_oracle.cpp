@@ -28,6 +28,13 @@
 //   * collide-then-stream with unit time step (the discrete LB update of
 //     Sec. 1.2): f_i(x + c_i, t+1) = f_i*(x, t).
 //
+//   * kinetic LES closure (les = 2; Sec. 4.1): the relaxation targets are the
+//     filtered equilibrium moments M^eq(filtered conserved moments) + the
+//     Delta^2 terms, obtained by applying the filter-width expansion of
+//     products (eq. FilterExampleSmall) and of ratios (eq. FilterExampleLarge)
+//     to every quadratic term of eqs. KinMomentEq and MagMomentEq, as the paper
+//     does for M_3 in eq. DeltaEqEx; linear terms are unchanged.
+//
 // Readings where the paper is silent or garbled:
 //   * weights w = (4/9, 1/9 x4, 1/36 x4), w' = (1/3, 1/6 x4): the only ones
 //     for which T f^eq reproduces the printed equilibrium moment table
@@ -41,7 +48,11 @@
 //     tau_m = (tau_m0 + sqrt(tau_m0^2 + 36 C_S Delta^2 |A|)) / 2 with
 //     A = (N_y1 - N_y1^eq) - (N_x2 - N_x2^eq);  C_Sv = C_Sb = C_S;
 //   * derivative of |.| and of the norm Q is taken as 0 where the argument is
-//     exactly 0 (tangent-linear mode only).
+//     exactly 0 (tangent-linear mode only);
+//   * kinetic closure: the lattice sites carry the filtered fields, and the
+//     gradients in the Delta^2 terms are the isotropic D2Q9 differences
+//     d_a X(x) = 3 sum_i w_i c_ia X(x + c_i) of the pre-collision rho, rho u, B;
+//     the relaxation times stay tau0 and tau_m0.
 //
 // State layout: 19 planes of nx*ny doubles, [plane][y][x] with x fastest.
 // Planes 0..8 hold f_0..f_8, planes 9..13 hold the x component of g_0..g_4,
@@ -52,6 +63,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #ifdef _OPENMP
@@ -111,11 +123,31 @@ struct Tables {
   double T[9][9];
   double Tinv[9][9];
   double Tm[5][5];
+  double Tminv[5][5];
   Tables() {
     for (int r = 0; r < 9; ++r)
       for (int i = 0; i < 9; ++i) T[r][i] = trow(r, i);
     for (int r = 0; r < 5; ++r)
       for (int k = 0; k < 5; ++k) Tm[r][k] = tmrow(r, k);
+    // T_m^-1 by Gauss-Jordan elimination with partial pivoting.
+    double a[5][10];
+    for (int r = 0; r < 5; ++r)
+      for (int c = 0; c < 10; ++c) a[r][c] = c < 5 ? Tm[r][c] : (c - 5 == r ? 1.0 : 0.0);
+    for (int c = 0; c < 5; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < 5; ++r)
+        if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+      for (int k = 0; k < 10; ++k) std::swap(a[c][k], a[piv][k]);
+      const double d = a[c][c];
+      for (int k = 0; k < 10; ++k) a[c][k] /= d;
+      for (int r = 0; r < 5; ++r)
+        if (r != c) {
+          const double m = a[r][c];
+          for (int k = 0; k < 10; ++k) a[r][k] -= m * a[c][k];
+        }
+    }
+    for (int r = 0; r < 5; ++r)
+      for (int c = 0; c < 5; ++c) Tminv[r][c] = a[r][5 + c];
     // The rows of T are mutually orthogonal (checked by the tests), so
     // T^-1 = T^T diag(1 / |row|^2).
     for (int r = 0; r < 9; ++r) {
@@ -205,7 +237,8 @@ typedef struct {
   int32_t nx, ny;
   double nu, eta;          // shear viscosity and resistivity, lattice units
   double s5, s6, s7, s8;   // rates of the non-hydrodynamic moments
-  int32_t les;             // 0: constant rates; 1: Smagorinsky-MHD closure
+  int32_t les;             // 0: constant rates; 1: Smagorinsky-MHD closure;
+                           // 2: kinetic closure (filtered equilibria)
   double cs, delta;        // closure constant C_S and filter width Delta
 } orc_params;
 
@@ -264,6 +297,60 @@ void moment_equilibria(R rho, R jx, R jy, R bx, R by, R meq[9], R neq[10]) {
   }
 }
 
+// Filter-width expansion of a filtered product (eq. FilterExampleSmall):
+// (XY)bar - Xbar Ybar = Delta^2 / 12 d_b X d_b Y + O(Delta^4).
+template <class R>
+R filtered_product_term(double d2, const R dX[2], const R dY[2]) {
+  return (d2 / 12.0) * (dX[0] * dY[0] + dX[1] * dY[1]);
+}
+
+// Filter-width expansion of a filtered ratio (eq. FilterExampleLarge):
+// (XY/Z)bar - Xbar Ybar / Zbar = Delta^2 / (12 Z) [ d_b X d_b Y
+//   - (d_b Z / Z) (X d_b Y + Y d_b X - X Y d_b Z / Z) ] + O(Delta^4).
+template <class R>
+R filtered_ratio_term(double d2, R X, R Y, R Z, const R dX[2], const R dY[2], const R dZ[2]) {
+  R acc = 0.0;
+  for (int b = 0; b < 2; ++b)
+    acc = acc + dX[b] * dY[b] - (dZ[b] / Z) * (X * dY[b] + Y * dX[b] - X * Y * dZ[b] / Z);
+  return (d2 / 12.0) / Z * acc;
+}
+
+// Delta^2 parts of the filtered equilibrium moments: each quadratic term of
+// eqs. KinMomentEq and MagMomentEq (rho u written as j, u = j / rho) replaced
+// by its expansion; the linear terms have none.  grad holds d_x, d_y of
+// (rho, j_x, j_y, B_x, B_y).
+template <class R>
+void filtered_moment_corrections(double d2, R rho, R jx, R jy, R bx, R by, const R grad[10],
+                                 R dmeq[9], R dneq[10]) {
+  const R* gr = grad + 0;
+  const R* gjx = grad + 2;
+  const R* gjy = grad + 4;
+  const R* gbx = grad + 6;
+  const R* gby = grad + 8;
+  for (int i = 0; i < 9; ++i) dmeq[i] = 0.0;
+  for (int i = 0; i < 10; ++i) dneq[i] = 0.0;
+  const R jxjx = filtered_ratio_term(d2, jx, jx, rho, gjx, gjx, gr);
+  const R jyjy = filtered_ratio_term(d2, jy, jy, rho, gjy, gjy, gr);
+  // M_3 = jx jy / rho - Bx By
+  dmeq[3] = filtered_ratio_term(d2, jx, jy, rho, gjx, gjy, gr) - filtered_product_term(d2, gbx, gby);
+  // M_4 = (jx^2 - jy^2) / rho - Bx^2 + By^2
+  dmeq[4] = jxjx - jyjy - filtered_product_term(d2, gbx, gbx) + filtered_product_term(d2, gby, gby);
+  // M_7 = -3 (jx^2 + jy^2) / rho,  M_8 = 5 rho / 3 - 3 (jx^2 + jy^2) / rho
+  dmeq[7] = -3.0 * (jxjx + jyjy);
+  dmeq[8] = -3.0 * (jxjx + jyjy);
+  // N_a1 = u_x B_a - u_a B_x,  N_a2 = u_y B_a - u_a B_y
+  const R b[2] = {bx, by};
+  const R j[2] = {jx, jy};
+  const R* gb[2] = {gbx, gby};
+  const R* gj[2] = {gjx, gjy};
+  for (int a = 0; a < 2; ++a) {
+    dneq[5 * a + 1] = filtered_ratio_term(d2, jx, b[a], rho, gjx, gb[a], gr) -
+                      filtered_ratio_term(d2, j[a], bx, rho, gj[a], gbx, gr);
+    dneq[5 * a + 2] = filtered_ratio_term(d2, jy, b[a], rho, gjy, gb[a], gr) -
+                      filtered_ratio_term(d2, j[a], by, rho, gj[a], gby, gr);
+  }
+}
+
 struct Rates {
   double tau0, taum0;   // constant relaxation times 1/s_3 and 1/s_m
   double s[9];          // s_0..s_8; s_3, s_4 replaced by the closure
@@ -288,7 +375,7 @@ Rates make_rates(const orc_params& p) {
 // times actually used.
 template <class R>
 void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
-                  double* tau_out, double* taum_out) {
+                  double* tau_out, double* taum_out, const R* grad = nullptr) {
   const Tables& tb = tables();
   // Conserved moments (Sec. 3, text after the kinetic equations).
   R rho = 0.0, jx = 0.0, jy = 0.0, bx = 0.0, by = 0.0;
@@ -317,8 +404,18 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
   R meq[9], neq[10];
   moment_equilibria(rho, jx, jy, bx, by, meq, neq);
 
+  // Kinetic LES closure: relax toward the filtered equilibrium moments.
+  R dneq[10];
+  for (int q = 0; q < 10; ++q) dneq[q] = 0.0;
+  if (p.les == 2) {
+    R dmeq[9];
+    filtered_moment_corrections(p.delta * p.delta, rho, jx, jy, bx, by, grad, dmeq, dneq);
+    for (int r = 0; r < 9; ++r) meq[r] = meq[r] + dmeq[r];
+    for (int q = 0; q < 10; ++q) neq[q] = neq[q] + dneq[q];
+  }
+
   R tau = rt.tau0, taum = rt.taum0;
-  if (p.les) {
+  if (p.les == 1) {
     double d2 = p.delta * p.delta;
     // Fluid: |S| = 3 Q / (2 rho tau) from the non-equilibrium M3, M4;
     // tau = tau0 + 3 C_S Delta^2 |S| solved for tau.
@@ -346,9 +443,17 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
     for (int r = 0; r < 9; ++r) acc = acc + tb.Tinv[i][r] * Mstar[r];
     f[i] = acc;
   }
-  // Magnetic: single relaxation toward g^eq(u, B).
+  // Magnetic: single relaxation toward g^eq(u, B) (plus, for the kinetic
+  // closure, T_m^-1 of the Delta^2 parts of the equilibrium moments).
   R feq_unused[9], geq[10];
   equilibrium(rho, jx / rho, jy / rho, bx, by, feq_unused, geq);
+  if (p.les == 2)
+    for (int a = 0; a < 2; ++a)
+      for (int k = 0; k < 5; ++k) {
+        R acc = 0.0;
+        for (int r = 0; r < 5; ++r) acc = acc + tb.Tminv[k][r] * dneq[5 * a + r];
+        geq[5 * a + k] = geq[5 * a + k] + acc;
+      }
   R sm = 1.0 / taum;
   for (int q = 0; q < 10; ++q) g[q] = g[q] - sm * (g[q] - geq[q]);
 }
@@ -356,20 +461,64 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
 inline int64_t wrap(int64_t a, int64_t n) { return ((a % n) + n) % n; }
 
 bool valid(const orc_params* p) {
-  return p && p->nx >= 2 && p->ny >= 2 && p->nu > 0.0 && p->eta > 0.0;
+  return p && p->nx >= 2 && p->ny >= 2 && p->nu > 0.0 && p->eta > 0.0 && p->les >= 0 &&
+         p->les <= 2;
+}
+
+// d_x and d_y of (rho, j_x, j_y, B_x, B_y) at every site: the isotropic D2Q9
+// difference d_a X(x) = 3 sum_i w_i c_ia X(x + c_i), periodic.  grad is 10
+// planes of n.
+template <class R>
+void lattice_gradients(const orc_params& p, const R* st, std::vector<R>& grad) {
+  const int64_t nx = p.nx, ny = p.ny, n = nx * ny;
+  std::vector<R> mac(5 * n);
+  for (int64_t s = 0; s < n; ++s) {
+    R rho = 0.0, jx = 0.0, jy = 0.0, bx = 0.0, by = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      rho = rho + st[i * n + s];
+      jx = jx + double(CX[i]) * st[i * n + s];
+      jy = jy + double(CY[i]) * st[i * n + s];
+    }
+    for (int k = 0; k < 5; ++k) {
+      bx = bx + st[(9 + k) * n + s];
+      by = by + st[(14 + k) * n + s];
+    }
+    mac[s] = rho;
+    mac[n + s] = jx;
+    mac[2 * n + s] = jy;
+    mac[3 * n + s] = bx;
+    mac[4 * n + s] = by;
+  }
+  grad.assign(10 * n, R(0.0));
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      const int64_t s = y * nx + x;
+      for (int i = 1; i < 9; ++i) {
+        const int64_t t = wrap(y + CY[i], ny) * nx + wrap(x + CX[i], nx);
+        for (int m = 0; m < 5; ++m) {
+          grad[(2 * m) * n + s] = grad[(2 * m) * n + s] + 3.0 * weight9(i) * double(CX[i]) * mac[m * n + t];
+          grad[(2 * m + 1) * n + s] =
+              grad[(2 * m + 1) * n + s] + 3.0 * weight9(i) * double(CY[i]) * mac[m * n + t];
+        }
+      }
+    }
 }
 
 template <class R>
 void collide_all(const orc_params& p, R* st, R cs, double* tau_out, double* taum_out) {
   const int64_t n = int64_t(p.nx) * p.ny;
   const Rates rt = make_rates(p);
+  std::vector<R> grad;
+  if (p.les == 2) lattice_gradients(p, st, grad);
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < n; ++s) {
-    R f[9], g[10];
+    R f[9], g[10], gs[10];
     for (int i = 0; i < 9; ++i) f[i] = st[i * n + s];
     for (int q = 0; q < 10; ++q) g[q] = st[(9 + q) * n + s];
+    if (p.les == 2)
+      for (int m = 0; m < 10; ++m) gs[m] = grad[m * n + s];
     collide_site(p, rt, cs, f, g, tau_out ? tau_out + s : nullptr,
-                 taum_out ? taum_out + s : nullptr);
+                 taum_out ? taum_out + s : nullptr, p.les == 2 ? gs : nullptr);
     for (int i = 0; i < 9; ++i) st[i * n + s] = f[i];
     for (int q = 0; q < 10; ++q) st[(9 + q) * n + s] = g[q];
   }
@@ -587,6 +736,39 @@ int orc_diag(const orc_params* p, const double* st, double out[ORC_NDIAG]) {
   out[11] = double(bad);
   out[12] = maxu;
   out[13] = maxj > 0.0 ? maxdiv / maxj : 0.0;
+  return 0;
+}
+
+// T_m^-1 (5x5, row-major).
+void orc_tm_inverse(double out[25]) {
+  const Tables& tb = tables();
+  for (int r = 0; r < 5; ++r)
+    for (int c = 0; c < 5; ++c) out[5 * r + c] = tb.Tminv[r][c];
+}
+
+// The two filter-width expansion terms at one point: out[0] = the product
+// term of eq. FilterExampleSmall, out[1] = the ratio term of eq.
+// FilterExampleLarge, for values X, Y, Z and gradients dX, dY, dZ (x, y).
+void orc_filter_terms(double d2, double X, double Y, double Z, const double dX[2],
+                      const double dY[2], const double dZ[2], double out[2]) {
+  out[0] = filtered_product_term<double>(d2, dX, dY);
+  out[1] = filtered_ratio_term<double>(d2, X, Y, Z, dX, dY, dZ);
+}
+
+// Delta^2 parts of the filtered equilibrium moments at one site (kinetic
+// closure), from rho, j, B and grad = d_x, d_y of (rho, j_x, j_y, B_x, B_y).
+void orc_filtered_moment_corrections(double d2, double rho, double jx, double jy, double bx,
+                                     double by, const double grad[10], double dmeq[9],
+                                     double dneq[10]) {
+  filtered_moment_corrections<double>(d2, rho, jx, jy, bx, by, grad, dmeq, dneq);
+}
+
+// Lattice gradients used by the kinetic closure: 10 planes of nx*ny.
+int orc_gradients(const orc_params* p, const double* st, double* grad) {
+  if (!valid(p)) return -1;
+  std::vector<double> g;
+  lattice_gradients<double>(*p, st, g);
+  std::memcpy(grad, g.data(), sizeof(double) * g.size());
   return 0;
 }
 

@@ -71,7 +71,8 @@ class Params:
 
     nu, eta: shear viscosity and resistivity (Sec. 4.3 gives s_3 = s_4 and s_m).
     s5..s8: rates of the non-hydrodynamic moments (not fixed by the paper).
-    les, cs, delta: Smagorinsky-MHD closure switch, constant and filter width.
+    les: 0 plain, 1 Smagorinsky-MHD closure, 2 kinetic closure (filtered
+    equilibria); cs: Smagorinsky constant; delta: filter width.
     """
     nx: int
     ny: int
@@ -81,13 +82,13 @@ class Params:
     s6: float = 1.0
     s7: float = 1.0
     s8: float = 1.0
-    les: bool = False
+    les: int = 0
     cs: float = 0.1
     delta: float = 1.0
 
     def c(self) -> OrcParams:
         return OrcParams(self.nx, self.ny, self.nu, self.eta, self.s5, self.s6, self.s7,
-                         self.s8, int(bool(self.les)), self.cs, self.delta)
+                         self.s8, int(self.les), self.cs, self.delta)
 
 
 _lib = None
@@ -116,6 +117,11 @@ def lib():
         L.orc_diag.argtypes = [pp, pd, pd]
         L.orc_energy.argtypes = [pp, pd]
         L.orc_energy.restype = d
+        L.orc_tm_inverse.argtypes = [pd]
+        L.orc_filter_terms.argtypes = [d] * 4 + [pd] * 4
+        L.orc_filtered_moment_corrections.argtypes = [d] * 6 + [pd] * 3
+        L.orc_gradients.argtypes = [pp, pd, pd]
+        L.orc_gradients.restype = ctypes.c_int
         L.orc_tl_collide.argtypes = [pp, pd, pd, pd, ctypes.c_int]
         L.orc_tl_energy.argtypes = [pp] + [pd] * 7 + [ctypes.c_int, ctypes.c_int64, pd, pd]
         for name in ("orc_init", "orc_collide", "orc_stream", "orc_run", "orc_macro",
@@ -151,6 +157,37 @@ def matrices():
     T, Ti, Tm = np.zeros((9, 9)), np.zeros((9, 9)), np.zeros((5, 5))
     lib().orc_matrices(_ptr(T), _ptr(Ti), _ptr(Tm))
     return T, Ti, Tm
+
+
+def tm_inverse():
+    out = np.zeros((5, 5))
+    lib().orc_tm_inverse(_ptr(out))
+    return out
+
+
+def filter_terms(d2, X, Y, Z, dX, dY, dZ):
+    """(product term, ratio term) of the filter-width expansions at one point."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (dX, dY, dZ)]
+    out = np.zeros(2)
+    lib().orc_filter_terms(d2, X, Y, Z, *[_ptr(a) for a in arrs], _ptr(out))
+    return out[0], out[1]
+
+
+def filtered_moment_corrections(d2, rho, jx, jy, bx, by, grad):
+    """Delta^2 parts (dM^eq (9,), dN^eq (2, 5)) at one site; grad = d_x, d_y of
+    (rho, j_x, j_y, B_x, B_y) as 10 values."""
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    dm, dn = np.zeros(9), np.zeros(10)
+    lib().orc_filtered_moment_corrections(d2, rho, jx, jy, bx, by, _ptr(g), _ptr(dm), _ptr(dn))
+    return dm, dn.reshape(2, 5)
+
+
+def gradients(p: Params, state: np.ndarray) -> np.ndarray:
+    """(10, ny, nx): d_x, d_y of rho, j_x, j_y, B_x, B_y (kinetic-closure stencil)."""
+    st = np.ascontiguousarray(state, dtype=np.float64)
+    out = np.zeros((10, p.ny, p.nx))
+    _check(lib().orc_gradients(ctypes.byref(p.c()), _ptr(st), _ptr(out)), "gradients")
+    return out
 
 
 def equilibrium(rho, ux, uy, bx, by):

@@ -1,0 +1,203 @@
+"""Pins of the oracle's kinetic LES closure (les = 2).
+
+Flint & Vahala, arXiv:1607.08675, Sec. 2 and Sec. 4.1: the filtered equilibrium
+moments are M^eq(filtered conserved moments) + Delta^2 M^(Delta), the Delta^2
+part coming from the filter-width expansions of products (eq. FilterExampleSmall)
+and ratios (eq. FilterExampleLarge); the paper works M_3 out in eq. DeltaEqEx.
+
+* The expansions are checked against their definition: smooth periodic fields
+  filtered with the paper's Gaussian (eq. Gaussian, whose second moment is
+  Delta^2/12 per direction, i.e. transfer function exp(-Delta^2 k^2 / 24)) by
+  FFT.  The expansion error must be O(Delta^4): halving Delta divides it by
+  about 16.  This is done for the two rules and for every equilibrium moment.
+* The oracle's M_3 correction equals eq. DeltaEqEx as printed.
+* The lattice gradient d_a X = 3 sum_i w_i c_ia X(x + c_i) gives sin(k) cos(kx)
+  for sin(kx) exactly; conservation, fixed point and lattice symmetries hold.
+"""
+import numpy as np
+import pytest
+
+from lbmhd_inputs import random_fields, random_planes
+
+N = 48
+X1 = 2 * np.pi * np.arange(N) / N
+XX, YY = np.meshgrid(X1, X1, indexing="xy")
+K1 = np.fft.fftfreq(N, 1.0 / N)
+KX, KY = np.meshgrid(K1, K1, indexing="xy")
+
+
+def gfilter(a, delta):
+    return np.real(np.fft.ifft2(np.fft.fft2(a) * np.exp(-delta ** 2 * (KX ** 2 + KY ** 2) / 24)))
+
+
+def grad(a):
+    A = np.fft.fft2(a)
+    return np.real(np.fft.ifft2(1j * KX * A)), np.real(np.fft.ifft2(1j * KY * A))
+
+
+def smooth_fields():
+    rho = 1.0 + 0.2 * np.sin(XX + 2 * YY) + 0.1 * np.cos(3 * XX - YY)
+    jx = 0.1 * np.sin(2 * XX) * np.cos(YY) + 0.05 * np.cos(XX + YY)
+    jy = -0.08 * np.cos(XX - 2 * YY) + 0.04 * np.sin(3 * YY)
+    bx = 0.07 * np.sin(YY + 1.0) + 0.03 * np.cos(2 * XX + YY)
+    by = 0.06 * np.cos(2 * XX) + 0.05 * np.sin(XX - YY)
+    return rho, jx, jy, bx, by
+
+
+def test_tm_inverse(orc):
+    _, _, Tm = orc.matrices()
+    np.testing.assert_allclose(orc.tm_inverse() @ Tm, np.eye(5), atol=1e-15)
+
+
+def _rule_residuals(orc, delta):
+    X, Y, Z = (0.3 + 0.5 * np.sin(XX) * np.cos(2 * YY), 0.2 + 0.4 * np.cos(XX + YY),
+               1.2 + 0.3 * np.sin(2 * XX - YY))
+    FX, FY, FZ = (gfilter(a, delta) for a in (X, Y, Z))
+    gX, gY, gZ = grad(FX), grad(FY), grad(FZ)
+    lhs_p = gfilter(X * Y, delta) - FX * FY
+    lhs_r = gfilter(X * Y / Z, delta) - FX * FY / FZ
+    rp, rr = np.zeros_like(X), np.zeros_like(X)
+    for j in range(N):
+        for i in range(N):
+            rp[j, i], rr[j, i] = orc.filter_terms(
+                delta ** 2, FX[j, i], FY[j, i], FZ[j, i], [gX[0][j, i], gX[1][j, i]],
+                [gY[0][j, i], gY[1][j, i]], [gZ[0][j, i], gZ[1][j, i]])
+    return (np.abs(lhs_p - rp).max(), np.abs(lhs_p).max(), np.abs(lhs_r - rr).max(),
+            np.abs(lhs_r).max())
+
+
+def test_filter_expansion_rules_are_second_order(orc):
+    """eqs. FilterExampleSmall and FilterExampleLarge against Gaussian filtering."""
+    a = _rule_residuals(orc, 0.2)
+    b = _rule_residuals(orc, 0.1)
+    for res_a, size_a, res_b in ((a[0], a[1], b[0]), (a[2], a[3], b[2])):
+        assert res_a < 0.05 * size_a
+        assert 12 < res_a / res_b < 20, res_a / res_b
+
+
+def _moment_residuals(orc, delta):
+    fields = smooth_fields()
+    F = [gfilter(a, delta) for a in fields]
+    G = [grad(a) for a in F]
+    filt_meq = np.zeros((9, N, N))
+    filt_neq = np.zeros((10, N, N))
+    raw_m, raw_n = np.zeros((9, N, N)), np.zeros((10, N, N))
+    model_m, model_n = np.zeros((9, N, N)), np.zeros((10, N, N))
+    for j in range(N):
+        for i in range(N):
+            m, nq = orc.moment_equilibria(*(a[j, i] for a in fields))
+            raw_m[:, j, i], raw_n[:, j, i] = m, nq.ravel()
+            m0, n0 = orc.moment_equilibria(*(a[j, i] for a in F))
+            g10 = [G[f][d][j, i] for f in range(5) for d in range(2)]
+            dm, dn = orc.filtered_moment_corrections(delta ** 2, *(a[j, i] for a in F), g10)
+            model_m[:, j, i], model_n[:, j, i] = m0 + dm, n0.ravel() + dn.ravel()
+    for q in range(9):
+        filt_meq[q] = gfilter(raw_m[q], delta)
+    for q in range(10):
+        filt_neq[q] = gfilter(raw_n[q], delta)
+    return (np.abs(filt_meq - model_m).max(axis=(1, 2)), np.abs(filt_neq - model_n).max(axis=(1, 2)),
+            np.abs(filt_meq - raw_m).max(axis=(1, 2)))
+
+
+def test_filtered_equilibrium_moments_match_gaussian_filtering(orc):
+    """Every equilibrium moment: filtering M^eq(rho, j, B) equals
+    M^eq(filtered fields) + the oracle's Delta^2 part, to O(Delta^4)."""
+    ma, na, _ = _moment_residuals(orc, 0.2)
+    mb, nb, _ = _moment_residuals(orc, 0.1)
+    for q in (3, 4, 7, 8):
+        assert 12 < ma[q] / mb[q] < 20, (q, ma[q], mb[q])
+    for q in (2, 6):   # N_x2, N_y1 (flattened (2, 5)); N_x1 = N_y2 = 0 identically
+        assert 12 < na[q] / nb[q] < 20, (q, na[q], nb[q])
+    # linear moments are reproduced to roundoff (filtering commutes with them)
+    for q in (0, 1, 2, 5, 6):
+        assert ma[q] < 1e-13 and mb[q] < 1e-13
+    for q in (0, 1, 3, 4, 5, 7, 8, 9):
+        assert na[q] < 1e-13
+
+
+def test_m3_correction_is_the_papers_worked_example(orc):
+    """eq. DeltaEqEx, typed as printed (j written rho u), at random points."""
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        rho = 1 + 0.2 * rng.standard_normal()
+        jx, jy, bx, by = 0.1 * rng.standard_normal(4)
+        g = 0.05 * rng.standard_normal(10)
+        d2 = rng.uniform(0.5, 2.0)
+        dm, _ = orc.filtered_moment_corrections(d2, rho, jx, jy, bx, by, g)
+        dr, djx, djy, dbx, dby = g[0:2], g[2:4], g[4:6], g[6:8], g[8:10]
+        printed = d2 / (12 * rho) * (
+            np.dot(djx, djy) - np.dot(dr, (jx * djy + jy * djx - jx * jy * dr / rho)) / rho
+        ) - d2 / 12 * np.dot(dbx, dby)
+        assert abs(dm[3] - printed) < 1e-15
+
+
+def test_lattice_gradient_closed_form(orc):
+    """d_x of sin(k x) on the lattice is sin(k) cos(k x) (the D2Q9 stencil)."""
+    n = 32
+    k = 2 * np.pi * 3 / n
+    x = np.arange(n)[None, :] * np.ones((n, 1))
+    p = orc.Params(n, n)
+    st = orc.init(p, 1.0 + 0.01 * np.sin(k * x), 0.02 * np.sin(k * x), 0.0,
+                  0.03 * np.sin(k * x), 0.0)
+    g = orc.gradients(p, st)
+    np.testing.assert_allclose(g[0], 0.01 * np.sin(k) * np.cos(k * x), atol=1e-15)
+    np.testing.assert_allclose(g[6], 0.03 * np.sin(k) * np.cos(k * x), atol=1e-15)
+    np.testing.assert_allclose(g[1], 0.0, atol=1e-15)
+    np.testing.assert_allclose(g[7], 0.0, atol=1e-15)
+
+
+def _random_state(orc, p, seed, amp=2e-3):
+    st = orc.init(p, *random_fields(p.nx, p.ny, seed))
+    return st + random_planes(19, p.nx, p.ny, seed + 100, np.zeros(19), np.full(19, amp))
+
+
+def test_kinetic_closure_conserves_and_keeps_fixed_point(orc):
+    p = orc.Params(12, 10, nu=0.01, eta=0.02, s5=1.1, s6=1.1, s7=1.3, s8=0.9, les=2, delta=1.5)
+    st = _random_state(orc, p, 3)
+    d0 = orc.diag(p, st)
+    d1 = orc.diag(p, orc.run(p, st, 100))
+    assert abs(d1["mass"] - d0["mass"]) < 1e-13 * d0["mass"]
+    for k in ("mom_x", "mom_y", "flux_x", "flux_y"):
+        assert abs(d1[k] - d0[k]) < 1e-14 * p.nx * p.ny
+    u = orc.init(p, 1.1, 0.04, -0.03, 0.05, 0.02)
+    np.testing.assert_allclose(orc.run(p, u, 10), u, atol=2e-16)
+
+
+def test_kinetic_closure_vanishes_with_the_filter_width(orc):
+    p0 = orc.Params(10, 8, nu=0.01, eta=0.02, les=0)
+    p2 = orc.Params(10, 8, nu=0.01, eta=0.02, les=2, delta=1e-6)
+    st = _random_state(orc, p0, 5)
+    np.testing.assert_allclose(orc.run(p2, st, 5), orc.run(p0, st, 5), atol=1e-15)
+    p2b = orc.Params(10, 8, nu=0.01, eta=0.02, les=2, delta=1.0)
+    assert np.abs(orc.run(p2b, st, 5) - orc.run(p0, st, 5)).max() > 1e-8
+
+
+@pytest.mark.parametrize("op", ["rotate", "mirror"])
+def test_kinetic_closure_commutes_with_lattice_symmetries(orc, op):
+    from test_oracle_physics import _mirror_x, _rotate
+    f = _rotate if op == "rotate" else _mirror_x
+    p = orc.Params(8, 8, nu=0.02, eta=0.01, s5=1.3, s6=1.3, s7=1.1, s8=0.7, les=2, delta=1.2)
+    st = _random_state(orc, p, 21, amp=3e-3)
+    np.testing.assert_allclose(f(orc.run(p, st, 3)), orc.run(p, f(st), 3), atol=1e-15)
+
+
+def test_unit_rates_land_on_the_filtered_equilibrium(orc):
+    """With every rate 1 (tau0 = tau_m0 = 1), one collision sets the moments to
+    their relaxation targets: T f* = M^eq + Delta^2 M^(Delta) and
+    T_m g* = N^eq + Delta^2 N^(Delta), with the lattice gradients of the
+    pre-collision fields."""
+    nx, ny, d = 9, 7, 1.3
+    p = orc.Params(nx, ny, nu=1 / 6, eta=1 / 6, s5=1, s6=1, s7=1, s8=1, les=2, delta=d)
+    st = _random_state(orc, p, 8, amp=5e-3)
+    m = orc.macro(p, st)
+    g = orc.gradients(p, st)
+    out = orc.collide(p, st)
+    T, _, Tm = orc.matrices()
+    for y in range(ny):
+        for x in range(nx):
+            rho = m["rho"][y, x]
+            args = (rho, rho * m["ux"][y, x], rho * m["uy"][y, x], m["bx"][y, x], m["by"][y, x])
+            meq, neq = orc.moment_equilibria(*args)
+            dm, dn = orc.filtered_moment_corrections(d * d, *args, g[:, y, x])
+            np.testing.assert_allclose(T @ out[:9, y, x], meq + dm, atol=1e-15)
+            np.testing.assert_allclose(out[9:, y, x].reshape(2, 5) @ Tm.T, neq + dn, atol=1e-15)

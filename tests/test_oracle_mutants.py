@@ -18,7 +18,8 @@ from conftest import ROOT
 
 SRC = os.path.join(ROOT, "oracle", "lbmhd_oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_tables.py"),
-        os.path.join(ROOT, "tests", "test_oracle_physics.py")]
+        os.path.join(ROOT, "tests", "test_oracle_physics.py"),
+        os.path.join(ROOT, "tests", "test_oracle_kinetic.py")]
 
 MUTANTS = {
     "diagonal weight 1/36 -> 1/18": ("1.0 / 9.0 : 1.0 / 36.0)", "1.0 / 9.0 : 1.0 / 18.0)"),
@@ -47,6 +48,19 @@ MUTANTS = {
     "streaming direction of f": ("int64_t xd = wrap(x + CX[i], nx), yd = wrap(y + CY[i], ny);",
                                  "int64_t xd = wrap(x - CX[i], nx), yd = wrap(y - CY[i], ny);"),
     "dual product rule": ("r.d[k] = a.d[k] * b.v + a.v * b.d[k];", "r.d[k] = a.d[k] * b.v;"),
+    "ratio rule sign": ("acc = acc + dX[b] * dY[b] - (dZ[b] / Z) * (X * dY[b] + Y * dX[b] - X * Y * dZ[b] / Z);",
+                        "acc = acc + dX[b] * dY[b] + (dZ[b] / Z) * (X * dY[b] + Y * dX[b] - X * Y * dZ[b] / Z);"),
+    "product rule 1/12 -> 1/24": ("return (d2 / 12.0) * (dX[0] * dY[0] + dX[1] * dY[1]);",
+                                  "return (d2 / 24.0) * (dX[0] * dY[0] + dX[1] * dY[1]);"),
+    "M4 correction magnetic sign": ("- filtered_product_term(d2, gbx, gbx) + filtered_product_term(d2, gby, gby);",
+                                    "+ filtered_product_term(d2, gbx, gbx) - filtered_product_term(d2, gby, gby);"),
+    "M8 correction dropped": ("  dmeq[8] = -3.0 * (jxjx + jyjy);", "  dmeq[8] = 0.0 * (jxjx + jyjy);"),
+    "N correction sign": ("    dneq[5 * a + 1] = filtered_ratio_term(d2, jx, b[a], rho, gjx, gb[a], gr) -",
+                          "    dneq[5 * a + 1] = filtered_ratio_term(d2, jx, b[a], rho, gjx, gb[a], gr) +"),
+    "gradient stencil weight": ("3.0 * weight9(i) * double(CX[i]) * mac[m * n + t];",
+                                "2.0 * weight9(i) * double(CX[i]) * mac[m * n + t];"),
+    "T_m inverse transposed in use": ("acc = acc + tb.Tminv[k][r] * dneq[5 * a + r];",
+                                      "acc = acc + tb.Tminv[r][k] * dneq[5 * a + r];"),
     "dual sqrt rule": ("double g = r.v > 0.0 ? 0.5 / r.v : 0.0;", "double g = r.v > 0.0 ? 1.0 / r.v : 0.0;"),
 }
 
