@@ -125,6 +125,25 @@ def fp32_leg(torch, args):
     return out
 
 
+def kinetic_leg(torch, args):
+    """FP32 step with the paper's kinetic closure (filtered equilibria, Delta = 1)
+    on the headline 4096^2 Orszag-Tang workload."""
+    from lbmhd_inputs import orszag_tang
+    from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
+    n = 4096
+    cfg = LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=2, delta=1.0, storage="fp32")
+    lat = Lattice(cfg)
+    lat.init_fields(*orszag_tang(n, n))
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    per_launch = burst_ms_per_launch(torch, lat, 200)
+    d = lat.diag()
+    log(f"kinetic closure 4096^2 FP32: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
+    del lat
+    torch.cuda.empty_cache()
+    return dict(per_launch=per_launch, sites=n * n, nonfinite=d["nonfinite"])
+
+
 def fp16_leg(torch, args):
     from lbmhd_inputs import decaying_turbulence
     from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
@@ -274,7 +293,7 @@ def main():
     ap.add_argument("--fit-iters", type=int, default=20)
     ap.add_argument("--fit-ref-steps", type=int, default=5000)
     ap.add_argument("--skip", default="",
-                    help="comma list of legs to skip: fp16,adjoint,fit,cpu")
+                    help="comma list of legs to skip: kinetic,fp16,adjoint,fit,cpu")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -289,6 +308,7 @@ def main():
     log(f"device: {props.name}, {props.multi_processor_count} CUs")
 
     r32 = fp32_leg(torch, args)
+    rkin = None if "kinetic" in skip else kinetic_leg(torch, args)
     r16 = None if "fp16" in skip else fp16_leg(torch, args)
     radj = None if "adjoint" in skip else adjoint_leg(torch, args)
     rfit = None if "fit" in skip else fit_leg(torch, args)
@@ -335,6 +355,16 @@ def main():
                           "full-size sampled sites)",
         },
     }
+    if rkin:
+        mk = rkin["sites"] / (rkin["per_launch"] * 1e-3) / 1e6
+        ak = FP32_BYTES_PER_SITE * rkin["sites"] / (rkin["per_launch"] * 1e-3) / 1e9
+        line["kinetic_closure"] = {
+            "workload": "Orszag-Tang 4096x4096, FP32, kinetic LES closure (filtered equilibria, "
+                        "Delta = 1), nu=eta=1e-5",
+            "mlups": round(mk, 1), "ms_per_step": round(rkin["per_launch"], 5),
+            "achieved_gbs": round(ak, 1), "frac": round(ak / HBM_PEAK_GBS, 4),
+            "bytes_per_site": FP32_BYTES_PER_SITE, "nonfinite": rkin["nonfinite"],
+        }
     if r16:
         m16 = r16["sites"] / (r16["ms"] / args.fp16_steps * 1e-3) / 1e6
         a16 = FP16_BYTES_PER_SITE * r16["sites"] / (r16["per_launch"] * 1e-3) / 1e9

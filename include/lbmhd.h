@@ -72,11 +72,23 @@ typedef struct {
                              tau_m0 = 3 eta + 1/2 = 1/s_m (Sec. 4.3) */
   double s5, s6, s7, s8;  /* rates of the non-hydrodynamic moments M5..M8
                              (Sec. 3), each in (0, 2); s5 must equal s6 */
-  int32_t les;            /* 0: rates fixed; 1: Smagorinsky-MHD closure */
-  double cs, delta;       /* closure constant C_S >= 0 (used for both the
-                             eddy viscosity C_S Delta^2 |S| and the eddy
+  int32_t les;            /* bit mask, 0..3.  0: rates fixed, plain equilibria;
+                             bit 0 (1): Smagorinsky-MHD closure (Sec. 1.1):
+                                per-site relaxation times from the site's own
+                                non-equilibrium moments;
+                             bit 1 (2): kinetic closure (Sec. 4.1): relaxation
+                                toward the filtered equilibrium moments
+                                M^eq + Delta^2 M^(Delta) of the filter-width
+                                expansions (eqs. FilterExampleSmall,
+                                FilterExampleLarge, DeltaEqEx), with gradients
+                                of the neighbours' rho, j, B by the isotropic
+                                D2Q9 difference 3 sum_i w_i c_i X(x + c_i);
+                             3: both, the Smagorinsky estimate of |S| and |j|
+                                then measured from the filtered equilibria */
+  double cs, delta;       /* closure constant C_S >= 0 (les = 1: used for both
+                             the eddy viscosity C_S Delta^2 |S| and the eddy
                              resistivity C_S Delta^2 |j|) and filter width
-                             Delta > 0 in lattice units */
+                             Delta > 0 in lattice units (les = 1, 2) */
   int32_t storage;        /* LBMHD_FP32 or LBMHD_FP16 */
 } lbmhd_params;
 
@@ -217,6 +229,9 @@ int lbmhd_adj_seed_energy(lbmhd_t* h, const void* state, float* lam);
 int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
                             const double* uy_t, const double* bx_t, const double* by_t,
                             double scale, float* lam);
+
+/* The adjoint calls below cover les = 0 and les = 1; with the kinetic
+ * closure (les = 2 or 3) lbmhd_adj_step returns LBMHD_ERR_UNSUPPORTED. */
 
 /* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next, where state_n is
  * the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc

@@ -28,7 +28,8 @@
 //   * collide-then-stream with unit time step (the discrete LB update of
 //     Sec. 1.2): f_i(x + c_i, t+1) = f_i*(x, t).
 //
-//   * kinetic LES closure (les = 2; Sec. 4.1): the relaxation targets are the
+//   * kinetic LES closure (les = 2, or 3 together with the Smagorinsky
+//     closure; Sec. 4.1): the relaxation targets are the
 //     filtered equilibrium moments M^eq(filtered conserved moments) + the
 //     Delta^2 terms, obtained by applying the filter-width expansion of
 //     products (eq. FilterExampleSmall) and of ratios (eq. FilterExampleLarge)
@@ -237,8 +238,8 @@ typedef struct {
   int32_t nx, ny;
   double nu, eta;          // shear viscosity and resistivity, lattice units
   double s5, s6, s7, s8;   // rates of the non-hydrodynamic moments
-  int32_t les;             // 0: constant rates; 1: Smagorinsky-MHD closure;
-                           // 2: kinetic closure (filtered equilibria)
+  int32_t les;             // bit 0: Smagorinsky-MHD closure; bit 1: kinetic
+                           // closure (filtered equilibria); 0: neither
   double cs, delta;        // closure constant C_S and filter width Delta
 } orc_params;
 
@@ -407,15 +408,18 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
   // Kinetic LES closure: relax toward the filtered equilibrium moments.
   R dneq[10];
   for (int q = 0; q < 10; ++q) dneq[q] = 0.0;
-  if (p.les == 2) {
+  if (p.les & 2) {
     R dmeq[9];
     filtered_moment_corrections(p.delta * p.delta, rho, jx, jy, bx, by, grad, dmeq, dneq);
     for (int r = 0; r < 9; ++r) meq[r] = meq[r] + dmeq[r];
     for (int q = 0; q < 10; ++q) neq[q] = neq[q] + dneq[q];
   }
 
+  // Smagorinsky closure.  With the kinetic closure as well (les = 3) the
+  // non-equilibrium moments are taken relative to the filtered equilibrium:
+  // the paper's first-order moment M3^(1) is the strain term plus M3^(Delta).
   R tau = rt.tau0, taum = rt.taum0;
-  if (p.les == 1) {
+  if (p.les & 1) {
     double d2 = p.delta * p.delta;
     // Fluid: |S| = 3 Q / (2 rho tau) from the non-equilibrium M3, M4;
     // tau = tau0 + 3 C_S Delta^2 |S| solved for tau.
@@ -447,7 +451,7 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
   // closure, T_m^-1 of the Delta^2 parts of the equilibrium moments).
   R feq_unused[9], geq[10];
   equilibrium(rho, jx / rho, jy / rho, bx, by, feq_unused, geq);
-  if (p.les == 2)
+  if (p.les & 2)
     for (int a = 0; a < 2; ++a)
       for (int k = 0; k < 5; ++k) {
         R acc = 0.0;
@@ -462,7 +466,7 @@ inline int64_t wrap(int64_t a, int64_t n) { return ((a % n) + n) % n; }
 
 bool valid(const orc_params* p) {
   return p && p->nx >= 2 && p->ny >= 2 && p->nu > 0.0 && p->eta > 0.0 && p->les >= 0 &&
-         p->les <= 2;
+         p->les <= 3;
 }
 
 // d_x and d_y of (rho, j_x, j_y, B_x, B_y) at every site: the isotropic D2Q9
@@ -509,16 +513,16 @@ void collide_all(const orc_params& p, R* st, R cs, double* tau_out, double* taum
   const int64_t n = int64_t(p.nx) * p.ny;
   const Rates rt = make_rates(p);
   std::vector<R> grad;
-  if (p.les == 2) lattice_gradients(p, st, grad);
+  if (p.les & 2) lattice_gradients(p, st, grad);
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < n; ++s) {
     R f[9], g[10], gs[10];
     for (int i = 0; i < 9; ++i) f[i] = st[i * n + s];
     for (int q = 0; q < 10; ++q) g[q] = st[(9 + q) * n + s];
-    if (p.les == 2)
+    if (p.les & 2)
       for (int m = 0; m < 10; ++m) gs[m] = grad[m * n + s];
     collide_site(p, rt, cs, f, g, tau_out ? tau_out + s : nullptr,
-                 taum_out ? taum_out + s : nullptr, p.les == 2 ? gs : nullptr);
+                 taum_out ? taum_out + s : nullptr, (p.les & 2) ? gs : nullptr);
     for (int i = 0; i < 9; ++i) st[i * n + s] = f[i];
     for (int q = 0; q < 10; ++q) st[(9 + q) * n + s] = g[q];
   }

@@ -71,8 +71,9 @@ class Params:
 
     nu, eta: shear viscosity and resistivity (Sec. 4.3 gives s_3 = s_4 and s_m).
     s5..s8: rates of the non-hydrodynamic moments (not fixed by the paper).
-    les: 0 plain, 1 Smagorinsky-MHD closure, 2 kinetic closure (filtered
-    equilibria); cs: Smagorinsky constant; delta: filter width.
+    les: bit 0 = Smagorinsky-MHD closure, bit 1 = kinetic closure (filtered
+    equilibria), so 0 plain, 1, 2, or 3 for both; cs: Smagorinsky constant;
+    delta: filter width.
     """
     nx: int
     ny: int

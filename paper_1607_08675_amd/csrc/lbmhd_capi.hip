@@ -29,6 +29,16 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+// One step src -> dst with the handle's closure.
+hipError_t launch_one_step(const lbmhd_t* h, const void* src, void* dst) {
+  // C_S = 0 makes the Smagorinsky closure the identity (tau = tau0): skip it.
+  const bool smag = (h->p.les & 1) && h->p.cs > 0.0;
+  if (h->p.les & 2)
+    return lbk::launch_step_kin(h->p.storage, smag, src, dst, h->geo, h->rates, h->p.delta,
+                                h->stream);
+  return lbk::launch_step(h->p.storage, smag, src, dst, h->geo, h->rates, h->stream);
+}
+
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int fail(lbmhd_t* h, int code, const std::string& msg) {
@@ -112,7 +122,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   if (!rate_ok(p->s5) || !rate_ok(p->s6) || !rate_ok(p->s7) || !rate_ok(p->s8))
     return LBMHD_ERR_INVALID_ARG;
   if (p->s5 != p->s6) return LBMHD_ERR_INVALID_ARG;
-  if (p->les != 0 && p->les != 1) return LBMHD_ERR_INVALID_ARG;
+  if (p->les < 0 || p->les > 3) return LBMHD_ERR_INVALID_ARG;
   if (!(p->cs >= 0.0) || !isfinite(p->cs) || !(p->delta > 0.0) || !isfinite(p->delta))
     return LBMHD_ERR_INVALID_ARG;
   if (p->storage != LBMHD_FP32 && p->storage != LBMHD_FP16) return LBMHD_ERR_INVALID_ARG;
@@ -206,9 +216,7 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   if (int rc = need_bound(h)) return rc;
   if (nsteps < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
   for (int64_t t = 0; t < nsteps; ++t) {
-    // C_S = 0 makes the closure the identity (tau = tau0): use the plain kernel.
-    hipError_t e = lbk::launch_step(h->p.storage, h->p.les != 0 && h->p.cs > 0.0, h->lat[h->cur],
-                                      h->lat[1 - h->cur], h->geo, h->rates, h->stream);
+    hipError_t e = launch_one_step(h, h->lat[h->cur], h->lat[1 - h->cur]);
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
     h->cur = 1 - h->cur;
     ++h->step;
@@ -225,8 +233,7 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst) {
   for (const void* b : {(const void*)h->lat[0], (const void*)h->lat[1]})
     if (overlap(dst, h->lattice_bytes, b, h->lattice_bytes))
       return fail(h, LBMHD_ERR_INVALID_ARG, "dst overlaps a bound lattice");
-  hipError_t e = lbk::launch_step(h->p.storage, h->p.les != 0 && h->p.cs > 0.0, src, dst,
-                                  h->geo, h->rates, h->stream);
+  hipError_t e = launch_one_step(h, src, dst);
   if (e != hipSuccess) return hip_fail(h, e, "step launch");
   return LBMHD_OK;
 }
@@ -369,11 +376,13 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
 int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float* lam_prev,
                    double* acc) {
   if (int rc = need_bound(h)) return rc;
+  if (h->p.les & 2)
+    return fail(h, LBMHD_ERR_UNSUPPORTED, "the adjoint of the kinetic closure is not provided");
   if (!state_n || !lam_next || !lam_prev || !acc)
     return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
   if (overlap(lam_next, h->adj_lattice_bytes, lam_prev, h->adj_lattice_bytes))
     return fail(h, LBMHD_ERR_INVALID_ARG, "lam_prev overlaps lam_next");
-  hipError_t e = lbk::launch_adj_step(h->p.storage, h->p.les != 0, state_n, lam_next, lam_prev,
+  hipError_t e = lbk::launch_adj_step(h->p.storage, (h->p.les & 1) != 0, state_n, lam_next, lam_prev,
                                         acc, h->geo, h->geoa, h->rates,
                                         h->p.delta * h->p.delta, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");

@@ -40,6 +40,10 @@ constexpr int kDiagBlocks = 1024;
 // Forward step: dst = C(S(src)).
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
                        const Rates& r, hipStream_t s);
+// Forward step with the kinetic closure (filtered equilibria, filter width
+// delta), optionally with the Smagorinsky relaxation times as well.
+hipError_t launch_step_kin(int storage, bool smag, const void* src, void* dst, const Geom& g,
+                           const Rates& r, double delta, hipStream_t s);
 // Equilibrium initialisation from FP64 fields.
 hipError_t launch_init(int storage, const double* rho, const double* ux, const double* uy,
                        const double* bx, const double* by, void* lat, const Geom& g,

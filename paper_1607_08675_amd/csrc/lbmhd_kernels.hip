@@ -105,8 +105,16 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 //  Q = sqrt((M4 - M4eq)^2 + 4 (M3 - M3eq)^2) (|S| = 3 Q / (2 rho tau)), and
 //  tau_m = (tau_m0 + sqrt(tau_m0^2 + 36 C_S Delta^2 |A|)) / 2 with A the
 //  antisymmetric non-equilibrium first moment of g (j = -3 A / tau_m).
-template <bool LES>
-__device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rates& r) {
+// Delta^2 parts of the filtered equilibrium moments (kinetic closure): added
+// to M3^eq, M4^eq, M7^eq = M8^eq and to the u x B term E of g^eq
+// (N_y1^eq = E, N_x2^eq = -E).
+struct KinCorr {
+  float m3, m4, m78, e;
+};
+
+template <bool LES, bool KIN = false>
+__device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rates& r,
+                                        const KinCorr& kc = KinCorr{0.f, 0.f, 0.f, 0.f}) {
   const float a13 = f[1] + f[3], a24 = f[2] + f[4];
   const float d13 = f[1] - f[3], d24 = f[2] - f[4];
   const float s57 = f[5] + f[7], s68 = f[6] + f[8];
@@ -129,13 +137,22 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
   const float By = (g[5] + g[6]) + (g[7] + g[8]) + g[9];
   const float jxux = jx * ux, jyuy = jy * uy;
   const float jj = jxux + jyuy;
-  const float n3 = M3 - (jx * uy - Bx * By);
-  const float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
+  float n3 = M3 - (jx * uy - Bx * By);
+  float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
   const float n5 = M5 + jx;
   const float n6 = M6 + jy;
-  const float n7 = M7 + 3.0f * jj;
-  const float n8 = M8 - (5.0f / 3.0f) * drho + 3.0f * jj;
-  const float E = ux * By - uy * Bx;
+  float n7 = M7 + 3.0f * jj;
+  float n8 = M8 - (5.0f / 3.0f) * drho + 3.0f * jj;
+  float E = ux * By - uy * Bx;
+  if (KIN) {
+    // relax toward the filtered equilibria; with the Smagorinsky closure as
+    // well, Q and A below are then measured from the filtered equilibria
+    n3 -= kc.m3;
+    n4 -= kc.m4;
+    n7 -= kc.m78;
+    n8 -= kc.m78;
+    E += kc.e;
+  }
 
   float s3q, sm;
   if (LES) {
@@ -254,6 +271,137 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
       for (int j = 0; j < V; ++j) w[j] = C::enc(out[q][j]);
     }
     st_plane_nt<VT>(dst + q * P, od, w);
+  }
+}
+
+// ------------------------------------------------- kinetic-closure step
+// Same update as k_step, relaxing toward the filtered equilibria of the
+// paper's kinetic LES closure: the Delta^2 parts of the equilibrium moments
+// need rho, j, B of the 8 neighbours, taken from their pre-collision
+// (gathered) populations, differenced with the isotropic D2Q9 stencil
+// d_a X = 3 sum_i w_i c_ia X(x + c_i).  A 256-thread block owns 256 columns
+// and a strip of kKinRows rows.  It walks the strip row by row: it gathers
+// row y+1 (each population is read once), writes that row's rho - 1, j, B
+// into a rolling 3-row LDS buffer with one halo column on each side, and then
+// collides row y, whose populations it gathered on the previous pass.
+constexpr int kKinRows = 16;
+constexpr int kKinCols = kStepThreads + 2;
+
+template <int ST>
+__device__ __forceinline__ void gather_site(const typename Codec<ST>::T* __restrict__ src,
+                                            const Geom& geo, int x, int y, float (&p)[kNPop]) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  const int xm = x == 0 ? geo.nx - 1 : x - 1;
+  const int xp = x == geo.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? geo.ny - 1 : y - 1;
+  const int yp = y == geo.ny - 1 ? 0 : y + 1;
+  const unsigned row[3] = {unsigned(yp) * geo.pitch, unsigned(y) * geo.pitch,
+                           unsigned(ym) * geo.pitch};
+  const long long P = geo.plane;
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) {
+    const int xs = kPlaneCx[q] == 0 ? x : (kPlaneCx[q] == 1 ? xm : xp);
+    p[q] = C::dec(ld_plane<T>(src + q * P, row[kPlaneCy[q] + 1] + unsigned(xs)));
+  }
+}
+
+// rho - 1, j_x, j_y, B_x, B_y of gathered populations (deviation variables).
+__device__ __forceinline__ void site_moments(const float (&p)[kNPop], float (&m)[5]) {
+  m[0] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])) + p[8];
+  m[1] = (p[1] - p[3]) + (p[5] - p[7]) - (p[6] - p[8]);
+  m[2] = (p[2] - p[4]) + (p[5] - p[7]) + (p[6] - p[8]);
+  m[3] = (p[9] + p[10]) + (p[11] + p[12]) + p[13];
+  m[4] = (p[14] + p[15]) + (p[16] + p[17]) + p[18];
+}
+
+template <int ST, bool SMAG>
+__global__ __launch_bounds__(kStepThreads) void k_step_kin(
+    const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
+    Geom geo, Rates rt, float c12, int tiles_x) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  __shared__ float mac[3][5][kKinCols];
+  const int tx = int(threadIdx.x);
+  const int xt = (int(blockIdx.x) % tiles_x) * kStepThreads;
+  const int y0 = (int(blockIdx.x) / tiles_x) * kKinRows;
+  const int y1 = min(y0 + kKinRows, geo.ny);
+  const int x = xt + tx;
+  const bool active = x < geo.nx;
+  const int xc = x % geo.nx;                                   // column staged by this thread
+  const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1)     // halo column (threads 0, 1)
+                         : (xt + kStepThreads) % geo.nx;
+  const int ch = tx == 0 ? 0 : kKinCols - 1;
+  auto stage = [&](int yy, int slot, float (&p)[kNPop]) {
+    gather_site<ST>(src, geo, xc, yy, p);
+    float m[5];
+    site_moments(p, m);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) mac[slot][k][tx + 1] = m[k];
+    if (tx < 2) {
+      float ph[kNPop], mh[5];
+      gather_site<ST>(src, geo, xh, yy, ph);
+      site_moments(ph, mh);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) mac[slot][k][ch] = mh[k];
+    }
+  };
+  float cur[kNPop], nxt[kNPop];
+  stage(y0 == 0 ? geo.ny - 1 : y0 - 1, 0, nxt);   // row y0 - 1: moments only
+  stage(y0, 1, cur);
+  const long long P = geo.plane;
+  for (int y = y0; y < y1; ++y) {
+    const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
+    stage(y == geo.ny - 1 ? 0 : y + 1, sp, nxt);
+    __syncthreads();
+    if (active) {
+      const int c = tx + 1;
+      // isotropic D2Q9 gradient: d_x = (E - W)/3 + (NE - NW + SE - SW)/12, d_y likewise
+      float gx[5], gy[5], v[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const float e = mac[s0][k][c + 1], w = mac[s0][k][c - 1];
+        const float nn = mac[sp][k][c], ss = mac[sm][k][c];
+        const float ne = mac[sp][k][c + 1], nw = mac[sp][k][c - 1];
+        const float se = mac[sm][k][c + 1], sw = mac[sm][k][c - 1];
+        gx[k] = (1.0f / 3.0f) * (e - w) + (1.0f / 12.0f) * ((ne - nw) + (se - sw));
+        gy[k] = (1.0f / 3.0f) * (nn - ss) + (1.0f / 12.0f) * ((ne + nw) - (se + sw));
+        v[k] = mac[s0][k][c];
+      }
+      // Ratio terms (X Y / rho) use h_X = grad X - X grad(rho) / rho; product
+      // terms (B B) use the plain gradients:
+      //   R(X, Y) = Delta^2 / (12 rho) h_X . h_Y,  S(X, Y) = Delta^2 / 12 grad X . grad Y.
+      const float ir = frcp(1.0f + v[0]);
+      const float grx = gx[0] * ir, gry = gy[0] * ir;
+      float hx[4], hy[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        hx[k] = gx[k + 1] - v[k + 1] * grx;
+        hy[k] = gy[k + 1] - v[k + 1] * gry;
+      }
+      const float cr = c12 * ir;
+      const float jxjx = cr * (hx[0] * hx[0] + hy[0] * hy[0]);
+      const float jyjy = cr * (hx[1] * hx[1] + hy[1] * hy[1]);
+      KinCorr kc;
+      kc.m3 = cr * (hx[0] * hx[1] + hy[0] * hy[1]) - c12 * (gx[3] * gx[4] + gy[3] * gy[4]);
+      kc.m4 = (jxjx - jyjy) - c12 * ((gx[3] * gx[3] + gy[3] * gy[3]) - (gx[4] * gx[4] + gy[4] * gy[4]));
+      kc.m78 = -3.0f * (jxjx + jyjy);
+      kc.e = cr * ((hx[0] * hx[3] + hy[0] * hy[3]) - (hx[1] * hx[2] + hy[1] * hy[2]));
+      float f[9], g[10];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = cur[i];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) g[k] = cur[9 + k];
+      collide<SMAG, true>(f, g, rt, kc);
+      const unsigned od = unsigned(y) * geo.pitch + unsigned(x);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st_plane_nt<T>(dst + i * P, od, C::enc(f[i]));
+#pragma unroll
+      for (int k = 0; k < 10; ++k) st_plane_nt<T>(dst + (9 + k) * P, od, C::enc(g[k]));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kNPop; ++q) cur[q] = nxt[q];
   }
 }
 
@@ -574,6 +722,34 @@ void launch_step_v(bool les, const void* src, void* dst, const Geom& g, const Ra
     hipLaunchKernelGGL((k_step<ST, V, true>), grid, block, 0, s, a, b, g, r, tiles_x);
   else
     hipLaunchKernelGGL((k_step<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x);
+}
+
+template <int ST, bool SMAG>
+void launch_step_kin_t(const void* src, void* dst, const Geom& g, const Rates& r, float c12,
+                       hipStream_t s) {
+  using T = typename Codec<ST>::T;
+  const int tiles_x = (g.nx + kStepThreads - 1) / kStepThreads;
+  const int strips = (g.ny + kKinRows - 1) / kKinRows;
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kStepThreads);
+  hipLaunchKernelGGL((k_step_kin<ST, SMAG>), grid, block, 0, s, static_cast<const T*>(src),
+                     static_cast<T*>(dst), g, r, c12, tiles_x);
+}
+
+hipError_t launch_step_kin(int storage, bool smag, const void* src, void* dst, const Geom& g,
+                           const Rates& r, double delta, hipStream_t s) {
+  const float c12 = float(delta * delta / 12.0);
+  if (storage == LBMHD_FP32) {
+    if (smag)
+      launch_step_kin_t<LBMHD_FP32, true>(src, dst, g, r, c12, s);
+    else
+      launch_step_kin_t<LBMHD_FP32, false>(src, dst, g, r, c12, s);
+  } else {
+    if (smag)
+      launch_step_kin_t<LBMHD_FP16, true>(src, dst, g, r, c12, s);
+    else
+      launch_step_kin_t<LBMHD_FP16, false>(src, dst, g, r, c12, s);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,

@@ -25,7 +25,8 @@ class LBMHDConfig:
 
     nu, eta: viscosity and resistivity (tau0 = 3 nu + 1/2, tau_m0 = 3 eta + 1/2).
     s5 (= s6), s7, s8: rates of the non-hydrodynamic moments.
-    les, cs, delta: Smagorinsky-MHD closure switch, C_S and filter width.
+    les: bit mask -- 0 plain, 1 Smagorinsky-MHD closure, 2 kinetic closure
+    (filtered equilibria), 3 both; cs: Smagorinsky constant; delta: filter width.
     storage: "fp32" or "fp16" (deviation from the rest state, FP16 scaled by 2^10).
     """
     nx: int
@@ -35,7 +36,7 @@ class LBMHDConfig:
     s5: float = 1.0
     s7: float = 1.0
     s8: float = 1.0
-    les: bool = True
+    les: int = 1
     cs: float = 0.1
     delta: float = 1.0
     storage: str = "fp32"
@@ -43,7 +44,7 @@ class LBMHDConfig:
     def c_params(self) -> C.Params:
         st = {"fp32": C.LBMHD_FP32, "fp16": C.LBMHD_FP16}[self.storage]
         return C.Params(self.nx, self.ny, self.nu, self.eta, self.s5, self.s5, self.s7,
-                        self.s8, int(bool(self.les)), self.cs, self.delta, st)
+                        self.s8, int(self.les), self.cs, self.delta, st)
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:

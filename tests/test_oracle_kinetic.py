@@ -151,8 +151,9 @@ def _random_state(orc, p, seed, amp=2e-3):
     return st + random_planes(19, p.nx, p.ny, seed + 100, np.zeros(19), np.full(19, amp))
 
 
-def test_kinetic_closure_conserves_and_keeps_fixed_point(orc):
-    p = orc.Params(12, 10, nu=0.01, eta=0.02, s5=1.1, s6=1.1, s7=1.3, s8=0.9, les=2, delta=1.5)
+@pytest.mark.parametrize("les", [2, 3])
+def test_kinetic_closure_conserves_and_keeps_fixed_point(orc, les):
+    p = orc.Params(12, 10, nu=0.01, eta=0.02, s5=1.1, s6=1.1, s7=1.3, s8=0.9, les=les, delta=1.5)
     st = _random_state(orc, p, 3)
     d0 = orc.diag(p, st)
     d1 = orc.diag(p, orc.run(p, st, 100))
@@ -172,11 +173,12 @@ def test_kinetic_closure_vanishes_with_the_filter_width(orc):
     assert np.abs(orc.run(p2b, st, 5) - orc.run(p0, st, 5)).max() > 1e-8
 
 
+@pytest.mark.parametrize("les", [2, 3])
 @pytest.mark.parametrize("op", ["rotate", "mirror"])
-def test_kinetic_closure_commutes_with_lattice_symmetries(orc, op):
+def test_kinetic_closure_commutes_with_lattice_symmetries(orc, op, les):
     from test_oracle_physics import _mirror_x, _rotate
     f = _rotate if op == "rotate" else _mirror_x
-    p = orc.Params(8, 8, nu=0.02, eta=0.01, s5=1.3, s6=1.3, s7=1.1, s8=0.7, les=2, delta=1.2)
+    p = orc.Params(8, 8, nu=0.02, eta=0.01, s5=1.3, s6=1.3, s7=1.1, s8=0.7, les=les, delta=1.2)
     st = _random_state(orc, p, 21, amp=3e-3)
     np.testing.assert_allclose(f(orc.run(p, st, 3)), orc.run(p, f(st), 3), atol=1e-15)
 
@@ -201,3 +203,27 @@ def test_unit_rates_land_on_the_filtered_equilibrium(orc):
             dm, dn = orc.filtered_moment_corrections(d * d, *args, g[:, y, x])
             np.testing.assert_allclose(T @ out[:9, y, x], meq + dm, atol=1e-15)
             np.testing.assert_allclose(out[9:, y, x].reshape(2, 5) @ Tm.T, neq + dn, atol=1e-15)
+
+
+def test_mixed_closure_reads_strain_from_the_filtered_equilibrium(orc):
+    """les = 3: the Smagorinsky relaxation time is computed from M - (M^eq +
+    Delta^2 M^(Delta)), the strain part of the paper's first-order moment."""
+    nx, ny, d, cs = 9, 7, 1.3, 0.2
+    p = orc.Params(nx, ny, nu=0.01, eta=0.02, les=3, cs=cs, delta=d)
+    st = _random_state(orc, p, 12, amp=5e-3)
+    m = orc.macro(p, st)
+    g = orc.gradients(p, st)
+    _, tau, taum = orc.collide(p, st, return_tau=True)
+    T, _, Tm = orc.matrices()
+    for y in range(ny):
+        for x in range(nx):
+            rho = m["rho"][y, x]
+            args = (rho, rho * m["ux"][y, x], rho * m["uy"][y, x], m["bx"][y, x], m["by"][y, x])
+            meq, neq = orc.moment_equilibria(*args)
+            dm, dn = orc.filtered_moment_corrections(d * d, *args, g[:, y, x])
+            nm = T @ st[:9, y, x] - meq - dm
+            S = 3 / (2 * rho * tau[y, x]) * np.hypot(nm[4], 2 * nm[3])
+            assert abs(tau[y, x] - (3 * p.nu + 0.5 + 3 * cs * d * d * S)) < 1e-14
+            nn = st[9:, y, x].reshape(2, 5) @ Tm.T - neq - dn
+            jz = -3 / taum[y, x] * (nn[1, 1] - nn[0, 2])
+            assert abs(taum[y, x] - (3 * p.eta + 0.5 + 3 * cs * d * d * abs(jz))) < 1e-14
