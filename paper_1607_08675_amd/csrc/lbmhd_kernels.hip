@@ -284,7 +284,10 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
 // row y+1 (each population is read once), writes that row's rho - 1, j, B
 // into a rolling 3-row LDS buffer with one halo column on each side, and then
 // collides row y, whose populations it gathered on the previous pass.
-constexpr int kKinRows = 16;
+#ifndef LBMHD_KIN_ROWS
+#define LBMHD_KIN_ROWS 16
+#endif
+constexpr int kKinRows = LBMHD_KIN_ROWS;
 constexpr int kKinCols = kStepThreads + 2;
 
 template <int ST>
@@ -332,15 +335,18 @@ __global__ __launch_bounds__(kStepThreads) void k_step_kin(
   const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1)     // halo column (threads 0, 1)
                          : (xt + kStepThreads) % geo.nx;
   const int ch = tx == 0 ? 0 : kKinCols - 1;
+  // Gather row yy (and, in threads 0 and 1, a halo column: both gathers are
+  // issued before either is used) and write its moments to LDS slot `slot`.
   auto stage = [&](int yy, int slot, float (&p)[kNPop]) {
+    float ph[kNPop];
     gather_site<ST>(src, geo, xc, yy, p);
+    if (tx < 2) gather_site<ST>(src, geo, xh, yy, ph);
     float m[5];
     site_moments(p, m);
 #pragma unroll
     for (int k = 0; k < 5; ++k) mac[slot][k][tx + 1] = m[k];
     if (tx < 2) {
-      float ph[kNPop], mh[5];
-      gather_site<ST>(src, geo, xh, yy, ph);
+      float mh[5];
       site_moments(ph, mh);
 #pragma unroll
       for (int k = 0; k < 5; ++k) mac[slot][k][ch] = mh[k];

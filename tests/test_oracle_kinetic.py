@@ -227,3 +227,44 @@ def test_mixed_closure_reads_strain_from_the_filtered_equilibrium(orc):
             nn = st[9:, y, x].reshape(2, 5) @ Tm.T - neq - dn
             jz = -3 / taum[y, x] * (nn[1, 1] - nn[0, 2])
             assert abs(taum[y, x] - (3 * p.eta + 0.5 + 3 * cs * d * d * abs(jz))) < 1e-14
+
+
+def test_chapman_enskog_coefficient_of_the_magnetic_delta_term(orc):
+    """Macroscopic limit of the kinetic closure in the induction equation.
+    A discrete Chapman-Enskog expansion of f(x + c, t + 1) - f = -s (f - f^eq
+    - df) with a Delta^2 part df of the equilibrium gives the conserved-moment
+    flux (1 - s/2) Lambda^(1) + (s/2) dLambda with Lambda^(1) = dLambda - ...,
+    so dLambda enters with coefficient exactly 1: dB/dt gains
+    (d_y dE, -d_x dE), dE = Delta^2 part of N_y1^eq.  (The paper's final
+    induction equation prints 6 eta / (6 eta + 1) = 1 - s_m/2 instead; at
+    eta = 0.005 that is 0.029, which the test would reject.)  Check: the
+    difference of a kinetic-closure and a plain run after T steps equals
+    T (d_y dE, -d_x dE) of the initial field to a few percent."""
+    n, T, nu = 64, 20, 0.005
+    x = 2 * np.pi * np.arange(n) / n
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    k = np.fft.fftfreq(n, 1.0 / n) * 2 * np.pi / n
+    KX, KY = np.meshgrid(k, k, indexing="xy")
+    ddx = lambda a: np.real(np.fft.ifft2(1j * KX * np.fft.fft2(a)))
+    ddy = lambda a: np.real(np.fft.ifft2(1j * KY * np.fft.fft2(a)))
+    fields = (np.ones_like(X), 0.05 * np.sin(X) * np.cos(2 * Y), -0.025 * np.cos(X) * np.sin(2 * Y),
+              0.04 * np.sin(2 * Y), 0.03 * np.cos(X))
+    out = {}
+    for les in (0, 2):
+        p = orc.Params(n, n, nu=nu, eta=nu, les=les, delta=1.0)
+        out[les] = orc.macro(p, orc.run(p, orc.init(p, *fields), T))
+    p = orc.Params(n, n, nu=nu, eta=nu, les=2, delta=1.0)
+    st = orc.init(p, *fields)
+    g, m = orc.gradients(p, st), orc.macro(p, st)
+    dE = np.zeros_like(X)
+    for j in range(n):
+        for i in range(n):
+            r = m["rho"][j, i]
+            _, dn = orc.filtered_moment_corrections(
+                1.0, r, r * m["ux"][j, i], r * m["uy"][j, i], m["bx"][j, i], m["by"][j, i], g[:, j, i])
+            dE[j, i] = dn[1, 1]
+    for key, pred in (("bx", T * ddy(dE)), ("by", -T * ddx(dE))):
+        d = out[2][key] - out[0][key]
+        corr = np.sum(d * pred) / np.sqrt(np.sum(d * d) * np.sum(pred * pred))
+        ratio = np.sum(d * pred) / np.sum(pred * pred)
+        assert corr > 0.95 and abs(ratio - 1) < 0.06, (key, corr, ratio)
