@@ -279,22 +279,28 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
 // paper's kinetic LES closure: the Delta^2 parts of the equilibrium moments
 // need rho, j, B of the 8 neighbours, taken from their pre-collision
 // (gathered) populations, differenced with the isotropic D2Q9 stencil
-// d_a X = 3 sum_i w_i c_ia X(x + c_i).  A 256-thread block owns 256 columns
-// and a strip of kKinRows rows.  It walks the strip row by row: it gathers
+// d_a X = 3 sum_i w_i c_ia X(x + c_i).  A block of kKinThreads threads owns
+// as many columns and a strip of kKinRows rows.  It walks the strip row by row: it gathers
 // row y+1 (each population is read once), writes that row's rho - 1, j, B
 // into a rolling 3-row LDS buffer with one halo column on each side, and then
 // collides row y, whose populations it gathered on the previous pass.
 #ifndef LBMHD_KIN_ROWS
 #define LBMHD_KIN_ROWS 16
 #endif
+#ifndef LBMHD_KIN_THREADS
+#define LBMHD_KIN_THREADS 512
+#endif
 constexpr int kKinRows = LBMHD_KIN_ROWS;
-constexpr int kKinCols = kStepThreads + 2;
+constexpr int kKinThreads = LBMHD_KIN_THREADS;
+constexpr int kKinCols = kKinThreads + 2;
 
+// Encoded populations of the pre-collision state at (x, y): pre_q(x) =
+// src_q(x - c_q), periodic.  The loads are only issued here; decoding happens
+// where the values are used, so they can stay in flight meanwhile.
 template <int ST>
-__device__ __forceinline__ void gather_site(const typename Codec<ST>::T* __restrict__ src,
-                                            const Geom& geo, int x, int y, float (&p)[kNPop]) {
-  using C = Codec<ST>;
-  using T = typename C::T;
+__device__ __forceinline__ void load_site(const typename Codec<ST>::T* __restrict__ src,
+                                          const Geom& geo, int x, int y,
+                                          typename Codec<ST>::T (&p)[kNPop]) {
   const int xm = x == 0 ? geo.nx - 1 : x - 1;
   const int xp = x == geo.nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? geo.ny - 1 : y - 1;
@@ -305,7 +311,7 @@ __device__ __forceinline__ void gather_site(const typename Codec<ST>::T* __restr
 #pragma unroll
   for (int q = 0; q < kNPop; ++q) {
     const int xs = kPlaneCx[q] == 0 ? x : (kPlaneCx[q] == 1 ? xm : xp);
-    p[q] = C::dec(ld_plane<T>(src + q * P, row[kPlaneCy[q] + 1] + unsigned(xs)));
+    p[q] = ld_plane<typename Codec<ST>::T>(src + q * P, row[kPlaneCy[q] + 1] + unsigned(xs));
   }
 }
 
@@ -319,46 +325,59 @@ __device__ __forceinline__ void site_moments(const float (&p)[kNPop], float (&m)
 }
 
 template <int ST, bool SMAG>
-__global__ __launch_bounds__(kStepThreads) void k_step_kin(
+__global__ __launch_bounds__(kKinThreads) void k_step_kin(
     const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
     Geom geo, Rates rt, float c12, int tiles_x) {
   using C = Codec<ST>;
   using T = typename C::T;
   __shared__ float mac[3][5][kKinCols];
   const int tx = int(threadIdx.x);
-  const int xt = (int(blockIdx.x) % tiles_x) * kStepThreads;
+  const int xt = (int(blockIdx.x) % tiles_x) * kKinThreads;
   const int y0 = (int(blockIdx.x) / tiles_x) * kKinRows;
   const int y1 = min(y0 + kKinRows, geo.ny);
   const int x = xt + tx;
   const bool active = x < geo.nx;
   const int xc = x % geo.nx;                                   // column staged by this thread
   const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1)     // halo column (threads 0, 1)
-                         : (xt + kStepThreads) % geo.nx;
+                         : (xt + kKinThreads) % geo.nx;
   const int ch = tx == 0 ? 0 : kKinCols - 1;
-  // Gather row yy (and, in threads 0 and 1, a halo column: both gathers are
-  // issued before either is used) and write its moments to LDS slot `slot`.
-  auto stage = [&](int yy, int slot, float (&p)[kNPop]) {
-    float ph[kNPop];
-    gather_site<ST>(src, geo, xc, yy, p);
-    if (tx < 2) gather_site<ST>(src, geo, xh, yy, ph);
+  // Rows are loaded one pass ahead of their use: the loads of row y + 2 (and,
+  // in threads 0 and 1, of a halo column) are issued before row y collides,
+  // and row y + 1, loaded on the previous pass, is decoded and its moments
+  // written to LDS slot `slot` (rows wrap periodically).
+  T raw[kNPop], rawh[kNPop];
+  auto issue = [&](int yy) {
+    yy = yy < 0 ? yy + geo.ny : (yy >= geo.ny ? yy - geo.ny : yy);
+    load_site<ST>(src, geo, xc, yy, raw);
+    if (tx < 2) load_site<ST>(src, geo, xh, yy, rawh);
+  };
+  auto commit = [&](int slot, float (&p)[kNPop]) {
+#pragma unroll
+    for (int q = 0; q < kNPop; ++q) p[q] = C::dec(raw[q]);
     float m[5];
     site_moments(p, m);
 #pragma unroll
     for (int k = 0; k < 5; ++k) mac[slot][k][tx + 1] = m[k];
     if (tx < 2) {
-      float mh[5];
+      float ph[kNPop], mh[5];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) ph[q] = C::dec(rawh[q]);
       site_moments(ph, mh);
 #pragma unroll
       for (int k = 0; k < 5; ++k) mac[slot][k][ch] = mh[k];
     }
   };
   float cur[kNPop], nxt[kNPop];
-  stage(y0 == 0 ? geo.ny - 1 : y0 - 1, 0, nxt);   // row y0 - 1: moments only
-  stage(y0, 1, cur);
+  issue(y0 - 1);                                  // row y0 - 1: moments only
+  commit(0, nxt);
+  issue(y0);
+  commit(1, cur);
+  issue(y0 + 1);
   const long long P = geo.plane;
   for (int y = y0; y < y1; ++y) {
     const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
-    stage(y == geo.ny - 1 ? 0 : y + 1, sp, nxt);
+    commit(sp, nxt);
+    if (y + 2 <= y1) issue(y + 2);
     __syncthreads();
     if (active) {
       const int c = tx + 1;
@@ -734,9 +753,9 @@ template <int ST, bool SMAG>
 void launch_step_kin_t(const void* src, void* dst, const Geom& g, const Rates& r, float c12,
                        hipStream_t s) {
   using T = typename Codec<ST>::T;
-  const int tiles_x = (g.nx + kStepThreads - 1) / kStepThreads;
+  const int tiles_x = (g.nx + kKinThreads - 1) / kKinThreads;
   const int strips = (g.ny + kKinRows - 1) / kKinRows;
-  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kStepThreads);
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kKinThreads);
   hipLaunchKernelGGL((k_step_kin<ST, SMAG>), grid, block, 0, s, static_cast<const T*>(src),
                      static_cast<T*>(dst), g, r, c12, tiles_x);
 }

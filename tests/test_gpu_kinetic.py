@@ -1,7 +1,7 @@
 """GPU parity of the kinetic LES closure (les = 2) against the FP64 oracle.
 
 The kernel stages rho, j, B of each row in LDS and walks strips of rows; the
-sizes below cover one and several strips (16 rows each) and tiles (256
+sizes below cover one and several strips (16 rows each) and tiles (512
 columns), ragged ends, and lattices narrower than a tile.  Tolerances as for
 the plain update: FP32 populations within 5e-7 after one step, 2e-6 after
 ten; relative L2 of u and B within 1e-5 after 500 steps of a 64^2
@@ -49,7 +49,7 @@ def gpu_state_after(orc, op, x0, n):
 
 @pytest.mark.parametrize("les", [2, 3])
 @pytest.mark.parametrize("nx,ny", [(8, 8), (100, 36), (300, 5), (2, 2), (257, 3), (64, 40),
-                                   (520, 33), (16, 17)])
+                                   (520, 33), (16, 17), (1100, 19), (513, 18), (1024, 33)])
 def test_one_step_fp32(lb, orc, nx, ny, les):
     L, op = make(lb, orc, nx, ny, les=les, nu=0.01, eta=0.02, s5=1.2, s7=1.5, s8=0.8, delta=1.3,
                  cs=0.15)
@@ -81,7 +81,7 @@ def test_ten_steps_fp32(lb, orc, les):
 
 
 @pytest.mark.parametrize("les", [2, 3])
-@pytest.mark.parametrize("nx,ny", [(8, 8), (300, 21), (257, 3)])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (300, 21), (257, 3), (1030, 17)])
 def test_one_step_fp16(lb, orc, nx, ny, les):
     L, op = make(lb, orc, nx, ny, "fp16", les=les, nu=0.01, eta=0.02, delta=1.0)
     dev = random_state(nx, ny, seed=3 + nx) - W19[:, None, None]
@@ -122,7 +122,7 @@ def test_full_size_sampled_sites(lb, orc, les):
     L.init_fields(*f).step(k)
     pops = L.populations()
     rng = np.random.default_rng(9)
-    sites = [(0, 0), (n - 1, n - 1), (255, 15), (256, 16), (n // 2, 1)]
+    sites = [(0, 0), (n - 1, n - 1), (511, 15), (512, 16), (n // 2, 1)]
     sites += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(15)]
     op = orc.Params(2 * r + 1, 2 * r + 1, nu=1e-5, eta=1e-5, les=les, cs=0.1, delta=1.0)
     for (x, y) in sites:
