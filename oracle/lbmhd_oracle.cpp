@@ -25,6 +25,10 @@
 //     strain read from the site's own non-equilibrium second moments (the
 //     Sec. 1.2 relation between sum_i c_a c_b f^(1) and the strain) and the
 //     current read from the non-equilibrium first moments of g;
+//   * the cross-helicity closure (les = 4, or 6 together with the kinetic
+//     closure; eqs. CHClosureV/B): nu_t = C_S Delta^2 |S^v : S^b|^(1/2) and
+//     eta_t = C_S Delta^2 sgn(j . omega) |j . omega|^(1/2), where S^v is the
+//     strain of u, S^b the symmetrised gradient of B and omega the vorticity;
 //   * collide-then-stream with unit time step (the discrete LB update of
 //     Sec. 1.2): f_i(x + c_i, t+1) = f_i*(x, t).
 //
@@ -53,7 +57,18 @@
 //   * kinetic closure: the lattice sites carry the filtered fields, and the
 //     gradients in the Delta^2 terms are the isotropic D2Q9 differences
 //     d_a X(x) = 3 sum_i w_i c_ia X(x + c_i) of the pre-collision rho, rho u, B;
-//     the relaxation times stay tau0 and tau_m0.
+//     the relaxation times stay tau0 and tau_m0;
+//   * cross-helicity closure: S^v from the non-equilibrium M3, M4 as for the
+//     Smagorinsky closure; S^b and j from the non-equilibrium first-moment
+//     tensor of g, Lambda_ab = sum_k C_ka g_kb ~ -(tau_m / 3) d_a B_b (its
+//     equilibrium is antisymmetric, so the symmetric part carries d_a B_b
+//     alone); only the traceless parts of S^v and S^b enter the contraction;
+//     omega = d_x u_y - d_y u_x with d_a u_b = (d_a j_b - u_b d_a rho) / rho
+//     from the isotropic lattice differences of the pre-collision rho and j;
+//     tau = tau0 + 3 nu_t and tau_m = tau_m0 + 3 eta_t solved self-consistently
+//     (each a cubic in the square root of the relaxation time, largest root);
+//     where backscatter (eta_t < 0) would make the total resistivity
+//     eta + eta_t negative, it is clipped at zero, tau_m = 1/2.
 //
 // State layout: 19 planes of nx*ny doubles, [plane][y][x] with x fastest.
 // Planes 0..8 hold f_0..f_8, planes 9..13 hold the x component of g_0..g_4,
@@ -239,7 +254,8 @@ typedef struct {
   double nu, eta;          // shear viscosity and resistivity, lattice units
   double s5, s6, s7, s8;   // rates of the non-hydrodynamic moments
   int32_t les;             // bit 0: Smagorinsky-MHD closure; bit 1: kinetic
-                           // closure (filtered equilibria); 0: neither
+                           // closure (filtered equilibria); bit 2: cross-
+                           // helicity closure (not with bit 0); 0: none
   double cs, delta;        // closure constant C_S and filter width Delta
 } orc_params;
 
@@ -352,6 +368,30 @@ void filtered_moment_corrections(double d2, R rho, R jx, R jy, R bx, R by, const
   }
 }
 
+// Largest real root of t^3 - p t - q = 0 for p > 0: the trigonometric form
+// where the cubic has three real roots, Cardano's formula where it has one
+// (q > 2 (p/3)^(3/2)).  Returns -1 when no root is positive (q below
+// -2 (p/3)^(3/2)).
+double largest_cubic_root(double p, double q) {
+  const double r = std::sqrt(p / 3.0);
+  const double h = q / (2.0 * r * r * r);
+  if (h > 1.0) {
+    const double d = std::sqrt(0.25 * q * q - r * r * r * r * r * r);
+    return std::cbrt(0.5 * q + d) + std::cbrt(0.5 * q - d);
+  }
+  if (h < -1.0) return -1.0;
+  return 2.0 * r * std::cos(std::acos(h) / 3.0);
+}
+
+// The same root in R: one Newton step from the FP64 root t keeps its value and
+// gives dual numbers the implicit-function derivative (t dp + dq) / (3 t^2 - p).
+template <class R>
+R cubic_root_in(R p, R q, double t) {
+  return t - (t * t * t - p * t - q) / (3.0 * t * t - p);
+}
+
+inline double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
 struct Rates {
   double tau0, taum0;   // constant relaxation times 1/s_3 and 1/s_m
   double s[9];          // s_0..s_8; s_3, s_4 replaced by the closure
@@ -431,6 +471,43 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
     R A = (N[5 + 1] - neq[5 + 1]) - (N[0 + 2] - neq[0 + 2]);
     taum = 0.5 * (rt.taum0 + root(rt.taum0 * rt.taum0 + 36.0 * d2 * cs * magnitude(A)));
   }
+  // Cross-helicity closure (eqs. CHClosureV/B), C_Sv = C_Sb = C_S.
+  if (p.les & 4) {
+    double d2 = p.delta * p.delta;
+    // Traceless strains: S^v_xx - S^v_yy = -3 n4 / (2 rho tau), S^v_xy =
+    // -3 n3 / (2 rho tau); S^b_xx - S^b_yy = -3 (L_xx - L_yy) / tau_m,
+    // S^b_xy = -3 (L_xy + L_yx) / (2 tau_m), L = non-equilibrium Lambda.
+    // For traceless symmetric 2x2 tensors S^v : S^b = (1/2) (S^v_xx - S^v_yy)
+    // (S^b_xx - S^b_yy) + 2 S^v_xy S^b_xy = 9 P / (4 rho tau tau_m) with
+    // P = n4 (L_xx - L_yy) + 2 n3 (L_xy + L_yx).
+    R n3 = M[3] - meq[3], n4 = M[4] - meq[4];
+    R dL = (N[0 + 1] - neq[0 + 1]) - (N[5 + 2] - neq[5 + 2]);
+    R sL = (N[5 + 1] - neq[5 + 1]) + (N[0 + 2] - neq[0 + 2]);
+    R P = n4 * dL + 2.0 * n3 * sL;
+    // j_z = -3 A / tau_m (as for the Smagorinsky closure) and the vorticity
+    // from the lattice gradients: grad = (d_x rho, d_y rho, d_x j_x, d_y j_x,
+    // d_x j_y, d_y j_y, ...).
+    R A = (N[5 + 1] - neq[5 + 1]) - (N[0 + 2] - neq[0 + 2]);
+    R ux = jx / rho, uy = jy / rho;
+    R omega = ((grad[4] - uy * grad[0]) - (grad[3] - ux * grad[1])) / rho;
+    // tau_m = tau_m0 + 3 eta_t with j . omega = -3 A omega / tau_m: for
+    // t = sqrt(tau_m), t^3 - tau_m0 t - qb = 0 with
+    // qb = -3 sqrt(3) C_S Delta^2 sgn(A omega) |A omega|^(1/2).
+    R X = A * omega;
+    R qb = -3.0 * std::sqrt(3.0) * d2 * cs * sign_of(value(X)) * root(magnitude(X));
+    const double tm = largest_cubic_root(rt.taum0, value(qb));
+    if (tm < std::sqrt(0.5)) {
+      taum = R(0.5);  // eta + eta_t clipped at zero
+    } else {
+      R t = cubic_root_in(R(rt.taum0), qb, tm);
+      taum = t * t;
+    }
+    // tau = tau0 + 3 nu_t, nu_t = C_S Delta^2 (9 |P| / (4 rho tau tau_m))^(1/2):
+    // for t = sqrt(tau), t^3 - tau0 t - qv = 0, qv = (9/2) C_S Delta^2 (|P| / (rho tau_m))^(1/2).
+    R qv = 4.5 * d2 * cs * root(magnitude(P) / (rho * taum));
+    R t = cubic_root_in(R(rt.tau0), qv, largest_cubic_root(rt.tau0, value(qv)));
+    tau = t * t;
+  }
   if (tau_out) *tau_out = value(tau);
   if (taum_out) *taum_out = value(taum);
 
@@ -466,7 +543,7 @@ inline int64_t wrap(int64_t a, int64_t n) { return ((a % n) + n) % n; }
 
 bool valid(const orc_params* p) {
   return p && p->nx >= 2 && p->ny >= 2 && p->nu > 0.0 && p->eta > 0.0 && p->les >= 0 &&
-         p->les <= 3;
+         p->les <= 6 && !((p->les & 1) && (p->les & 4));
 }
 
 // d_x and d_y of (rho, j_x, j_y, B_x, B_y) at every site: the isotropic D2Q9
@@ -513,16 +590,17 @@ void collide_all(const orc_params& p, R* st, R cs, double* tau_out, double* taum
   const int64_t n = int64_t(p.nx) * p.ny;
   const Rates rt = make_rates(p);
   std::vector<R> grad;
-  if (p.les & 2) lattice_gradients(p, st, grad);
+  const bool stencil = (p.les & 6) != 0;
+  if (stencil) lattice_gradients(p, st, grad);
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < n; ++s) {
     R f[9], g[10], gs[10];
     for (int i = 0; i < 9; ++i) f[i] = st[i * n + s];
     for (int q = 0; q < 10; ++q) g[q] = st[(9 + q) * n + s];
-    if (p.les & 2)
+    if (stencil)
       for (int m = 0; m < 10; ++m) gs[m] = grad[m * n + s];
     collide_site(p, rt, cs, f, g, tau_out ? tau_out + s : nullptr,
-                 taum_out ? taum_out + s : nullptr, (p.les & 2) ? gs : nullptr);
+                 taum_out ? taum_out + s : nullptr, stencil ? gs : nullptr);
     for (int i = 0; i < 9; ++i) st[i * n + s] = f[i];
     for (int q = 0; q < 10; ++q) st[(9 + q) * n + s] = g[q];
   }

@@ -72,8 +72,9 @@ class Params:
     nu, eta: shear viscosity and resistivity (Sec. 4.3 gives s_3 = s_4 and s_m).
     s5..s8: rates of the non-hydrodynamic moments (not fixed by the paper).
     les: bit 0 = Smagorinsky-MHD closure, bit 1 = kinetic closure (filtered
-    equilibria), so 0 plain, 1, 2, or 3 for both; cs: Smagorinsky constant;
-    delta: filter width.
+    equilibria), bit 2 = cross-helicity closure (eqs. CHClosureV/B; not with
+    bit 0), so 0 plain, 1, 2, 3, 4 or 6; cs: closure constant; delta: filter
+    width.
     """
     nx: int
     ny: int

@@ -3,9 +3,9 @@
 Each case plants one mistake in a copy of ``oracle/lbmhd_oracle.cpp`` (a
 wrong weight, a flipped sign, a dropped factor, a transposed inverse, the
 wrong streaming direction, a wrong closure constant, a wrong rate index, a
-broken dual-number rule), builds it with the same flags into a temporary
-library, and runs the pin suite (test_oracle_tables.py, test_oracle_physics.py)
-against it in a subprocess.  Every mutant must make at least one pin fail; the
+wrong root or sign in a closure, a broken dual-number rule), builds it with the same flags into a temporary
+library, and runs the pin suites (tables, physics, kinetic and cross-helicity
+closures) against it in a subprocess.  Every mutant must make at least one pin fail; the
 unmodified source must pass.  Everything runs on the CPU.
 """
 import os
@@ -19,7 +19,8 @@ from conftest import ROOT
 SRC = os.path.join(ROOT, "oracle", "lbmhd_oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_tables.py"),
         os.path.join(ROOT, "tests", "test_oracle_physics.py"),
-        os.path.join(ROOT, "tests", "test_oracle_kinetic.py")]
+        os.path.join(ROOT, "tests", "test_oracle_kinetic.py"),
+        os.path.join(ROOT, "tests", "test_oracle_crosshelicity.py")]
 
 MUTANTS = {
     "diagonal weight 1/36 -> 1/18": ("1.0 / 9.0 : 1.0 / 36.0)", "1.0 / 9.0 : 1.0 / 18.0)"),
@@ -61,6 +62,24 @@ MUTANTS = {
                                 "2.0 * weight9(i) * double(CX[i]) * mac[m * n + t];"),
     "T_m inverse transposed in use": ("acc = acc + tb.Tminv[k][r] * dneq[5 * a + r];",
                                       "acc = acc + tb.Tminv[r][k] * dneq[5 * a + r];"),
+    "cross-helicity contraction drops factor 2": ("R P = n4 * dL + 2.0 * n3 * sL;",
+                                                 "R P = n4 * dL + n3 * sL;"),
+    "cross-helicity S^b takes the antisymmetric part": (
+        "R sL = (N[5 + 1] - neq[5 + 1]) + (N[0 + 2] - neq[0 + 2]);",
+        "R sL = (N[5 + 1] - neq[5 + 1]) - (N[0 + 2] - neq[0 + 2]);"),
+    "cross-helicity normal strain of B summed": (
+        "R dL = (N[0 + 1] - neq[0 + 1]) - (N[5 + 2] - neq[5 + 2]);",
+        "R dL = (N[0 + 1] - neq[0 + 1]) + (N[5 + 2] - neq[5 + 2]);"),
+    "cross-helicity sign of the backscatter": ("R qb = -3.0 * std::sqrt(3.0) * d2",
+                                               "R qb = 3.0 * std::sqrt(3.0) * d2"),
+    "vorticity sign of d_y u_x": ("R omega = ((grad[4] - uy * grad[0]) - (grad[3] - ux * grad[1])) / rho;",
+                                  "R omega = ((grad[4] - uy * grad[0]) + (grad[3] - ux * grad[1])) / rho;"),
+    "cross-helicity resistivity not clipped": ("if (tm < std::sqrt(0.5)) {", "if (tm < 0.0) {"),
+    "cubic takes the middle root": ("return 2.0 * r * std::cos(std::acos(h) / 3.0);",
+                                    "return 2.0 * r * std::cos((std::acos(h) - 2.0 * M_PI) / 3.0);"),
+    "Cardano sign": ("return std::cbrt(0.5 * q + d) + std::cbrt(0.5 * q - d);",
+                     "return std::cbrt(0.5 * q + d) - std::cbrt(0.5 * q - d);"),
+    "cross-helicity viscosity factor 9/2 -> 3": ("R qv = 4.5 * d2 * cs", "R qv = 3.0 * d2 * cs"),
     "dual sqrt rule": ("double g = r.v > 0.0 ? 0.5 / r.v : 0.0;", "double g = r.v > 0.0 ? 1.0 / r.v : 0.0;"),
 }
 
