@@ -125,20 +125,26 @@ def fp32_leg(torch, args):
     return out
 
 
-def kinetic_leg(torch, args):
-    """FP32 step with the paper's kinetic closure (filtered equilibria, Delta = 1)
-    on the headline 4096^2 Orszag-Tang workload."""
+CLOSURES = {2: "kinetic closure", 4: "cross-helicity closure"}
+
+
+def closure_leg(torch, args, les):
+    """FP32 step with one of the paper's neighbour-dependent closures on the
+    headline 4096^2 Orszag-Tang workload: les = 2, the kinetic closure
+    (filtered equilibria, Delta = 1); les = 4, the cross-helicity closure
+    (C_S = 0.1, backscatter clipped at zero total resistivity)."""
     from lbmhd_inputs import orszag_tang
     from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
     n = 4096
-    cfg = LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=2, delta=1.0, storage="fp32")
+    cfg = LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=les, cs=0.1, delta=1.0,
+                      storage="fp32")
     lat = Lattice(cfg)
     lat.init_fields(*orszag_tang(n, n))
     lat.step(args.warmup)
     torch.cuda.synchronize()
     per_launch = burst_ms_per_launch(torch, lat, 200)
     d = lat.diag()
-    log(f"kinetic closure 4096^2 FP32: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
+    log(f"{CLOSURES[les]} 4096^2 FP32: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
     del lat
     torch.cuda.empty_cache()
     return dict(per_launch=per_launch, sites=n * n, nonfinite=d["nonfinite"])
@@ -293,7 +299,7 @@ def main():
     ap.add_argument("--fit-iters", type=int, default=20)
     ap.add_argument("--fit-ref-steps", type=int, default=5000)
     ap.add_argument("--skip", default="",
-                    help="comma list of legs to skip: kinetic,fp16,adjoint,fit,cpu")
+                    help="comma list of legs to skip: kinetic,crosshelicity,fp16,adjoint,fit,cpu")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -308,7 +314,8 @@ def main():
     log(f"device: {props.name}, {props.multi_processor_count} CUs")
 
     r32 = fp32_leg(torch, args)
-    rkin = None if "kinetic" in skip else kinetic_leg(torch, args)
+    rkin = None if "kinetic" in skip else closure_leg(torch, args, 2)
+    rch = None if "crosshelicity" in skip else closure_leg(torch, args, 4)
     r16 = None if "fp16" in skip else fp16_leg(torch, args)
     radj = None if "adjoint" in skip else adjoint_leg(torch, args)
     rfit = None if "fit" in skip else fit_leg(torch, args)
@@ -355,15 +362,19 @@ def main():
                           "full-size sampled sites)",
         },
     }
-    if rkin:
-        mk = rkin["sites"] / (rkin["per_launch"] * 1e-3) / 1e6
-        ak = FP32_BYTES_PER_SITE * rkin["sites"] / (rkin["per_launch"] * 1e-3) / 1e9
-        line["kinetic_closure"] = {
-            "workload": "Orszag-Tang 4096x4096, FP32, kinetic LES closure (filtered equilibria, "
-                        "Delta = 1), nu=eta=1e-5",
-            "mlups": round(mk, 1), "ms_per_step": round(rkin["per_launch"], 5),
+    for key, res, what in (
+            ("kinetic_closure", rkin, "kinetic LES closure (filtered equilibria, Delta = 1)"),
+            ("cross_helicity_closure", rch,
+             "cross-helicity LES closure with backscatter (C_S = 0.1, Delta = 1)")):
+        if not res:
+            continue
+        mk = res["sites"] / (res["per_launch"] * 1e-3) / 1e6
+        ak = FP32_BYTES_PER_SITE * res["sites"] / (res["per_launch"] * 1e-3) / 1e9
+        line[key] = {
+            "workload": f"Orszag-Tang 4096x4096, FP32, {what}, nu=eta=1e-5",
+            "mlups": round(mk, 1), "ms_per_step": round(res["per_launch"], 5),
             "achieved_gbs": round(ak, 1), "frac": round(ak / HBM_PEAK_GBS, 4),
-            "bytes_per_site": FP32_BYTES_PER_SITE, "nonfinite": rkin["nonfinite"],
+            "bytes_per_site": FP32_BYTES_PER_SITE, "nonfinite": res["nonfinite"],
         }
     if r16:
         m16 = r16["sites"] / (r16["ms"] / args.fp16_steps * 1e-3) / 1e6

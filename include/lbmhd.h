@@ -72,7 +72,8 @@ typedef struct {
                              tau_m0 = 3 eta + 1/2 = 1/s_m (Sec. 4.3) */
   double s5, s6, s7, s8;  /* rates of the non-hydrodynamic moments M5..M8
                              (Sec. 3), each in (0, 2); s5 must equal s6 */
-  int32_t les;            /* bit mask, 0..3.  0: rates fixed, plain equilibria;
+  int32_t les;            /* bit mask: 0, 1, 2, 3, 4 or 6.
+                             0: rates fixed, plain equilibria;
                              bit 0 (1): Smagorinsky-MHD closure (Sec. 1.1):
                                 per-site relaxation times from the site's own
                                 non-equilibrium moments;
@@ -84,11 +85,20 @@ typedef struct {
                                 of the neighbours' rho, j, B by the isotropic
                                 D2Q9 difference 3 sum_i w_i c_i X(x + c_i);
                              3: both, the Smagorinsky estimate of |S| and |j|
-                                then measured from the filtered equilibria */
-  double cs, delta;       /* closure constant C_S >= 0 (les = 1: used for both
-                             the eddy viscosity C_S Delta^2 |S| and the eddy
-                             resistivity C_S Delta^2 |j|) and filter width
-                             Delta > 0 in lattice units (les = 1, 2) */
+                                then measured from the filtered equilibria;
+                             bit 2 (4): cross-helicity closure (eqs.
+                                CHClosureV/B): nu_t = C_S Delta^2 |S^v:S^b|^(1/2),
+                                eta_t = C_S Delta^2 sgn(j.w) |j.w|^(1/2) with
+                                backscatter (eta_t < 0) clipped where
+                                eta + eta_t would be negative (tau_m = 1/2);
+                                S^v, S^b, j from the site's non-equilibrium
+                                moments, the vorticity w from the neighbours;
+                                self-consistent tau, tau_m (cubic roots);
+                             6: kinetic and cross-helicity closures together.
+                             Bits 0 and 2 exclude each other. */
+  double cs, delta;       /* closure constant C_S >= 0 (the same constant for
+                             the eddy viscosity and the eddy resistivity) and
+                             filter width Delta > 0 in lattice units */
   int32_t storage;        /* LBMHD_FP32 or LBMHD_FP16 */
 } lbmhd_params;
 
@@ -152,7 +162,7 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
                       const double* bx, const double* by);
 
 /* Advance nsteps >= 0 steps of stream + collide (Sec. 1.2 update with the
- * moment-space collision of Sec. 3; closure per site when les = 1).  One
+ * moment-space collision of Sec. 3; closures as selected by les).  One
  * fused kernel launch per step, ping-ponging the two bound lattices.
  * Asynchronous. */
 int lbmhd_step(lbmhd_t* h, int64_t nsteps);
@@ -230,8 +240,9 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
                             const double* uy_t, const double* bx_t, const double* by_t,
                             double scale, float* lam);
 
-/* The adjoint calls below cover les = 0 and les = 1; with the kinetic
- * closure (les = 2 or 3) lbmhd_adj_step returns LBMHD_ERR_UNSUPPORTED. */
+/* The adjoint calls below cover les = 0 and les = 1; with the kinetic or the
+ * cross-helicity closure (les = 2, 3, 4, 6) lbmhd_adj_step returns
+ * LBMHD_ERR_UNSUPPORTED. */
 
 /* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next, where state_n is
  * the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc

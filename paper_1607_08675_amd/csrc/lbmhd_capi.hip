@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <new>
 #include <string>
 
@@ -31,12 +33,14 @@ constexpr size_t kAlign = 256;
 
 // One step src -> dst with the handle's closure.
 hipError_t launch_one_step(const lbmhd_t* h, const void* src, void* dst) {
-  // C_S = 0 makes the Smagorinsky closure the identity (tau = tau0): skip it.
-  const bool smag = (h->p.les & 1) && h->p.cs > 0.0;
-  if (h->p.les & 2)
-    return lbk::launch_step_kin(h->p.storage, smag, src, dst, h->geo, h->rates, h->p.delta,
-                                h->stream);
-  return lbk::launch_step(h->p.storage, smag, src, dst, h->geo, h->rates, h->stream);
+  // C_S = 0 makes the eddy closures the identity (tau = tau0): skip them.
+  const int les = h->p.les;
+  const bool on = h->p.cs > 0.0;
+  const int eddy = (les & 1) && on ? 1 : ((les & 4) && on ? 2 : 0);
+  if ((les & 2) || eddy == 2)
+    return lbk::launch_step_nb(h->p.storage, eddy, (les & 2) != 0, src, dst, h->geo, h->rates,
+                               h->p.delta, h->stream);
+  return lbk::launch_step(h->p.storage, eddy == 1, src, dst, h->geo, h->rates, h->stream);
 }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -122,7 +126,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   if (!rate_ok(p->s5) || !rate_ok(p->s6) || !rate_ok(p->s7) || !rate_ok(p->s8))
     return LBMHD_ERR_INVALID_ARG;
   if (p->s5 != p->s6) return LBMHD_ERR_INVALID_ARG;
-  if (p->les < 0 || p->les > 3) return LBMHD_ERR_INVALID_ARG;
+  if (p->les < 0 || p->les > 6 || ((p->les & 1) && (p->les & 4))) return LBMHD_ERR_INVALID_ARG;
   if (!(p->cs >= 0.0) || !isfinite(p->cs) || !(p->delta > 0.0) || !isfinite(p->delta))
     return LBMHD_ERR_INVALID_ARG;
   if (p->storage != LBMHD_FP32 && p->storage != LBMHD_FP16) return LBMHD_ERR_INVALID_ARG;
@@ -152,6 +156,14 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   r.taum0sq = float(taum0 * taum0);
   r.cf = float(18.0 * p->cs * d2);
   r.cm = float(36.0 * p->cs * d2);
+  r.stau0 = float(std::sqrt(tau0));
+  r.staum0 = float(std::sqrt(taum0));
+  r.kv = float(4.5 * p->cs * d2);
+  r.kb = float(3.0 * std::sqrt(3.0) * p->cs * d2);
+  // the largest root of t^3 - tau_m0 t - q is below t* = max(sqrt(1/2),
+  // sqrt(tau_m0 / 3)) (or absent) exactly when q < t*^3 - tau_m0 t*
+  const double ts = std::max(std::sqrt(0.5), std::sqrt(taum0 / 3.0));
+  r.qclip = float(ts * ts * ts - taum0 * ts);
   h->lattice_bytes = size_t(lbk::kNPop) * size_t(g.plane) * esize;
   h->adj_lattice_bytes = size_t(lbk::kNPop) * size_t(ga.plane) * 4;
   h->workspace_bytes = round_up(workspace_doubles(g) * sizeof(double), kAlign);
@@ -376,8 +388,9 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
 int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float* lam_prev,
                    double* acc) {
   if (int rc = need_bound(h)) return rc;
-  if (h->p.les & 2)
-    return fail(h, LBMHD_ERR_UNSUPPORTED, "the adjoint of the kinetic closure is not provided");
+  if (h->p.les & 6)
+    return fail(h, LBMHD_ERR_UNSUPPORTED,
+                "the adjoint of the kinetic and cross-helicity closures is not provided");
   if (!state_n || !lam_next || !lam_prev || !acc)
     return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
   if (overlap(lam_next, h->adj_lattice_bytes, lam_prev, h->adj_lattice_bytes))

@@ -31,6 +31,13 @@ struct Rates {
   float taum0sq;  // tau_m0^2
   float cf;       // 18 C_S Delta^2
   float cm;       // 36 C_S Delta^2
+  // cross-helicity closure: sqrt(tau) and sqrt(tau_m) are the largest roots
+  // of t^3 - p t - q = 0 (p = tau0, tau_m0)
+  float stau0;    // sqrt(tau0)
+  float staum0;   // sqrt(tau_m0)
+  float kv;       // (9/2) C_S Delta^2:  q_v = kv (|P| / (rho tau_m))^(1/2)
+  float kb;       // 3 sqrt(3) C_S Delta^2:  q_b = -kb sgn(X) |X|^(1/2)
+  float qclip;    // q_b below which the root lies under max(sqrt(1/2), sqrt(tau_m0/3))
 };
 
 constexpr int kNPop = 19;
@@ -40,10 +47,11 @@ constexpr int kDiagBlocks = 1024;
 // Forward step: dst = C(S(src)).
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
                        const Rates& r, hipStream_t s);
-// Forward step with the kinetic closure (filtered equilibria, filter width
-// delta), optionally with the Smagorinsky relaxation times as well.
-hipError_t launch_step_kin(int storage, bool smag, const void* src, void* dst, const Geom& g,
-                           const Rates& r, double delta, hipStream_t s);
+// Forward step that needs the neighbours' rho, j, B (lattice gradients):
+// the kinetic closure (kin: filtered equilibria, filter width delta) and/or
+// the eddy closure `eddy` (0 none, 1 Smagorinsky, 2 cross-helicity).
+hipError_t launch_step_nb(int storage, int eddy, bool kin, const void* src, void* dst,
+                          const Geom& g, const Rates& r, double delta, hipStream_t s);
 // Equilibrium initialisation from FP64 fields.
 hipError_t launch_init(int storage, const double* rho, const double* ux, const double* uy,
                        const double* bx, const double* by, void* lat, const Geom& g,

@@ -105,16 +105,44 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 //  Q = sqrt((M4 - M4eq)^2 + 4 (M3 - M3eq)^2) (|S| = 3 Q / (2 rho tau)), and
 //  tau_m = (tau_m0 + sqrt(tau_m0^2 + 36 C_S Delta^2 |A|)) / 2 with A the
 //  antisymmetric non-equilibrium first moment of g (j = -3 A / tau_m).
-// Delta^2 parts of the filtered equilibrium moments (kinetic closure): added
-// to M3^eq, M4^eq, M7^eq = M8^eq and to the u x B term E of g^eq
-// (N_y1^eq = E, N_x2^eq = -E).
-struct KinCorr {
-  float m3, m4, m78, e;
+//  With EDDY = 2 the cross-helicity closure (eqs. CHClosureV/B) sets them:
+//  nu_t = C_S Delta^2 |S^v : S^b|^(1/2), eta_t = C_S Delta^2 sgn(j w) |j w|^(1/2),
+//  with S^v from M3, M4 as above, S^b and j from the non-equilibrium
+//  first-moment tensor L_ab = sum_k C_ka g_kb ~ -(tau_m / 3) d_a B_b, and the
+//  vorticity w from the neighbours (NbTerms).  For traceless strains
+//  S^v : S^b = 9 P / (4 rho tau tau_m), P = n4 (L_xx - L_yy) + 2 n3 (L_xy + L_yx),
+//  and j w = -3 A w / tau_m, so sqrt(tau_m) and sqrt(tau) are the largest
+//  roots of t^3 - tau_m0 t - q_b and t^3 - tau0 t - q_v with
+//  q_b = -3 sqrt(3) C_S Delta^2 sgn(A w) |A w|^(1/2) and
+//  q_v = (9/2) C_S Delta^2 (|P| / (rho tau_m))^(1/2).  Where backscatter would
+//  make eta + eta_t negative, tau_m = 1/2.
+// Terms that need the neighbours: Delta^2 parts of the filtered equilibrium
+// moments (kinetic closure), added to M3^eq, M4^eq, M7^eq = M8^eq and to the
+// u x B term E of g^eq (N_y1^eq = E, N_x2^eq = -E); the vorticity w.
+struct NbTerms {
+  float m3, m4, m78, e, w;
 };
 
-template <bool LES, bool KIN = false>
+// Largest root t of t^3 - p t - q = 0 (p > 0, sp = sqrt(p)), returned as
+// t^2 = p + d (2 sp + d), d = t - sp: Newton steps on the convex, increasing
+// h(d) = d (2 p + 3 sp d + d^2) - q from an upper bound of the root
+// (min(q / (2 p), q^(1/3)) for q > 0, 0 otherwise), so the iterates fall
+// monotonically; six steps reach FP32 resolution for p <= 0.8 and all q
+// down to the clip.  For q < 0 the caller guarantees a root >= sqrt(p / 3).
+__device__ __forceinline__ float cubic_root_sq(float p, float sp, float q) {
+  float d = q > 0.0f ? fminf(q * (0.5f * frcp(p)), cbrtf(q)) : 0.0f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float h = d * (2.0f * p + d * (3.0f * sp + d)) - q;
+    const float hp = 2.0f * p + d * (6.0f * sp + 3.0f * d);
+    d -= h * frcp(hp);
+  }
+  return p + d * (2.0f * sp + d);
+}
+
+template <int EDDY, bool KIN = false>
 __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rates& r,
-                                        const KinCorr& kc = KinCorr{0.f, 0.f, 0.f, 0.f}) {
+                                        const NbTerms& kc = NbTerms{0.f, 0.f, 0.f, 0.f, 0.f}) {
   const float a13 = f[1] + f[3], a24 = f[2] + f[4];
   const float d13 = f[1] - f[3], d24 = f[2] - f[4];
   const float s57 = f[5] + f[7], s68 = f[6] + f[8];
@@ -155,12 +183,21 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
   }
 
   float s3q, sm;
-  if (LES) {
+  if (EDDY == 1) {
     const float Q = fsqrt(n4 * n4 + 4.0f * (n3 * n3));
     const float tau = 0.5f * (r.tau0 + fsqrt(r.tau0sq + r.cf * Q * ir));
     s3q = 0.25f * frcp(tau);
     const float A = (g[6] - g[8]) - (g[2] - g[4]) - 2.0f * E;
     const float taum = 0.5f * (r.taum0 + fsqrt(r.taum0sq + r.cm * fabsf(A)));
+    sm = frcp(taum);
+  } else if (EDDY == 2) {
+    const float lxy = g[6] - g[8], lyx = g[2] - g[4];
+    const float P = n4 * ((g[1] - g[3]) - (g[7] - g[9])) + 2.0f * (n3 * (lxy + lyx));
+    const float X = ((lxy - lyx) - 2.0f * E) * kc.w;
+    const float qb = -r.kb * copysignf(fsqrt(fabsf(X)), X);
+    const float taum = qb < r.qclip ? 0.5f : fmaxf(0.5f, cubic_root_sq(r.taum0, r.staum0, qb));
+    const float qv = r.kv * fsqrt(fabsf(P) * ir * frcp(taum));
+    s3q = 0.25f * frcp(cubic_root_sq(r.tau0, r.stau0, qv));
     sm = frcp(taum);
   } else {
     s3q = r.s3q;
@@ -254,7 +291,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
     for (int i = 0; i < 9; ++i) f[i] = v[i][j];
 #pragma unroll
     for (int k = 0; k < 10; ++k) g[k] = v[9 + k][j];
-    collide<LES>(f, g, rt);
+    collide<LES ? 1 : 0>(f, g, rt);
 #pragma unroll
     for (int i = 0; i < 9; ++i) out[i][j] = f[i];
 #pragma unroll
@@ -274,16 +311,18 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
   }
 }
 
-// ------------------------------------------------- kinetic-closure step
-// Same update as k_step, relaxing toward the filtered equilibria of the
-// paper's kinetic LES closure: the Delta^2 parts of the equilibrium moments
-// need rho, j, B of the 8 neighbours, taken from their pre-collision
-// (gathered) populations, differenced with the isotropic D2Q9 stencil
+// --------------------------------------------- steps with lattice gradients
+// Same update as k_step for the closures that need the neighbours: the
+// kinetic closure (KIN) relaxes toward the filtered equilibria, whose Delta^2
+// parts need gradients of rho, j, B; the cross-helicity closure (EDDY = 2)
+// needs the vorticity.  The gradients are those of the pre-collision
+// (gathered) neighbours, by the isotropic D2Q9 difference
 // d_a X = 3 sum_i w_i c_ia X(x + c_i).  A block of kKinThreads threads owns
-// as many columns and a strip of kKinRows rows.  It walks the strip row by row: it gathers
-// row y+1 (each population is read once), writes that row's rho - 1, j, B
-// into a rolling 3-row LDS buffer with one halo column on each side, and then
-// collides row y, whose populations it gathered on the previous pass.
+// as many columns and a strip of kKinRows rows.  It walks the strip row by
+// row: it gathers row y+1 (each population is read once), writes that row's
+// rho - 1, j (and B for KIN) into a rolling 3-row LDS buffer with one halo
+// column on each side, and then collides row y, whose populations it
+// gathered on the previous pass.
 #ifndef LBMHD_KIN_ROWS
 #define LBMHD_KIN_ROWS 16
 #endif
@@ -324,13 +363,14 @@ __device__ __forceinline__ void site_moments(const float (&p)[kNPop], float (&m)
   m[4] = (p[14] + p[15]) + (p[16] + p[17]) + p[18];
 }
 
-template <int ST, bool SMAG>
-__global__ __launch_bounds__(kKinThreads) void k_step_kin(
+template <int ST, int EDDY, bool KIN>
+__global__ __launch_bounds__(kKinThreads) void k_step_nb(
     const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
     Geom geo, Rates rt, float c12, int tiles_x) {
   using C = Codec<ST>;
   using T = typename C::T;
-  __shared__ float mac[3][5][kKinCols];
+  constexpr int NF = KIN ? 5 : 3;   // staged fields: rho - 1, j (, B)
+  __shared__ float mac[3][NF][kKinCols];
   const int tx = int(threadIdx.x);
   const int xt = (int(blockIdx.x) % tiles_x) * kKinThreads;
   const int y0 = (int(blockIdx.x) / tiles_x) * kKinRows;
@@ -357,14 +397,14 @@ __global__ __launch_bounds__(kKinThreads) void k_step_kin(
     float m[5];
     site_moments(p, m);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) mac[slot][k][tx + 1] = m[k];
+    for (int k = 0; k < NF; ++k) mac[slot][k][tx + 1] = m[k];
     if (tx < 2) {
       float ph[kNPop], mh[5];
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) ph[q] = C::dec(rawh[q]);
       site_moments(ph, mh);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) mac[slot][k][ch] = mh[k];
+      for (int k = 0; k < NF; ++k) mac[slot][k][ch] = mh[k];
     }
   };
   float cur[kNPop], nxt[kNPop];
@@ -382,9 +422,9 @@ __global__ __launch_bounds__(kKinThreads) void k_step_kin(
     if (active) {
       const int c = tx + 1;
       // isotropic D2Q9 gradient: d_x = (E - W)/3 + (NE - NW + SE - SW)/12, d_y likewise
-      float gx[5], gy[5], v[5];
+      float gx[NF], gy[NF], v[NF];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
+      for (int k = 0; k < NF; ++k) {
         const float e = mac[s0][k][c + 1], w = mac[s0][k][c - 1];
         const float nn = mac[sp][k][c], ss = mac[sm][k][c];
         const float ne = mac[sp][k][c + 1], nw = mac[sp][k][c - 1];
@@ -393,31 +433,37 @@ __global__ __launch_bounds__(kKinThreads) void k_step_kin(
         gy[k] = (1.0f / 3.0f) * (nn - ss) + (1.0f / 12.0f) * ((ne + nw) - (se + sw));
         v[k] = mac[s0][k][c];
       }
-      // Ratio terms (X Y / rho) use h_X = grad X - X grad(rho) / rho; product
-      // terms (B B) use the plain gradients:
-      //   R(X, Y) = Delta^2 / (12 rho) h_X . h_Y,  S(X, Y) = Delta^2 / 12 grad X . grad Y.
+      // h_X = grad X - X grad(rho) / rho (= rho grad(X / rho)).  Ratio terms
+      // (X Y / rho) of the kinetic closure use it, product terms (B B) the
+      // plain gradients:
+      //   R(X, Y) = Delta^2 / (12 rho) h_X . h_Y,  S(X, Y) = Delta^2 / 12 grad X . grad Y;
+      // the vorticity is d_x u_y - d_y u_x = (h_jy,x - h_jx,y) / rho.
       const float ir = frcp(1.0f + v[0]);
       const float grx = gx[0] * ir, gry = gy[0] * ir;
-      float hx[4], hy[4];
+      float hx[NF - 1], hy[NF - 1];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < NF - 1; ++k) {
         hx[k] = gx[k + 1] - v[k + 1] * grx;
         hy[k] = gy[k + 1] - v[k + 1] * gry;
       }
-      const float cr = c12 * ir;
-      const float jxjx = cr * (hx[0] * hx[0] + hy[0] * hy[0]);
-      const float jyjy = cr * (hx[1] * hx[1] + hy[1] * hy[1]);
-      KinCorr kc;
-      kc.m3 = cr * (hx[0] * hx[1] + hy[0] * hy[1]) - c12 * (gx[3] * gx[4] + gy[3] * gy[4]);
-      kc.m4 = (jxjx - jyjy) - c12 * ((gx[3] * gx[3] + gy[3] * gy[3]) - (gx[4] * gx[4] + gy[4] * gy[4]));
-      kc.m78 = -3.0f * (jxjx + jyjy);
-      kc.e = cr * ((hx[0] * hx[3] + hy[0] * hy[3]) - (hx[1] * hx[2] + hy[1] * hy[2]));
+      NbTerms kc{0.f, 0.f, 0.f, 0.f, 0.f};
+      if constexpr (KIN) {
+        const float cr = c12 * ir;
+        const float jxjx = cr * (hx[0] * hx[0] + hy[0] * hy[0]);
+        const float jyjy = cr * (hx[1] * hx[1] + hy[1] * hy[1]);
+        kc.m3 = cr * (hx[0] * hx[1] + hy[0] * hy[1]) - c12 * (gx[3] * gx[4] + gy[3] * gy[4]);
+        kc.m4 = (jxjx - jyjy) -
+                c12 * ((gx[3] * gx[3] + gy[3] * gy[3]) - (gx[4] * gx[4] + gy[4] * gy[4]));
+        kc.m78 = -3.0f * (jxjx + jyjy);
+        kc.e = cr * ((hx[0] * hx[3] + hy[0] * hy[3]) - (hx[1] * hx[2] + hy[1] * hy[2]));
+      }
+      if constexpr (EDDY == 2) kc.w = (hx[1] - hy[0]) * ir;
       float f[9], g[10];
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = cur[i];
 #pragma unroll
       for (int k = 0; k < 10; ++k) g[k] = cur[9 + k];
-      collide<SMAG, true>(f, g, rt, kc);
+      collide<EDDY, KIN>(f, g, rt, kc);
       const unsigned od = unsigned(y) * geo.pitch + unsigned(x);
 #pragma unroll
       for (int i = 0; i < 9; ++i) st_plane_nt<T>(dst + i * P, od, C::enc(f[i]));
@@ -749,32 +795,38 @@ void launch_step_v(bool les, const void* src, void* dst, const Geom& g, const Ra
     hipLaunchKernelGGL((k_step<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x);
 }
 
-template <int ST, bool SMAG>
-void launch_step_kin_t(const void* src, void* dst, const Geom& g, const Rates& r, float c12,
-                       hipStream_t s) {
+template <int ST, int EDDY, bool KIN>
+void launch_step_nb_t(const void* src, void* dst, const Geom& g, const Rates& r, float c12,
+                      hipStream_t s) {
   using T = typename Codec<ST>::T;
   const int tiles_x = (g.nx + kKinThreads - 1) / kKinThreads;
   const int strips = (g.ny + kKinRows - 1) / kKinRows;
   const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kKinThreads);
-  hipLaunchKernelGGL((k_step_kin<ST, SMAG>), grid, block, 0, s, static_cast<const T*>(src),
+  hipLaunchKernelGGL((k_step_nb<ST, EDDY, KIN>), grid, block, 0, s, static_cast<const T*>(src),
                      static_cast<T*>(dst), g, r, c12, tiles_x);
 }
 
-hipError_t launch_step_kin(int storage, bool smag, const void* src, void* dst, const Geom& g,
-                           const Rates& r, double delta, hipStream_t s) {
-  const float c12 = float(delta * delta / 12.0);
-  if (storage == LBMHD_FP32) {
-    if (smag)
-      launch_step_kin_t<LBMHD_FP32, true>(src, dst, g, r, c12, s);
-    else
-      launch_step_kin_t<LBMHD_FP32, false>(src, dst, g, r, c12, s);
-  } else {
-    if (smag)
-      launch_step_kin_t<LBMHD_FP16, true>(src, dst, g, r, c12, s);
-    else
-      launch_step_kin_t<LBMHD_FP16, false>(src, dst, g, r, c12, s);
-  }
+template <int ST>
+hipError_t launch_step_nb_s(int eddy, bool kin, const void* src, void* dst, const Geom& g,
+                            const Rates& r, float c12, hipStream_t s) {
+  if (kin && eddy == 0)
+    launch_step_nb_t<ST, 0, true>(src, dst, g, r, c12, s);
+  else if (kin && eddy == 1)
+    launch_step_nb_t<ST, 1, true>(src, dst, g, r, c12, s);
+  else if (kin && eddy == 2)
+    launch_step_nb_t<ST, 2, true>(src, dst, g, r, c12, s);
+  else if (!kin && eddy == 2)
+    launch_step_nb_t<ST, 2, false>(src, dst, g, r, c12, s);
+  else
+    return hipErrorInvalidValue;   // no neighbour terms: the plain step applies
   return hipGetLastError();
+}
+
+hipError_t launch_step_nb(int storage, int eddy, bool kin, const void* src, void* dst,
+                          const Geom& g, const Rates& r, double delta, hipStream_t s) {
+  const float c12 = float(delta * delta / 12.0);
+  if (storage == LBMHD_FP32) return launch_step_nb_s<LBMHD_FP32>(eddy, kin, src, dst, g, r, c12, s);
+  return launch_step_nb_s<LBMHD_FP16>(eddy, kin, src, dst, g, r, c12, s);
 }
 
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,

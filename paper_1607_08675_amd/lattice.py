@@ -26,7 +26,8 @@ class LBMHDConfig:
     nu, eta: viscosity and resistivity (tau0 = 3 nu + 1/2, tau_m0 = 3 eta + 1/2).
     s5 (= s6), s7, s8: rates of the non-hydrodynamic moments.
     les: bit mask -- 0 plain, 1 Smagorinsky-MHD closure, 2 kinetic closure
-    (filtered equilibria), 3 both; cs: Smagorinsky constant; delta: filter width.
+    (filtered equilibria), 3 both, 4 cross-helicity closure (with backscatter),
+    6 kinetic and cross-helicity; cs: closure constant; delta: filter width.
     storage: "fp32" or "fp16" (deviation from the rest state, FP16 scaled by 2^10).
     """
     nx: int

@@ -58,7 +58,7 @@ def _create(capi, p):
 
 @pytest.mark.parametrize("bad", [
     dict(nx=1), dict(ny=0), dict(nu=0.0), dict(eta=-1.0), dict(nu=float("nan")),
-    dict(s5=2.0), dict(s7=0.0), dict(s8=-0.5), dict(s5=1.1, s6=1.2), dict(les=4), dict(les=-1),
+    dict(s5=2.0), dict(s7=0.0), dict(s8=-0.5), dict(s5=1.1, s6=1.2), dict(les=5), dict(les=7), dict(les=-1),
     dict(cs=-0.1), dict(delta=0.0), dict(storage=7), dict(nx=70000, ny=70000),
 ])
 def test_create_rejects_invalid_parameters(capi, bad):

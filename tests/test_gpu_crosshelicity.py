@@ -1,0 +1,181 @@
+"""GPU parity of the cross-helicity closure (les = 4, and 6 with the kinetic
+closure) against the FP64 oracle.
+
+The kernel takes the vorticity from the neighbours staged in LDS (strips of
+16 rows, tiles of 512 columns) and solves the two relaxation-time cubics by
+Newton steps in FP32, where the oracle uses the closed-form roots in FP64.
+The sizes cover one and several strips and tiles, ragged ends and lattices
+narrower than a tile; the random states put roughly half the sites into
+backscatter.  Tolerances as for the other closures: FP32 populations within
+5e-7 after one step, 2e-6 after ten; relative L2 of u and B within 1e-5 after
+500 steps of a 64^2 Orszag-Tang vortex.  After k steps a site depends on
+sites within distance 2k, so full-size samples use patches of radius 2k + 2.
+"""
+import numpy as np
+import pytest
+import torch
+
+from lbmhd_inputs import decaying_turbulence, orszag_tang, random_planes
+
+pytestmark = pytest.mark.gpu
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+W19 = np.concatenate([W9, np.zeros(10)])
+
+
+@pytest.fixture(scope="module")
+def lb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_08675_amd import lattice
+    return lattice
+
+
+def random_state(nx, ny, seed, famp=0.02, gamp=0.01):
+    scale = np.concatenate([W9 * famp, np.full(10, gamp)])
+    return random_planes(19, nx, ny, seed, W19, scale)
+
+
+def make(lb, orc, nx, ny, storage="fp32", les=4, **kw):
+    cfg = lb.LBMHDConfig(nx=nx, ny=ny, storage=storage, les=les, **kw)
+    op = orc.Params(nx, ny, nu=cfg.nu, eta=cfg.eta, s5=cfg.s5, s6=cfg.s5, s7=cfg.s7, s8=cfg.s8,
+                    les=les, cs=cfg.cs, delta=cfg.delta)
+    return lb.Lattice(cfg), op
+
+
+def gpu_state_after(orc, op, x0, n):
+    st = orc.stream(op, x0)
+    st = orc.run(op, st, n - 1)
+    return orc.collide(op, st)
+
+
+@pytest.mark.parametrize("les", [4, 6])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (100, 36), (300, 5), (2, 2), (257, 3), (64, 40),
+                                   (16, 17), (1100, 19), (513, 18)])
+def test_one_step_fp32(lb, orc, nx, ny, les):
+    L, op = make(lb, orc, nx, ny, les=les, nu=0.01, eta=0.005, s5=1.2, s7=1.5, s8=0.8, delta=1.3,
+                 cs=0.15)
+    x0 = random_state(nx, ny, seed=nx * 1000 + ny + 5)
+    L.set_populations(x0).step(1)
+    err = np.abs(L.populations().cpu().numpy() - orc.collide(op, orc.stream(op, x0))).max()
+    assert err < 5e-7, err
+
+
+def test_closure_matters_and_backscatter_occurs(lb, orc):
+    """On the parity states the closure moves the populations well beyond
+    the tolerance, and a good share of the sites backscatters (tau_m < tau_m0),
+    some of them (about 6%) down to the clip (tau_m = 1/2)."""
+    nx, ny = 100, 36
+    op0 = orc.Params(nx, ny, nu=0.01, eta=0.005, s5=1.2, s6=1.2, s7=1.5, s8=0.8, les=0)
+    _, op4 = make(lb, orc, nx, ny, nu=0.01, eta=0.005, s5=1.2, s7=1.5, s8=0.8, delta=1.3, cs=0.15)
+    x0 = random_state(nx, ny, seed=nx * 1000 + ny + 5)
+    pre = orc.stream(op4, x0)
+    a, _, taum = orc.collide(op4, pre, return_tau=True)
+    assert np.abs(a - orc.collide(op0, pre)).max() > 1e-5
+    assert 0.2 < np.mean(taum < 3 * op4.eta + 0.5) < 0.8
+    assert np.any(taum == 0.5)
+
+
+@pytest.mark.parametrize("les", [4, 6])
+def test_ten_steps_fp32(lb, orc, les):
+    nx, ny = 100, 36
+    L, op = make(lb, orc, nx, ny, les=les, nu=0.005, eta=0.01, s5=1.1, s7=1.3, s8=1.2, delta=1.0)
+    x0 = random_state(nx, ny, seed=17)
+    L.set_populations(x0).step(10)
+    err = np.abs(L.populations().cpu().numpy() - gpu_state_after(orc, op, x0, 10)).max()
+    assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("les", [4, 6])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (300, 21), (1030, 17)])
+def test_one_step_fp16(lb, orc, nx, ny, les):
+    L, op = make(lb, orc, nx, ny, "fp16", les=les, nu=0.01, eta=0.005, delta=1.0)
+    dev = random_state(nx, ny, seed=3 + nx) - W19[:, None, None]
+    h = (dev.astype(np.float32) * np.float32(1024)).astype(np.float16)
+    x0 = W19[:, None, None] + h.astype(np.float64) / 1024.0
+    L.set_populations(x0).step(1)
+    want = orc.collide(op, orc.stream(op, x0))
+    got = L.populations().cpu().numpy()
+    assert np.all(np.abs(got - want) <= np.abs(want - W19[:, None, None]) * 2.0 ** -11 + 1e-6)
+
+
+@pytest.mark.parametrize("les", [4, 6])
+def test_orszag_tang_64(lb, orc, les):
+    n = 64
+    L, op = make(lb, orc, n, n, les=les, nu=0.01, eta=0.01, delta=1.0)
+    f = orszag_tang(n, n)
+    L.init_fields(*f)
+    st = orc.init(op, *f)
+    done = 0
+    for target in (100, 500):
+        L.step(target - done)
+        st = orc.run(op, st, target - done)
+        done = target
+        g = {k: v.cpu().numpy() for k, v in L.macro().items()}
+        o = orc.macro(op, st)
+        for a, b in (("ux", "uy"), ("bx", "by")):
+            num = np.sqrt(np.sum((g[a] - o[a]) ** 2 + (g[b] - o[b]) ** 2))
+            den = np.sqrt(np.sum(o[a] ** 2 + o[b] ** 2))
+            assert num / den < 1e-5, (target, a, num / den)
+
+
+@pytest.mark.parametrize("les", [4, 6])
+def test_full_size_sampled_sites(lb, orc, les):
+    """4096^2 FP32 Orszag-Tang at nu = eta = 1e-5 (most backscatter sites
+    clipped), 2 steps."""
+    n, k, r = 4096, 2, 6
+    f = orszag_tang(n, n)
+    L, _ = make(lb, orc, n, n, les=les, nu=1e-5, eta=1e-5, delta=1.0)
+    L.init_fields(*f).step(k)
+    pops = L.populations()
+    rng = np.random.default_rng(11)
+    sites = [(0, 0), (n - 1, n - 1), (511, 15), (512, 16), (n // 2, 1)]
+    sites += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(15)]
+    op = orc.Params(2 * r + 1, 2 * r + 1, nu=1e-5, eta=1e-5, les=les, cs=0.1, delta=1.0)
+    for (x, y) in sites:
+        ys = (np.arange(y - r, y + r + 1)) % n
+        xs = (np.arange(x - r, x + r + 1)) % n
+        st = orc.init(op, *[a[np.ix_(ys, xs)] for a in f])
+        want = gpu_state_after(orc, op, st, k)[:, r, r]
+        err = np.abs(pops[:, y, x].cpu().numpy() - want).max()
+        assert err < 1e-6, (x, y, err)
+    del pops, L
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("les", [4, 6])
+def test_conservation_and_stability(lb, orc, les):
+    """1000 steps of 128^2 turbulence at nu = eta = 1e-4, where the update
+    without an eddy closure diverges: mass, momentum and flux are conserved
+    and the run stays finite."""
+    n = 128
+    L, _ = make(lb, orc, n, n, les=les, nu=1e-4, eta=1e-4, delta=1.0)
+    L.init_fields(*decaying_turbulence(n, n))
+    d0 = L.diag()
+    d1 = L.step(1000).diag()
+    assert abs(d1["mass"] - d0["mass"]) < 1e-6 * d0["mass"]
+    for key in ("mom_x", "mom_y", "flux_x", "flux_y"):
+        assert abs(d1[key] - d0[key]) < 1e-7 * n * n, key
+    assert d1["nonfinite"] == 0
+
+
+def test_zero_constant_is_the_plain_step(lb, orc):
+    """les = 4 with C_S = 0 runs the plain step (bitwise equal to les = 0)."""
+    nx, ny = 64, 40
+    x0 = random_state(nx, ny, seed=5)
+    out = []
+    for les in (0, 4):
+        L, _ = make(lb, orc, nx, ny, les=les, cs=0.0)
+        out.append(L.set_populations(x0).step(3).populations().cpu().numpy())
+    np.testing.assert_array_equal(out[0], out[1])
+
+
+def test_adjoint_refuses_cross_helicity_closure(lb, orc):
+    from paper_1607_08675_amd._capi import LBMHD_ERR_UNSUPPORTED, LbmhdError
+    L, _ = make(lb, orc, 16, 16)
+    L.init_fields(*orszag_tang(16, 16))
+    st = L.save_state()
+    lam, lam2, acc = L.new_adj_buffer().zero_(), L.new_adj_buffer(), L.new_adj_acc()
+    with pytest.raises(LbmhdError) as e:
+        L.adj_step(st, lam, lam2, acc)
+    assert e.value.code == LBMHD_ERR_UNSUPPORTED
