@@ -20,14 +20,14 @@
 //     collision invariants;
 //   * rates from the transport coefficients nu = 1/(3 s_3) - 1/6 = 1/(3 s_4) - 1/6
 //     and eta = 1/(3 s_m) - 1/6 (Sec. 4.3);
-//   * the Smagorinsky closures nu_T = C_S Delta^2 |S| (eq. SmagorinskyClosure)
-//     and eta_T = C_Sb Delta^2 |j| (eqs. SmagorinskyMHDClosureV/B), with the
+//   * the Smagorinsky closures nu_T = C_Sv Delta^2 |S| and eta_T = C_Sb Delta^2 |j|
+//     (eqs. SmagorinskyClosure, SmagorinskyMHDClosureV/B), with the
 //     strain read from the site's own non-equilibrium second moments (the
 //     Sec. 1.2 relation between sum_i c_a c_b f^(1) and the strain) and the
 //     current read from the non-equilibrium first moments of g;
 //   * the cross-helicity closure (les = 4, or 6 together with the kinetic
-//     closure; eqs. CHClosureV/B): nu_t = C_S Delta^2 |S^v : S^b|^(1/2) and
-//     eta_t = C_S Delta^2 sgn(j . omega) |j . omega|^(1/2), where S^v is the
+//     closure; eqs. CHClosureV/B): nu_t = C_Sv Delta^2 |S^v : S^b|^(1/2) and
+//     eta_t = C_Sb Delta^2 sgn(j . omega) |j . omega|^(1/2), where S^v is the
 //     strain of u, S^b the symmetrised gradient of B and omega the vorticity;
 //   * collide-then-stream with unit time step (the discrete LB update of
 //     Sec. 1.2): f_i(x + c_i, t+1) = f_i*(x, t).
@@ -51,7 +51,8 @@
 //     same tau, giving tau = (tau0 + sqrt(tau0^2 + 18 C_S Delta^2 Q / rho)) / 2
 //     with Q = sqrt((M4 - M4eq)^2 + 4 (M3 - M3eq)^2); likewise
 //     tau_m = (tau_m0 + sqrt(tau_m0^2 + 36 C_S Delta^2 |A|)) / 2 with
-//     A = (N_y1 - N_y1^eq) - (N_x2 - N_x2^eq);  C_Sv = C_Sb = C_S;
+//     A = (N_y1 - N_y1^eq) - (N_x2 - N_x2^eq), with C_Sv in tau and C_Sb
+//     in tau_m (cs and csb of the parameters);
 //   * derivative of |.| and of the norm Q is taken as 0 where the argument is
 //     exactly 0 (tangent-linear mode only);
 //   * kinetic closure: the lattice sites carry the filtered fields, and the
@@ -256,7 +257,8 @@ typedef struct {
   int32_t les;             // bit 0: Smagorinsky-MHD closure; bit 1: kinetic
                            // closure (filtered equilibria); bit 2: cross-
                            // helicity closure (not with bit 0); 0: none
-  double cs, delta;        // closure constant C_S and filter width Delta
+  double cs, csb;          // closure constants: C_Sv (fluid) and C_Sb (field)
+  double delta;            // filter width Delta
 } orc_params;
 
 enum { ORC_NPOP = 19, ORC_NDIAG = 14, ORC_ND = ND };
@@ -415,7 +417,7 @@ Rates make_rates(const orc_params& p) {
 // post-collision populations.  tau_out / taum_out receive the relaxation
 // times actually used.
 template <class R>
-void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
+void collide_site(const orc_params& p, const Rates& rt, R cs, R csb, R f[9], R g[10],
                   double* tau_out, double* taum_out, const R* grad = nullptr) {
   const Tables& tb = tables();
   // Conserved moments (Sec. 3, text after the kinetic equations).
@@ -469,9 +471,9 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
     // Magnetic: j_z = -3 A / tau_m from the antisymmetric part of the
     // non-equilibrium first-moment tensor of g; tau_m = tau_m0 + 3 C_S Delta^2 |j|.
     R A = (N[5 + 1] - neq[5 + 1]) - (N[0 + 2] - neq[0 + 2]);
-    taum = 0.5 * (rt.taum0 + root(rt.taum0 * rt.taum0 + 36.0 * d2 * cs * magnitude(A)));
+    taum = 0.5 * (rt.taum0 + root(rt.taum0 * rt.taum0 + 36.0 * d2 * csb * magnitude(A)));
   }
-  // Cross-helicity closure (eqs. CHClosureV/B), C_Sv = C_Sb = C_S.
+  // Cross-helicity closure (eqs. CHClosureV/B): C_Sv in nu_t, C_Sb in eta_t.
   if (p.les & 4) {
     double d2 = p.delta * p.delta;
     // Traceless strains: S^v_xx - S^v_yy = -3 n4 / (2 rho tau), S^v_xy =
@@ -494,7 +496,7 @@ void collide_site(const orc_params& p, const Rates& rt, R cs, R f[9], R g[10],
     // t = sqrt(tau_m), t^3 - tau_m0 t - qb = 0 with
     // qb = -3 sqrt(3) C_S Delta^2 sgn(A omega) |A omega|^(1/2).
     R X = A * omega;
-    R qb = -3.0 * std::sqrt(3.0) * d2 * cs * sign_of(value(X)) * root(magnitude(X));
+    R qb = -3.0 * std::sqrt(3.0) * d2 * csb * sign_of(value(X)) * root(magnitude(X));
     const double tm = largest_cubic_root(rt.taum0, value(qb));
     if (tm < std::sqrt(0.5)) {
       taum = R(0.5);  // eta + eta_t clipped at zero
@@ -586,7 +588,7 @@ void lattice_gradients(const orc_params& p, const R* st, std::vector<R>& grad) {
 }
 
 template <class R>
-void collide_all(const orc_params& p, R* st, R cs, double* tau_out, double* taum_out) {
+void collide_all(const orc_params& p, R* st, R cs, R csb, double* tau_out, double* taum_out) {
   const int64_t n = int64_t(p.nx) * p.ny;
   const Rates rt = make_rates(p);
   std::vector<R> grad;
@@ -599,7 +601,7 @@ void collide_all(const orc_params& p, R* st, R cs, double* tau_out, double* taum
     for (int q = 0; q < 10; ++q) g[q] = st[(9 + q) * n + s];
     if (stencil)
       for (int m = 0; m < 10; ++m) gs[m] = grad[m * n + s];
-    collide_site(p, rt, cs, f, g, tau_out ? tau_out + s : nullptr,
+    collide_site(p, rt, cs, csb, f, g, tau_out ? tau_out + s : nullptr,
                  taum_out ? taum_out + s : nullptr, stencil ? gs : nullptr);
     for (int i = 0; i < 9; ++i) st[i * n + s] = f[i];
     for (int q = 0; q < 10; ++q) st[(9 + q) * n + s] = g[q];
@@ -721,7 +723,7 @@ int orc_init(const orc_params* p, const double* rho, const double* ux, const dou
 // receive the relaxation times used.
 int orc_collide(const orc_params* p, double* state, double* tau, double* taum) {
   if (!valid(p)) return -1;
-  collide_all<double>(*p, state, p->cs, tau, taum);
+  collide_all<double>(*p, state, p->cs, p->csb, tau, taum);
   return 0;
 }
 
@@ -737,7 +739,7 @@ int orc_run(const orc_params* p, double* state, int64_t nsteps) {
   const int64_t n = int64_t(p->nx) * p->ny;
   std::vector<double> tmp(size_t(ORC_NPOP) * n);
   for (int64_t t = 0; t < nsteps; ++t) {
-    collide_all<double>(*p, state, p->cs, nullptr, nullptr);
+    collide_all<double>(*p, state, p->cs, p->csb, nullptr, nullptr);
     stream_all<double>(*p, state, tmp.data());
     std::memcpy(state, tmp.data(), sizeof(double) * tmp.size());
   }
@@ -862,7 +864,7 @@ double orc_energy(const orc_params* p, const double* st) {
 // ---------------------------------------------------------- tangent-linear
 // Tangent of one collision at every site: state (19*n) is advanced in place,
 // dstate (ndir planes of 19*n, direction-major) carries the tangents, and
-// dcs[ndir] are the tangents of C_S.
+// dcs[2 * ndir] are the tangents of (C_Sv, C_Sb) per direction.
 int orc_tl_collide(const orc_params* p, double* state, double* dstate, const double* dcs,
                    int ndir) {
   if (!valid(p) || ndir < 1 || ndir > ND) return -1;
@@ -872,9 +874,12 @@ int orc_tl_collide(const orc_params* p, double* state, double* dstate, const dou
     st[q].v = state[q];
     for (int k = 0; k < ndir; ++k) st[q].d[k] = dstate[k * m + q];
   }
-  Dual cs(p->cs);
-  for (int k = 0; k < ndir; ++k) cs.d[k] = dcs ? dcs[k] : 0.0;
-  collide_all<Dual>(*p, st.data(), cs, nullptr, nullptr);
+  Dual cs(p->cs), csb(p->csb);
+  for (int k = 0; k < ndir; ++k) {
+    cs.d[k] = dcs ? dcs[2 * k] : 0.0;
+    csb.d[k] = dcs ? dcs[2 * k + 1] : 0.0;
+  }
+  collide_all<Dual>(*p, st.data(), cs, csb, nullptr, nullptr);
   for (int64_t q = 0; q < m; ++q) {
     state[q] = st[q].v;
     for (int k = 0; k < ndir; ++k) dstate[k * m + q] = st[q].d[k];
@@ -882,9 +887,10 @@ int orc_tl_collide(const orc_params* p, double* state, double* dstate, const dou
   return 0;
 }
 
-// Directional derivatives of the final total energy J(u0, B0, C_S) after
-// nsteps, starting from equilibrium with rho0 fixed.  dfields holds ndir
-// blocks of 4 planes (du_x, du_y, dB_x, dB_y), each nx*ny; dcs[ndir].
+// Directional derivatives of the final total energy J(u0, B0, C_Sv, C_Sb)
+// after nsteps, starting from equilibrium with rho0 fixed.  dfields holds ndir
+// blocks of 4 planes (du_x, du_y, dB_x, dB_y), each nx*ny; dcs[2 * ndir] the
+// tangents of (C_Sv, C_Sb) per direction.
 // Writes J and dJ[k] = <grad J, v_k>.
 int orc_tl_energy(const orc_params* p, const double* rho, const double* ux, const double* uy,
                   const double* bx, const double* by, const double* dfields, const double* dcs,
@@ -908,10 +914,13 @@ int orc_tl_energy(const orc_params* p, const double* rho, const double* ux, cons
   }
   std::vector<Dual> st(size_t(ORC_NPOP) * n), tmp(size_t(ORC_NPOP) * n);
   init_all<Dual>(*p, r.data(), u.data(), v.data(), a.data(), b.data(), st.data());
-  Dual cs(p->cs);
-  for (int k = 0; k < ndir; ++k) cs.d[k] = dcs ? dcs[k] : 0.0;
+  Dual cs(p->cs), csb(p->csb);
+  for (int k = 0; k < ndir; ++k) {
+    cs.d[k] = dcs ? dcs[2 * k] : 0.0;
+    csb.d[k] = dcs ? dcs[2 * k + 1] : 0.0;
+  }
   for (int64_t t = 0; t < nsteps; ++t) {
-    collide_all<Dual>(*p, st.data(), cs, nullptr, nullptr);
+    collide_all<Dual>(*p, st.data(), cs, csb, nullptr, nullptr);
     stream_all<Dual>(*p, st.data(), tmp.data());
     st.swap(tmp);
   }

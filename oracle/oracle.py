@@ -61,7 +61,7 @@ class OrcParams(ctypes.Structure):
         ("s5", ctypes.c_double), ("s6", ctypes.c_double),
         ("s7", ctypes.c_double), ("s8", ctypes.c_double),
         ("les", ctypes.c_int32),
-        ("cs", ctypes.c_double), ("delta", ctypes.c_double),
+        ("cs", ctypes.c_double), ("csb", ctypes.c_double), ("delta", ctypes.c_double),
     ]
 
 
@@ -73,8 +73,9 @@ class Params:
     s5..s8: rates of the non-hydrodynamic moments (not fixed by the paper).
     les: bit 0 = Smagorinsky-MHD closure, bit 1 = kinetic closure (filtered
     equilibria), bit 2 = cross-helicity closure (eqs. CHClosureV/B; not with
-    bit 0), so 0 plain, 1, 2, 3, 4 or 6; cs: closure constant; delta: filter
-    width.
+    bit 0), so 0 plain, 1, 2, 3, 4 or 6; cs: closure constant C_Sv of the eddy
+    viscosity; csb: constant C_Sb of the eddy resistivity (eqs.
+    SmagorinskyMHDClosureV/B), None for the same as cs; delta: filter width.
     """
     nx: int
     ny: int
@@ -87,10 +88,12 @@ class Params:
     les: int = 0
     cs: float = 0.1
     delta: float = 1.0
+    csb: float | None = None
 
     def c(self) -> OrcParams:
+        csb = self.cs if self.csb is None else self.csb
         return OrcParams(self.nx, self.ny, self.nu, self.eta, self.s5, self.s6, self.s7,
-                         self.s8, int(self.les), self.cs, self.delta)
+                         self.s8, int(self.les), self.cs, csb, self.delta)
 
 
 _lib = None
@@ -266,15 +269,27 @@ def energy(p: Params, state: np.ndarray) -> float:
     return float(lib().orc_energy(ctypes.byref(p.c()), _ptr(st)))
 
 
+def _cs_tangents(dcs, ndir):
+    if dcs is None:
+        return np.zeros(2 * ndir)
+    d = np.asarray(dcs, dtype=np.float64)
+    if d.shape == (ndir,):
+        d = np.stack([d, d], axis=1)
+    if d.shape != (ndir, 2):
+        raise ValueError("closure-constant tangents must have shape (ndir,) or (ndir, 2)")
+    return np.ascontiguousarray(d.reshape(-1))
+
+
 def tl_collide(p: Params, state: np.ndarray, dstate: np.ndarray, dcs=None):
     """Tangent-linear collision: returns (state', dstate') for ndir directions.
 
-    dstate has shape (ndir, 19, ny, nx); dcs (ndir,) are tangents of C_S.
+    dstate has shape (ndir, 19, ny, nx); dcs, the tangents of the closure
+    constants, is (ndir, 2) for (C_Sv, C_Sb) or (ndir,) for both moving together.
     """
     st = np.array(state, dtype=np.float64, order="C", copy=True)
     ds = np.array(dstate, dtype=np.float64, order="C", copy=True)
     ndir = ds.shape[0]
-    dc = np.zeros(ndir) if dcs is None else np.ascontiguousarray(dcs, dtype=np.float64)
+    dc = _cs_tangents(dcs, ndir)
     _check(lib().orc_tl_collide(ctypes.byref(p.c()), _ptr(st), _ptr(ds), _ptr(dc), ndir),
            "tl_collide")
     return st, ds
@@ -284,12 +299,13 @@ def tl_energy(p: Params, fields, dfields, dcs, nsteps: int):
     """J and <grad J, v_k> for the final total energy after nsteps.
 
     fields: (rho, ux, uy, bx, by); dfields: (ndir, 4, ny, nx) tangents of
-    (ux, uy, bx, by); dcs: (ndir,) tangents of C_S.
+    (ux, uy, bx, by); dcs: tangents of the closure constants, (ndir, 2) for
+    (C_Sv, C_Sb) or (ndir,) for both moving together.
     """
     fs = _fields(p, *fields)
     dfl = np.ascontiguousarray(dfields, dtype=np.float64)
     ndir = dfl.shape[0]
-    dc = np.ascontiguousarray(dcs, dtype=np.float64)
+    dc = _cs_tangents(dcs, ndir)
     J = np.zeros(1)
     dJ = np.zeros(ndir)
     _check(lib().orc_tl_energy(ctypes.byref(p.c()), *[_ptr(f) for f in fs], _ptr(dfl),

@@ -41,7 +41,10 @@ MUTANTS = {
     "closure Q drops factor 4": ("R Q = root(n4 * n4 + 4.0 * n3 * n3);", "R Q = root(n4 * n4 + n3 * n3);"),
     "magnetic closure sign of A": ("R A = (N[5 + 1] - neq[5 + 1]) - (N[0 + 2] - neq[0 + 2]);",
                                    "R A = (N[5 + 1] - neq[5 + 1]) + (N[0 + 2] - neq[0 + 2]);"),
-    "magnetic closure factor 36 -> 18": ("36.0 * d2 * cs * magnitude(A)", "18.0 * d2 * cs * magnitude(A)"),
+    "magnetic closure factor 36 -> 18": ("36.0 * d2 * csb * magnitude(A)", "18.0 * d2 * csb * magnitude(A)"),
+    "eddy resistivity takes C_Sv": ("36.0 * d2 * csb * magnitude(A)", "36.0 * d2 * cs * magnitude(A)"),
+    "cross-helicity resistivity takes C_Sv": ("d2 * csb * sign_of(value(X))", "d2 * cs * sign_of(value(X))"),
+    "eddy viscosity takes C_Sb": ("18.0 * d2 * cs * Q / rho", "18.0 * d2 * csb * Q / rho"),
     "shear rate s4 takes s5": ("  s[4] = 1.0 / tau;\n", "  s[4] = R(rt.s[5]);\n"),
     "relaxation sign": ("Mstar[r] = M[r] - s[r] * (M[r] - meq[r]);",
                         "Mstar[r] = M[r] + s[r] * (M[r] - meq[r]);"),

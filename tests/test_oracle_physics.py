@@ -340,6 +340,49 @@ def test_tangent_matches_central_differences(orc):
     assert abs(J - orc.energy(p, orc.run(p, orc.init(p, *fields), steps))) < 1e-13
 
 
+@pytest.mark.parametrize("les", [1, 4])
+def test_each_constant_drives_its_own_rate(orc, les):
+    """Eqs. SmagorinskyMHDClosureV/B (and CHClosureV/B): C_Sv sets the eddy
+    viscosity, C_Sb the eddy resistivity.  With one of them zero its
+    relaxation time is the molecular one, and the other matches the run
+    with both constants equal."""
+    p = orc.Params(10, 8, nu=0.01, eta=0.02, les=les, cs=0.2)
+    st = _random_state(orc, p, 6, amp=5e-3)
+    _, tau, taum = orc.collide(p, st, return_tau=True)
+    _, tv, tmv = orc.collide(orc.Params(10, 8, nu=0.01, eta=0.02, les=les, cs=0.2, csb=0.0), st,
+                             return_tau=True)
+    _, tb, tmb = orc.collide(orc.Params(10, 8, nu=0.01, eta=0.02, les=les, cs=0.0, csb=0.2), st,
+                             return_tau=True)
+    np.testing.assert_allclose(tmv, 3 * p.eta + 0.5, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(tb, 3 * p.nu + 0.5, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(tmb, taum, rtol=0, atol=1e-15)
+    if les == 1:   # the Smagorinsky fluid rate does not depend on tau_m
+        np.testing.assert_allclose(tv, tau, rtol=0, atol=1e-15)
+    assert np.all(tv > 3 * p.nu + 0.5) and np.all(np.abs(tmb - (3 * p.eta + 0.5)) > 0)
+
+
+def test_tangent_splits_over_the_two_constants(orc):
+    """d/dC_Sv + d/dC_Sb = d/dC_S (both moving), each against central
+    differences in its own constant."""
+    n, steps = 10, 12
+    p = orc.Params(n, n, nu=0.01, eta=0.01, les=1, cs=0.1, csb=0.15)
+    fields = orszag_tang(n, n, u0=0.08, b0=0.08)
+    d = np.zeros((3, 4, n, n))
+    J, dJ = orc.tl_energy(p, fields, d, np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]]), steps)
+    assert abs(dJ[0] + dJ[1] - dJ[2]) < 1e-12 * abs(dJ[2])
+    eps = 1e-5
+    for k, key in ((0, "cs"), (1, "csb")):
+        Js = []
+        for sgn in (1, -1):
+            kw = dict(cs=p.cs, csb=p.csb)
+            kw[key] += sgn * eps
+            q = orc.Params(n, n, nu=0.01, eta=0.01, les=1, **kw)
+            Js.append(orc.energy(q, orc.run(q, orc.init(q, *fields), steps)))
+        fd = (Js[0] - Js[1]) / (2 * eps)
+        assert abs(fd - dJ[k]) < 1e-6 * abs(dJ[k]) + 1e-12, (key, fd, dJ[k])
+        assert abs(dJ[k]) > 1e-6
+
+
 def test_tangent_collide_is_linear_in_direction(orc):
     p = orc.Params(6, 6, nu=0.01, eta=0.02, les=True, cs=0.2)
     st = _random_state(orc, p, 2, amp=3e-3)
