@@ -215,7 +215,8 @@ def adjoint_leg(torch, args):
     log(f"adjoint: J={J:.6e}, backward {t2 - t1:.3f}s, adjoint kernel {adj_kernel_ms:.4f} ms, "
         f"recompute+adjoint {seg_ms:.4f} ms/step, forward {fwd_ms:.4f} ms/step")
     out = dict(J=J, fwd_s=t1 - t0, bwd_s=t2 - t1, fwd_ms=fwd_ms, adj_kernel_ms=adj_kernel_ms,
-               seg_ms=seg_ms, sites=n * n, nsteps=nsteps, dJ_dcs=g[4])
+               seg_ms=seg_ms, sites=n * n, nsteps=nsteps, dJ_dcs=g[4] + g[5],
+               dJ_dcsv=g[4], dJ_dcsb=g[5])
     del run, lat, states, lam, lam2
     torch.cuda.empty_cache()
     # the adjoint kernel where its working set (3 x 1.3 GB) is far above the caches
@@ -243,9 +244,9 @@ def adjoint_leg(torch, args):
 
 
 def fit_leg(torch, args):
-    """Adjoint-driven C_S fit: 8192^2 FP32 LES reference after 5000 steps,
-    box-filtered (width 4) onto 2048^2; the 2048^2 FP16 model from the same
-    realisation runs 1250 steps at nu = eta = 2.5e-7 (acoustic scaling)."""
+    """Adjoint-driven joint fit of (C_Sv, C_Sb): 8192^2 FP32 LES reference after
+    5000 steps, box-filtered (width 4) onto 2048^2; the 2048^2 FP16 model from
+    the same realisation runs 1250 steps at nu = eta = 2.5e-7 (acoustic scaling)."""
     from lbmhd_inputs import decaying_turbulence
     from paper_1607_08675_amd.fit import fit_cs, reference
     from paper_1607_08675_amd.lattice import LBMHDConfig
@@ -260,7 +261,7 @@ def fit_leg(torch, args):
     nc = nf // w
     cfg = LBMHDConfig(nx=nc, ny=nc, nu=1e-6 / w, eta=1e-6 / w, les=True, cs=0.1, storage="fp16")
     res = fit_cs(decaying_turbulence(nc, nc), targets, cfg, args.fit_ref_steps // w,
-                 iters=args.fit_iters, every=100, log=log)
+                 iters=args.fit_iters, every=100, joint=True, log=log)
     return dict(t_ref=t_ref, res=res, steps=args.fit_ref_steps // w)
 
 
@@ -399,7 +400,7 @@ def main():
             "forward_ms_per_step": round(radj["fwd_ms"], 5),
             "ratio_to_forward": round(radj["seg_ms"] / radj["fwd_ms"], 3),
             "adj_kernel_gbs": round(3 * 19 * 4 * s / (radj["adj_kernel_ms"] * 1e-3) / 1e9, 1),
-            "dJ_dcs": radj["dJ_dcs"],
+            "dJ_dcs": radj["dJ_dcs"], "dJ_dcsv": radj["dJ_dcsv"], "dJ_dcsb": radj["dJ_dcsb"],
             "adj_kernel_ms_4096": round(radj["adj_ms_4096"], 5),
             "adj_kernel_gbs_4096": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9, 1),
             "adj_kernel_frac_4096": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -407,14 +408,17 @@ def main():
         }
     if rfit:
         r = rfit["res"]
+        ib = min(range(len(r.loss)), key=r.loss.__getitem__)
         line["cs_fit"] = {
-            "workload": f"C_S fit: 2048x2048 FP16-storage LES ({rfit['steps']} steps, nu=eta=2.5e-7) "
+            "workload": f"joint (C_Sv, C_Sb) fit: 2048x2048 FP16-storage LES "
+                        f"({rfit['steps']} steps, nu=eta=2.5e-7) "
                         f"against the width-4 box filter of an 8192x8192 FP32 LES run "
                         f"({args.fit_ref_steps} steps, nu=eta=1e-6), decaying turbulence",
             "iterations": len(r.cs), "seconds": round(r.seconds, 3),
             "reference_seconds": round(rfit["t_ref"], 3),
-            "cs": [round(c, 6) for c in r.cs], "loss": [float(f"{v:.6e}") for v in r.loss],
-            "best_cs": round(r.cs[min(range(len(r.loss)), key=r.loss.__getitem__)], 6),
+            "cs_v": [round(c, 6) for c in r.cs], "cs_b": [round(c, 6) for c in r.cs_b],
+            "loss": [float(f"{v:.6e}") for v in r.loss],
+            "best": [round(r.cs[ib], 6), round(r.cs_b[ib], 6)],
         }
     print(json.dumps(line), flush=True)
 

@@ -96,9 +96,10 @@ typedef struct {
                                 self-consistent tau, tau_m (cubic roots);
                              6: kinetic and cross-helicity closures together.
                              Bits 0 and 2 exclude each other. */
-  double cs, delta;       /* closure constant C_S >= 0 (the same constant for
-                             the eddy viscosity and the eddy resistivity) and
-                             filter width Delta > 0 in lattice units */
+  double cs, cs_b;        /* closure constants C_Sv >= 0 of the eddy viscosity
+                             and C_Sb >= 0 of the eddy resistivity (eqs.
+                             SmagorinskyMHDClosureV/B, CHClosureV/B) */
+  double delta;           /* filter width Delta > 0 in lattice units */
   int32_t storage;        /* LBMHD_FP32 or LBMHD_FP16 */
 } lbmhd_params;
 
@@ -246,14 +247,16 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
 
 /* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next, where state_n is
  * the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc
- * bytes, FP64) gains, slot per thread block, the contribution
- * lam_next . d x_{n+1} / d C_S; slots are only ever added to, so zero acc
+ * bytes, FP64) holds two arrays of slots, one slot per thread block in each:
+ * the first gains lam_next . d x_{n+1} / d C_Sv, the second
+ * lam_next . d x_{n+1} / d C_Sb.  Slots are only ever added to, so zero acc
  * once before a backward sweep.  lam_prev must not alias lam_next.
  * Asynchronous. */
 int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float* lam_prev,
                    double* acc);
 
-/* Sum the slots of acc into *out (host), in FP64.  Synchronises. */
+/* Sum the two slot arrays of acc into out[0] (C_Sv) and out[1] (C_Sb), host,
+ * in FP64.  Synchronises. */
 int lbmhd_adj_acc_total(lbmhd_t* h, const double* acc, double* out);
 
 /* Pull an adjoint lattice back through the initial equilibria: with

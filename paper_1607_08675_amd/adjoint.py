@@ -1,6 +1,6 @@
 """Gradients of the final total energy through the GPU adjoint step.
 
-``LBMHDFunction.apply(ux0, uy0, bx0, by0, cs, lattice, nsteps, every)`` runs
+``LBMHDFunction.apply(ux0, uy0, bx0, by0, cs, cfg, nsteps, every)`` runs
 ``nsteps`` steps from equilibrium at (rho = 1, u0, B0) and returns
 J = sum |rho u|^2 / (2 rho) + |B|^2 / 2 of the final state (FP64).  Its backward
 pass is the discrete adjoint: checkpoints of the encoded lattice are kept every
@@ -8,7 +8,9 @@ pass is the discrete adjoint: checkpoints of the encoded lattice are kept every
 segment from its checkpoint, recomputes that segment's states straight into
 stored buffers (one step kernel per state, no copies), and walks them in reverse with ``lbmhd_adj_step``.  The result holds the exact
 derivative of the FP32 update map (storage rounding counted as the identity)
-with respect to the initial fields and the closure constant C_S.
+with respect to the initial fields and the closure constants: ``cs`` is a
+scalar (C_Sv = C_Sb = cs) or a pair (C_Sv, C_Sb), and its gradient has the
+same shape.
 """
 from __future__ import annotations
 
@@ -48,8 +50,8 @@ class Checkpointed:
         return lat.energy() if targets is None else lat.mismatch(targets)
 
     def backward(self, scale: float = 1.0):
-        """Returns scale * (dJ/du_x, dJ/du_y, dJ/dB_x, dJ/dB_y, dJ/dC_S) for the
-        functional returned by forward()."""
+        """Returns scale * (dJ/du_x, dJ/du_y, dJ/dB_x, dJ/dB_y, dJ/dC_Sv, dJ/dC_Sb)
+        for the functional returned by forward()."""
         lat = self.lat
         lam = lat.new_adj_buffer()
         lam2 = lat.new_adj_buffer()
@@ -71,7 +73,7 @@ class Checkpointed:
                 lat.adj_step(states[j], lam, lam2, acc)
                 lam, lam2 = lam2, lam
         g = lat.adj_fields(lam, self.fields)
-        return (*g, lat.adj_acc_total(acc))
+        return (*g, *lat.adj_acc_total(acc))
 
 
 class LBMHDFunction(torch.autograd.Function):
@@ -79,7 +81,11 @@ class LBMHDFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, ux0, uy0, bx0, by0, cs, cfg: LBMHDConfig, nsteps: int, every: int = 100):
-        cfg = LBMHDConfig(**{**cfg.__dict__, "cs": float(cs)})
+        c = cs.detach().to(torch.float64).reshape(-1).cpu()
+        if c.numel() not in (1, 2):
+            raise ValueError("cs must be a scalar or a pair (C_Sv, C_Sb)")
+        csv, csb = float(c[0]), float(c[-1])
+        cfg = LBMHDConfig(**{**cfg.__dict__, "cs": csv, "cs_b": csb})
         lat = Lattice(cfg, device=ux0.device)
         rho0 = torch.ones_like(ux0, dtype=torch.float64)
         fields = (rho0, *(t.detach().to(torch.float64) for t in (ux0, uy0, bx0, by0)))
@@ -87,14 +93,20 @@ class LBMHDFunction(torch.autograd.Function):
         J = run.forward(fields, nsteps)
         ctx.run = run
         ctx.dtypes = tuple(t.dtype for t in (ux0, uy0, bx0, by0, cs))
+        ctx.cs_shape = cs.shape
         return torch.tensor(J, dtype=torch.float64, device=ux0.device)
 
     @staticmethod
     def backward(ctx, gJ):
-        gux, guy, gbx, gby, gcs = ctx.run.backward()
+        gux, guy, gbx, gby, gv, gb = ctx.run.backward()
         s = gJ.to(torch.float64)
         outs = [s * g for g in (gux, guy, gbx, gby)]
         outs = [o.to(dt) for o, dt in zip(outs, ctx.dtypes[:4])]
-        gc = (s * gcs).to(ctx.dtypes[4]).reshape(())
+        if ctx.cs_shape.numel() == 1:
+            gc = (s * (gv + gb)).reshape(ctx.cs_shape)
+        else:
+            gc = s * torch.tensor([gv, gb], dtype=torch.float64,
+                                  device=s.device).reshape(ctx.cs_shape)
+        gc = gc.to(ctx.dtypes[4])
         ctx.run = None
         return (*outs, gc, None, None, None)

@@ -8,8 +8,9 @@
 // the collision from the gathered x_n, applies the hand-derived transposed
 // Jacobian to its own lam_{n+1}, and scatters component i back to x - c_i.
 // The scatter writes each (site, population) exactly once, so no atomics are
-// needed.  The derivative with respect to the closure constant C_S is
-// accumulated per thread block in FP64, into a slot owned by that block.
+// needed.  The derivatives with respect to the closure constants C_Sv (eddy
+// viscosity) and C_Sb (eddy resistivity) are accumulated per thread block in
+// FP64, each into a slot owned by that block.
 //
 // Reverse-mode rules follow the forward collision operation by operation;
 // the kinks of |A| and of the norm Q take derivative 0 at exactly 0.
@@ -59,16 +60,21 @@ __device__ __forceinline__ void st_plane_nt(float* __restrict__ base, unsigned o
 }
 
 struct AdjConsts {
-  float dcf;  // d(18 C_S Delta^2) / dC_S
-  float dcm;  // d(36 C_S Delta^2) / dC_S
+  float dcf;  // d(18 C_Sv Delta^2) / dC_Sv
+  float dcm;  // d(36 C_Sb Delta^2) / dC_Sb
+};
+
+// Contributions of one site to dJ/dC_Sv and dJ/dC_Sb.
+struct CsGrad {
+  float v, b;
 };
 
 // lam (19 values, in: adjoint of the post-collision populations; out:
 // adjoint of the pre-collision populations) for the collision at the
 // pre-collision state f[9], g[10] (deviation variables).  Returns the
-// site's contribution to dJ/dC_S.
+// site's contributions to dJ/dC_Sv and dJ/dC_Sb.
 template <bool LES>
-__device__ __forceinline__ float collide_adjoint(const float (&f)[9], const float (&g)[10],
+__device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const float (&g)[10],
                                                  float (&lf)[9], float (&lg)[10],
                                                  const Rates& r, const AdjConsts& ac) {
   // ---- forward recompute of what the reverse sweep needs (same operations
@@ -141,14 +147,15 @@ __device__ __forceinline__ float collide_adjoint(const float (&f)[9], const floa
   float Byb = (1.0f / 3.0f) * geqb[5] + (1.0f / 6.0f) * (geqb[6] + geqb[7] + geqb[8] + geqb[9]);
   float Eb = 0.5f * (-geqb[2] + geqb[4] + geqb[6] - geqb[8]);
 
-  float dcs = 0.0f, irb = 0.0f;
+  CsGrad dcs{0.0f, 0.0f};
+  float irb = 0.0f;
   if (LES) {
     // sm = 1 / taum, taum = (taum0 + Rm) / 2, Rm = sqrt(taum0^2 + cm |A|)
     const float taumb = -smb * sm * sm;
     const float amb = 0.5f * taumb * 0.5f * frcp(Rm);
     const float absAb = r.cm * amb;
     const float Ab = A > 0.0f ? absAb : (A < 0.0f ? -absAb : 0.0f);
-    dcs += ac.dcm * fabsf(A) * amb;
+    dcs.b += ac.dcm * fabsf(A) * amb;
     lgo[6] += Ab;
     lgo[8] -= Ab;
     lgo[2] -= Ab;
@@ -160,7 +167,7 @@ __device__ __forceinline__ float collide_adjoint(const float (&f)[9], const floa
     const float ab = 0.5f * taub * 0.5f * frcp(Rr);
     const float Qb = r.cf * ir * ab;
     irb += r.cf * Q * ab;
-    dcs += ac.dcf * Q * ir * ab;
+    dcs.v += ac.dcf * Q * ir * ab;
     if (Q > 0.0f) {
       const float iQ = frcp(Q);
       nb4 += Qb * n4 * iQ;
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
   const int b = int(blockIdx.x);
   const int x = (b % tiles_x) * LBMHD_ADJ_TX + int(threadIdx.x);
   const int y = b / tiles_x;
-  float dcs = 0.0f;
+  CsGrad dcs{0.0f, 0.0f};
   if (x < geo.nx) {
     const int xm = x == 0 ? geo.nx - 1 : x - 1;
     const int xp = x == geo.nx - 1 ? 0 : x + 1;
@@ -265,14 +272,22 @@ __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
     }
   }
   if (LES) {
-    __shared__ double sh[LBMHD_ADJ_TX];
-    sh[threadIdx.x] = double(dcs);
+    // acc[b] gains the block's dJ/dC_Sv, acc[gridDim.x + b] its dJ/dC_Sb
+    __shared__ double sh[2][LBMHD_ADJ_TX];
+    sh[0][threadIdx.x] = double(dcs.v);
+    sh[1][threadIdx.x] = double(dcs.b);
     __syncthreads();
     for (int w = LBMHD_ADJ_TX / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      if ((int)threadIdx.x < w) {
+        sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+        sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0) acc[blockIdx.x] += sh[0];
+    if (threadIdx.x == 0) {
+      acc[blockIdx.x] += sh[0][0];
+      acc[gridDim.x + blockIdx.x] += sh[1][0];
+    }
   }
 }
 
@@ -409,7 +424,7 @@ hipError_t launch_adj_step(int storage, bool les, const void* state, const float
                            const Rates& r, double delta2, hipStream_t s) {
   const int tiles_x = (g.nx + LBMHD_ADJ_TX - 1) / LBMHD_ADJ_TX;
   const dim3 grid(unsigned(adj_step_blocks(g))), block(LBMHD_ADJ_TX);
-  // cf = 18 C_S Delta^2 and cm = 36 C_S Delta^2 are linear in C_S.
+  // cf = 18 C_Sv Delta^2 and cm = 36 C_Sb Delta^2 are linear in their constants.
   const AdjConsts ac{float(18.0 * delta2), float(36.0 * delta2)};
   if (storage == LBMHD_FP32) {
     auto* st = static_cast<const float*>(state);

@@ -35,7 +35,7 @@ constexpr size_t kAlign = 256;
 hipError_t launch_one_step(const lbmhd_t* h, const void* src, void* dst) {
   // C_S = 0 makes the eddy closures the identity (tau = tau0): skip them.
   const int les = h->p.les;
-  const bool on = h->p.cs > 0.0;
+  const bool on = h->p.cs > 0.0 || h->p.cs_b > 0.0;
   const int eddy = (les & 1) && on ? 1 : ((les & 4) && on ? 2 : 0);
   if ((les & 2) || eddy == 2)
     return lbk::launch_step_nb(h->p.storage, eddy, (les & 2) != 0, src, dst, h->geo, h->rates,
@@ -127,7 +127,8 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
     return LBMHD_ERR_INVALID_ARG;
   if (p->s5 != p->s6) return LBMHD_ERR_INVALID_ARG;
   if (p->les < 0 || p->les > 6 || ((p->les & 1) && (p->les & 4))) return LBMHD_ERR_INVALID_ARG;
-  if (!(p->cs >= 0.0) || !isfinite(p->cs) || !(p->delta > 0.0) || !isfinite(p->delta))
+  if (!(p->cs >= 0.0) || !isfinite(p->cs) || !(p->cs_b >= 0.0) || !isfinite(p->cs_b) ||
+      !(p->delta > 0.0) || !isfinite(p->delta))
     return LBMHD_ERR_INVALID_ARG;
   if (p->storage != LBMHD_FP32 && p->storage != LBMHD_FP16) return LBMHD_ERR_INVALID_ARG;
   const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
@@ -155,11 +156,11 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   r.taum0 = float(taum0);
   r.taum0sq = float(taum0 * taum0);
   r.cf = float(18.0 * p->cs * d2);
-  r.cm = float(36.0 * p->cs * d2);
+  r.cm = float(36.0 * p->cs_b * d2);
   r.stau0 = float(std::sqrt(tau0));
   r.staum0 = float(std::sqrt(taum0));
   r.kv = float(4.5 * p->cs * d2);
-  r.kb = float(3.0 * std::sqrt(3.0) * p->cs * d2);
+  r.kb = float(3.0 * std::sqrt(3.0) * p->cs_b * d2);
   // the largest root of t^3 - tau_m0 t - q is below t* = max(sqrt(1/2),
   // sqrt(tau_m0 / 3)) (or absent) exactly when q < t*^3 - tau_m0 t*
   const double ts = std::max(std::sqrt(0.5), std::sqrt(taum0 / 3.0));
@@ -167,7 +168,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   h->lattice_bytes = size_t(lbk::kNPop) * size_t(g.plane) * esize;
   h->adj_lattice_bytes = size_t(lbk::kNPop) * size_t(ga.plane) * 4;
   h->workspace_bytes = round_up(workspace_doubles(g) * sizeof(double), kAlign);
-  h->adj_acc_bytes = round_up(size_t(lbk::adj_step_blocks(g)) * sizeof(double), kAlign);
+  h->adj_acc_bytes = round_up(2 * size_t(lbk::adj_step_blocks(g)) * sizeof(double), kAlign);
   *out = h;
   return LBMHD_OK;
 }
@@ -405,11 +406,15 @@ int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float
 int lbmhd_adj_acc_total(lbmhd_t* h, const double* acc, double* out) {
   if (int rc = need_bound(h)) return rc;
   if (!acc || !out) return fail(h, LBMHD_ERR_INVALID_ARG, "null argument");
+  // workspace tail: [16] the C_Sv sum, [17] the mismatch, [18] the C_Sb sum
   double* dev = ws_out(h) + lbk::kDiagSlots;
-  hipError_t e = lbk::launch_sum(acc, (long long)(h->adj_acc_bytes / sizeof(double)), dev,
-                                   h->stream);
+  const long long nb = lbk::adj_step_blocks(h->geo);
+  hipError_t e = lbk::launch_sum(acc, nb, dev, h->stream);
+  if (e == hipSuccess) e = lbk::launch_sum(acc + nb, nb, dev + 2, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "sum launch");
   e = hipMemcpyAsync(out, dev, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out + 1, dev + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "sum copy");
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "sum synchronise");

@@ -27,7 +27,9 @@ class LBMHDConfig:
     s5 (= s6), s7, s8: rates of the non-hydrodynamic moments.
     les: bit mask -- 0 plain, 1 Smagorinsky-MHD closure, 2 kinetic closure
     (filtered equilibria), 3 both, 4 cross-helicity closure (with backscatter),
-    6 kinetic and cross-helicity; cs: closure constant; delta: filter width.
+    6 kinetic and cross-helicity; cs: closure constant C_Sv of the eddy
+    viscosity; cs_b: constant C_Sb of the eddy resistivity (None: same as cs);
+    delta: filter width.
     storage: "fp32" or "fp16" (deviation from the rest state, FP16 scaled by 2^10).
     """
     nx: int
@@ -41,11 +43,16 @@ class LBMHDConfig:
     cs: float = 0.1
     delta: float = 1.0
     storage: str = "fp32"
+    cs_b: float | None = None
+
+    @property
+    def csb(self) -> float:
+        return self.cs if self.cs_b is None else self.cs_b
 
     def c_params(self) -> C.Params:
         st = {"fp32": C.LBMHD_FP32, "fp16": C.LBMHD_FP16}[self.storage]
         return C.Params(self.nx, self.ny, self.nu, self.eta, self.s5, self.s5, self.s7,
-                        self.s8, int(self.les), self.cs, self.delta, st)
+                        self.s8, int(self.les), self.cs, self.csb, self.delta, st)
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
@@ -207,11 +214,12 @@ class Lattice:
         self._check(self._L.lbmhd_adj_step(self._h, _ptr(state_n), _ptr(lam_next),
                                            _ptr(lam_prev), _ptr(acc)), "lbmhd_adj_step")
 
-    def adj_acc_total(self, acc: torch.Tensor) -> float:
-        out = ctypes.c_double()
-        self._check(self._L.lbmhd_adj_acc_total(self._h, _ptr(acc), ctypes.byref(out)),
+    def adj_acc_total(self, acc: torch.Tensor) -> tuple[float, float]:
+        """(sum lam . dx/dC_Sv, sum lam . dx/dC_Sb) accumulated in acc."""
+        out = (ctypes.c_double * 2)()
+        self._check(self._L.lbmhd_adj_acc_total(self._h, _ptr(acc), out),
                     "lbmhd_adj_acc_total")
-        return out.value
+        return float(out[0]), float(out[1])
 
     def adj_fields(self, lam0: torch.Tensor, fields) -> tuple:
         fs = [self._field(a) for a in fields]

@@ -55,7 +55,7 @@ def _to_adj(L, a):
 @pytest.mark.parametrize("nx,ny", [(8, 8), (100, 36), (300, 5)])
 def test_adjoint_step_dot_product(lb, orc, nx, ny, les, storage):
     cfg = lb.LBMHDConfig(nx=nx, ny=ny, nu=0.01, eta=0.02, s5=1.2, s7=1.5, s8=0.8, les=les,
-                         cs=0.15, storage=storage)
+                         cs=0.15, cs_b=0.1, storage=storage)
     L = lb.Lattice(cfg)
     x = random_state(nx, ny, seed=nx + 7 * ny)
     L.set_populations(x)
@@ -71,20 +71,22 @@ def test_adjoint_step_dot_product(lb, orc, nx, ny, les, storage):
     L.adj_step(state, lam_next, lam_prev, acc)
     JTa = L.adj_view(lam_prev).double().cpu().numpy()
     assert np.isfinite(JTa).all()
-    dcs_gpu = L.adj_acc_total(acc)
+    dcs_gpu = L.adj_acc_total(acc)       # (d/dC_Sv, d/dC_Sb)
 
     op = orc.Params(nx, ny, nu=cfg.nu, eta=cfg.eta, s5=cfg.s5, s6=cfg.s5, s7=cfg.s7, s8=cfg.s8,
-                    les=les, cs=cfg.cs)
+                    les=les, cs=cfg.cs, csb=cfg.cs_b)
     sx = orc.stream(op, x)
     _, Jb = orc.tl_collide(op, sx, orc.stream(op, b)[None], np.zeros(1))
     lhs, rhs = float(np.sum(a * Jb[0])), float(np.sum(JTa * b))
     assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(a * a) * np.sum(b * b)), (lhs, rhs)
-    _, Jc = orc.tl_collide(op, sx, np.zeros((1, 19, ny, nx)), np.ones(1))
-    want = float(np.sum(a * Jc[0]))
-    if les:
-        assert abs(dcs_gpu - want) <= 1e-5 * (abs(want) + np.sqrt(np.sum(a * a))), (dcs_gpu, want)
-    else:
-        assert dcs_gpu == 0.0 and want == 0.0
+    _, Jc = orc.tl_collide(op, sx, np.zeros((2, 19, ny, nx)), np.eye(2))
+    for k in range(2):
+        want = float(np.sum(a * Jc[k]))
+        if les:
+            assert abs(dcs_gpu[k] - want) <= 1e-5 * (abs(want) + np.sqrt(np.sum(a * a))), \
+                (k, dcs_gpu[k], want)
+        else:
+            assert dcs_gpu[k] == 0.0 and want == 0.0
 
 
 @pytest.mark.parametrize("les", [True, False])
@@ -127,6 +129,26 @@ def test_gradient_of_cs_alone(lb, orc):
     _, dJ = orc.tl_energy(op, fields, np.zeros((1, 4, n, n)), np.ones(1), steps)
     assert abs(float(cs.grad) - dJ[0]) <= 1e-3 * abs(dJ[0]), (float(cs.grad), dJ[0])
     assert dJ[0] < 0   # more eddy viscosity / resistivity dissipates more energy
+
+
+def test_gradient_of_the_two_constants(lb, orc):
+    """cs given as the pair (C_Sv, C_Sb): its gradient is the pair of partial
+    derivatives, each against the oracle's tangent in that constant alone."""
+    from paper_1607_08675_amd.adjoint import LBMHDFunction
+    n, steps = 32, 40
+    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=0.002, eta=0.002, les=True, cs=0.2)
+    fields = perturbed_orszag_tang(n, n, u0=0.1, b0=0.1)
+    dev = torch.device("cuda")
+    t = [torch.tensor(f, dtype=torch.float64, device=dev, requires_grad=True) for f in fields[1:]]
+    cs = torch.tensor([0.2, 0.1], dtype=torch.float64, device=dev, requires_grad=True)
+    LBMHDFunction.apply(*t, cs, cfg, steps, 10).backward()
+    op = orc.Params(n, n, nu=cfg.nu, eta=cfg.eta, les=True, cs=0.2, csb=0.1)
+    _, dJ = orc.tl_energy(op, fields, np.zeros((2, 4, n, n)), np.eye(2), steps)
+    got = cs.grad.cpu().numpy()
+    assert got.shape == (2,)
+    for k in range(2):
+        assert abs(got[k] - dJ[k]) <= 1e-3 * abs(dJ[k]), (k, got[k], dJ[k])
+        assert dJ[k] < 0
 
 
 def test_seed_is_energy_gradient(lb, orc):
@@ -198,5 +220,5 @@ def test_adjoint_step_full_size_patches(lb, orc, storage, n, nu, gen):
         assert abs(lhs - rhs) <= 2e-5 * scale, ((cx, cy), lhs, rhs)
         _, Jc = orc.tl_collide(op, sx, np.zeros((1, 19, 2 * R + 1, 2 * R + 1)), np.ones(1))
         want = float(np.sum(a * Jc[0]))
-        got = L.adj_acc_total(acc)
+        got = sum(L.adj_acc_total(acc))   # C_Sv = C_Sb: the tied derivative
         assert abs(got - want) <= 2e-4 * abs(want) + 1e-5 * np.sqrt(np.sum(a * a)), ((cx, cy), got, want)

@@ -72,23 +72,26 @@ def test_mismatch_value_and_seed(lb, orc):
 
 
 def test_mismatch_gradient_wrt_cs_matches_oracle_fd(lb, orc):
-    """dL/dC_S through 30 steps (checkpoint every 8) against central
-    differences of the FP64 oracle; targets are unrelated synthetic fields."""
+    """dL/dC_Sv and dL/dC_Sb through 30 steps (checkpoint every 8) against
+    central differences of the FP64 oracle in each constant; targets are
+    unrelated synthetic fields."""
     from paper_1607_08675_amd.adjoint import Checkpointed
-    n, steps, cs = 24, 30, 0.15
+    n, steps, cs, csb = 24, 30, 0.15, 0.1
     fields = orszag_tang(n, n, u0=0.1, b0=0.1)
     targets = decaying_turbulence(n, n)[1:]
-    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-3, eta=1e-3, les=True, cs=cs)
+    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-3, eta=1e-3, les=True, cs=cs, cs_b=csb)
     run = Checkpointed(lb.Lattice(cfg), 8)
     Lg = run.forward(fields, steps, targets=targets)
     g = run.backward()
-    def oracle_L(c):
-        op = orc.Params(n, n, nu=1e-3, eta=1e-3, les=True, cs=c)
+    def oracle_L(c, cb):
+        op = orc.Params(n, n, nu=1e-3, eta=1e-3, les=True, cs=c, csb=cb)
         return _mismatch(orc.macro(op, orc.run(op, orc.init(op, *fields), steps)), targets)
-    assert abs(Lg - oracle_L(cs)) <= 1e-6 * abs(Lg)
+    assert abs(Lg - oracle_L(cs, csb)) <= 1e-6 * abs(Lg)
     eps = 1e-5
-    fd = (oracle_L(cs + eps) - oracle_L(cs - eps)) / (2 * eps)
-    assert abs(g[4] - fd) <= 1e-3 * abs(fd), (g[4], fd)
+    fdv = (oracle_L(cs + eps, csb) - oracle_L(cs - eps, csb)) / (2 * eps)
+    fdb = (oracle_L(cs, csb + eps) - oracle_L(cs, csb - eps)) / (2 * eps)
+    assert abs(g[4] - fdv) <= 1e-3 * abs(fdv), (g[4], fdv)
+    assert abs(g[5] - fdb) <= 1e-3 * abs(fdb), (g[5], fdb)
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
@@ -107,3 +110,20 @@ def test_fit_recovers_known_cs(lb, orc, storage):
     res = fit_cs(fields, targets, start, steps, iters=14, every=16)
     assert res.loss[-1] < 1e-2 * res.loss[0], res.loss
     assert abs(res.cs[-1] - 0.2) < 0.01 * (5 if storage == "fp16" else 1), res.cs
+
+
+def test_joint_fit_recovers_both_constants(lb, orc):
+    """Twin experiment with C_Sv = 0.2, C_Sb = 0.1: the joint fit started at
+    0.05 for both returns to the pair."""
+    from paper_1607_08675_amd.fit import fit_cs
+    n, steps = 32, 60
+    fields = decaying_turbulence(n, n, u_rms=0.08, b_rms=0.08)
+    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-4, eta=1e-4, les=True, cs=0.2, cs_b=0.1)
+    L = lb.Lattice(cfg)
+    L.init_fields(*fields).step(steps)
+    m = L.macro()
+    targets = (m["ux"], m["uy"], m["bx"], m["by"])
+    start = lb.LBMHDConfig(**{**cfg.__dict__, "cs": 0.05, "cs_b": 0.05})
+    res = fit_cs(fields, targets, start, steps, iters=24, every=16, joint=True)
+    assert res.loss[-1] < 1e-2 * res.loss[0], res.loss
+    assert abs(res.cs[-1] - 0.2) < 0.02 and abs(res.cs_b[-1] - 0.1) < 0.01, (res.cs, res.cs_b)
