@@ -125,6 +125,28 @@ def fp32_leg(torch, args):
     return out
 
 
+def inplace_leg(torch, args):
+    """The headline workload (4096^2 Orszag-Tang, FP32, LES) on one lattice
+    updated in place (AA pattern): an even number of back-to-back launches,
+    so the timing covers both step kinds equally and no layout pass."""
+    from lbmhd_inputs import orszag_tang
+    from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
+    n = 4096
+    cfg = LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=1, cs=0.1, storage="fp32",
+                      inplace=True)
+    lat = Lattice(cfg)
+    lat.init_fields(*orszag_tang(n, n))
+    lat.step(2 * (args.warmup // 2))
+    torch.cuda.synchronize()
+    per_launch = burst_ms_per_launch(torch, lat, 200)
+    d = lat.diag()
+    log(f"in-place 4096^2 FP32: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
+    mem = lat.lattice_bytes
+    del lat
+    torch.cuda.empty_cache()
+    return dict(per_launch=per_launch, sites=n * n, nonfinite=d["nonfinite"], lattice_bytes=mem)
+
+
 CLOSURES = {2: "kinetic closure", 4: "cross-helicity closure"}
 
 
@@ -300,7 +322,7 @@ def main():
     ap.add_argument("--fit-iters", type=int, default=20)
     ap.add_argument("--fit-ref-steps", type=int, default=5000)
     ap.add_argument("--skip", default="",
-                    help="comma list of legs to skip: kinetic,crosshelicity,fp16,adjoint,fit,cpu")
+                    help="comma list of legs to skip: kinetic,crosshelicity,inplace,fp16,adjoint,fit,cpu")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -317,6 +339,7 @@ def main():
     r32 = fp32_leg(torch, args)
     rkin = None if "kinetic" in skip else closure_leg(torch, args, 2)
     rch = None if "crosshelicity" in skip else closure_leg(torch, args, 4)
+    rin = None if "inplace" in skip else inplace_leg(torch, args)
     r16 = None if "fp16" in skip else fp16_leg(torch, args)
     radj = None if "adjoint" in skip else adjoint_leg(torch, args)
     rfit = None if "fit" in skip else fit_leg(torch, args)
@@ -363,6 +386,17 @@ def main():
                           "full-size sampled sites)",
         },
     }
+    if rin:
+        mi = rin["sites"] / (rin["per_launch"] * 1e-3) / 1e6
+        ai = FP32_BYTES_PER_SITE * rin["sites"] / (rin["per_launch"] * 1e-3) / 1e9
+        line["inplace"] = {
+            "workload": "Orszag-Tang 4096x4096, FP32, LES C_S=0.1, nu=eta=1e-5, one lattice "
+                        "updated in place (AA pattern)",
+            "mlups": round(mi, 1), "ms_per_step": round(rin["per_launch"], 5),
+            "achieved_gbs": round(ai, 1), "frac": round(ai / HBM_PEAK_GBS, 4),
+            "bytes_per_site": FP32_BYTES_PER_SITE, "nonfinite": rin["nonfinite"],
+            "state_bytes": rin["lattice_bytes"], "state_bytes_two_lattices": 2 * rin["lattice_bytes"],
+        }
     for key, res, what in (
             ("kinetic_closure", rkin, "kinetic LES closure (filtered equilibria, Delta = 1)"),
             ("cross_helicity_closure", rch,

@@ -101,6 +101,13 @@ typedef struct {
                              SmagorinskyMHDClosureV/B, CHClosureV/B) */
   double delta;           /* filter width Delta > 0 in lattice units */
   int32_t storage;        /* LBMHD_FP32 or LBMHD_FP16 */
+  int32_t inplace;        /* 0: two lattices, each step writes the other one;
+                             1: one lattice updated in place (AA pattern: the
+                             steps alternate between a pull-gather /
+                             push-scatter step into reversed slots and a fully
+                             local step back, the same bytes per step as the
+                             two-lattice update).  Not with les = 2, 3, 4, 6
+                             (those read the neighbours' populations). */
 } lbmhd_params;
 
 /* Global diagnostics of the current state, accumulated in FP64.
@@ -138,7 +145,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out);
 int lbmhd_destroy(lbmhd_t* h);
 
 /* Byte sizes the caller must allocate in device memory:
- *   lattice    -- one encoded population lattice (two are bound);
+ *   lattice    -- one encoded population lattice (two are bound, one in place);
  *   workspace  -- scratch used by diagnostics, energy and reductions;
  *   adj_lattice -- one FP32 adjoint lattice (lambda), for the adjoint calls;
  *   adj_acc    -- the FP64 accumulator array of lbmhd_adj_step.
@@ -149,7 +156,8 @@ int lbmhd_sizes(const lbmhd_t* h, size_t* lattice, size_t* workspace, size_t* ad
 /* Attach caller-owned device buffers and the HIP stream (a hipStream_t, or
  * NULL for the null stream).  lat_a and lat_b must each hold `lattice`
  * bytes and workspace `workspace` bytes (lbmhd_sizes), 256-byte aligned, and
- * must not overlap.  The stored sizes are checked against the requirement.
+ * must not overlap; with inplace = 1 only lat_a is used (lat_b may be NULL).
+ * The stored sizes are checked against the requirement.
  * Does not initialise the state.  Errors: LBMHD_ERR_INVALID_ARG. */
 int lbmhd_bind(lbmhd_t* h, void* lat_a, size_t lat_a_bytes, void* lat_b, size_t lat_b_bytes,
                void* workspace, size_t workspace_bytes, void* stream);

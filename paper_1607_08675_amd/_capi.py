@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
         ("s7", ctypes.c_double), ("s8", ctypes.c_double),
         ("les", ctypes.c_int32),
         ("cs", ctypes.c_double), ("cs_b", ctypes.c_double), ("delta", ctypes.c_double),
-        ("storage", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("inplace", ctypes.c_int32),
     ]
 
 

@@ -23,6 +23,7 @@ struct lbmhd {
   hipStream_t stream = nullptr;
   bool bound = false;
   int cur = 0;  // index of the lattice holding the current state
+  bool reversed = false;  // in-place mode: the lattice is in the reversed layout
   int64_t step = 0;
   std::string err;
 };
@@ -79,6 +80,19 @@ int need_bound(lbmhd_t* h) {
   return LBMHD_OK;
 }
 
+// The bound lattice holding the current state in the natural layout: an
+// in-place lattice left in the reversed layout by an odd number of steps is
+// turned back first (one in-place pass).
+int current(lbmhd_t* h, const void** out) {
+  if (h->p.inplace && h->reversed) {
+    hipError_t e = lbk::launch_unswap_aa(h->p.storage, h->lat[0], h->geo, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "layout launch");
+    h->reversed = false;
+  }
+  *out = h->lat[h->cur];
+  return LBMHD_OK;
+}
+
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
 
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -131,6 +145,10 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
       !(p->delta > 0.0) || !isfinite(p->delta))
     return LBMHD_ERR_INVALID_ARG;
   if (p->storage != LBMHD_FP32 && p->storage != LBMHD_FP16) return LBMHD_ERR_INVALID_ARG;
+  // the in-place update keeps every site's reads and writes within its own
+  // locations; closures that read the neighbours' populations cannot
+  if (p->inplace != 0 && p->inplace != 1) return LBMHD_ERR_INVALID_ARG;
+  if (p->inplace && (p->les & 6)) return LBMHD_ERR_INVALID_ARG;
   const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
   lbk::Geom g = make_geom(p->nx, p->ny, esize);
   lbk::Geom ga = make_geom(p->nx, p->ny, 4);
@@ -192,22 +210,27 @@ int lbmhd_bind(lbmhd_t* h, void* lat_a, size_t lat_a_bytes, void* lat_b, size_t 
                void* workspace, size_t workspace_bytes, void* stream) {
   if (!h) return LBMHD_ERR_INVALID_ARG;
   h->bound = false;
-  if (!lat_a || !lat_b || !workspace)
+  if (h->p.inplace) {  // one lattice: lat_b is not used
+    lat_b = nullptr;
+    lat_b_bytes = 0;
+  }
+  if (!lat_a || (!lat_b && !h->p.inplace) || !workspace)
     return fail(h, LBMHD_ERR_INVALID_ARG, "null buffer passed to lbmhd_bind");
-  if (lat_a_bytes < h->lattice_bytes || lat_b_bytes < h->lattice_bytes ||
+  if (lat_a_bytes < h->lattice_bytes || (!h->p.inplace && lat_b_bytes < h->lattice_bytes) ||
       workspace_bytes < h->workspace_bytes)
     return fail(h, LBMHD_ERR_INVALID_ARG, "buffer smaller than lbmhd_sizes() requires");
-  if (!aligned(lat_a) || !aligned(lat_b) || !aligned(workspace))
+  if (!aligned(lat_a) || (lat_b && !aligned(lat_b)) || !aligned(workspace))
     return fail(h, LBMHD_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
-  if (overlap(lat_a, h->lattice_bytes, lat_b, h->lattice_bytes) ||
-      overlap(lat_a, h->lattice_bytes, workspace, h->workspace_bytes) ||
-      overlap(lat_b, h->lattice_bytes, workspace, h->workspace_bytes))
+  if (overlap(lat_a, h->lattice_bytes, workspace, h->workspace_bytes) ||
+      (lat_b && (overlap(lat_a, h->lattice_bytes, lat_b, h->lattice_bytes) ||
+                 overlap(lat_b, h->lattice_bytes, workspace, h->workspace_bytes))))
     return fail(h, LBMHD_ERR_INVALID_ARG, "bound buffers overlap");
   h->lat[0] = lat_a;
   h->lat[1] = lat_b;
   h->ws = static_cast<double*>(workspace);
   h->stream = static_cast<hipStream_t>(stream);
   h->cur = 0;
+  h->reversed = false;
   h->step = 0;
   h->bound = true;
   return LBMHD_OK;
@@ -221,6 +244,7 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
                                     h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "init launch");
   h->cur = 0;
+  h->reversed = false;
   h->step = 0;
   return LBMHD_OK;
 }
@@ -228,10 +252,18 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
 int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   if (int rc = need_bound(h)) return rc;
   if (nsteps < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
+  const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
   for (int64_t t = 0; t < nsteps; ++t) {
-    hipError_t e = launch_one_step(h, h->lat[h->cur], h->lat[1 - h->cur]);
+    hipError_t e;
+    if (h->p.inplace) {
+      e = lbk::launch_step_aa(h->p.storage, les, h->reversed ? 1 : 0, h->lat[0], h->geo,
+                              h->rates, h->stream);
+      h->reversed = !h->reversed;
+    } else {
+      e = launch_one_step(h, h->lat[h->cur], h->lat[1 - h->cur]);
+      h->cur = 1 - h->cur;
+    }
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
-    h->cur = 1 - h->cur;
     ++h->step;
   }
   return LBMHD_OK;
@@ -244,7 +276,7 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst) {
   if (overlap(src, h->lattice_bytes, dst, h->lattice_bytes))
     return fail(h, LBMHD_ERR_INVALID_ARG, "src and dst overlap");
   for (const void* b : {(const void*)h->lat[0], (const void*)h->lat[1]})
-    if (overlap(dst, h->lattice_bytes, b, h->lattice_bytes))
+    if (b && overlap(dst, h->lattice_bytes, b, h->lattice_bytes))
       return fail(h, LBMHD_ERR_INVALID_ARG, "dst overlaps a bound lattice");
   hipError_t e = launch_one_step(h, src, dst);
   if (e != hipSuccess) return hip_fail(h, e, "step launch");
@@ -254,8 +286,9 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst) {
 int lbmhd_macro(lbmhd_t* h, double* rho, double* ux, double* uy, double* bx, double* by) {
   if (int rc = need_bound(h)) return rc;
   if (!rho || !ux || !uy || !bx || !by) return fail(h, LBMHD_ERR_INVALID_ARG, "null field");
-  hipError_t e = lbk::launch_macro(h->p.storage, h->lat[h->cur], rho, ux, uy, bx, by, h->geo,
-                                     h->stream);
+  const void* st = nullptr;
+  if (int rc = current(h, &st)) return rc;
+  hipError_t e = lbk::launch_macro(h->p.storage, st, rho, ux, uy, bx, by, h->geo, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "macro launch");
   return LBMHD_OK;
 }
@@ -266,8 +299,10 @@ int lbmhd_macro_box(lbmhd_t* h, int32_t w, double* rho, double* ux, double* uy, 
   if (!rho || !ux || !uy || !bx || !by) return fail(h, LBMHD_ERR_INVALID_ARG, "null field");
   if (w < 1 || h->p.nx % w != 0 || h->p.ny % w != 0)
     return fail(h, LBMHD_ERR_INVALID_ARG, "box width must divide nx and ny");
-  hipError_t e = lbk::launch_macro_box(h->p.storage, h->lat[h->cur], w, rho, ux, uy, bx, by,
-                                       h->geo, h->stream);
+  const void* st = nullptr;
+  if (int rc = current(h, &st)) return rc;
+  hipError_t e = lbk::launch_macro_box(h->p.storage, st, w, rho, ux, uy, bx, by, h->geo,
+                                       h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "box macro launch");
   return LBMHD_OK;
 }
@@ -279,8 +314,10 @@ int lbmhd_mismatch(lbmhd_t* h, const void* state, const double* ux_t, const doub
     return fail(h, LBMHD_ERR_INVALID_ARG, "null target or output");
   double* part = h->ws + 5 * size_t(h->geo.nx) * h->geo.ny;  // diagnostics partials area
   double* dev = ws_out(h) + lbk::kDiagSlots + 1;
-  hipError_t e = lbk::launch_mismatch(h->p.storage, state ? state : h->lat[h->cur], ux_t, uy_t,
-                                      bx_t, by_t, part, dev, h->geo, h->stream);
+  if (!state)
+    if (int rc = current(h, &state)) return rc;
+  hipError_t e = lbk::launch_mismatch(h->p.storage, state, ux_t, uy_t, bx_t, by_t, part, dev,
+                                      h->geo, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "mismatch launch");
   e = hipMemcpyAsync(L, dev, sizeof(double), hipMemcpyDeviceToHost, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "mismatch copy");
@@ -293,7 +330,9 @@ int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out) {
   if (int rc = need_bound(h)) return rc;
   if (!out) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
   double v[lbk::kDiagSlots];
-  if (int rc = run_diag(h, h->lat[h->cur], v)) return rc;
+  const void* st = nullptr;
+  if (int rc = current(h, &st)) return rc;
+  if (int rc = run_diag(h, st, v)) return rc;
   out->mass = v[0];
   out->mom_x = v[1];
   out->mom_y = v[2];
@@ -317,7 +356,9 @@ int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out) {
 int lbmhd_get_populations(lbmhd_t* h, double* out) {
   if (int rc = need_bound(h)) return rc;
   if (!out) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
-  hipError_t e = lbk::launch_decode(h->p.storage, h->lat[h->cur], out, h->geo, h->stream);
+  const void* st = nullptr;
+  if (int rc = current(h, &st)) return rc;
+  hipError_t e = lbk::launch_decode(h->p.storage, st, out, h->geo, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "decode launch");
   return LBMHD_OK;
 }
@@ -328,6 +369,7 @@ int lbmhd_set_populations(lbmhd_t* h, const double* in, int64_t step) {
   hipError_t e = lbk::launch_encode(h->p.storage, in, h->lat[0], h->geo, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "encode launch");
   h->cur = 0;
+  h->reversed = false;
   h->step = step;
   return LBMHD_OK;
 }
@@ -335,7 +377,9 @@ int lbmhd_set_populations(lbmhd_t* h, const double* in, int64_t step) {
 int lbmhd_save_state(lbmhd_t* h, void* dst) {
   if (int rc = need_bound(h)) return rc;
   if (!dst || !aligned(dst)) return fail(h, LBMHD_ERR_INVALID_ARG, "null or unaligned dst");
-  hipError_t e = lbk::launch_copy(h->lat[h->cur], dst, h->lattice_bytes, h->stream);
+  const void* st = nullptr;
+  if (int rc = current(h, &st)) return rc;
+  hipError_t e = lbk::launch_copy(st, dst, h->lattice_bytes, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "copy launch");
   return LBMHD_OK;
 }
@@ -347,6 +391,7 @@ int lbmhd_load_state(lbmhd_t* h, const void* src, int64_t step) {
   hipError_t e = lbk::launch_copy(src, h->lat[0], h->lattice_bytes, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "copy launch");
   h->cur = 0;
+  h->reversed = false;
   h->step = step;
   return LBMHD_OK;
 }
@@ -361,7 +406,9 @@ int lbmhd_energy(lbmhd_t* h, const void* state, double* J) {
   if (int rc = need_bound(h)) return rc;
   if (!J) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
   double v[lbk::kDiagSlots];
-  if (int rc = run_diag(h, state ? state : h->lat[h->cur], v)) return rc;
+  if (!state)
+    if (int rc = current(h, &state)) return rc;
+  if (int rc = run_diag(h, state, v)) return rc;
   *J = v[5] + v[6];
   return LBMHD_OK;
 }

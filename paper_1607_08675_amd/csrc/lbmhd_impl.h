@@ -47,6 +47,12 @@ constexpr int kDiagBlocks = 1024;
 // Forward step: dst = C(S(src)).
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
                        const Rates& r, hipStream_t s);
+// In-place step on one lattice (AA pattern): phase 0 takes the natural
+// layout to the reversed one, phase 1 back; launch_unswap_aa turns a
+// reversed layout into the natural one in place.
+hipError_t launch_step_aa(int storage, bool les, int phase, void* lat, const Geom& g,
+                          const Rates& r, hipStream_t s);
+hipError_t launch_unswap_aa(int storage, void* lat, const Geom& g, hipStream_t s);
 // Forward step that needs the neighbours' rho, j, B (lattice gradients):
 // the kinetic closure (kin: filtered equilibria, filter width delta) and/or
 // the eddy closure `eddy` (0 none, 1 Smagorinsky, 2 cross-helicity).

@@ -39,9 +39,16 @@ template <>
 struct Codec<LBMHD_FP16> {
   using T = _Float16;
   // deviation = half * 2^-10; scaling by a power of two is exact, the only
-  // rounding is the RNE conversion to half.
+  // rounding is the RNE conversion of the FP32 value to half.  The empty asm
+  // keeps that FP32 value: without it the compiler may fuse the conversion
+  // with the multiply-add that produced v (v_fma_mix*), rounding straight to
+  // half, and kernels storing the same value would then differ in rare
+  // last bits.
   __device__ static __forceinline__ float dec(_Float16 v) { return float(v) * 0x1p-10f; }
-  __device__ static __forceinline__ _Float16 enc(float v) { return _Float16(v * 0x1p10f); }
+  __device__ static __forceinline__ _Float16 enc(float v) {
+    asm("" : "+v"(v));
+    return _Float16(v * 0x1p10f);
+  }
 };
 
 // V consecutive stored elements moved as one vector access.
@@ -476,6 +483,144 @@ __global__ __launch_bounds__(kKinThreads) void k_step_nb(
   }
 }
 
+// ------------------------------------------------------ in-place (AA) step
+// One lattice updated in place by two alternating steps.  Layout N (natural,
+// as for k_step): slot q at x holds the post-collision f*_q(x).  Layout R
+// (reversed): slot opp(q) at x + c_q holds f*_q(x).
+//   PHASE 0, N -> R: pre_q(x) = N_q(x - c_q), the pull gather of k_step;
+//     collide; f*_q(x) is stored in slot opp(q) at x + c_q.
+//   PHASE 1, R -> N: pre_q(x) = R_opp(q)(x), all local; collide; f*_q(x) is
+//     stored in slot q at x.
+// In both phases the locations whose values a thread uses and the locations
+// it writes are the same set, and no two threads share one, so no thread
+// reads a value another thread writes in the same launch.  (With V = 2 the
+// paired loads of x-moving planes also fetch one neighbour element that is
+// not used; x-moving planes are stored element by element.)
+__device__ constexpr int kPlaneOpp[kNPop] = {0,  3,  4,  1,  2,  7,  8,  5,  6, 9,
+                                             12, 13, 10, 11, 14, 17, 18, 15, 16};
+
+template <int ST, int V, bool LES, int PHASE>
+__global__ __launch_bounds__(kStepThreads) void k_step_aa(typename Codec<ST>::T* __restrict__ lat,
+                                                          Geom geo, Rates rt, int tiles_x) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  using VT = typename Vec<T, V>::type;
+  const int x0 = ((int(blockIdx.x) % tiles_x) * kStepThreads + int(threadIdx.x)) * V;
+  const int y = int(blockIdx.x) / tiles_x;
+  if (x0 >= geo.nx) return;
+  const int xl = x0 == 0 ? geo.nx - 1 : x0 - 1;
+  const int xr = x0 + V == geo.nx ? 0 : x0 + V;
+  const int ym = y == 0 ? geo.ny - 1 : y - 1;
+  const int yp = y == geo.ny - 1 ? 0 : y + 1;
+  // row[c + 1] is the row of y - c
+  const unsigned row[3] = {unsigned(yp) * geo.pitch, unsigned(y) * geo.pitch,
+                           unsigned(ym) * geo.pitch};
+  const long long P = geo.plane;
+  float v[kNPop][V];
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) {
+    if (PHASE == 1) {
+      const VT a = ld_plane<VT>(lat + kPlaneOpp[q] * P, row[1] + unsigned(x0));
+      if constexpr (V == 1) {
+        v[q][0] = C::dec(a);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[q][j] = C::dec(a[j]);
+      }
+    } else {
+      const T* __restrict__ base = lat + q * P;
+      const unsigned r = row[kPlaneCy[q] + 1];
+      if (V == 1 || kPlaneCx[q] == 0) {
+        const int xs = kPlaneCx[q] == 0 ? x0 : (kPlaneCx[q] == 1 ? xl : xr);
+        const VT a = ld_plane<VT>(base, r + unsigned(xs));
+        if constexpr (V == 1) {
+          v[q][0] = C::dec(a);
+        } else {
+#pragma unroll
+          for (int j = 0; j < V; ++j) v[q][j] = C::dec(a[j]);
+        }
+      } else if constexpr (V > 1) {
+        const VT a = ld_plane<VT>(base, r + unsigned(x0));
+        const float e = C::dec(ld_plane<T>(base, r + unsigned(kPlaneCx[q] == 1 ? xl : xr)));
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          if (kPlaneCx[q] == 1)
+            v[q][j] = j == 0 ? e : C::dec(a[j > 0 ? j - 1 : 0]);
+          else
+            v[q][j] = j == V - 1 ? e : C::dec(a[j < V - 1 ? j + 1 : 0]);
+        }
+      }
+    }
+  }
+  float out[kNPop][V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    float f[9], g[10];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = v[i][j];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) g[k] = v[9 + k][j];
+    collide<LES ? 1 : 0>(f, g, rt);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i][j] = f[i];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[9 + k][j] = g[k];
+  }
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) {
+    if (PHASE == 1 || kPlaneCx[q] == 0) {
+      // local store (PHASE 1), or the unshifted x of a plane moving along y only
+      T* __restrict__ base = lat + (PHASE == 1 ? q : kPlaneOpp[q]) * P;
+      const unsigned r = PHASE == 1 ? row[1] : row[1 - kPlaneCy[q]];
+      VT w;
+      if constexpr (V == 1) {
+        w = C::enc(out[q][0]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) w[j] = C::enc(out[q][j]);
+      }
+      st_plane_nt<VT>(base, r + unsigned(x0), w);
+    } else {
+      // f*_q(x0 + j) goes to x0 + j + c_x: one element at a time
+      T* __restrict__ base = lat + kPlaneOpp[q] * P;
+      const unsigned r = row[1 - kPlaneCy[q]];
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        int xd = x0 + j + kPlaneCx[q];
+        xd = xd < 0 ? geo.nx - 1 : (xd >= geo.nx ? xd - geo.nx : xd);
+        st_plane_nt<T>(base, r + unsigned(xd), C::enc(out[q][j]));
+      }
+    }
+  }
+}
+
+// Layout R -> N in place: for each plane q of one direction of every
+// opposite pair (the other is opp(q)), swap slot q at x with slot opp(q) at
+// x + c_q.  Each pair of locations belongs to exactly one (x, q), so the
+// swaps are independent.  One workgroup per row.
+template <int ST>
+__global__ __launch_bounds__(256) void k_unswap_aa(typename Codec<ST>::T* __restrict__ lat,
+                                                   Geom geo) {
+  using T = typename Codec<ST>::T;
+  constexpr int kHalf[8] = {1, 2, 5, 6, 10, 11, 15, 16};
+  const int y = int(blockIdx.x);
+  const long long P = geo.plane;
+  for (int x = int(threadIdx.x); x < geo.nx; x += int(blockDim.x)) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int q = kHalf[h];
+      int xd = x + kPlaneCx[q], yd = y + kPlaneCy[q];
+      xd = xd < 0 ? geo.nx - 1 : (xd >= geo.nx ? 0 : xd);
+      yd = yd < 0 ? geo.ny - 1 : (yd >= geo.ny ? 0 : yd);
+      T* a = lat + q * P + (long long)y * geo.pitch + x;
+      T* b = lat + kPlaneOpp[q] * P + (long long)yd * geo.pitch + xd;
+      const T t = *a;
+      *a = *b;
+      *b = t;
+    }
+  }
+}
+
 // ------------------------------------------------------- initialisation etc.
 // f^eq - w and g^eq of Sec. 3 in FP64 at one site.
 __device__ __forceinline__ void equilibrium_dev(double rho, double ux, double uy, double bx,
@@ -837,6 +982,52 @@ hipError_t launch_step(int storage, bool les, const void* src, void* dst, const 
     launch_step_v<LBMHD_FP16, 2>(les, src, dst, g, r, s);
   else
     launch_step_v<LBMHD_FP16, 1>(les, src, dst, g, r, s);
+  return hipGetLastError();
+}
+
+template <int ST, int V, int PHASE>
+void launch_step_aa_v(bool les, void* lat, const Geom& g, const Rates& r, hipStream_t s) {
+  using T = typename Codec<ST>::T;
+  const int tiles_x = (g.nx / V + kStepThreads - 1) / kStepThreads;
+  const dim3 grid(unsigned(tiles_x) * unsigned(g.ny)), block(kStepThreads);
+  auto* a = static_cast<T*>(lat);
+  if (les)
+    hipLaunchKernelGGL((k_step_aa<ST, V, true, PHASE>), grid, block, 0, s, a, g, r, tiles_x);
+  else
+    hipLaunchKernelGGL((k_step_aa<ST, V, false, PHASE>), grid, block, 0, s, a, g, r, tiles_x);
+}
+
+// Both steps keep the widths of k_step: 1 FP32 or 2 FP16 sites per thread
+// (16-byte vectors in the local step measured slower: 0.534 against 0.482
+// ms per FP32 step at 4096^2, the register cost halving the occupancy).
+template <int ST, int V>
+void launch_step_aa_p(bool les, int phase, void* lat, const Geom& g, const Rates& r,
+                      hipStream_t s) {
+  if (phase == 0)
+    launch_step_aa_v<ST, V, 0>(les, lat, g, r, s);
+  else
+    launch_step_aa_v<ST, V, 1>(les, lat, g, r, s);
+}
+
+hipError_t launch_step_aa(int storage, bool les, int phase, void* lat, const Geom& g,
+                          const Rates& r, hipStream_t s) {
+  if (storage == LBMHD_FP32)
+    launch_step_aa_p<LBMHD_FP32, 1>(les, phase, lat, g, r, s);
+  else if (g.nx % 2 == 0)
+    launch_step_aa_p<LBMHD_FP16, 2>(les, phase, lat, g, r, s);
+  else
+    launch_step_aa_p<LBMHD_FP16, 1>(les, phase, lat, g, r, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_unswap_aa(int storage, void* lat, const Geom& g, hipStream_t s) {
+  const unsigned nb = unsigned(g.ny);
+  if (storage == LBMHD_FP32)
+    hipLaunchKernelGGL(k_unswap_aa<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
+                       static_cast<float*>(lat), g);
+  else
+    hipLaunchKernelGGL(k_unswap_aa<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
+                       static_cast<_Float16*>(lat), g);
   return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ class LBMHDConfig:
     viscosity; cs_b: constant C_Sb of the eddy resistivity (None: same as cs);
     delta: filter width.
     storage: "fp32" or "fp16" (deviation from the rest state, FP16 scaled by 2^10).
+    inplace: one lattice updated in place (AA pattern) instead of two; not with
+    the closures that read neighbours (les = 2, 3, 4, 6).
     """
     nx: int
     ny: int
@@ -44,6 +46,7 @@ class LBMHDConfig:
     delta: float = 1.0
     storage: str = "fp32"
     cs_b: float | None = None
+    inplace: bool = False
 
     @property
     def csb(self) -> float:
@@ -52,7 +55,8 @@ class LBMHDConfig:
     def c_params(self) -> C.Params:
         st = {"fp32": C.LBMHD_FP32, "fp16": C.LBMHD_FP16}[self.storage]
         return C.Params(self.nx, self.ny, self.nu, self.eta, self.s5, self.s5, self.s7,
-                        self.s8, int(self.les), self.cs, self.csb, self.delta, st)
+                        self.s8, int(self.les), self.cs, self.csb, self.delta, st,
+                        int(self.inplace))
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
@@ -77,10 +81,13 @@ class Lattice:
          self.adj_lattice_bytes, self.adj_acc_bytes) = (s.value for s in sizes)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._a = torch.empty(self.lattice_bytes, dtype=torch.uint8, device=self.device)
-        self._b = torch.empty(self.lattice_bytes, dtype=torch.uint8, device=self.device)
+        self._b = (None if cfg.inplace else
+                   torch.empty(self.lattice_bytes, dtype=torch.uint8, device=self.device))
         self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
-        C.check(L.lbmhd_bind(h, _ptr(self._a), self.lattice_bytes, _ptr(self._b),
-                             self.lattice_bytes, _ptr(self._ws), self.workspace_bytes,
+        b = ctypes.c_void_p(0) if self._b is None else _ptr(self._b)
+        C.check(L.lbmhd_bind(h, _ptr(self._a), self.lattice_bytes, b,
+                             0 if self._b is None else self.lattice_bytes, _ptr(self._ws),
+                             self.workspace_bytes,
                              ctypes.c_void_p(self.stream.cuda_stream)), "lbmhd_bind", h)
 
     def __del__(self):

@@ -45,7 +45,7 @@ def test_every_declared_function_is_exported(capi):
 
 def _params(capi, **kw):
     base = dict(nx=64, ny=48, nu=0.01, eta=0.02, s5=1.0, s6=1.0, s7=1.1, s8=0.9, les=1,
-                cs=0.1, cs_b=0.1, delta=1.0, storage=capi.LBMHD_FP32)
+                cs=0.1, cs_b=0.1, delta=1.0, storage=capi.LBMHD_FP32, inplace=0)
     base.update(kw)
     return capi.Params(*[base[n] for n, _ in capi.Params._fields_])
 
@@ -59,7 +59,8 @@ def _create(capi, p):
 @pytest.mark.parametrize("bad", [
     dict(nx=1), dict(ny=0), dict(nu=0.0), dict(eta=-1.0), dict(nu=float("nan")),
     dict(s5=2.0), dict(s7=0.0), dict(s8=-0.5), dict(s5=1.1, s6=1.2), dict(les=5), dict(les=7), dict(les=-1),
-    dict(cs=-0.1), dict(cs_b=-0.1), dict(cs_b=float("inf")), dict(delta=0.0), dict(storage=7), dict(nx=70000, ny=70000),
+    dict(cs=-0.1), dict(cs_b=-0.1), dict(cs_b=float("inf")), dict(delta=0.0),
+    dict(inplace=2), dict(inplace=1, les=2), dict(inplace=1, les=4), dict(inplace=1, les=6), dict(storage=7), dict(nx=70000, ny=70000),
 ])
 def test_create_rejects_invalid_parameters(capi, bad):
     rc, h = _create(capi, _params(capi, **bad))
