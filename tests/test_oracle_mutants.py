@@ -5,7 +5,7 @@ wrong weight, a flipped sign, a dropped factor, a transposed inverse, the
 wrong streaming direction, a wrong closure constant, a wrong rate index, a
 wrong root or sign in a closure, a broken dual-number rule), builds it with the same flags into a temporary
 library, and runs the pin suites (tables, physics, kinetic and cross-helicity
-closures) against it in a subprocess.  Every mutant must make at least one pin fail; the
+closures; the 3D suite for the 3D oracle) against it in a subprocess.  Every mutant must make at least one pin fail; the
 unmodified source must pass.  Everything runs on the CPU.
 """
 import os
@@ -17,6 +17,8 @@ import pytest
 from conftest import ROOT
 
 SRC = os.path.join(ROOT, "oracle", "lbmhd_oracle.cpp")
+SRC3 = os.path.join(ROOT, "oracle", "lbmhd3_oracle.cpp")
+PINS3 = [os.path.join(ROOT, "tests", "test_oracle3.py")]
 PINS = [os.path.join(ROOT, "tests", "test_oracle_tables.py"),
         os.path.join(ROOT, "tests", "test_oracle_physics.py"),
         os.path.join(ROOT, "tests", "test_oracle_kinetic.py"),
@@ -87,10 +89,28 @@ MUTANTS = {
 }
 
 
-def _run_pins(lib_path):
-    env = dict(os.environ, LBMHD_ORACLE_LIB=lib_path, OMP_NUM_THREADS="4")
+MUTANTS3 = {
+    "3D lattice weights 2/3, 1/6 -> 1/2, 1/4": ("C27[i][a] == 0 ? 2.0 / 3.0 : 1.0 / 6.0",
+                                               "C27[i][a] == 0 ? 1.0 / 2.0 : 1.0 / 4.0"),
+    "3D Maxwell stress sign": ("(a == b ? 0.5 * b2 : 0.0) - B[a] * B[b];",
+                               "(a == b ? 0.5 * b2 : 0.0) + B[a] * B[b];"),
+    "3D Hermite trace 1/3 -> 1/2": ("(C27[i][a] * C27[i][b] - (a == b ? 1.0 / 3.0 : 0.0))",
+                                    "(C27[i][a] * C27[i][b] - (a == b ? 0.5 : 0.0))"),
+    "3D g^eq induction sign": ("(B[b] + 3.0 * (cu * B[b] - cb * u[b])) / 6.0",
+                               "(B[b] + 3.0 * (cu * B[b] + cb * u[b])) / 6.0"),
+    "3D streaming along z reversed": ("wrap(z + c[2], nz)", "wrap(z - c[2], nz)"),
+    "3D current from the symmetric part": ("L[0][1] - L[1][0]", "L[0][1] + L[1][0]"),
+    "3D closure factor 36 -> 18": ("36.0 * d2 * p.csb * An", "18.0 * d2 * p.csb * An"),
+    "3D eddy viscosity takes C_Sb": ("18.0 * d2 * p.cs * Q / rho", "18.0 * d2 * p.csb * Q / rho"),
+    "3D strain drops the factor 2": ("std::sqrt(2.0 * ss)", "std::sqrt(ss)"),
+}
+
+
+def _run_pins(lib_path, pins=PINS, var="LBMHD_ORACLE_LIB"):
+    env = dict(os.environ, OMP_NUM_THREADS="4")
+    env[var] = lib_path
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                           *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+                           *pins], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
 
 
 def _build(tmp_path, text, name):
@@ -113,4 +133,20 @@ def test_mutant_is_caught(tmp_path, name):
     assert text.count(old) >= 1, f"mutation site not found: {old}"
     lib = _build(tmp_path, text.replace(old, new, 1), "mut")
     r = _run_pins(lib)
+    assert r.returncode != 0, f"mutant '{name}' passed every pin"
+
+
+def test_unmodified_3d_oracle_passes_pins(tmp_path):
+    lib = _build(tmp_path, open(SRC3).read(), "orig3")
+    r = _run_pins(lib, PINS3, "LBMHD3_ORACLE_LIB")
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS3))
+def test_3d_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS3[name]
+    text = open(SRC3).read()
+    assert text.count(old) >= 1, f"mutation site not found: {old}"
+    lib = _build(tmp_path, text.replace(old, new, 1), "mut3")
+    r = _run_pins(lib, PINS3, "LBMHD3_ORACLE_LIB")
     assert r.returncode != 0, f"mutant '{name}' passed every pin"
