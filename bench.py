@@ -147,6 +147,25 @@ def inplace_leg(torch, args):
     return dict(per_launch=per_launch, sites=n * n, nonfinite=d["nonfinite"], lattice_bytes=mem)
 
 
+def threed_leg(torch, args):
+    """The 3D update (D3Q27 + six magnetic vectors, Smagorinsky-MHD closure)
+    on a 256^3 Orszag-Tang-type vortex, FP32: 45 populations, 360 B per
+    site-step."""
+    from lbmhd_inputs import orszag_tang_3d
+    from paper_1607_08675_amd.lattice3 import Lattice3, LBMHD3Config
+    n = 256
+    lat = Lattice3(LBMHD3Config(nx=n, ny=n, nz=n, nu=1e-5, eta=1e-5, les=1, cs=0.1))
+    lat.init_fields(*orszag_tang_3d(n, n, n))
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    per_launch = burst_ms_per_launch(torch, lat, 100)
+    d = lat.diag()
+    log(f"3D 256^3 FP32: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
+    del lat
+    torch.cuda.empty_cache()
+    return dict(per_launch=per_launch, sites=n ** 3, nonfinite=d["nonfinite"])
+
+
 CLOSURES = {2: "kinetic closure", 4: "cross-helicity closure"}
 
 
@@ -322,7 +341,7 @@ def main():
     ap.add_argument("--fit-iters", type=int, default=20)
     ap.add_argument("--fit-ref-steps", type=int, default=5000)
     ap.add_argument("--skip", default="",
-                    help="comma list of legs to skip: kinetic,crosshelicity,inplace,fp16,adjoint,fit,cpu")
+                    help="comma list of legs to skip: kinetic,crosshelicity,inplace,3d,fp16,adjoint,fit,cpu")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -340,6 +359,7 @@ def main():
     rkin = None if "kinetic" in skip else closure_leg(torch, args, 2)
     rch = None if "crosshelicity" in skip else closure_leg(torch, args, 4)
     rin = None if "inplace" in skip else inplace_leg(torch, args)
+    r3 = None if "3d" in skip else threed_leg(torch, args)
     r16 = None if "fp16" in skip else fp16_leg(torch, args)
     radj = None if "adjoint" in skip else adjoint_leg(torch, args)
     rfit = None if "fit" in skip else fit_leg(torch, args)
@@ -386,6 +406,16 @@ def main():
                           "full-size sampled sites)",
         },
     }
+    if r3:
+        m3 = r3["sites"] / (r3["per_launch"] * 1e-3) / 1e6
+        a3 = 360 * r3["sites"] / (r3["per_launch"] * 1e-3) / 1e9
+        line["three_d"] = {
+            "workload": "3D Orszag-Tang-type vortex 256^3, FP32, D3Q27 + 6 magnetic vectors, "
+                        "LES C_S=0.1, nu=eta=1e-5",
+            "mlups": round(m3, 1), "ms_per_step": round(r3["per_launch"], 5),
+            "achieved_gbs": round(a3, 1), "frac": round(a3 / HBM_PEAK_GBS, 4),
+            "bytes_per_site": 360, "nonfinite": r3["nonfinite"],
+        }
     if rin:
         mi = rin["sites"] / (rin["per_launch"] * 1e-3) / 1e6
         ai = FP32_BYTES_PER_SITE * rin["sites"] / (rin["per_launch"] * 1e-3) / 1e9

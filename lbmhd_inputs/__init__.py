@@ -116,3 +116,21 @@ def directions(ndir: int, nx: int, ny: int, seed0: int, rms_u: float, rms_b: flo
         d[k, 2], d[k, 3] = solenoidal(nx, ny, 2 * s + 1, rms_b, kmax=min(64, nx // 2 - 1))
         dcs[k] = cs_scale * np.random.default_rng(s).standard_normal()
     return d, dcs
+
+
+def orszag_tang_3d(nx: int, ny: int, nz: int, u0: float = 0.05, b0: float = 0.05):
+    """A 3D Orszag-Tang-type vortex on the nodes of [0, 2 pi)^3, arrays [z][y][x]:
+    rho = 1, u = u0 (-sin y + 0.2 sin z, sin x + 0.2 sin z, 0.2 (sin x + sin y)),
+    B = b0 (-sin y + 0.5 sin z, sin 2x + 0.5 sin z, 0.5 (sin x + sin y)).
+    Each component is independent of its own coordinate, so the centred
+    discrete divergence of u and of B is exactly zero."""
+    z, y, x = np.meshgrid(2 * np.pi * np.arange(nz) / nz, 2 * np.pi * np.arange(ny) / ny,
+                          2 * np.pi * np.arange(nx) / nx, indexing="ij")
+    rho = np.ones_like(x)
+    ux = u0 * (-np.sin(y) + 0.2 * np.sin(z))
+    uy = u0 * (np.sin(x) + 0.2 * np.sin(z))
+    uz = u0 * 0.2 * (np.sin(x) + np.sin(y))
+    bx = b0 * (-np.sin(y) + 0.5 * np.sin(z))
+    by = b0 * (np.sin(2 * x) + 0.5 * np.sin(z))
+    bz = b0 * 0.5 * (np.sin(x) + np.sin(y))
+    return rho, ux, uy, uz, bx, by, bz

@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in ``include/lbmhd.h`` (argument marshalling only).
+"""ctypes declarations of the C ABI in ``include/lbmhd.h`` and ``include/lbmhd3.h``
+(argument marshalling only).
 
 ``torch`` is imported first so that the library resolves its HIP runtime to the
 one torch already loaded: device pointers and streams then belong to a single
@@ -32,6 +33,12 @@ EXPORTS = (
     "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_seed_mismatch", "lbmhd_adj_step",
     "lbmhd_adj_acc_total", "lbmhd_adj_fields",
 )
+# Every function declared in include/lbmhd3.h.
+EXPORTS3 = (
+    "lbmhd3_create", "lbmhd3_destroy", "lbmhd3_sizes", "lbmhd3_bind", "lbmhd3_init_fields",
+    "lbmhd3_step", "lbmhd3_macro", "lbmhd3_diag", "lbmhd3_get_populations",
+    "lbmhd3_set_populations", "lbmhd3_last_error",
+)
 
 
 class Params(ctypes.Structure):
@@ -44,6 +51,23 @@ class Params(ctypes.Structure):
         ("cs", ctypes.c_double), ("cs_b", ctypes.c_double), ("delta", ctypes.c_double),
         ("storage", ctypes.c_int32), ("inplace", ctypes.c_int32),
     ]
+
+
+class Params3(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("les", ctypes.c_int32),
+        ("cs", ctypes.c_double), ("cs_b", ctypes.c_double), ("delta", ctypes.c_double),
+    ]
+
+
+class Diag3(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "mass", "mom_x", "mom_y", "mom_z", "flux_x", "flux_y", "flux_z", "e_kin", "e_mag",
+        "max_abs_divB", "max_u")] + [("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Diag(ctypes.Structure):
@@ -80,6 +104,8 @@ def lib():
         L.lbmhd_strerror.restype = ctypes.c_char_p
         L.lbmhd_last_error.argtypes = [vp]
         L.lbmhd_last_error.restype = ctypes.c_char_p
+        L.lbmhd3_last_error.argtypes = [vp]
+        L.lbmhd3_last_error.restype = ctypes.c_char_p
         sig = {
             "lbmhd_create": [P(Params), P(vp)],
             "lbmhd_destroy": [vp],
@@ -103,6 +129,16 @@ def lib():
             "lbmhd_adj_step": [vp, vp, vp, vp, vp],
             "lbmhd_adj_acc_total": [vp, vp, P(ctypes.c_double)],
             "lbmhd_adj_fields": [vp] * 11,
+            "lbmhd3_create": [P(Params3), P(vp)],
+            "lbmhd3_destroy": [vp],
+            "lbmhd3_sizes": [vp, P(sz), P(sz)],
+            "lbmhd3_bind": [vp, vp, sz, vp, sz, vp, sz, vp],
+            "lbmhd3_init_fields": [vp] * 8,
+            "lbmhd3_step": [vp, i64],
+            "lbmhd3_macro": [vp] * 4,
+            "lbmhd3_diag": [vp, P(Diag3)],
+            "lbmhd3_get_populations": [vp, vp],
+            "lbmhd3_set_populations": [vp, vp, i64],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -116,7 +152,8 @@ def strerror(code: int) -> str:
     return lib().lbmhd_strerror(code).decode()
 
 
-def check(rc: int, what: str, handle=None):
+def check(rc: int, what: str, handle=None, last_error=None):
     if rc != LBMHD_OK:
-        detail = lib().lbmhd_last_error(handle).decode() if handle else ""
+        fn = last_error or lib().lbmhd_last_error
+        detail = fn(handle).decode() if handle else ""
         raise LbmhdError(rc, what, detail)

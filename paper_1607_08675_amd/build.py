@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbmhd.so")
-SOURCES = ["lbmhd_kernels.hip", "lbmhd_adjoint.hip", "lbmhd_capi.hip"]
+SOURCES = ["lbmhd_kernels.hip", "lbmhd_adjoint.hip", "lbmhd_capi.hip", "lbmhd3.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

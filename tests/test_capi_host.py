@@ -23,19 +23,19 @@ def capi():
     return _capi
 
 
-def _header_functions():
-    text = open(os.path.join(ROOT, "include", "lbmhd.h")).read()
+def _header_functions(name="lbmhd.h", prefix="lbmhd_"):
+    text = open(os.path.join(ROOT, "include", name)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbmhd_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_0-9]+)\s*\(", text)))
 
 
 def test_every_declared_function_is_exported(capi):
-    declared = _header_functions()
-    assert len(declared) >= 20
-    assert set(declared) == set(capi.EXPORTS)
+    declared = _header_functions() + _header_functions("lbmhd3.h", "lbmhd3_")
+    assert len(declared) >= 30
+    assert set(declared) == set(capi.EXPORTS) | set(capi.EXPORTS3)
     out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], check=True,
                          capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\bT (lbmhd_\w+)", out))
+    exported = set(re.findall(r"\bT (lbmhd3?_\w+)", out))
     missing = set(declared) - exported
     assert not missing, missing
     L = capi.lib()
@@ -111,3 +111,32 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no non-GPU fallback"):
         _capi.lib()
+
+
+def _params3(capi, **kw):
+    base = dict(nx=16, ny=8, nz=4, nu=0.01, eta=0.02, les=1, cs=0.1, cs_b=0.1, delta=1.0)
+    base.update(kw)
+    return capi.Params3(*[base[n] for n, _ in capi.Params3._fields_])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(nz=0), dict(nu=0.0), dict(eta=float("nan")), dict(les=2), dict(cs=-1.0),
+    dict(cs_b=-1.0), dict(delta=0.0), dict(nx=1 << 14, ny=1 << 14, nz=8),
+])
+def test_3d_create_rejects_invalid_parameters(capi, bad):
+    h = ctypes.c_void_p()
+    rc = capi.lib().lbmhd3_create(ctypes.byref(_params3(capi, **bad)), ctypes.byref(h))
+    assert rc == capi.LBMHD_ERR_INVALID_ARG and not h.value
+
+
+def test_3d_sizes_and_unbound_calls(capi):
+    L = capi.lib()
+    h = ctypes.c_void_p()
+    assert L.lbmhd3_create(ctypes.byref(_params3(capi, nx=100, ny=6, nz=5)), ctypes.byref(h)) == 0
+    lat, ws = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.lbmhd3_sizes(h, ctypes.byref(lat), ctypes.byref(ws)) == 0
+    assert lat.value == 45 * 5 * 6 * 128 * 4      # rows padded to 256 bytes
+    assert ws.value >= 7 * 100 * 6 * 5 * 8 and ws.value % 256 == 0
+    assert L.lbmhd3_step(h, 1) == capi.LBMHD_ERR_NOT_BOUND
+    assert b"bind" in L.lbmhd3_last_error(h)
+    assert L.lbmhd3_destroy(h) == 0 and L.lbmhd3_destroy(None) == 0
