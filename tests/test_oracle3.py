@@ -167,26 +167,41 @@ def test_transport_coefficients_along_z(o3):
     assert abs(r / (p.eta * k * k) - 1) < 2e-3, r / (p.eta * k * k)
 
 
-def test_closure_matches_resolved_strain_and_current(o3):
-    """u_x = U sin(k z): tau = tau0 + 3 C_Sv |d u_x / d z|.  B = B0 (sin k y,
-    sin k x, 0) has both d_x B_y and d_y B_x: tau_m = tau_m0 + 3 C_Sb |j| with
-    j_z = d_x B_y - d_y B_x (eqs. SmagorinskyClosure, SmagorinskyMHDClosureB)."""
-    n, U, cs, csb = 64, 0.01, 0.1, 0.2
+def _d(a, axis):
+    return 0.5 * (np.roll(a, -1, axis) - np.roll(a, 1, axis))
+
+
+def test_closure_matches_resolved_strain(o3):
+    """u_x = U sin(k z): tau = tau0 + 3 C_Sv |d u_x / d z| (eq. SmagorinskyClosure)."""
+    n, U, cs = 64, 0.01, 0.1
     k = 2 * np.pi / n
-    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
-    zero = np.zeros(xx.shape)
-    p = o3.Params(n, n, n, nu=0.01, eta=0.01, les=1, cs=cs, csb=csb)
-    st = o3.run(p, o3.init(p, 1.0, U * np.sin(k * zz), zero, zero, U * np.sin(k * yy),
-                           U * np.sin(k * xx), zero), 60)
-    m = o3.macro(p, st)
-    def d(a, axis):
-        return 0.5 * (np.roll(a, -1, axis) - np.roll(a, 1, axis))
-    dudz = d(m["ux"], 0)
-    jz = d(m["by"], 2) - d(m["bx"], 1)
-    _, tau, taum = o3.collide(p, st, return_tau=True)
+    z = np.arange(n)[:, None, None] * np.ones((1, 2, 2))
+    zero = np.zeros_like(z)
+    p = o3.Params(2, 2, n, nu=0.01, eta=0.01, les=1, cs=cs, csb=0.2)
+    st = o3.run(p, o3.init(p, 1.0, U * np.sin(k * z), zero, zero, zero, zero, zero), 60)
+    dudz = _d(o3.macro(p, st)["ux"], 0)
+    _, tau, _ = o3.collide(p, st, return_tau=True)
     sel = np.abs(dudz) > 0.3 * np.abs(dudz).max()
     rel = np.abs(tau - 3 * p.nu - 0.5 - 3 * cs * np.abs(dudz))[sel] / (3 * cs * np.abs(dudz[sel]))
     assert rel.max() < 0.03, rel.max()
+
+
+def test_closure_matches_resolved_current(o3):
+    """B = B0 (sin k y, sin k x, 0) has both d_x B_y and d_y B_x: tau_m =
+    tau_m0 + 3 C_Sb |j| with j_z = d_x B_y - d_y B_x (eq.
+    SmagorinskyMHDClosureB); a symmetric-part mix-up would give |d_x B_y +
+    d_y B_x| instead."""
+    n, B0, csb = 64, 0.01, 0.2
+    k = 2 * np.pi / n
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    y, x = np.broadcast_to(y, (2, n, n)), np.broadcast_to(x, (2, n, n))
+    zero = np.zeros((2, n, n))
+    p = o3.Params(n, n, 2, nu=0.01, eta=0.01, les=1, cs=0.1, csb=csb)
+    st = o3.run(p, o3.init(p, 1.0, zero, zero, zero, B0 * np.sin(k * y), B0 * np.sin(k * x), zero),
+                60)
+    m = o3.macro(p, st)
+    jz = _d(m["by"], 2) - _d(m["bx"], 1)
+    _, _, taum = o3.collide(p, st, return_tau=True)
     sel = np.abs(jz) > 0.3 * np.abs(jz).max()
     rel = np.abs(taum - 3 * p.eta - 0.5 - 3 * csb * np.abs(jz))[sel] / (3 * csb * np.abs(jz[sel]))
     assert rel.max() < 0.03, rel.max()
