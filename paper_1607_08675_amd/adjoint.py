@@ -4,9 +4,11 @@
 ``nsteps`` steps from equilibrium at (rho = 1, u0, B0) and returns
 J = sum |rho u|^2 / (2 rho) + |B|^2 / 2 of the final state (FP64).  Its backward
 pass is the discrete adjoint: checkpoints of the encoded lattice are kept every
-``every`` steps during the forward run; the backward sweep restores each
-segment from its checkpoint, recomputes that segment's states straight into
-stored buffers (one step kernel per state, no copies), and walks them in reverse with ``lbmhd_adj_step``.  The result holds the exact
+``every`` steps during the forward run (every state when they fit in device
+memory); the backward sweep restores each segment from its checkpoint,
+recomputes that segment's states straight into stored buffers (one step kernel
+per state, no copies), and walks them in reverse with ``lbmhd_adj_step``.  The
+result holds the exact
 derivative of the FP32 update map (storage rounding counted as the identity)
 with respect to the initial fields and the closure constants: ``cs`` is a
 scalar (C_Sv = C_Sb = cs) or a pair (C_Sv, C_Sb), and its gradient has the
@@ -19,16 +21,56 @@ import torch
 from .lattice import LBMHDConfig, Lattice
 
 
+def states_needed(nsteps: int, every: int) -> int:
+    """Lattice-sized buffers a run of nsteps with checkpoints every `every`
+    steps holds at once: every state when every == 1; otherwise the
+    checkpoints, the final state and the every - 1 recomputed states of one
+    segment."""
+    if every == 1:
+        return nsteps + 1
+    return -(-nsteps // every) + 1 + (every - 1)
+
+
+def choose_interval(nsteps: int, state_bytes: int, budget_bytes: int) -> int:
+    """The smallest checkpoint interval whose buffers fit the budget (1 keeps
+    every state and makes the backward sweep recompute nothing)."""
+    fit = budget_bytes // max(state_bytes, 1)
+    for k in range(1, max(nsteps, 1) + 1):
+        if states_needed(nsteps, k) <= fit:
+            return k
+    raise MemoryError("not even one checkpoint segment fits the memory budget")
+
+
 class Checkpointed:
     """Forward run with checkpoints every ``every`` steps and the matching
-    reverse sweep (the C ABI does the arithmetic; this class only orders calls)."""
+    reverse sweep (the C ABI does the arithmetic; this class only orders calls).
 
-    def __init__(self, lat: Lattice, every: int = 100):
-        if every < 1:
-            raise ValueError("checkpoint interval must be >= 1")
+    every = "auto" picks the smallest interval whose state buffers fit
+    ``budget_bytes`` (default: 70% of the device memory free when the forward
+    run starts).  With interval 1 every state is kept: the forward steps write
+    straight into the stored buffers and the backward sweep recomputes
+    nothing, which is the case whenever the run fits in HBM (2000 steps of a
+    1024^2 FP32 lattice take 160 GB)."""
+
+    def __init__(self, lat: Lattice, every=100, budget_bytes: int | None = None):
+        if every != "auto" and (not isinstance(every, int) or every < 1):
+            raise ValueError("checkpoint interval must be >= 1 or 'auto'")
         self.lat = lat
         self.every = every
+        self.budget_bytes = budget_bytes
+        self.interval = None
         self.ckpts: list[torch.Tensor] = []
+
+    def _interval(self, nsteps: int) -> int:
+        if self.every != "auto":
+            return self.every
+        budget = self.budget_bytes
+        if budget is None:
+            free, _ = torch.cuda.mem_get_info(self.lat.device)
+            cached = (torch.cuda.memory_reserved(self.lat.device)
+                      - torch.cuda.memory_allocated(self.lat.device))
+            budget = int(0.7 * (free + cached))
+        return choose_interval(nsteps, self.lat.lattice_bytes, budget)
 
     def forward(self, fields, nsteps: int, targets=None) -> float:
         """Run nsteps from equilibrium at `fields` (rho, ux, uy, bx, by) keeping
@@ -39,15 +81,37 @@ class Checkpointed:
         lat.init_fields(*fields)
         self.fields = fields
         self.nsteps = nsteps
-        self.ckpts = []
-        done = 0
-        while done < nsteps:
-            self.ckpts.append(lat.save_state())
-            k = min(self.every, nsteps - done)
-            lat.step(k)
-            done += k
-        self.final = lat.save_state()
-        return lat.energy() if targets is None else lat.mismatch(targets)
+        self.ckpts, self.final = [], None
+        k = self._interval(nsteps)
+        store = None
+        if k == 1:
+            try:
+                store = torch.empty(nsteps + 1, lat.lattice_bytes, dtype=torch.uint8,
+                                    device=lat.device)
+            except torch.OutOfMemoryError:
+                # the free memory was not in one piece: fall back to checkpoints
+                # within half of what every state would have taken
+                k = choose_interval(nsteps, lat.lattice_bytes,
+                                    (nsteps + 1) * lat.lattice_bytes // 2)
+        self.interval = k
+        if k == 1:
+            # every state kept, in one allocation: each step reads one stored
+            # state and writes the next; the lattice ends on the final state
+            self.ckpts = list(store.unbind(0))
+            lat.save_state(self.ckpts[0])
+            for t in range(nsteps):
+                lat.step_between(self.ckpts[t], self.ckpts[t + 1])
+            self.final = self.ckpts[-1]
+            lat.load_state(self.final, lat.step_count + nsteps)
+        else:
+            done = 0
+            while done < nsteps:
+                self.ckpts.append(lat.save_state())
+                step = min(k, nsteps - done)
+                lat.step(step)
+                done += step
+            self.final = lat.save_state()
+        return lat.energy(self.final) if targets is None else lat.mismatch(targets, self.final)
 
     def backward(self, scale: float = 1.0):
         """Returns scale * (dJ/du_x, dJ/du_y, dJ/dB_x, dJ/dB_y, dJ/dC_Sv, dJ/dC_Sb)
@@ -62,16 +126,22 @@ class Checkpointed:
             lat.adj_seed_energy(self.final, lam)
         else:
             lat.adj_seed_mismatch(self.final, self.targets, scale, lam)
-        seg_states = [lat.new_state_buffer() for _ in range(self.every - 1)]
-        for s in reversed(range(len(self.ckpts))):
-            start = s * self.every
-            k = min(self.every, self.nsteps - start)
-            states = [self.ckpts[s]] + seg_states[: k - 1]
-            for j in range(k - 1):
-                lat.step_between(states[j], states[j + 1])
-            for j in reversed(range(k)):
-                lat.adj_step(states[j], lam, lam2, acc)
+        k = self.interval
+        if k == 1:
+            for j in reversed(range(self.nsteps)):
+                lat.adj_step(self.ckpts[j], lam, lam2, acc)
                 lam, lam2 = lam2, lam
+        else:
+            seg_states = [lat.new_state_buffer() for _ in range(k - 1)]
+            for s in reversed(range(len(self.ckpts))):
+                start = s * k
+                n = min(k, self.nsteps - start)
+                states = [self.ckpts[s]] + seg_states[: n - 1]
+                for j in range(n - 1):
+                    lat.step_between(states[j], states[j + 1])
+                for j in reversed(range(n)):
+                    lat.adj_step(states[j], lam, lam2, acc)
+                    lam, lam2 = lam2, lam
         g = lat.adj_fields(lam, self.fields)
         return (*g, *lat.adj_acc_total(acc))
 

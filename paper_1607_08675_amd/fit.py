@@ -46,7 +46,7 @@ class FitResult:
 
 
 def fit_cs(coarse_fields, targets, cfg: LBMHDConfig, steps: int, iters: int = 20,
-           every: int = 100, step0: float = 0.5, joint: bool = False, log=None) -> FitResult:
+           every="auto", step0: float = 0.5, joint: bool = False, log=None) -> FitResult:
     """Minimise the relative mismatch over the closure constants, starting from
     cfg.cs (and cfg.cs_b).  joint=False fits one constant C_Sv = C_Sb; joint=True
     fits C_Sv and C_Sb together, each with its own sign-based step on its log."""

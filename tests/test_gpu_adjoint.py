@@ -222,3 +222,43 @@ def test_adjoint_step_full_size_patches(lb, orc, storage, n, nu, gen):
         want = float(np.sum(a * Jc[0]))
         got = sum(L.adj_acc_total(acc))   # C_Sv = C_Sb: the tied derivative
         assert abs(got - want) <= 2e-4 * abs(want) + 1e-5 * np.sqrt(np.sum(a * a)), ((cx, cy), got, want)
+
+
+@pytest.mark.parametrize("target", [False, True])
+def test_stored_states_match_checkpointed_sweep(lb, target):
+    """Keeping every state (interval 1, no recompute) and recomputing each
+    segment from checkpoints (interval 16, ragged last segment) walk the same
+    FP32 states, so the gradients agree bit for bit; "auto" under a budget of
+    twenty states (interval 3) picks the smallest interval that fits and
+    agrees too."""
+    from paper_1607_08675_amd.adjoint import Checkpointed, choose_interval
+    nx, ny, steps = 40, 36, 50
+    cfg = lb.LBMHDConfig(nx=nx, ny=ny, nu=0.004, eta=0.004, les=True, cs=0.12, cs_b=0.08)
+    fields = perturbed_orszag_tang(nx, ny, u0=0.08, b0=0.08)
+    tg = None
+    if target:
+        tg = tuple(0.9 * np.asarray(f) for f in fields[1:])
+    outs, finals = [], []
+    for every, budget in ((1, None), (16, None), ("auto", None), ("auto", 20)):
+        lat = lb.Lattice(cfg)
+        run = Checkpointed(lat, every,
+                           budget_bytes=None if budget is None else budget * lat.lattice_bytes)
+        J = run.forward(fields, steps, targets=tg)
+        assert lat.step_count == steps
+        g = run.backward()
+        torch.cuda.synchronize()
+        outs.append((J, [x.cpu().numpy() if torch.is_tensor(x) else x for x in g]))
+        finals.append(lat.populations().cpu().numpy())
+        if every == "auto":
+            want = 1 if budget is None else choose_interval(steps, lat.lattice_bytes,
+                                                            budget * lat.lattice_bytes)
+            assert run.interval == want
+            assert want == (1 if budget is None else 3)
+    assert outs[2][0] == outs[0][0]
+    assert outs[3][0] == outs[0][0]
+    for J, g in outs[1:]:
+        assert J == outs[0][0]
+        for a, b in zip(g, outs[0][1]):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+    for f in finals[1:]:
+        assert np.array_equal(f, finals[0])
