@@ -233,16 +233,20 @@ int lbmhd_energy(lbmhd_t* h, const void* state, double* J);
  * Adjoint (reverse mode) of the step.  The step maps an encoded lattice x_n
  * to x_{n+1} = C(S(x_n)) (S: periodic gather, C: per-site collision with
  * the closure).  Adjoint lattices are FP32, adj_lattice bytes, 19 planes in
- * the same padded layout as an FP32 state; they hold dJ/d(population).
- * Storage rounding is treated as the identity (its derivative is zero
- * almost everywhere).
+ * the same padded layout as an FP32 state; they hold dJ/d(population) in
+ * streamed position: plane i at site x + c_i (periodic; the D2Q5 planes of
+ * vector k at x + C_k) holds dJ/dx_i(x), the sensitivity to population i of
+ * site x kept where that population arrives in the next streaming.  With
+ * this placement the reverse step gathers and stores aligned.  Storage
+ * rounding is treated as the identity (its derivative is zero almost
+ * everywhere).
  * ------------------------------------------------------------------- */
 
-/* lam = dJ/dx for the total energy J of `state` (see lbmhd_energy):
- * dJ/df_i = c_i . u - |u|^2 / 2, dJ/dg_k = B.  Asynchronous. */
+/* lam = dJ/dx (streamed position) for the total energy J of `state` (see
+ * lbmhd_energy): dJ/df_i = c_i . u - |u|^2 / 2, dJ/dg_k = B.  Asynchronous. */
 int lbmhd_adj_seed_energy(lbmhd_t* h, const void* state, float* lam);
 
-/* lam = scale * dL/dx for the mismatch L of lbmhd_mismatch evaluated on
+/* lam = scale * dL/dx (streamed position) for the mismatch L of lbmhd_mismatch evaluated on
  * `state`: dL/df_i = 2 (u - u_t) . (c_i - u) / rho, dL/dg_k = 2 (B - B_t).
  * Asynchronous. */
 int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
@@ -253,8 +257,8 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
  * cross-helicity closure (les = 2, 3, 4, 6) lbmhd_adj_step returns
  * LBMHD_ERR_UNSUPPORTED. */
 
-/* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next, where state_n is
- * the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc
+/* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next (both in streamed
+ * position), where state_n is the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc
  * bytes, FP64) holds two arrays of slots, one slot per thread block in each:
  * the first gains lam_next . d x_{n+1} / d C_Sv, the second
  * lam_next . d x_{n+1} / d C_Sb.  Slots are only ever added to, so zero acc
@@ -267,7 +271,7 @@ int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float
  * in FP64.  Synchronises. */
 int lbmhd_adj_acc_total(lbmhd_t* h, const double* acc, double* out);
 
-/* Pull an adjoint lattice back through the initial equilibria: with
+/* Pull an adjoint lattice (streamed position) back through the initial equilibria: with
  * x_0 = encode(f^eq(rho0, u0, B0), g^eq(u0, B0)), write
  * dJ/du_x, dJ/du_y, dJ/dB_x, dJ/dB_y (device fields) from lam0 and the
  * initial fields (device fields).  Asynchronous. */

@@ -4,11 +4,16 @@
 // The forward step is x_{n+1}(x) = C(pre(x)), pre_i(x) = x_n,i(x - c_i): a
 // periodic gather S followed by the per-site collision C (moment-space MRT
 // for f, single-rate relaxation for g, Smagorinsky-MHD relaxation times).
-// Its transpose is lam_n = S^T J_C(pre)^T lam_{n+1}: every site recomputes
-// the collision from the gathered x_n, applies the hand-derived transposed
-// Jacobian to its own lam_{n+1}, and scatters component i back to x - c_i.
-// The scatter writes each (site, population) exactly once, so no atomics are
-// needed.  The derivatives with respect to the closure constants C_Sv (eddy
+// Its transpose is lam_n = S^T J_C(pre)^T lam_{n+1}.  Adjoint lattices are
+// kept in streamed position: plane i at site x + c_i holds dJ/dx_i(x), the
+// sensitivity of population i stored where that population arrives after
+// the next streaming (nu = S lam, nu_i(y) = lam_i(y - c_i)).  The reverse step
+// then is nu_n = J_C(pre)^T S^T nu_{n+1}: every site recomputes the collision
+// from the gathered x_n, gathers its own lam_{n+1,i}(x) = nu_{n+1,i}(x + c_i),
+// applies the hand-derived transposed Jacobian and stores nu_n at x.  All
+// shifted accesses are loads; every store is aligned (a scatter of shifted
+// stores leaves partial cache lines at tile edges and measured 15% slower).
+// The derivatives with respect to the closure constants C_Sv (eddy
 // viscosity) and C_Sb (eddy resistivity) are accumulated per thread block in
 // FP64, each into a slot owned by that block.
 //
@@ -239,15 +244,16 @@ __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
     const int xp = x == geo.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? geo.ny - 1 : y - 1;
     const int yp = y == geo.ny - 1 ? 0 : y + 1;
-    // offsets of x - c_i in the state layout and in the adjoint layout
+    // offsets of x - c_i in the state layout and of x + c_i in the adjoint
+    // layout
     const unsigned r0 = unsigned(y) * geo.pitch, rm = unsigned(ym) * geo.pitch,
                    rp = unsigned(yp) * geo.pitch;
     const unsigned o[9] = {r0 + x,  r0 + xm, rm + x,  r0 + xp, rp + x,
                            rm + xm, rm + xp, rp + xp, rp + xm};
     const unsigned a0 = unsigned(y) * ga.pitch, am = unsigned(ym) * ga.pitch,
                    ap = unsigned(yp) * ga.pitch;
-    const unsigned oa[9] = {a0 + x,  a0 + xm, am + x,  a0 + xp, ap + x,
-                            am + xm, am + xp, ap + xp, ap + xm};
+    const unsigned on[9] = {a0 + x,  a0 + xp, ap + x,  a0 + xm, am + x,
+                            ap + xp, ap + xm, am + xm, am + xp};
     const long long P = geo.plane, PA = ga.plane;
     float f[9], g[10], lf[9], lg[10];
 #pragma unroll
@@ -257,19 +263,19 @@ __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
       g[k] = D::dec(ld_plane(st + (9 + k) * P, o[k]));
       g[5 + k] = D::dec(ld_plane(st + (14 + k) * P, o[k]));
     }
-    const unsigned oc = a0 + x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam_next + i * PA, oc);
-#pragma unroll
-    for (int q = 0; q < 10; ++q) lg[q] = ld_plane(lam_next + (9 + q) * PA, oc);
-    dcs = collide_adjoint<LES>(f, g, lf, lg, rt, ac);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) st_plane_nt(lam_prev + i * PA, oa[i], lf[i]);
+    for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam_next + i * PA, on[i]);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      st_plane_nt(lam_prev + (9 + k) * PA, oa[k], lg[k]);
-      st_plane_nt(lam_prev + (14 + k) * PA, oa[k], lg[5 + k]);
+      lg[k] = ld_plane(lam_next + (9 + k) * PA, on[k]);
+      lg[5 + k] = ld_plane(lam_next + (14 + k) * PA, on[k]);
     }
+    dcs = collide_adjoint<LES>(f, g, lf, lg, rt, ac);
+    const unsigned oc = a0 + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st_plane_nt(lam_prev + i * PA, oc, lf[i]);
+#pragma unroll
+    for (int q = 0; q < 10; ++q) st_plane_nt(lam_prev + (9 + q) * PA, oc, lg[q]);
   }
   if (LES) {
     // acc[b] gains the block's dJ/dC_Sv, acc[gridDim.x + b] its dJ/dC_Sb
@@ -291,6 +297,26 @@ __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
   }
 }
 
+// Offsets of x + c_i (i = 0..8, D2Q9 order; the five D2Q5 vectors are the
+// first five) in the adjoint layout: where the adjoint of population i at x
+// is kept.
+__device__ __forceinline__ void streamed_offsets(const Geom& ga, int x, int y, unsigned (&on)[9]) {
+  const int xm = x == 0 ? ga.nx - 1 : x - 1;
+  const int xp = x == ga.nx - 1 ? 0 : x + 1;
+  const unsigned a0 = unsigned(y) * ga.pitch,
+                 am = unsigned(y == 0 ? ga.ny - 1 : y - 1) * ga.pitch,
+                 ap = unsigned(y == ga.ny - 1 ? 0 : y + 1) * ga.pitch;
+  on[0] = a0 + x;
+  on[1] = a0 + xp;
+  on[2] = ap + x;
+  on[3] = a0 + xm;
+  on[4] = am + x;
+  on[5] = ap + xp;
+  on[6] = ap + xm;
+  on[7] = am + xm;
+  on[8] = am + xp;
+}
+
 // lam = dJ/dx for J = sum |rho u|^2 / (2 rho) + |B|^2 / 2:
 // dJ/df_i = c_i . u - |u|^2 / 2, dJ/dg = B.
 template <int ST>
@@ -301,7 +327,7 @@ __global__ void k_adj_seed(const typename Dec<ST>::T* __restrict__ st, float* __
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int y = int(s / geo.nx), x = int(s % geo.nx);
-  const long long o = (long long)y * geo.pitch + x, oa = (long long)y * ga.pitch + x;
+  const long long o = (long long)y * geo.pitch + x;
   double v[kNPop];
 #pragma unroll
   for (int q = 0; q < kNPop; ++q) v[q] = double(D::dec(st[q * geo.plane + o]));
@@ -318,12 +344,14 @@ __global__ void k_adj_seed(const typename Dec<ST>::T* __restrict__ st, float* __
     by += v[14 + k];
   }
   const double rho = 1.0 + dr, ux = jx / rho, uy = jy / rho, h = 0.5 * (ux * ux + uy * uy);
+  unsigned on[9];
+  streamed_offsets(ga, x, y, on);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) lam[i * ga.plane + oa] = float(kCx[i] * ux + kCy[i] * uy - h);
+  for (int i = 0; i < 9; ++i) lam[i * ga.plane + on[i]] = float(kCx[i] * ux + kCy[i] * uy - h);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    lam[(9 + k) * ga.plane + oa] = float(bx);
-    lam[(14 + k) * ga.plane + oa] = float(by);
+    lam[(9 + k) * ga.plane + on[k]] = float(bx);
+    lam[(14 + k) * ga.plane + on[k]] = float(by);
   }
 }
 
@@ -341,7 +369,7 @@ __global__ void k_adj_seed_mismatch(const typename Dec<ST>::T* __restrict__ st,
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int y = int(s / geo.nx), x = int(s % geo.nx);
-  const long long o = (long long)y * geo.pitch + x, oa = (long long)y * ga.pitch + x;
+  const long long o = (long long)y * geo.pitch + x;
   double v[kNPop];
 #pragma unroll
   for (int q = 0; q < kNPop; ++q) v[q] = double(D::dec(st[q * geo.plane + o]));
@@ -359,18 +387,21 @@ __global__ void k_adj_seed_mismatch(const typename Dec<ST>::T* __restrict__ st,
   }
   const double rho = 1.0 + dr, ux = jx / rho, uy = jy / rho;
   const double eu = 2.0 * scale * (ux - ux_t[s]) / rho, ev = 2.0 * scale * (uy - uy_t[s]) / rho;
+  unsigned on[9];
+  streamed_offsets(ga, x, y, on);
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    lam[i * ga.plane + oa] = float(eu * (kCx[i] - ux) + ev * (kCy[i] - uy));
+    lam[i * ga.plane + on[i]] = float(eu * (kCx[i] - ux) + ev * (kCy[i] - uy));
   const double gx = 2.0 * scale * (bx - bx_t[s]), gy = 2.0 * scale * (by - by_t[s]);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    lam[(9 + k) * ga.plane + oa] = float(gx);
-    lam[(14 + k) * ga.plane + oa] = float(gy);
+    lam[(9 + k) * ga.plane + on[k]] = float(gx);
+    lam[(14 + k) * ga.plane + on[k]] = float(gy);
   }
 }
 
-// Pull lam0 back through x_0 = (f^eq(rho0, u0, B0), g^eq(u0, B0)).
+// Pull lam0 (streamed position) back through x_0 = (f^eq(rho0, u0, B0),
+// g^eq(u0, B0)).
 __global__ void k_adj_fields(const float* __restrict__ lam, const double* __restrict__ rho0,
                              const double* __restrict__ ux0, const double* __restrict__ uy0,
                              const double* __restrict__ bx0, const double* __restrict__ by0,
@@ -381,12 +412,13 @@ __global__ void k_adj_fields(const float* __restrict__ lam, const double* __rest
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int y = int(s / nx), x = int(s % nx);
-  const long long oa = (long long)y * ga.pitch + x;
+  unsigned on[9];
+  streamed_offsets(ga, x, y, on);
   const double rho = rho0[s], ux = ux0[s], uy = uy0[s], bx = bx0[s], by = by0[s];
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const double l = double(lam[i * ga.plane + oa]);
+    const double l = double(lam[i * ga.plane + on[i]]);
     const double cx = kCx[i], cy = kCy[i], w = kW[i];
     const double cu = cx * ux + cy * uy, cb = cx * bx + cy * by, c2 = cx * cx + cy * cy;
     // f^eq_i = w rho (1 + 3 cu + 4.5 cu^2 - 1.5 u^2) + 4.5 w (B^2 c^2 / 2 - cb^2)
@@ -397,8 +429,8 @@ __global__ void k_adj_fields(const float* __restrict__ lam, const double* __rest
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double lx = double(lam[(9 + k) * ga.plane + oa]);
-    const double ly = double(lam[(14 + k) * ga.plane + oa]);
+    const double lx = double(lam[(9 + k) * ga.plane + on[k]]);
+    const double ly = double(lam[(14 + k) * ga.plane + on[k]]);
     const double cx = kMx[k], cy = kMy[k], w = kWm[k];
     const double cu = cx * ux + cy * uy, cb = cx * bx + cy * by;
     // g^eq_x = w (B_x + 3 (cu B_x - cb u_x)), g^eq_y = w (B_y + 3 (cu B_y - cb u_y))

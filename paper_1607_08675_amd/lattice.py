@@ -237,6 +237,7 @@ class Lattice:
         return tuple(outs)
 
     def adj_view(self, lam: torch.Tensor) -> torch.Tensor:
-        """(19, ny, nx) view of an adjoint buffer (drops the row padding)."""
+        """(19, ny, nx) view of an adjoint buffer (drops the row padding).  Entries
+        are in streamed position: plane i at site x + c_i holds dJ/dx_i(x)."""
         pitch = (self.adj_lattice_bytes // 4) // (19 * self.cfg.ny)
         return lam.view(19, self.cfg.ny, pitch)[:, :, : self.cfg.nx]

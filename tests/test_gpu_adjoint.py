@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+from adjoint_layout import streamed, unstreamed
 from lbmhd_inputs import directions, perturbed_orszag_tang, random_planes
 
 pytestmark = pytest.mark.gpu
@@ -45,9 +46,14 @@ def stored(x, storage):
 
 
 def _to_adj(L, a):
+    """An adjoint lattice holding the per-site sensitivities a (19, ny, nx)."""
     lam = L.new_adj_buffer().zero_()
-    L.adj_view(lam)[:] = torch.as_tensor(a, dtype=torch.float32, device=lam.device)
+    L.adj_view(lam)[:] = torch.as_tensor(streamed(a), dtype=torch.float32, device=lam.device)
     return lam
+
+
+def _from_adj(L, lam):
+    return unstreamed(L.adj_view(lam).double().cpu().numpy())
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
@@ -69,7 +75,7 @@ def test_adjoint_step_dot_product(lb, orc, nx, ny, les, storage):
     lam_prev = L.new_adj_buffer().fill_(float("nan"))   # every entry must be written
     acc = L.new_adj_acc()
     L.adj_step(state, lam_next, lam_prev, acc)
-    JTa = L.adj_view(lam_prev).double().cpu().numpy()
+    JTa = _from_adj(L, lam_prev)
     assert np.isfinite(JTa).all()
     dcs_gpu = L.adj_acc_total(acc)       # (d/dC_Sv, d/dC_Sb)
 
@@ -159,7 +165,7 @@ def test_seed_is_energy_gradient(lb, orc):
     x = stored(x, "fp32")
     lam = L.new_adj_buffer()
     L.adj_seed_energy(L.save_state(), lam)
-    got = L.adj_view(lam).double().cpu().numpy()
+    got = _from_adj(L, lam)
     op = orc.Params(nx, ny)
     eps = 1e-6
     rng = np.random.default_rng(1)
@@ -202,14 +208,18 @@ def test_adjoint_step_full_size_patches(lb, orc, storage, n, nu, gen):
         d = np.maximum(np.abs(np.arange(-R, R + 1))[:, None], np.abs(np.arange(-R, R + 1))[None, :])
         a = rng.standard_normal((19, 2 * R + 1, 2 * R + 1)) * (d <= ra)
         b = rng.standard_normal((19, 2 * R + 1, 2 * R + 1)) * (d <= rb)
+        # a (support d <= 4) and J^T a (d <= 5) move by at most one site
+        # between the two placements, so both stay inside the patch
         lam = L.new_adj_buffer().zero_()
         view = L.adj_view(lam)
         ti = torch.as_tensor
-        view[:, ti(ys).cuda()[:, None], ti(xs).cuda()[None, :]] = ti(a, dtype=torch.float32).cuda()
+        view[:, ti(ys).cuda()[:, None], ti(xs).cuda()[None, :]] = \
+            ti(streamed(a), dtype=torch.float32).cuda()
         out = L.new_adj_buffer().zero_()
         acc = L.new_adj_acc()
         L.adj_step(state, lam, out, acc)
-        JTa = L.adj_view(out)[:, ti(ys).cuda()[:, None], ti(xs).cuda()[None, :]].double().cpu().numpy()
+        JTa = unstreamed(L.adj_view(out)[:, ti(ys).cuda()[:, None],
+                                          ti(xs).cuda()[None, :]].double().cpu().numpy())
         rhs = float(np.sum(JTa * b))
         x = orc.init(op, *[f[np.ix_(ys, xs)] for f in fields])
         x = _stored16(x) if storage == "fp16" else stored(x, "fp32")
