@@ -226,7 +226,9 @@ def adjoint_leg(torch, args):
     # the checkpoint interval follows the free device memory: every state is
     # kept when the run fits, and the backward sweep then recomputes nothing
     run = Checkpointed(lat, "auto")
-    run.forward(fields, min(nsteps, 200))   # warm-up of both passes
+    # warm-up of both passes at the full length, so that the state store is
+    # allocated once and reused by the timed run (as in a fit loop)
+    run.forward(fields, nsteps)
     run.backward()
     torch.cuda.synchronize()
     log(f"adjoint 1024^2: forward + backward of {nsteps} steps")
