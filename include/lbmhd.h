@@ -107,7 +107,10 @@ typedef struct {
                              push-scatter step into reversed slots and a fully
                              local step back, the same bytes per step as the
                              two-lattice update).  Not with les = 2, 3, 4, 6
-                             (those read the neighbours' populations). */
+                             (those read the neighbours' populations).  Calls
+                             that read the state, or take a state argument
+                             that is the bound lattice itself, first return
+                             a reversed lattice to the natural layout. */
 } lbmhd_params;
 
 /* Global diagnostics of the current state, accumulated in FP64.

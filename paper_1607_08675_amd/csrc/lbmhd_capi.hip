@@ -101,6 +101,17 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// A caller-supplied state that is the bound in-place lattice must be read in
+// the natural layout: turn that lattice back first if it is reversed.
+int natural(lbmhd_t* h, const void* state) {
+  if (h->p.inplace && h->reversed && state &&
+      overlap(state, h->lattice_bytes, h->lat[0], h->lattice_bytes)) {
+    const void* st = nullptr;
+    return current(h, &st);
+  }
+  return LBMHD_OK;
+}
+
 // Run the diagnostics kernels on `lat` and copy the 16 results to host.
 int run_diag(lbmhd_t* h, const void* lat, double out[lbk::kDiagSlots]) {
   hipError_t e = lbk::launch_diag(h->p.storage, lat, h->ws, ws_out(h), h->geo, h->stream);
@@ -278,6 +289,7 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst) {
   for (const void* b : {(const void*)h->lat[0], (const void*)h->lat[1]})
     if (b && overlap(dst, h->lattice_bytes, b, h->lattice_bytes))
       return fail(h, LBMHD_ERR_INVALID_ARG, "dst overlaps a bound lattice");
+  if (int rc = natural(h, src)) return rc;
   hipError_t e = launch_one_step(h, src, dst);
   if (e != hipSuccess) return hip_fail(h, e, "step launch");
   return LBMHD_OK;
@@ -314,8 +326,11 @@ int lbmhd_mismatch(lbmhd_t* h, const void* state, const double* ux_t, const doub
     return fail(h, LBMHD_ERR_INVALID_ARG, "null target or output");
   double* part = h->ws + 5 * size_t(h->geo.nx) * h->geo.ny;  // diagnostics partials area
   double* dev = ws_out(h) + lbk::kDiagSlots + 1;
-  if (!state)
+  if (!state) {
     if (int rc = current(h, &state)) return rc;
+  } else if (int rc = natural(h, state)) {
+    return rc;
+  }
   hipError_t e = lbk::launch_mismatch(h->p.storage, state, ux_t, uy_t, bx_t, by_t, part, dev,
                                       h->geo, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "mismatch launch");
@@ -406,8 +421,11 @@ int lbmhd_energy(lbmhd_t* h, const void* state, double* J) {
   if (int rc = need_bound(h)) return rc;
   if (!J) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
   double v[lbk::kDiagSlots];
-  if (!state)
+  if (!state) {
     if (int rc = current(h, &state)) return rc;
+  } else if (int rc = natural(h, state)) {
+    return rc;
+  }
   if (int rc = run_diag(h, state, v)) return rc;
   *J = v[5] + v[6];
   return LBMHD_OK;
@@ -416,6 +434,7 @@ int lbmhd_energy(lbmhd_t* h, const void* state, double* J) {
 int lbmhd_adj_seed_energy(lbmhd_t* h, const void* state, float* lam) {
   if (int rc = need_bound(h)) return rc;
   if (!state || !lam) return fail(h, LBMHD_ERR_INVALID_ARG, "null state or lambda");
+  if (int rc = natural(h, state)) return rc;
   hipError_t e = lbk::launch_adj_seed(h->p.storage, state, lam, h->geo, h->geoa, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint seed launch");
   return LBMHD_OK;
@@ -427,6 +446,7 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
   if (int rc = need_bound(h)) return rc;
   if (!state || !ux_t || !uy_t || !bx_t || !by_t || !lam)
     return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
+  if (int rc = natural(h, state)) return rc;
   hipError_t e = lbk::launch_adj_seed_mismatch(h->p.storage, state, ux_t, uy_t, bx_t, by_t, scale,
                                                lam, h->geo, h->geoa, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "mismatch seed launch");
@@ -443,6 +463,7 @@ int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float
     return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
   if (overlap(lam_next, h->adj_lattice_bytes, lam_prev, h->adj_lattice_bytes))
     return fail(h, LBMHD_ERR_INVALID_ARG, "lam_prev overlaps lam_next");
+  if (int rc = natural(h, state_n)) return rc;
   hipError_t e = lbk::launch_adj_step(h->p.storage, (h->p.les & 1) != 0, state_n, lam_next, lam_prev,
                                         acc, h->geo, h->geoa, h->rates,
                                         h->p.delta * h->p.delta, h->stream);
