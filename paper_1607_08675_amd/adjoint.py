@@ -1,6 +1,6 @@
 """Gradients of the final total energy through the GPU adjoint step.
 
-``LBMHDFunction.apply(ux0, uy0, bx0, by0, cs, cfg, nsteps, every)`` runs
+``LBMHDFunction.apply(ux0, uy0, bx0, by0, cs, cfg, nsteps, every="auto")`` runs
 ``nsteps`` steps from equilibrium at (rho = 1, u0, B0) and returns
 J = sum |rho u|^2 / (2 rho) + |B|^2 / 2 of the final state (FP64).  Its backward
 pass is the discrete adjoint: checkpoints of the encoded lattice are kept every
@@ -52,7 +52,7 @@ class Checkpointed:
     nothing, which is the case whenever the run fits in HBM (2000 steps of a
     1024^2 FP32 lattice take 160 GB)."""
 
-    def __init__(self, lat: Lattice, every=100, budget_bytes: int | None = None):
+    def __init__(self, lat: Lattice, every="auto", budget_bytes: int | None = None):
         if every != "auto" and (not isinstance(every, int) or every < 1):
             raise ValueError("checkpoint interval must be >= 1 or 'auto'")
         self.lat = lat
@@ -150,7 +150,7 @@ class LBMHDFunction(torch.autograd.Function):
     """J(u0, B0, C_S) with a hand-written adjoint backward (see module doc)."""
 
     @staticmethod
-    def forward(ctx, ux0, uy0, bx0, by0, cs, cfg: LBMHDConfig, nsteps: int, every: int = 100):
+    def forward(ctx, ux0, uy0, bx0, by0, cs, cfg: LBMHDConfig, nsteps: int, every="auto"):
         c = cs.detach().to(torch.float64).reshape(-1).cpu()
         if c.numel() not in (1, 2):
             raise ValueError("cs must be a scalar or a pair (C_Sv, C_Sb)")
