@@ -180,10 +180,20 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
 int lbmhd_step(lbmhd_t* h, int64_t nsteps);
 
 /* One step from the encoded lattice src into dst (device, `lattice` bytes
- * each, not overlapping each other or the bound buffers), same update as
- * lbmhd_step.  Leaves the handle's current state and step count untouched;
- * used to recompute stored states for the adjoint.  Asynchronous. */
+ * each, 256-byte aligned; dst overlaps neither src nor the bound buffers, src
+ * may be a bound lattice), same update as lbmhd_step.  Leaves the handle's
+ * current state and step count untouched; used to recompute stored states
+ * for the adjoint.  Asynchronous. */
 int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst);
+
+/* n >= 0 steps from the encoded lattice src, keeping every state: state t
+ * (t = 1 .. n) is written to store + (t - 1) * stride bytes (device; stride a
+ * multiple of 256 and >= `lattice` bytes).  The same kernels as lbmhd_step,
+ * launched from the library in one call; the handle's current state and step
+ * count are untouched.  The store range overlaps neither src nor the bound
+ * buffers.  Used to keep the whole trajectory for the adjoint when it fits
+ * in device memory.  Asynchronous. */
+int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, int64_t n);
 
 /* Macroscopic fields of the current state: rho = sum f, u = (sum c f) / rho,
  * B = sum g (Sec. 3).  Outputs: device fields.  Asynchronous. */
@@ -269,6 +279,16 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
  * Asynchronous. */
 int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float* lam_prev,
                    double* acc);
+
+/* Reverse sweep over n >= 0 steps in one call: with x_0 = src and x_t at
+ * store + (t - 1) * stride for t = 1 .. n - 1 (the layout lbmhd_step_store
+ * writes), and lam holding lam_n (streamed position) on entry, apply
+ * lbmhd_adj_step for t = n - 1 down to 0 and leave lam_0 in lam.  tmp is a
+ * second adjoint lattice used as scratch (not overlapping lam); acc gains the
+ * closure-constant sums as in lbmhd_adj_step.  Asynchronous.  Errors as
+ * lbmhd_adj_step. */
+int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t stride, int64_t n,
+                    float* lam, float* tmp, double* acc);
 
 /* Sum the two slot arrays of acc into out[0] (C_Sv) and out[1] (C_Sb), host,
  * in FP64.  Synchronises. */

@@ -27,11 +27,12 @@ LBMHD_FP16 = 1
 # Every function declared in include/lbmhd.h, in declaration order.
 EXPORTS = (
     "lbmhd_strerror", "lbmhd_last_error", "lbmhd_create", "lbmhd_destroy", "lbmhd_sizes",
-    "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_step_between", "lbmhd_macro",
+    "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_step_between", "lbmhd_step_store",
+    "lbmhd_macro",
     "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_get_populations",
     "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state", "lbmhd_get_step",
     "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_seed_mismatch", "lbmhd_adj_step",
-    "lbmhd_adj_acc_total", "lbmhd_adj_fields",
+    "lbmhd_adj_sweep", "lbmhd_adj_acc_total", "lbmhd_adj_fields",
 )
 # Every function declared in include/lbmhd3.h.
 EXPORTS3 = (
@@ -114,6 +115,7 @@ def lib():
             "lbmhd_init_fields": [vp] * 6,
             "lbmhd_step": [vp, i64],
             "lbmhd_step_between": [vp, vp, vp],
+            "lbmhd_step_store": [vp, vp, vp, sz, i64],
             "lbmhd_macro": [vp] * 6,
             "lbmhd_macro_box": [vp, ctypes.c_int32] + [vp] * 5,
             "lbmhd_mismatch": [vp] * 6 + [P(ctypes.c_double)],
@@ -127,6 +129,7 @@ def lib():
             "lbmhd_energy": [vp, vp, P(ctypes.c_double)],
             "lbmhd_adj_seed_energy": [vp, vp, vp],
             "lbmhd_adj_step": [vp, vp, vp, vp, vp],
+            "lbmhd_adj_sweep": [vp, vp, vp, sz, i64, vp, vp, vp],
             "lbmhd_adj_acc_total": [vp, vp, P(ctypes.c_double)],
             "lbmhd_adj_fields": [vp] * 11,
             "lbmhd3_create": [P(Params3), P(vp)],

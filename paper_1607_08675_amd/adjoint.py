@@ -5,10 +5,10 @@
 J = sum |rho u|^2 / (2 rho) + |B|^2 / 2 of the final state (FP64).  Its backward
 pass is the discrete adjoint: checkpoints of the encoded lattice are kept every
 ``every`` steps during the forward run (every state when they fit in device
-memory); the backward sweep restores each segment from its checkpoint,
-recomputes that segment's states straight into stored buffers (one step kernel
-per state, no copies), and walks them in reverse with ``lbmhd_adj_step``.  The
-result holds the exact
+memory); the backward sweep recomputes each segment's states from its
+checkpoint straight into one stored block (``lbmhd_step_store``, one step
+kernel per state, no copies) and walks them in reverse (``lbmhd_adj_sweep``),
+each a single library call.  The result holds the exact
 derivative of the FP32 update map (storage rounding counted as the identity)
 with respect to the initial fields and the closure constants: ``cs`` is a
 scalar (C_Sv = C_Sb = cs) or a pair (C_Sv, C_Sb), and its gradient has the
@@ -81,7 +81,7 @@ class Checkpointed:
         lat.init_fields(*fields)
         self.fields = fields
         self.nsteps = nsteps
-        self.ckpts, self.final = [], None
+        self.ckpts, self.final, self.store = [], None, None
         k = self._interval(nsteps)
         store = None
         if k == 1:
@@ -95,12 +95,12 @@ class Checkpointed:
                                     (nsteps + 1) * lat.lattice_bytes // 2)
         self.interval = k
         if k == 1:
-            # every state kept, in one allocation: each step reads one stored
-            # state and writes the next; the lattice ends on the final state
+            # every state kept, in one allocation, written by one library call;
+            # the lattice ends on the final state
+            self.store = store
             self.ckpts = list(store.unbind(0))
             lat.save_state(self.ckpts[0])
-            for t in range(nsteps):
-                lat.step_between(self.ckpts[t], self.ckpts[t + 1])
+            lat.step_store(self.ckpts[0], store[1:], nsteps)
             self.final = self.ckpts[-1]
             lat.load_state(self.final, lat.step_count + nsteps)
         else:
@@ -128,20 +128,15 @@ class Checkpointed:
             lat.adj_seed_mismatch(self.final, self.targets, scale, lam)
         k = self.interval
         if k == 1:
-            for j in reversed(range(self.nsteps)):
-                lat.adj_step(self.ckpts[j], lam, lam2, acc)
-                lam, lam2 = lam2, lam
+            lat.adj_sweep(self.ckpts[0], self.store[1:], self.nsteps, lam, lam2, acc)
         else:
-            seg_states = [lat.new_state_buffer() for _ in range(k - 1)]
+            # per segment, from the last: recompute its states into one block,
+            # then sweep back over them (lambda stays in lam)
+            seg = torch.empty(k - 1, lat.lattice_bytes, dtype=torch.uint8, device=lat.device)
             for s in reversed(range(len(self.ckpts))):
-                start = s * k
-                n = min(k, self.nsteps - start)
-                states = [self.ckpts[s]] + seg_states[: n - 1]
-                for j in range(n - 1):
-                    lat.step_between(states[j], states[j + 1])
-                for j in reversed(range(n)):
-                    lat.adj_step(states[j], lam, lam2, acc)
-                    lam, lam2 = lam2, lam
+                n = min(k, self.nsteps - s * k)
+                lat.step_store(self.ckpts[s], seg, n - 1)
+                lat.adj_sweep(self.ckpts[s], seg, n, lam, lam2, acc)
         g = lat.adj_fields(lam, self.fields)
         return (*g, *lat.adj_acc_total(acc))
 

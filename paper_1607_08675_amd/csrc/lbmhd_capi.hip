@@ -2,6 +2,7 @@
 // parameter validation, the handle, buffer binding and kernel sequencing.
 // No exception crosses the interface; every HIP status is checked and kept.
 #include <math.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -9,6 +10,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <utility>
 
 #include "lbmhd_impl.h"
 
@@ -295,6 +297,34 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst) {
   return LBMHD_OK;
 }
 
+int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, int64_t n) {
+  if (int rc = need_bound(h)) return rc;
+  if (n < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
+  if (n == 0) return LBMHD_OK;
+  if (!src || !store || !aligned(src) || !aligned(store))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null or unaligned lattice");
+  if (stride < h->lattice_bytes || stride % kAlign != 0)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "stride below the lattice size or not 256-aligned");
+  if (size_t(n - 1) > (SIZE_MAX - h->lattice_bytes) / stride)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "store range overflows");
+  const size_t span = size_t(n - 1) * stride + h->lattice_bytes;
+  if (overlap(src, h->lattice_bytes, store, span))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "store overlaps src");
+  for (const void* b : {(const void*)h->lat[0], (const void*)h->lat[1], (const void*)h->ws})
+    if (b && overlap(store, span, b, b == h->ws ? h->workspace_bytes : h->lattice_bytes))
+      return fail(h, LBMHD_ERR_INVALID_ARG, "store overlaps a bound buffer");
+  if (int rc = natural(h, src)) return rc;
+  const char* prev = static_cast<const char*>(src);
+  char* out = static_cast<char*>(store);
+  for (int64_t t = 0; t < n; ++t) {
+    hipError_t e = launch_one_step(h, prev, out);
+    if (e != hipSuccess) return hip_fail(h, e, "step launch");
+    prev = out;
+    out += stride;
+  }
+  return LBMHD_OK;
+}
+
 int lbmhd_macro(lbmhd_t* h, double* rho, double* ux, double* uy, double* bx, double* by) {
   if (int rc = need_bound(h)) return rc;
   if (!rho || !ux || !uy || !bx || !by) return fail(h, LBMHD_ERR_INVALID_ARG, "null field");
@@ -468,6 +498,42 @@ int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float
                                         acc, h->geo, h->geoa, h->rates,
                                         h->p.delta * h->p.delta, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t stride, int64_t n,
+                    float* lam, float* tmp, double* acc) {
+  if (int rc = need_bound(h)) return rc;
+  if (h->p.les & 6)
+    return fail(h, LBMHD_ERR_UNSUPPORTED,
+                "the adjoint of the kinetic and cross-helicity closures is not provided");
+  if (n < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
+  if (n == 0) return LBMHD_OK;
+  if (!src || !lam || !tmp || !acc || (n > 1 && !store))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
+  if (n > 1 && (stride < h->lattice_bytes || stride % kAlign != 0))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "stride below the lattice size or not 256-aligned");
+  if (overlap(lam, h->adj_lattice_bytes, tmp, h->adj_lattice_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "tmp overlaps lam");
+  if (int rc = natural(h, src)) return rc;
+  const bool les = (h->p.les & 1) != 0;
+  const double d2 = h->p.delta * h->p.delta;
+  // the last step must write lam: with an odd count the sweep starts from tmp
+  float* from = lam;
+  float* to = tmp;
+  if (n % 2) {
+    hipError_t e = lbk::launch_copy(lam, tmp, h->adj_lattice_bytes, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copy launch");
+    from = tmp;
+    to = lam;
+  }
+  for (int64_t t = n - 1; t >= 0; --t) {
+    const void* x = t == 0 ? src : static_cast<const char*>(store) + size_t(t - 1) * stride;
+    hipError_t e = lbk::launch_adj_step(h->p.storage, les, x, from, to, acc, h->geo, h->geoa,
+                                        h->rates, d2, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
+    std::swap(from, to);
+  }
   return LBMHD_OK;
 }
 

@@ -126,6 +126,26 @@ class Lattice:
         self._check(self._L.lbmhd_step_between(self._h, _ptr(src), _ptr(dst)),
                     "lbmhd_step_between")
 
+    def step_store(self, src: torch.Tensor, store: torch.Tensor, n: int):
+        """n steps from encoded lattice src; state t (1..n) goes to row t - 1 of
+        store, a (>= n, lattice_bytes or more) uint8 tensor whose row stride is a
+        multiple of 256 bytes.  One library call for all n steps."""
+        stride = self._store_stride(store, n)
+        if src.numel() < self.lattice_bytes:
+            raise ValueError("state buffer too small")
+        self._check(self._L.lbmhd_step_store(self._h, _ptr(src),
+                                             _ptr(store) if n else ctypes.c_void_p(0),
+                                             stride, int(n)), "lbmhd_step_store")
+
+    def _store_stride(self, store: torch.Tensor, n: int) -> int:
+        if n == 0:
+            return self.lattice_bytes
+        if store.dim() != 2 or store.dtype != torch.uint8 or store.shape[0] < n:
+            raise ValueError("store must be a 2D uint8 tensor with a row per state")
+        if store.shape[1] < self.lattice_bytes or store.stride(1) != 1:
+            raise ValueError("store rows must hold a lattice each")
+        return int(store.stride(0))
+
     def macro(self) -> dict:
         out = [torch.empty(self.cfg.ny, self.cfg.nx, dtype=torch.float64, device=self.device)
                for _ in FIELDS]
@@ -220,6 +240,16 @@ class Lattice:
                  acc: torch.Tensor):
         self._check(self._L.lbmhd_adj_step(self._h, _ptr(state_n), _ptr(lam_next),
                                            _ptr(lam_prev), _ptr(acc)), "lbmhd_adj_step")
+
+    def adj_sweep(self, src: torch.Tensor, store: torch.Tensor | None, n: int,
+                  lam: torch.Tensor, tmp: torch.Tensor, acc: torch.Tensor):
+        """Reverse sweep over n steps in one library call: x_0 = src, x_t = row
+        t - 1 of store (t = 1 .. n - 1); lam holds lam_n on entry and lam_0 on
+        return; tmp is scratch."""
+        stride = self._store_stride(store, n - 1) if n > 1 else self.lattice_bytes
+        sp = _ptr(store) if n > 1 else ctypes.c_void_p(0)
+        self._check(self._L.lbmhd_adj_sweep(self._h, _ptr(src), sp, stride, int(n), _ptr(lam),
+                                            _ptr(tmp), _ptr(acc)), "lbmhd_adj_sweep")
 
     def adj_acc_total(self, acc: torch.Tensor) -> tuple[float, float]:
         """(sum lam . dx/dC_Sv, sum lam . dx/dC_Sb) accumulated in acc."""

@@ -307,3 +307,60 @@ def test_sixteen_directions_against_tangent_and_differences(lb, orc):
         assert abs(g - dJ[k]) <= 1e-3 * abs(dJ[k]), (k, g, dJ[k])
         fd = (J_gpu(1, k) - J_gpu(-1, k)) / (2 * eps)
         assert abs(g - fd) <= 1e-2 * abs(fd), (k, g, fd)
+
+
+@pytest.mark.parametrize("n", [0, 1, 6, 7])
+def test_store_and_sweep_calls_match_step_by_step(lb, n):
+    """lbmhd_step_store writes the same states as n calls of
+    lbmhd_step_between, with a row stride larger than a lattice; lbmhd_adj_sweep
+    leaves the same lambda_0 and closure sums as n calls of lbmhd_adj_step,
+    for even and odd n (an odd count starts from the scratch lattice)."""
+    cfg = lb.LBMHDConfig(nx=40, ny=20, nu=0.01, eta=0.01, les=1, cs=0.12, cs_b=0.07)
+    L = lb.Lattice(cfg)
+    L.init_fields(*perturbed_orszag_tang(40, 20, u0=0.08, b0=0.08)).step(2)
+    x0 = L.save_state()
+    stride = L.lattice_bytes + 512
+    store = torch.zeros(max(n, 1), stride, dtype=torch.uint8, device="cuda")
+    L.step_store(x0, store, n)
+    states = [x0]
+    for _ in range(n):   # zeroed like the store: the kernels leave row padding alone
+        states.append(L.new_state_buffer().zero_())
+        L.step_between(states[-2], states[-1])
+    for t in range(n):
+        assert torch.equal(store[t, :L.lattice_bytes], states[t + 1][:L.lattice_bytes]), t
+    lam_a, tmp_a, acc_a = L.new_adj_buffer(), L.new_adj_buffer(), L.new_adj_acc()
+    L.adj_seed_energy(states[-1], lam_a)
+    lam_b, tmp_b, acc_b = L.new_adj_buffer(), L.new_adj_buffer(), L.new_adj_acc()
+    lam_b.copy_(lam_a)
+    L.adj_sweep(x0, store, n, lam_a, tmp_a, acc_a)
+    for t in reversed(range(n)):
+        L.adj_step(states[t], lam_b, tmp_b, acc_b)
+        lam_b, tmp_b = tmp_b, lam_b
+    assert torch.equal(L.adj_view(lam_a), L.adj_view(lam_b))
+    assert torch.equal(acc_a, acc_b)
+
+
+def test_store_and_sweep_reject_bad_layouts(lb):
+    import ctypes
+    from paper_1607_08675_amd import _capi as C
+    L = lb.Lattice(lb.LBMHDConfig(nx=16, ny=8))
+    x0 = L.save_state()
+    store = torch.empty(3, L.lattice_bytes + 256, dtype=torch.uint8, device="cuda")
+    h, lib = L._h, L._L
+    p = ctypes.c_void_p
+    assert lib.lbmhd_step_store(h, p(x0.data_ptr()), p(store.data_ptr()),
+                                L.lattice_bytes + 128, 2) == C.LBMHD_ERR_INVALID_ARG
+    assert lib.lbmhd_step_store(h, p(x0.data_ptr()), p(store.data_ptr()),
+                                L.lattice_bytes - 256, 2) == C.LBMHD_ERR_INVALID_ARG
+    assert lib.lbmhd_step_store(h, p(x0.data_ptr()), p(L._a.data_ptr()),
+                                L.lattice_bytes, 1) == C.LBMHD_ERR_INVALID_ARG
+    assert lib.lbmhd_step_store(h, p(store.data_ptr()), p(store.data_ptr()),
+                                L.lattice_bytes + 256, 2) == C.LBMHD_ERR_INVALID_ARG
+    assert lib.lbmhd_step_store(h, p(x0.data_ptr()), p(store.data_ptr()),
+                                L.lattice_bytes, -1) == C.LBMHD_ERR_INVALID_ARG
+    lam = L.new_adj_buffer()
+    acc = L.new_adj_acc()
+    assert lib.lbmhd_adj_sweep(h, p(x0.data_ptr()), p(store.data_ptr()), L.lattice_bytes, 2,
+                               p(lam.data_ptr()), p(lam.data_ptr()),
+                               p(acc.data_ptr())) == C.LBMHD_ERR_INVALID_ARG
+    torch.cuda.synchronize()
