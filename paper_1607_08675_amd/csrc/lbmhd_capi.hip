@@ -68,13 +68,11 @@ lbk::Geom make_geom(int nx, int ny, size_t esize) {
 
 bool rate_ok(double s) { return s > 0.0 && s < 2.0; }
 
-// Workspace (doubles): 5 macro planes, diagnostics partials, 16 results.
-size_t workspace_doubles(const lbk::Geom& g) {
-  return 5 * size_t(g.nx) * g.ny + size_t(lbk::kDiagBlocks) * lbk::kDiagSlots + 32;
-}
-double* ws_out(lbmhd_t* h) {
-  return h->ws + 5 * size_t(h->geo.nx) * h->geo.ny + size_t(lbk::kDiagBlocks) * lbk::kDiagSlots;
-}
+// Workspace (doubles): per-block partials of the reductions, then 32 result
+// slots ([0, 16) diagnostics, [16] the C_Sv sum, [17] the mismatch, [18] the
+// C_Sb sum).  Its size does not depend on the lattice.
+size_t workspace_doubles() { return size_t(lbk::kDiagBlocks) * lbk::kDiagSlots + 32; }
+double* ws_out(lbmhd_t* h) { return h->ws + size_t(lbk::kDiagBlocks) * lbk::kDiagSlots; }
 
 int need_bound(lbmhd_t* h) {
   if (!h) return LBMHD_ERR_INVALID_ARG;
@@ -198,7 +196,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   r.qclip = float(ts * ts * ts - taum0 * ts);
   h->lattice_bytes = size_t(lbk::kNPop) * size_t(g.plane) * esize;
   h->adj_lattice_bytes = size_t(lbk::kNPop) * size_t(ga.plane) * 4;
-  h->workspace_bytes = round_up(workspace_doubles(g) * sizeof(double), kAlign);
+  h->workspace_bytes = round_up(workspace_doubles() * sizeof(double), kAlign);
   h->adj_acc_bytes = round_up(2 * size_t(lbk::adj_step_blocks(g)) * sizeof(double), kAlign);
   *out = h;
   return LBMHD_OK;
@@ -354,7 +352,7 @@ int lbmhd_mismatch(lbmhd_t* h, const void* state, const double* ux_t, const doub
   if (int rc = need_bound(h)) return rc;
   if (!ux_t || !uy_t || !bx_t || !by_t || !L)
     return fail(h, LBMHD_ERR_INVALID_ARG, "null target or output");
-  double* part = h->ws + 5 * size_t(h->geo.nx) * h->geo.ny;  // diagnostics partials area
+  double* part = h->ws;  // the partials area of the reductions
   double* dev = ws_out(h) + lbk::kDiagSlots + 1;
   if (!state) {
     if (int rc = current(h, &state)) return rc;

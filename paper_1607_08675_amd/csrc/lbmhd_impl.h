@@ -42,7 +42,7 @@ struct Rates {
 
 constexpr int kNPop = 19;
 constexpr int kDiagSlots = 16;   // doubles per diagnostics partial
-constexpr int kDiagBlocks = 1024;
+constexpr int kDiagBlocks = 4096; // partials in the workspace (one per reducing block)
 
 // Forward step: dst = C(S(src)).
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
@@ -72,13 +72,15 @@ hipError_t launch_macro(int storage, const void* lat, double* rho, double* ux, d
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // Diagnostics: macro planes (5 x nx*ny doubles at ws), partials, final 16
 // doubles at out_dev.
-hipError_t launch_diag(int storage, const void* lat, double* ws, double* out_dev, const Geom& g,
-                       hipStream_t s);
+// Diagnostics in one pass over the lattice: per-block partials (at most
+// kDiagBlocks x kDiagSlots doubles at part) folded into out_dev[0 .. 12].
+hipError_t launch_diag(int storage, const void* lat, double* part, double* out_dev,
+                       const Geom& g, hipStream_t s);
 
 // Box-averaged macroscopic fields (w x w blocks).
 hipError_t launch_macro_box(int storage, const void* lat, int w, double* rho, double* ux,
                             double* uy, double* bx, double* by, const Geom& g, hipStream_t s);
-// Mismatch to target fields: per-block partials (kDiagBlocks doubles at part)
+// Mismatch to target fields: per-block partials (at most kDiagBlocks doubles at part)
 // folded into out_dev[0].
 hipError_t launch_mismatch(int storage, const void* lat, const double* ux_t, const double* uy_t,
                            const double* bx_t, const double* by_t, double* part, double* out_dev,

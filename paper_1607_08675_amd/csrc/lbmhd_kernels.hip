@@ -807,24 +807,6 @@ __global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, l
 }
 
 // ------------------------------------------------------------ diagnostics
-// Pass 1: FP64 macro planes (rho, ux, uy, bx, by) into ws; rho = NaN marks a
-// site with a non-finite population.
-template <int ST>
-__global__ void k_diag_macro(const typename Codec<ST>::T* __restrict__ lat, double* __restrict__ ws,
-                             Geom geo) {
-  const long long n = (long long)geo.nx * geo.ny;
-  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int y = int(s / geo.nx), x = int(s % geo.nx);
-  double r, a, b, c, d;
-  const bool ok = macro_site<ST>(lat, geo, (long long)y * geo.pitch + x, r, a, b, c, d);
-  ws[s] = ok ? r : __builtin_nan("");
-  ws[n + s] = a;
-  ws[2 * n + s] = b;
-  ws[3 * n + s] = c;
-  ws[4 * n + s] = d;
-}
-
 enum {
   kSumMass = 0, kSumMx, kSumMy, kSumBx, kSumBy, kSumEk, kSumEm, kSumHc, kSumOm, kSumJ2,
   kSumBad, kNSum,          // slots 0..10 are sums
@@ -851,45 +833,135 @@ __device__ void block_reduce(double (&v)[kNRed], double* __restrict__ out) {
   if (t < kNRed) out[t] = sh[t][0];
 }
 
-// Pass 2: per-block partial sums / maxima over a grid-stride range of sites.
-__global__ __launch_bounds__(256) void k_diag_reduce(const double* __restrict__ ws,
-                                                     double* __restrict__ part, int nx, int ny) {
-  const long long n = (long long)nx * ny;
-  const double* rho = ws;
-  const double* ux = ws + n;
-  const double* uy = ws + 2 * n;
-  const double* bx = ws + 3 * n;
-  const double* by = ws + 4 * n;
+// One pass over the lattice: a block of kDiagThreads threads owns as many
+// columns and walks strips of kDiagRows rows (tile t, strip r: unit
+// r * tiles_x + t; a block takes units blockIdx.x, + gridDim.x, ...).  Per row
+// it loads the populations of row y + 1 (no streaming: the moments of the
+// current state), forms rho, u, B in FP64 into a rolling 3-row LDS buffer with
+// one halo column on each side, and then accumulates row y: the sums and
+// maxima of the site's own fields and the centred differences
+// d_x a = (a(x + 1) - a(x - 1)) / 2 of div B, w = d_x u_y - d_y u_x and
+// j = d_x B_y - d_y B_x.  A site with a non-finite population has rho = NaN.
+// Each block writes one partial (sums, maxima) to part[blockIdx.x].
+constexpr int kDiagThreads = 256;
+constexpr int kDiagRows = 16;
+
+template <int ST>
+__global__ __launch_bounds__(kDiagThreads) void k_diag(const typename Codec<ST>::T* __restrict__ lat,
+                                                       double* __restrict__ part, Geom geo,
+                                                       int tiles_x, int units) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  constexpr int NC = kDiagThreads + 2;
+  __shared__ double mac[3][5][NC];
+  const int tx = int(threadIdx.x);
   double v[kNRed];
 #pragma unroll
   for (int q = 0; q < kNRed; ++q) v[q] = 0.0;
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
-       s += (long long)gridDim.x * blockDim.x) {
-    const int y = int(s / nx), x = int(s % nx);
-    const long long row = (long long)y * nx;
-    const long long e = row + (x == nx - 1 ? 0 : x + 1), w = row + (x == 0 ? nx - 1 : x - 1);
-    const long long nn = (long long)(y == ny - 1 ? 0 : y + 1) * nx + x;
-    const long long so = (long long)(y == 0 ? ny - 1 : y - 1) * nx + x;
-    const double r = rho[s], u = ux[s], vv = uy[s], b0 = bx[s], b1 = by[s];
-    const double jx = r * u, jy = r * vv;
-    v[kSumMass] += r;
-    v[kSumMx] += jx;
-    v[kSumMy] += jy;
-    v[kSumBx] += b0;
-    v[kSumBy] += b1;
-    v[kSumEk] += (jx * jx + jy * jy) / (2.0 * r);
-    v[kSumEm] += 0.5 * (b0 * b0 + b1 * b1);
-    v[kSumHc] += u * b0 + vv * b1;
-    const double div = 0.5 * (bx[e] - bx[w]) + 0.5 * (by[nn] - by[so]);
-    const double om = 0.5 * (uy[e] - uy[w]) - 0.5 * (ux[nn] - ux[so]);
-    const double jz = 0.5 * (by[e] - by[w]) - 0.5 * (bx[nn] - bx[so]);
-    v[kSumOm] += 0.5 * om * om;
-    v[kSumJ2] += 0.5 * jz * jz;
-    v[kSumBad] += isfinite(r) ? 0.0 : 1.0;
-    v[kMaxDiv] = fmax(v[kMaxDiv], fabs(div));
-    v[kMaxU] = fmax(v[kMaxU], sqrt(u * u + vv * vv));
+  for (int u = int(blockIdx.x); u < units; u += int(gridDim.x)) {
+    const int xt = (u % tiles_x) * kDiagThreads;
+    const int y0 = (u / tiles_x) * kDiagRows;
+    const int y1 = min(y0 + kDiagRows, geo.ny);
+    const int x = xt + tx;
+    const bool active = x < geo.nx;
+    const int xc = x % geo.nx;   // past the last column: its periodic images
+    const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1) : (xt + kDiagThreads) % geo.nx;
+    const int ch = tx == 0 ? 0 : NC - 1;
+    T raw[kNPop], rawh[kNPop];
+    auto load = [&](int xx, int yy, T (&p)[kNPop]) {
+      const unsigned o = unsigned(yy) * geo.pitch + unsigned(xx);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) p[q] = ld_plane<T>(lat + q * geo.plane, o);
+    };
+    auto issue = [&](int yy) {
+      yy = yy < 0 ? yy + geo.ny : (yy >= geo.ny ? yy - geo.ny : yy);
+      load(xc, yy, raw);
+      if (tx < 2) load(xh, yy, rawh);
+    };
+    auto moments = [&](const T (&p)[kNPop], int slot, int col) {
+      bool ok = true;
+      double dr = 0.0, jx = 0.0, jy = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const float f = C::dec(p[i]);
+        ok = ok && isfinite(f);
+        dr += double(f);
+        jx += kCx[i] * double(f);
+        jy += kCy[i] * double(f);
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const float gx = C::dec(p[9 + k]), gy = C::dec(p[14 + k]);
+        ok = ok && isfinite(gx) && isfinite(gy);
+        b0 += double(gx);
+        b1 += double(gy);
+      }
+      const double r = 1.0 + dr;
+      mac[slot][0][col] = ok ? r : __builtin_nan("");
+      mac[slot][1][col] = jx / r;
+      mac[slot][2][col] = jy / r;
+      mac[slot][3][col] = b0;
+      mac[slot][4][col] = b1;
+    };
+    auto commit = [&](int slot) {
+      moments(raw, slot, tx + 1);
+      if (tx < 2) moments(rawh, slot, ch);
+    };
+    issue(y0 - 1);
+    commit(0);
+    issue(y0);
+    commit(1);
+    issue(y0 + 1);
+    for (int y = y0; y < y1; ++y) {
+      const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
+      commit(sp);
+      if (y + 2 <= y1) issue(y + 2);
+      __syncthreads();
+      if (active) {
+        const int c = tx + 1;
+        const double r = mac[s0][0][c], ux = mac[s0][1][c], uy = mac[s0][2][c];
+        const double b0 = mac[s0][3][c], b1 = mac[s0][4][c];
+        const double jx = r * ux, jy = r * uy;
+        v[kSumMass] += r;
+        v[kSumMx] += jx;
+        v[kSumMy] += jy;
+        v[kSumBx] += b0;
+        v[kSumBy] += b1;
+        v[kSumEk] += (jx * jx + jy * jy) / (2.0 * r);
+        v[kSumEm] += 0.5 * (b0 * b0 + b1 * b1);
+        v[kSumHc] += ux * b0 + uy * b1;
+        const double div = 0.5 * (mac[s0][3][c + 1] - mac[s0][3][c - 1]) +
+                           0.5 * (mac[sp][4][c] - mac[sm][4][c]);
+        const double om = 0.5 * (mac[s0][2][c + 1] - mac[s0][2][c - 1]) -
+                          0.5 * (mac[sp][1][c] - mac[sm][1][c]);
+        const double jz = 0.5 * (mac[s0][4][c + 1] - mac[s0][4][c - 1]) -
+                          0.5 * (mac[sp][3][c] - mac[sm][3][c]);
+        v[kSumOm] += 0.5 * om * om;
+        v[kSumJ2] += 0.5 * jz * jz;
+        v[kSumBad] += isfinite(r) ? 0.0 : 1.0;
+        v[kMaxDiv] = fmax(v[kMaxDiv], fabs(div));
+        v[kMaxU] = fmax(v[kMaxU], sqrt(ux * ux + uy * uy));
+      }
+      __syncthreads();
+    }
   }
-  block_reduce<256>(v, part + (long long)blockIdx.x * kDiagSlots);
+  // block reduction in the (now idle) row buffer
+  static_assert(3 * 5 * NC >= kNRed * kDiagThreads, "row buffer too small to reduce in");
+  double* red = &mac[0][0][0];
+#pragma unroll
+  for (int q = 0; q < kNRed; ++q) red[q * kDiagThreads + tx] = v[q];
+  __syncthreads();
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    if (tx < w) {
+#pragma unroll
+      for (int q = 0; q < kNSum; ++q) red[q * kDiagThreads + tx] += red[q * kDiagThreads + tx + w];
+#pragma unroll
+      for (int q = kNSum; q < kNRed; ++q)
+        red[q * kDiagThreads + tx] = fmax(red[q * kDiagThreads + tx], red[q * kDiagThreads + tx + w]);
+    }
+    __syncthreads();
+  }
+  if (tx < kNRed) part[(long long)blockIdx.x * kDiagSlots + tx] = red[tx * kDiagThreads];
 }
 
 // Pass 3: one block folds the partials.
@@ -1089,19 +1161,17 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_diag(int storage, const void* lat, double* ws, double* out_dev, const Geom& g,
-                       hipStream_t s) {
-  const long long n = (long long)g.nx * g.ny;
-  const unsigned nb = blocks_for(n, 256);
+hipError_t launch_diag(int storage, const void* lat, double* part, double* out_dev,
+                       const Geom& g, hipStream_t s) {
+  const int tiles_x = (g.nx + kDiagThreads - 1) / kDiagThreads;
+  const long long units = (long long)tiles_x * ((g.ny + kDiagRows - 1) / kDiagRows);
+  const int nparts = int(std::min<long long>(kDiagBlocks, units));
   if (storage == LBMHD_FP32)
-    hipLaunchKernelGGL(k_diag_macro<LBMHD_FP32>, dim3(nb), dim3(256), 0, s,
-                       static_cast<const float*>(lat), ws, g);
+    hipLaunchKernelGGL(k_diag<LBMHD_FP32>, dim3(nparts), dim3(kDiagThreads), 0, s,
+                       static_cast<const float*>(lat), part, g, tiles_x, int(units));
   else
-    hipLaunchKernelGGL(k_diag_macro<LBMHD_FP16>, dim3(nb), dim3(256), 0, s,
-                       static_cast<const _Float16*>(lat), ws, g);
-  double* part = ws + 5 * n;
-  const int nparts = int(std::min<long long>(kDiagBlocks, blocks_for(n, 256)));
-  hipLaunchKernelGGL(k_diag_reduce, dim3(nparts), dim3(256), 0, s, ws, part, g.nx, g.ny);
+    hipLaunchKernelGGL(k_diag<LBMHD_FP16>, dim3(nparts), dim3(kDiagThreads), 0, s,
+                       static_cast<const _Float16*>(lat), part, g, tiles_x, int(units));
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out_dev);
   return hipGetLastError();
 }

@@ -79,7 +79,7 @@ def test_sizes_and_layout(capi):
         pitch = -(-100 * esize // 256) * 256 // esize   # rows padded to 256 bytes
         assert lat == 19 * 36 * pitch * esize
         assert adj == 19 * 36 * 128 * 4
-        assert ws >= 5 * 100 * 36 * 8 and ws % 256 == 0
+        assert ws >= 16 * 8 and ws % 256 == 0   # reduction partials and results only
         assert acc % 256 == 0 and acc >= 2 * 8 * 36   # two slot arrays, >= 1 block per row
         assert L.lbmhd_destroy(h) == 0
 
