@@ -1,0 +1,100 @@
+"""The largest lattice the library accepts.
+
+In-plane byte offsets are 32-bit, so lbmhd_create takes a lattice only while
+one FP32 plane stays below 4 GiB: 32768 x 32767 sites is the largest square-
+ish one (its last site sits 131,076 bytes below 2^32 in every plane).  The
+Orszag-Tang vortex runs k = 2 steps with the Smagorinsky-MHD closure, in FP32
+on two lattices (163 GB), in place on one, and in FP16; the oracle then
+recomputes sampled sites, the four corners and the last row and column among
+them, on (2k + 5)^2 patches, and the FP64 diagnostics of the initial state
+are checked against their closed forms (sum over the nodes of sin^2 is N / 2).
+Skipped when the GPU has too little free memory.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+NX, NY = 32768, 32767
+U0 = B0 = 0.05
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+W19 = np.concatenate([W9, np.zeros(10)])
+
+
+@pytest.fixture(scope="module")
+def lb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_08675_amd import lattice
+    return lattice
+
+
+def ot_patch(xs, ys):
+    """Orszag-Tang fields at global node indices (xs, ys) of the NX x NY lattice."""
+    X = 2 * np.pi * np.asarray(xs)[None, :] / NX
+    Y = 2 * np.pi * np.asarray(ys)[:, None] / NY
+    one = np.ones((len(ys), len(xs)))
+    return (one, -U0 * np.sin(Y) * one, U0 * np.sin(X) * one, -B0 * np.sin(Y) * one,
+            B0 * np.sin(2 * X) * one)
+
+
+def oracle_after(orc, op, x0, k):
+    # the GPU state after k steps is C (S C)^(k - 1) S x0
+    st = orc.stream(op, x0)
+    st = orc.run(op, st, k - 1)
+    return orc.collide(op, st)
+
+
+@pytest.mark.parametrize("storage,inplace,tol", [("fp32", False, 1e-6), ("fp32", True, 1e-6),
+                                                 ("fp16", False, 1e-4)])
+def test_largest_lattice(lb, orc, storage, inplace, tol):
+    n = NX * NY
+    esize = 4 if storage == "fp32" else 2
+    need = (1 if inplace else 2) * 19 * n * esize + 5 * 8 * n
+    free, _ = torch.cuda.mem_get_info()
+    if free < 1.05 * need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
+    cfg = lb.LBMHDConfig(nx=NX, ny=NY, nu=1e-5, eta=1e-5, les=1, cs=0.1, storage=storage,
+                         inplace=inplace)
+    L = lb.Lattice(cfg)
+    assert (L.lattice_bytes // esize // 19) * 4 < 2 ** 32
+    dev = L.device
+    x = torch.arange(NX, device=dev, dtype=torch.float64) * (2 * math.pi / NX)
+    y = torch.arange(NY, device=dev, dtype=torch.float64) * (2 * math.pi / NY)
+    sy = torch.sin(y)[:, None].expand(NY, NX)
+    L.init_fields(torch.ones((), dtype=torch.float64, device=dev), -U0 * sy,
+                  (U0 * torch.sin(x))[None, :].expand(NY, NX), -B0 * sy,
+                  (B0 * torch.sin(2 * x))[None, :].expand(NY, NX))
+    torch.cuda.synchronize()
+    L._keep = None
+    d = L.diag()
+    assert abs(d["mass"] - n) <= 1e-8 * n
+    assert abs(d["e_kin"] - U0 ** 2 * n / 2) <= 1e-6 * U0 ** 2 * n
+    assert abs(d["e_mag"] - B0 ** 2 * n / 2) <= 1e-6 * B0 ** 2 * n
+    k = 2
+    L.step(k)
+    d = L.diag()                      # also returns an in-place lattice to its natural layout
+    assert d["nonfinite"] == 0 and abs(d["mass"] - n) <= 1e-6 * n
+    cur = L._a if (inplace or k % 2 == 0) else L._b
+    plane = L.lattice_bytes // esize // 19
+    pitch = plane // NY
+    raw = cur.view(torch.float32 if storage == "fp32" else torch.float16)
+    rng = np.random.default_rng(7)
+    sites = [(0, 0), (NX - 1, NY - 1), (0, NY - 1), (NX - 1, 0), (NX // 2, NY // 2), (NX - 1, 5)]
+    sites += [(int(a), int(b)) for a, b in zip(rng.integers(0, NX, 10), rng.integers(0, NY, 10))]
+    r = k + 2
+    op = orc.Params(2 * r + 1, 2 * r + 1, nu=cfg.nu, eta=cfg.eta, les=1, cs=cfg.cs)
+    for (sx, sy_) in sites:
+        idx = torch.tensor([q * plane + sy_ * pitch + sx for q in range(19)], device=dev)
+        v = raw[idx].double().cpu().numpy()
+        got = W19 + (v if storage == "fp32" else v / 1024.0)
+        xs = (np.arange(sx - r, sx + r + 1)) % NX
+        ys = (np.arange(sy_ - r, sy_ + r + 1)) % NY
+        want = oracle_after(orc, op, orc.init(op, *ot_patch(xs, ys)), k)[:, r, r]
+        err = float(np.abs(got - want).max())
+        assert err < tol, ((sx, sy_), err)
+    del raw, cur, L
+    torch.cuda.empty_cache()
