@@ -149,21 +149,26 @@ def inplace_leg(torch, args):
 
 def threed_leg(torch, args):
     """The 3D update (D3Q27 + six magnetic vectors, Smagorinsky-MHD closure)
-    on a 256^3 Orszag-Tang-type vortex, FP32: 45 populations, 360 B per
-    site-step."""
+    on a 256^3 Orszag-Tang-type vortex: 45 populations, 360 B per site-step in
+    FP32 storage, 180 B in FP16."""
     from lbmhd_inputs import orszag_tang_3d
     from paper_1607_08675_amd.lattice3 import Lattice3, LBMHD3Config
     n = 256
-    lat = Lattice3(LBMHD3Config(nx=n, ny=n, nz=n, nu=1e-5, eta=1e-5, les=1, cs=0.1))
-    lat.init_fields(*orszag_tang_3d(n, n, n))
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-    per_launch = burst_ms_per_launch(torch, lat, 100)
-    d = lat.diag()
-    log(f"3D 256^3 FP32: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
-    del lat
-    torch.cuda.empty_cache()
-    return dict(per_launch=per_launch, sites=n ** 3, nonfinite=d["nonfinite"])
+    fields = orszag_tang_3d(n, n, n)
+    out = dict(sites=n ** 3)
+    for st in ("fp32", "fp16"):
+        lat = Lattice3(LBMHD3Config(nx=n, ny=n, nz=n, nu=1e-5, eta=1e-5, les=1, cs=0.1,
+                                    storage=st))
+        lat.init_fields(*fields)
+        lat.step(args.warmup)
+        torch.cuda.synchronize()
+        per_launch = burst_ms_per_launch(torch, lat, 100)
+        d = lat.diag()
+        log(f"3D 256^3 {st.upper()}: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
+        out[st] = dict(per_launch=per_launch, nonfinite=d["nonfinite"])
+        del lat
+        torch.cuda.empty_cache()
+    return out
 
 
 CLOSURES = {2: "kinetic closure", 4: "cross-helicity closure"}
@@ -415,14 +420,21 @@ def main():
         },
     }
     if r3:
-        m3 = r3["sites"] / (r3["per_launch"] * 1e-3) / 1e6
-        a3 = 360 * r3["sites"] / (r3["per_launch"] * 1e-3) / 1e9
+        t32, t16 = r3["fp32"], r3["fp16"]
+        m3 = r3["sites"] / (t32["per_launch"] * 1e-3) / 1e6
+        a3 = 360 * r3["sites"] / (t32["per_launch"] * 1e-3) / 1e9
+        m316 = r3["sites"] / (t16["per_launch"] * 1e-3) / 1e6
+        a316 = 180 * r3["sites"] / (t16["per_launch"] * 1e-3) / 1e9
         line["three_d"] = {
             "workload": "3D Orszag-Tang-type vortex 256^3, FP32, D3Q27 + 6 magnetic vectors, "
                         "LES C_S=0.1, nu=eta=1e-5",
-            "mlups": round(m3, 1), "ms_per_step": round(r3["per_launch"], 5),
+            "mlups": round(m3, 1), "ms_per_step": round(t32["per_launch"], 5),
             "achieved_gbs": round(a3, 1), "frac": round(a3 / HBM_PEAK_GBS, 4),
-            "bytes_per_site": 360, "nonfinite": r3["nonfinite"],
+            "bytes_per_site": 360, "nonfinite": t32["nonfinite"],
+            "fp16": {"mlups": round(m316, 1), "ms_per_step": round(t16["per_launch"], 5),
+                     "achieved_gbs": round(a316, 1), "frac": round(a316 / HBM_PEAK_GBS, 4),
+                     "bytes_per_site": 180, "nonfinite": t16["nonfinite"],
+                     "speedup_vs_fp32_mlups": round(m316 / m3, 3)},
         }
     if rin:
         mi = rin["sites"] / (rin["per_launch"] * 1e-3) / 1e6

@@ -34,8 +34,9 @@
  * planes 27..32 the x component of g for C = +x, -x, +y, -y, +z, -z,
  * 33..38 the y component, 39..44 the z component.  The state is the
  * post-collision population at the current step (the step gathers from the
- * neighbours, then collides).  The lattice holds FP32 deviations f - w and g
- * in 45 planes of [z][y][row pitch padded to 256 bytes].
+ * neighbours, then collides).  The lattice holds the encoded deviations f - w
+ * and g (FP32, or FP16 scaled by 2^10, as `storage` selects) in 45 planes of
+ * [z][y][row pitch padded to 256 bytes].
  */
 #ifndef LBMHD3_H
 #define LBMHD3_H
@@ -52,12 +53,15 @@ extern "C" {
 typedef struct lbmhd3 lbmhd3_t;
 
 typedef struct {
-  int32_t nx, ny, nz;     /* periodic lattice, each >= 1; one FP32 plane (nz *
-                             ny * padded row) must stay below 4 GiB */
+  int32_t nx, ny, nz;     /* periodic lattice, each >= 1; one plane (nz * ny *
+                             padded row) must stay below 4 GiB */
   double nu, eta;         /* viscosity and resistivity in lattice units, > 0 */
   int32_t les;            /* 0: fixed rates; 1: Smagorinsky-MHD closure */
   double cs, cs_b;        /* closure constants C_Sv, C_Sb >= 0 */
   double delta;           /* filter width Delta > 0 */
+  int32_t storage;        /* LBMHD_FP32: deviations f - w (g as is) in FP32;
+                             LBMHD_FP16: half(2^10 (f - w)), round to nearest
+                             even (the 2D encodings); arithmetic in FP32 */
 } lbmhd3_params;
 
 typedef struct {

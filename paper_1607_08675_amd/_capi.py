@@ -59,6 +59,7 @@ class Params3(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("les", ctypes.c_int32),
         ("cs", ctypes.c_double), ("cs_b", ctypes.c_double), ("delta", ctypes.c_double),
+        ("storage", ctypes.c_int32),
     ]
 
 

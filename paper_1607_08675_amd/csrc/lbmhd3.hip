@@ -7,10 +7,12 @@
 //
 // One thread updates one site: it gathers the 45 post-collision populations
 // of the neighbours (pull streaming, all loads issued first), collides in
-// registers and writes 45 values to the other lattice.  HBM-bound: 45 x 4
-// bytes read + 45 x 4 bytes written per site.  Plane element offsets are
-// 32-bit byte offsets from a wavefront-uniform plane base (create checks that
-// a plane stays below 4 GiB).
+// registers and writes 45 values to the other lattice.  HBM-bound: 45 x e
+// bytes read + 45 x e bytes written per site, e = 4 (FP32 storage) or 2
+// (FP16).  Stored values are the deviations f - w (g as is), in FP32 or as
+// half(2^10 (f - w)) rounded to nearest even; the collision runs in FP32.
+// Plane element offsets are 32-bit byte offsets from a wavefront-uniform
+// plane base (create checks that a plane stays below 4 GiB).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -61,11 +63,36 @@ struct Rates3 {
   float cf, cm;           // 18 C_Sv Delta^2, 36 C_Sb Delta^2
 };
 
-__device__ __forceinline__ float ld(const float* __restrict__ base, unsigned off) {
-  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off * 4u);
+// Storage codecs: FP32 deviations, or FP16 deviations scaled by 2^10 (the
+// scaling is exact; the conversion to half rounds to nearest even).  The
+// empty asm keeps the FP32 value, so the conversion is not fused with the
+// multiply-add that produced it.
+template <int ST>
+struct Codec3;
+template <>
+struct Codec3<LBMHD_FP32> {
+  using T = float;
+  __device__ static __forceinline__ float dec(float v) { return v; }
+  __device__ static __forceinline__ float enc(float v) { return v; }
+};
+template <>
+struct Codec3<LBMHD_FP16> {
+  using T = _Float16;
+  __device__ static __forceinline__ float dec(_Float16 v) { return float(v) * 0x1p-10f; }
+  __device__ static __forceinline__ _Float16 enc(float v) {
+    asm("" : "+v"(v));
+    return _Float16(v * 0x1p10f);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off * unsigned(sizeof(T)));
 }
-__device__ __forceinline__ void st_nt(float* __restrict__ base, unsigned off, float v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off * 4u));
+template <typename T>
+__device__ __forceinline__ void st_nt(T* __restrict__ base, unsigned off, T v) {
+  __builtin_nontemporal_store(
+      v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off * unsigned(sizeof(T))));
 }
 
 // One collision at one site.  d[27] = f - w (deviations), g[18] (x, y, z
@@ -182,10 +209,11 @@ __device__ __forceinline__ void collide3(float (&d)[kQ], float (&g)[18], const R
 
 // Thread t of block b updates site x = (b mod tiles_x) * 256 + t of row
 // (y, z), b / tiles_x = z * ny + y.
-template <bool LES>
-__global__ __launch_bounds__(kThreads) void k_step3(const float* __restrict__ src,
-                                                    float* __restrict__ dst, Geom3 g, Rates3 r,
-                                                    int tiles_x) {
+template <int ST, bool LES>
+__global__ __launch_bounds__(kThreads) void k_step3(const typename Codec3<ST>::T* __restrict__ src,
+                                                    typename Codec3<ST>::T* __restrict__ dst,
+                                                    Geom3 g, Rates3 r, int tiles_x) {
+  using C = Codec3<ST>;
   const int x = (int(blockIdx.x) % tiles_x) * kThreads + int(threadIdx.x);
   const int row = int(blockIdx.x) / tiles_x;
   const int y = row % g.ny, z = row / g.ny;
@@ -198,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_step3(const float* __restrict__ sr
   for (int q = 0; q < kNPop; ++q) {
     const unsigned off = (unsigned(zs[kCz[q] + 1]) * unsigned(g.ny) + unsigned(ys[kCy[q] + 1])) *
                              g.pitch + unsigned(xs[kCx[q] + 1]);
-    v[q] = ld(src + q * g.plane, off);
+    v[q] = C::dec(ld(src + q * g.plane, off));
   }
   float d[kQ], gg[18];
 #pragma unroll
@@ -208,9 +236,9 @@ __global__ __launch_bounds__(kThreads) void k_step3(const float* __restrict__ sr
   collide3<LES>(d, gg, r);
   const unsigned o = (unsigned(z) * unsigned(g.ny) + unsigned(y)) * g.pitch + unsigned(x);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) st_nt(dst + i * g.plane, o, d[i]);
+  for (int i = 0; i < kQ; ++i) st_nt(dst + i * g.plane, o, C::enc(d[i]));
 #pragma unroll
-  for (int k = 0; k < 18; ++k) st_nt(dst + (kQ + k) * g.plane, o, gg[k]);
+  for (int k = 0; k < 18; ++k) st_nt(dst + (kQ + k) * g.plane, o, C::enc(gg[k]));
 }
 
 __device__ __forceinline__ long long site_index(const Geom3& g, long long s, unsigned* off) {
@@ -220,7 +248,8 @@ __device__ __forceinline__ long long site_index(const Geom3& g, long long s, uns
   return s;
 }
 
-// Equilibria of FP64 fields, stored as FP32 deviations.
+// Equilibria of FP64 fields, stored as deviations.
+template <int ST>
 __global__ __launch_bounds__(256) void k_init3(const double* __restrict__ rho,
                                                const double* __restrict__ ux,
                                                const double* __restrict__ uy,
@@ -228,7 +257,9 @@ __global__ __launch_bounds__(256) void k_init3(const double* __restrict__ rho,
                                                const double* __restrict__ bx,
                                                const double* __restrict__ by,
                                                const double* __restrict__ bz,
-                                               float* __restrict__ lat, Geom3 g) {
+                                               typename Codec3<ST>::T* __restrict__ lat,
+                                               Geom3 g) {
+  using C = Codec3<ST>;
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
@@ -249,7 +280,7 @@ __global__ __launch_bounds__(256) void k_init3(const double* __restrict__ rho,
       for (int b = 0; b < 3; ++b) cqc += c[a] * c[b] * P[a][b];
     }
     const double w = weight27(c[0], c[1], c[2]);
-    lat[i * g.plane + o] = float(w * ((r - 1.0) + 3.0 * cj + 4.5 * (cqc - tr)));
+    lat[i * g.plane + o] = C::enc(float(w * ((r - 1.0) + 3.0 * cj + 4.5 * (cqc - tr))));
   }
   for (int b = 0; b < 3; ++b)
     for (int k = 0; k < 6; ++k) {
@@ -257,12 +288,14 @@ __global__ __launch_bounds__(256) void k_init3(const double* __restrict__ rho,
       const int c[3] = {kCx[q], kCy[q], kCz[q]};
       const double cu = c[0] * U[0] + c[1] * U[1] + c[2] * U[2];
       const double cb = c[0] * B[0] + c[1] * B[1] + c[2] * B[2];
-      lat[q * g.plane + o] = float((B[b] + 3.0 * (cu * B[b] - cb * U[b])) / 6.0);
+      lat[q * g.plane + o] = C::enc(float((B[b] + 3.0 * (cu * B[b] - cb * U[b])) / 6.0));
     }
 }
 
-__global__ __launch_bounds__(256) void k_decode3(const float* __restrict__ lat,
+template <int ST>
+__global__ __launch_bounds__(256) void k_decode3(const typename Codec3<ST>::T* __restrict__ lat,
                                                  double* __restrict__ out, Geom3 g) {
+  using C = Codec3<ST>;
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
@@ -270,12 +303,15 @@ __global__ __launch_bounds__(256) void k_decode3(const float* __restrict__ lat,
   site_index(g, s, &o);
   for (int q = 0; q < kNPop; ++q) {
     const double w = q < kQ ? weight27(kCx[q], kCy[q], kCz[q]) : 0.0;
-    out[q * n + s] = w + double(lat[q * g.plane + o]);
+    out[q * n + s] = w + double(C::dec(lat[q * g.plane + o]));
   }
 }
 
+template <int ST>
 __global__ __launch_bounds__(256) void k_encode3(const double* __restrict__ in,
-                                                 float* __restrict__ lat, Geom3 g) {
+                                                 typename Codec3<ST>::T* __restrict__ lat,
+                                                 Geom3 g) {
+  using C = Codec3<ST>;
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
@@ -283,14 +319,16 @@ __global__ __launch_bounds__(256) void k_encode3(const double* __restrict__ in,
   site_index(g, s, &o);
   for (int q = 0; q < kNPop; ++q) {
     const double w = q < kQ ? weight27(kCx[q], kCy[q], kCz[q]) : 0.0;
-    lat[q * g.plane + o] = float(in[q * n + s] - w);
+    lat[q * g.plane + o] = C::enc(float(in[q * n + s] - w));
   }
 }
 
 // rho, u, B of the state in FP64 (7 fields of n)
-__global__ __launch_bounds__(256) void k_macro3(const float* __restrict__ lat,
+template <int ST>
+__global__ __launch_bounds__(256) void k_macro3(const typename Codec3<ST>::T* __restrict__ lat,
                                                 double* __restrict__ rho, double* __restrict__ u,
                                                 double* __restrict__ B, Geom3 g) {
+  using C = Codec3<ST>;
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
@@ -298,14 +336,14 @@ __global__ __launch_bounds__(256) void k_macro3(const float* __restrict__ lat,
   site_index(g, s, &o);
   double dr = 0.0, j[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < kQ; ++i) {
-    const double v = lat[i * g.plane + o];
+    const double v = C::dec(lat[i * g.plane + o]);
     dr += v;
     j[0] += kCx[i] * v;
     j[1] += kCy[i] * v;
     j[2] += kCz[i] * v;
   }
   for (int c = 0; c < 3; ++c)
-    for (int k = 0; k < 6; ++k) b[c] += lat[(kQ + 6 * c + k) * g.plane + o];
+    for (int k = 0; k < 6; ++k) b[c] += C::dec(lat[(kQ + 6 * c + k) * g.plane + o]);
   const double r = 1.0 + dr;
   rho[s] = r;
   for (int c = 0; c < 3; ++c) {
@@ -425,6 +463,16 @@ unsigned blocks3(long long n) { return unsigned((n + 255) / 256); }
 size_t ws_doubles3(long long n) {
   return 7 * size_t(n) + size_t(lbk3::kReduceBlocks) * lbk3::kRed + 16;
 }
+// rho, u (3 fields), B (3 fields) of the current state, FP64 device fields
+void launch_macro3(lbmhd3_t* h, double* rho, double* u, double* B) {
+  const dim3 grid(blocks3(sites3(h)));
+  if (h->p.storage == LBMHD_FP32)
+    hipLaunchKernelGGL(lbk3::k_macro3<LBMHD_FP32>, grid, dim3(256), 0, h->stream,
+                       static_cast<const float*>(h->lat[h->cur]), rho, u, B, h->geo);
+  else
+    hipLaunchKernelGGL(lbk3::k_macro3<LBMHD_FP16>, grid, dim3(256), 0, h->stream,
+                       static_cast<const _Float16*>(h->lat[h->cur]), rho, u, B, h->geo);
+}
 
 }  // namespace
 
@@ -437,6 +485,8 @@ int lbmhd3_create(const lbmhd3_params* p, lbmhd3_t** out) {
   if (!(p->nu > 0.0) || !(p->eta > 0.0) || !std::isfinite(p->nu) || !std::isfinite(p->eta))
     return LBMHD_ERR_INVALID_ARG;
   if (p->les != 0 && p->les != 1) return LBMHD_ERR_INVALID_ARG;
+  if (p->storage != LBMHD_FP32 && p->storage != LBMHD_FP16) return LBMHD_ERR_INVALID_ARG;
+  const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
   if (!(p->cs >= 0.0) || !(p->cs_b >= 0.0) || !std::isfinite(p->cs) || !std::isfinite(p->cs_b) ||
       !(p->delta > 0.0) || !std::isfinite(p->delta))
     return LBMHD_ERR_INVALID_ARG;
@@ -444,10 +494,10 @@ int lbmhd3_create(const lbmhd3_params* p, lbmhd3_t** out) {
   g.nx = p->nx;
   g.ny = p->ny;
   g.nz = p->nz;
-  g.pitch = unsigned((size_t(p->nx) * 4 + kAlign3 - 1) / kAlign3 * kAlign3 / 4);
+  g.pitch = unsigned((size_t(p->nx) * esize + kAlign3 - 1) / kAlign3 * kAlign3 / esize);
   g.plane = (long long)g.pitch * p->ny * p->nz;
   // in-plane byte offsets are 32-bit in the step kernel
-  if ((unsigned long long)g.plane * 4ull >= (1ull << 32)) return LBMHD_ERR_INVALID_ARG;
+  if ((unsigned long long)g.plane * esize >= (1ull << 32)) return LBMHD_ERR_INVALID_ARG;
   lbmhd3_t* h = new (std::nothrow) lbmhd3;
   if (!h) return LBMHD_ERR_INVALID_ARG;
   h->p = *p;
@@ -456,7 +506,7 @@ int lbmhd3_create(const lbmhd3_params* p, lbmhd3_t** out) {
   h->rates = lbk3::Rates3{float(1.0 / tau0), float(1.0 / taum0), float(tau0), float(tau0 * tau0),
                           float(taum0), float(taum0 * taum0), float(18.0 * p->cs * d2),
                           float(36.0 * p->cs_b * d2)};
-  h->lattice_bytes = size_t(lbk3::kNPop) * size_t(g.plane) * 4;
+  h->lattice_bytes = size_t(lbk3::kNPop) * size_t(g.plane) * esize;
   h->workspace_bytes =
       (ws_doubles3((long long)p->nx * p->ny * p->nz) * sizeof(double) + kAlign3 - 1) / kAlign3 *
       kAlign3;
@@ -506,8 +556,14 @@ int lbmhd3_init_fields(lbmhd3_t* h, const double* rho, const double* ux, const d
   if (int rc = need3(h)) return rc;
   if (!rho || !ux || !uy || !uz || !bx || !by || !bz)
     return fail3(h, LBMHD_ERR_INVALID_ARG, "null field");
-  hipLaunchKernelGGL(lbk3::k_init3, dim3(blocks3(sites3(h))), dim3(256), 0, h->stream, rho, ux,
-                     uy, uz, bx, by, bz, static_cast<float*>(h->lat[0]), h->geo);
+  if (h->p.storage == LBMHD_FP32)
+    hipLaunchKernelGGL(lbk3::k_init3<LBMHD_FP32>, dim3(blocks3(sites3(h))), dim3(256), 0,
+                       h->stream, rho, ux, uy, uz, bx, by, bz, static_cast<float*>(h->lat[0]),
+                       h->geo);
+  else
+    hipLaunchKernelGGL(lbk3::k_init3<LBMHD_FP16>, dim3(blocks3(sites3(h))), dim3(256), 0,
+                       h->stream, rho, ux, uy, uz, bx, by, bz,
+                       static_cast<_Float16*>(h->lat[0]), h->geo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail3(h, e, "init launch");
   h->cur = 0;
@@ -522,14 +578,27 @@ int lbmhd3_step(lbmhd3_t* h, int64_t nsteps) {
   const int tiles_x = (h->geo.nx + lbk3::kThreads - 1) / lbk3::kThreads;
   const dim3 grid(unsigned(tiles_x) * unsigned(h->geo.ny) * unsigned(h->geo.nz));
   for (int64_t t = 0; t < nsteps; ++t) {
-    const float* src = static_cast<const float*>(h->lat[h->cur]);
-    float* dst = static_cast<float*>(h->lat[1 - h->cur]);
-    if (les)
-      hipLaunchKernelGGL(lbk3::k_step3<true>, grid, dim3(lbk3::kThreads), 0, h->stream, src, dst,
-                         h->geo, h->rates, tiles_x);
-    else
-      hipLaunchKernelGGL(lbk3::k_step3<false>, grid, dim3(lbk3::kThreads), 0, h->stream, src,
-                         dst, h->geo, h->rates, tiles_x);
+    const void* src = h->lat[h->cur];
+    void* dst = h->lat[1 - h->cur];
+    if (h->p.storage == LBMHD_FP32) {
+      auto* a = static_cast<const float*>(src);
+      auto* b = static_cast<float*>(dst);
+      if (les)
+        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP32, true>), grid, dim3(lbk3::kThreads), 0,
+                           h->stream, a, b, h->geo, h->rates, tiles_x);
+      else
+        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP32, false>), grid, dim3(lbk3::kThreads), 0,
+                           h->stream, a, b, h->geo, h->rates, tiles_x);
+    } else {
+      auto* a = static_cast<const _Float16*>(src);
+      auto* b = static_cast<_Float16*>(dst);
+      if (les)
+        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP16, true>), grid, dim3(lbk3::kThreads), 0,
+                           h->stream, a, b, h->geo, h->rates, tiles_x);
+      else
+        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP16, false>), grid, dim3(lbk3::kThreads), 0,
+                           h->stream, a, b, h->geo, h->rates, tiles_x);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail3(h, e, "step launch");
     h->cur = 1 - h->cur;
@@ -541,8 +610,7 @@ int lbmhd3_step(lbmhd3_t* h, int64_t nsteps) {
 int lbmhd3_macro(lbmhd3_t* h, double* rho, double* u, double* B) {
   if (int rc = need3(h)) return rc;
   if (!rho || !u || !B) return fail3(h, LBMHD_ERR_INVALID_ARG, "null field");
-  hipLaunchKernelGGL(lbk3::k_macro3, dim3(blocks3(sites3(h))), dim3(256), 0, h->stream,
-                     static_cast<const float*>(h->lat[h->cur]), rho, u, B, h->geo);
+  launch_macro3(h, rho, u, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail3(h, e, "macro launch");
   return LBMHD_OK;
@@ -554,9 +622,7 @@ int lbmhd3_diag(lbmhd3_t* h, lbmhd3_diag_t* out) {
   const long long n = sites3(h);
   double* part = h->ws + 7 * n;
   double* res = part + size_t(lbk3::kReduceBlocks) * lbk3::kRed;
-  hipLaunchKernelGGL(lbk3::k_macro3, dim3(blocks3(n)), dim3(256), 0, h->stream,
-                     static_cast<const float*>(h->lat[h->cur]), h->ws, h->ws + n, h->ws + 4 * n,
-                     h->geo);
+  launch_macro3(h, h->ws, h->ws + n, h->ws + 4 * n);
   const int nb = int(std::min<long long>(lbk3::kReduceBlocks, blocks3(n)));
   hipLaunchKernelGGL(lbk3::k_reduce3, dim3(nb), dim3(256), 0, h->stream, h->ws, part, h->geo);
   hipLaunchKernelGGL(lbk3::k_final3, dim3(1), dim3(256), 0, h->stream, part, nb, res);
@@ -588,8 +654,12 @@ int lbmhd3_diag(lbmhd3_t* h, lbmhd3_diag_t* out) {
 int lbmhd3_get_populations(lbmhd3_t* h, double* out) {
   if (int rc = need3(h)) return rc;
   if (!out) return fail3(h, LBMHD_ERR_INVALID_ARG, "null output");
-  hipLaunchKernelGGL(lbk3::k_decode3, dim3(blocks3(sites3(h))), dim3(256), 0, h->stream,
-                     static_cast<const float*>(h->lat[h->cur]), out, h->geo);
+  if (h->p.storage == LBMHD_FP32)
+    hipLaunchKernelGGL(lbk3::k_decode3<LBMHD_FP32>, dim3(blocks3(sites3(h))), dim3(256), 0,
+                       h->stream, static_cast<const float*>(h->lat[h->cur]), out, h->geo);
+  else
+    hipLaunchKernelGGL(lbk3::k_decode3<LBMHD_FP16>, dim3(blocks3(sites3(h))), dim3(256), 0,
+                       h->stream, static_cast<const _Float16*>(h->lat[h->cur]), out, h->geo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail3(h, e, "decode launch");
   return LBMHD_OK;
@@ -598,8 +668,12 @@ int lbmhd3_get_populations(lbmhd3_t* h, double* out) {
 int lbmhd3_set_populations(lbmhd3_t* h, const double* in, int64_t step) {
   if (int rc = need3(h)) return rc;
   if (!in || step < 0) return fail3(h, LBMHD_ERR_INVALID_ARG, "null input or negative step");
-  hipLaunchKernelGGL(lbk3::k_encode3, dim3(blocks3(sites3(h))), dim3(256), 0, h->stream, in,
-                     static_cast<float*>(h->lat[0]), h->geo);
+  if (h->p.storage == LBMHD_FP32)
+    hipLaunchKernelGGL(lbk3::k_encode3<LBMHD_FP32>, dim3(blocks3(sites3(h))), dim3(256), 0,
+                       h->stream, in, static_cast<float*>(h->lat[0]), h->geo);
+  else
+    hipLaunchKernelGGL(lbk3::k_encode3<LBMHD_FP16>, dim3(blocks3(sites3(h))), dim3(256), 0,
+                       h->stream, in, static_cast<_Float16*>(h->lat[0]), h->geo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail3(h, e, "encode launch");
   h->cur = 0;

@@ -19,7 +19,8 @@ class LBMHD3Config:
     """nx, ny, nz: periodic lattice; nu, eta: viscosity and resistivity
     (tau0 = 3 nu + 1/2, tau_m0 = 3 eta + 1/2); les: 1 for the Smagorinsky-MHD
     closure; cs, cs_b: closure constants C_Sv and C_Sb (None: same as cs);
-    delta: filter width."""
+    delta: filter width; storage: "fp32" or "fp16" (deviation from the rest
+    state, FP16 scaled by 2^10)."""
     nx: int
     ny: int
     nz: int
@@ -29,10 +30,12 @@ class LBMHD3Config:
     cs: float = 0.1
     delta: float = 1.0
     cs_b: float | None = None
+    storage: str = "fp32"
 
     def c_params(self) -> C.Params3:
+        st = {"fp32": C.LBMHD_FP32, "fp16": C.LBMHD_FP16}[self.storage]
         return C.Params3(self.nx, self.ny, self.nz, self.nu, self.eta, int(self.les), self.cs,
-                         self.cs if self.cs_b is None else self.cs_b, self.delta)
+                         self.cs if self.cs_b is None else self.cs_b, self.delta, st)
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:

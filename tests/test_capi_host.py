@@ -114,14 +114,16 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
 
 
 def _params3(capi, **kw):
-    base = dict(nx=16, ny=8, nz=4, nu=0.01, eta=0.02, les=1, cs=0.1, cs_b=0.1, delta=1.0)
+    base = dict(nx=16, ny=8, nz=4, nu=0.01, eta=0.02, les=1, cs=0.1, cs_b=0.1, delta=1.0,
+                storage=capi.LBMHD_FP32)
     base.update(kw)
     return capi.Params3(*[base[n] for n, _ in capi.Params3._fields_])
 
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(nz=0), dict(nu=0.0), dict(eta=float("nan")), dict(les=2), dict(cs=-1.0),
-    dict(cs_b=-1.0), dict(delta=0.0), dict(nx=1 << 14, ny=1 << 14, nz=8),
+    dict(cs_b=-1.0), dict(delta=0.0), dict(nx=1 << 14, ny=1 << 14, nz=8), dict(storage=5),
+    dict(nx=1 << 14, ny=1 << 14, nz=16, storage=1),
 ])
 def test_3d_create_rejects_invalid_parameters(capi, bad):
     h = ctypes.c_void_p()
@@ -140,3 +142,16 @@ def test_3d_sizes_and_unbound_calls(capi):
     assert L.lbmhd3_step(h, 1) == capi.LBMHD_ERR_NOT_BOUND
     assert b"bind" in L.lbmhd3_last_error(h)
     assert L.lbmhd3_destroy(h) == 0 and L.lbmhd3_destroy(None) == 0
+    p16 = _params3(capi, nx=100, ny=6, nz=5, storage=capi.LBMHD_FP16)
+    assert L.lbmhd3_create(ctypes.byref(p16), ctypes.byref(h)) == 0
+    assert L.lbmhd3_sizes(h, ctypes.byref(lat), None) == 0
+    assert lat.value == 45 * 5 * 6 * 128 * 2      # 128 halves = 256 bytes per row
+    assert L.lbmhd3_destroy(h) == 0
+    # a plane of 2^14 x 2^14 x 4 sites takes 4 GiB in FP32 (refused: in-plane
+    # byte offsets are 32-bit) and 2 GiB in FP16 (accepted)
+    big = dict(nx=1 << 14, ny=1 << 14, nz=4)
+    assert L.lbmhd3_create(ctypes.byref(_params3(capi, **big)), ctypes.byref(h)) == \
+        capi.LBMHD_ERR_INVALID_ARG
+    p16 = _params3(capi, storage=capi.LBMHD_FP16, **big)
+    assert L.lbmhd3_create(ctypes.byref(p16), ctypes.byref(h)) == 0
+    assert L.lbmhd3_destroy(h) == 0

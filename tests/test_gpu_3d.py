@@ -155,3 +155,91 @@ def test_production_size_sampled_sites(lb3, o3):
         assert err < 1e-6, ((x, y, z), err)
     del pops, L
     torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------- FP16 storage
+def weights45(o3):
+    _, w27, _, _ = o3.lattice()
+    return np.concatenate([w27, np.zeros(18)])[:, None, None, None]
+
+
+def fp16_representable(o3, x):
+    """The state the FP16 lattice stores for x: half(float32(x - w) * 2^10) / 2^10 + w."""
+    w = weights45(o3)
+    h = ((x - w).astype(np.float32) * np.float32(1024)).astype(np.float16)
+    return w + h.astype(np.float64) / 1024.0
+
+
+@pytest.mark.parametrize("les", [0, 1])
+@pytest.mark.parametrize("nx,ny,nz", [(8, 8, 8), (37, 5, 3), (300, 4, 2), (2, 2, 2), (513, 2, 3)])
+def test_one_step_fp16(lb3, o3, nx, ny, nz, les):
+    """FP16 storage: encoding of a representable state is exact, and one step
+    lands within one half-precision rounding of the oracle's step."""
+    L, p = make(lb3, o3, nx, ny, nz, nu=0.01, eta=0.02, les=les, cs=0.15, cs_b=0.1, delta=1.3,
+                storage="fp16")
+    x0 = fp16_representable(o3, random_state(o3, p, nx * 100 + ny * 10 + nz + 1))
+    L.set_populations(x0)
+    np.testing.assert_array_equal(L.populations().cpu().numpy(), x0)
+    L.step(1)
+    got = L.populations().cpu().numpy()
+    want = after(o3, p, x0, 1)
+    dev = np.abs(want - weights45(o3))
+    assert np.all(np.abs(got - want) <= dev * 2.0 ** -11 + 1e-6)
+
+
+def test_fp16_codec_matches_numpy(lb3, o3):
+    """Stored halves are numpy's round-to-nearest-even of float32(f - w) * 2^10."""
+    L, p = make(lb3, o3, 40, 3, 2, storage="fp16")
+    x = random_state(o3, p, 11, amp=5e-2)
+    L.set_populations(x)
+    np.testing.assert_array_equal(L.populations().cpu().numpy(), fp16_representable(o3, x))
+
+
+@pytest.mark.parametrize("les", [0, 1])
+def test_orszag_tang_24_fp16(lb3, o3, les):
+    """FP16 storage on the 24^3 vortex: relative L2 of u and B within 1e-3
+    after 50 and 100 steps (the rounding of the stored deviations each step;
+    measured 2.8e-4 / 3.3e-4 at step 50 and 3.8e-4 / 4.2e-4 at step 100
+    without the closure, a little less with it); mass and energies within
+    1e-4."""
+    n = 24
+    L, p = make(lb3, o3, n, n, n, nu=0.01, eta=0.01, les=les, cs=0.1, storage="fp16")
+    f = orszag_tang_3d(n, n, n)
+    L.init_fields(*f)
+    st = o3.init(p, *f)
+    done = 0
+    for target, tol in ((50, 1e-3), (100, 1e-3)):
+        L.step(target - done)
+        st = o3.run(p, st, target - done)
+        done = target
+        g = {k: v.cpu().numpy() for k, v in L.macro().items()}
+        o = o3.macro(p, st)
+        for keys in (("ux", "uy", "uz"), ("bx", "by", "bz")):
+            num = np.sqrt(sum(np.sum((g[k] - o[k]) ** 2) for k in keys))
+            den = np.sqrt(sum(np.sum(o[k] ** 2) for k in keys))
+            assert num / den < tol, (target, keys, num / den)
+    d, do = L.diag(), o3.diag(p, st)
+    for key in ("mass", "e_kin", "e_mag"):
+        assert abs(d[key] - do[key]) < 1e-4 * abs(do[key]), key
+
+
+def test_production_size_sampled_sites_fp16(lb3, o3):
+    """256^3 vortex in FP16 storage, 2 steps, sampled sites against oracle
+    patches within 1e-4 (FP16 rounding of O(0.1) populations)."""
+    n, k, r = 256, 2, 3
+    f = orszag_tang_3d(n, n, n)
+    L, _ = make(lb3, o3, n, n, n, nu=1e-5, eta=1e-5, les=1, cs=0.1, storage="fp16")
+    L.init_fields(*f).step(k)
+    pops = L.populations()
+    rng = np.random.default_rng(5)
+    sites = [(0, 0, 0), (n - 1, n - 1, n - 1), (255, 17, 3)]
+    sites += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(9)]
+    p = o3.Params(2 * r + 1, 2 * r + 1, 2 * r + 1, nu=1e-5, eta=1e-5, les=1, cs=0.1)
+    for (x, y, z) in sites:
+        idx = [(np.arange(c - r, c + r + 1)) % n for c in (z, y, x)]
+        st = o3.init(p, *[a[np.ix_(*idx)] for a in f])
+        want = after(o3, p, st, k)[:, r, r, r]
+        err = np.abs(pops[:, z, y, x].cpu().numpy() - want).max()
+        assert err < 1e-4, ((x, y, z), err)
+    del pops, L
+    torch.cuda.empty_cache()
