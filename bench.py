@@ -294,6 +294,26 @@ def adjoint_leg(torch, args):
     log(f"adjoint kernel 4096^2: {out['adj_ms_4096']:.4f} ms, forward {out['fwd_ms_4096']:.4f} ms")
     del lat, st, lam, lam2, acc
     torch.cuda.empty_cache()
+    # the reverse step of the kinetic closure (two passes) at the same size
+    lat = Lattice(LBMHDConfig(nx=nb, ny=nb, nu=1e-5, eta=1e-5, les=2, cs=0.1, delta=1.0,
+                              storage="fp32"))
+    lat.init_fields(*orszag_tang(nb, nb)).step(10)
+    st = lat.save_state()
+    lam, lam2, acc = lat.new_adj_buffer(), lat.new_adj_buffer(), lat.new_adj_acc()
+    lat.adj_seed_energy(st, lam)
+    lat.adj_step(st, lam, lam2, acc)
+    torch.cuda.synchronize()
+    e0.record(lat.stream)
+    for _ in range(20):
+        lat.adj_step(st, lam, lam2, acc)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    out["adj_kin_ms_4096"] = e0.elapsed_time(e1) / 20
+    out["fwd_kin_ms_4096"] = burst_ms_per_launch(torch, lat, 50)
+    log(f"kinetic-closure adjoint 4096^2: {out['adj_kin_ms_4096']:.4f} ms, forward "
+        f"{out['fwd_kin_ms_4096']:.4f} ms")
+    del lat, st, lam, lam2, acc
+    torch.cuda.empty_cache()
     return out
 
 
@@ -493,6 +513,9 @@ def main():
             "adj_kernel_gbs_4096": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9, 1),
             "adj_kernel_frac_4096": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "ratio_to_forward_4096": round((radj["adj_ms_4096"] + radj["fwd_ms_4096"]) / radj["fwd_ms_4096"], 3),
+            "kinetic_closure_adj_ms_4096": round(radj["adj_kin_ms_4096"], 5),
+            "kinetic_closure_adj_gbs_4096": round(460 * 4096 * 4096 / (radj["adj_kin_ms_4096"] * 1e-3) / 1e9, 1),
+            "kinetic_closure_adj_over_forward_4096": round(radj["adj_kin_ms_4096"] / radj["fwd_kin_ms_4096"], 3),
         }
     if rfit:
         r = rfit["res"]

@@ -149,7 +149,8 @@ int lbmhd_destroy(lbmhd_t* h);
 
 /* Byte sizes the caller must allocate in device memory:
  *   lattice    -- one encoded population lattice (two are bound, one in place);
- *   workspace  -- scratch used by diagnostics, energy and reductions;
+ *   workspace  -- scratch used by diagnostics, energy and reductions, and
+ *                 with the kinetic closure by the adjoint step;
  *   adj_lattice -- one FP32 adjoint lattice (lambda), for the adjoint calls;
  *   adj_acc    -- the FP64 accumulator array of lbmhd_adj_step.
  * Any output pointer may be NULL. */
@@ -266,9 +267,12 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
                             const double* uy_t, const double* bx_t, const double* by_t,
                             double scale, float* lam);
 
-/* The adjoint calls below cover les = 0 and les = 1; with the kinetic or the
- * cross-helicity closure (les = 2, 3, 4, 6) lbmhd_adj_step returns
- * LBMHD_ERR_UNSUPPORTED. */
+/* The adjoint calls below cover les = 0, 1, 2 and 3.  With the kinetic
+ * closure (les = 2, 3) the step is taken in two passes: the equilibrium
+ * terms depend on the neighbours' moments, whose adjoints go back through
+ * the transposed gradient stencil (scratch planes in the workspace).  With
+ * the cross-helicity closure (les = 4, 6) lbmhd_adj_step and lbmhd_adj_sweep
+ * return LBMHD_ERR_UNSUPPORTED. */
 
 /* One reverse step: lam_prev = (dx_{n+1}/dx_n)^T lam_next (both in streamed
  * position), where state_n is the encoded lattice x_n (device, `lattice` bytes).  acc (device, adj_acc

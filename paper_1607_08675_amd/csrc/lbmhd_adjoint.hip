@@ -74,14 +74,26 @@ struct CsGrad {
   float v, b;
 };
 
+// Filter-width parts of the kinetic closure's equilibrium moments (added to
+// M3^eq, M4^eq, M7^eq = M8^eq and to the u x B term E of g^eq), or their
+// adjoints.
+struct KinTerms {
+  float m3, m4, m78, e;
+};
+
 // lam (19 values, in: adjoint of the post-collision populations; out:
 // adjoint of the pre-collision populations) for the collision at the
 // pre-collision state f[9], g[10] (deviation variables).  Returns the
-// site's contributions to dJ/dC_Sv and dJ/dC_Sb.
-template <bool LES>
+// site's contributions to dJ/dC_Sv and dJ/dC_Sb.  With KIN the equilibria
+// carry the kinetic closure's terms kc (held fixed here: their dependence on
+// the site's own and its neighbours' moments is taken by the caller from the
+// adjoints written to *kcb).
+template <bool LES, bool KIN = false>
 __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const float (&g)[10],
                                                  float (&lf)[9], float (&lg)[10],
-                                                 const Rates& r, const AdjConsts& ac) {
+                                                 const Rates& r, const AdjConsts& ac,
+                                                 const KinTerms& kc = KinTerms{0.f, 0.f, 0.f, 0.f},
+                                                 KinTerms* kcb = nullptr) {
   // ---- forward recompute of what the reverse sweep needs (same operations
   // as the forward collision)
   const float a13 = f[1] + f[3], a24 = f[2] + f[4];
@@ -100,9 +112,14 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
   const float Bx = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
   const float By = (g[5] + g[6]) + (g[7] + g[8]) + g[9];
   const float jxux = jx * ux, jyuy = jy * uy;
-  const float n3 = M3 - (jx * uy - Bx * By);
-  const float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
-  const float E = ux * By - uy * Bx;
+  float n3 = M3 - (jx * uy - Bx * By);
+  float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
+  float E = ux * By - uy * Bx;
+  if (KIN) {
+    n3 -= kc.m3;
+    n4 -= kc.m4;
+    E += kc.e;
+  }
   float s3q, sm, Q = 0.0f, Rr = 1.0f, tau = 1.0f, A = 0.0f, Rm = 1.0f, taum = 1.0f;
   if (LES) {
     Q = fsqrt(n4 * n4 + 4.0f * (n3 * n3));
@@ -179,7 +196,13 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
       nb3 += 4.0f * Qb * n3 * iQ;
     }
   }
-  // E = ux By - uy Bx
+  if (KIN) {
+    kcb->m3 = -nb3;
+    kcb->m4 = -nb4;
+    kcb->m78 = -(nb7 + nb8);
+    kcb->e = Eb;
+  }
+  // E = ux By - uy Bx (+ e)
   float uxb = Eb * By, uyb = -Eb * Bx;
   Byb += Eb * ux;
   Bxb -= Eb * uy;
@@ -445,6 +468,283 @@ __global__ void k_adj_fields(const float* __restrict__ lam, const double* __rest
   gby[s] = d;
 }
 
+// ------------------------------------------------------ kinetic closure
+// The kinetic closure's equilibrium terms depend on the gradients of
+// rho - 1, j, B over the eight neighbours (isotropic D2Q9 difference
+// d_a X = 3 sum_i w_i c_ia X(x + c_i)) and on the site's own moments, all of
+// the gathered pre-collision state.  The reverse step therefore takes two
+// passes.  Pass A, per site: recompute the forward terms, apply the transposed
+// collision Jacobian with those terms held fixed, carry the adjoints of the
+// terms back to the site's own moments (added to its populations in lam_prev)
+// and to the ten gradient components (written to scratch planes).  Pass B,
+// per site: add the transposed stencil of the neighbours' gradient adjoints
+// to the site's moment adjoints and map them onto its populations.  Pass A
+// walks strips of rows with a rolling 3-row LDS buffer of moments, as the
+// forward step does.
+constexpr int kAdjKinThreads = 512;
+constexpr int kAdjKinRows = 16;
+constexpr int kAdjKinCols = kAdjKinThreads + 2;
+
+// The closure's terms from the gradients gx, gy and the site's moments v of
+// (rho - 1, j_x, j_y, B_x, B_y); c12 = Delta^2 / 12.  Same operations as the
+// forward step.
+__device__ __forceinline__ KinTerms kin_terms(const float (&gx)[5], const float (&gy)[5],
+                                              const float (&v)[5], float c12) {
+  const float ir = frcp(1.0f + v[0]);
+  const float grx = gx[0] * ir, gry = gy[0] * ir;
+  float hx[4], hy[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    hx[k] = gx[k + 1] - v[k + 1] * grx;
+    hy[k] = gy[k + 1] - v[k + 1] * gry;
+  }
+  const float cr = c12 * ir;
+  const float jxjx = cr * (hx[0] * hx[0] + hy[0] * hy[0]);
+  const float jyjy = cr * (hx[1] * hx[1] + hy[1] * hy[1]);
+  KinTerms k;
+  k.m3 = cr * (hx[0] * hx[1] + hy[0] * hy[1]) - c12 * (gx[3] * gx[4] + gy[3] * gy[4]);
+  k.m4 = (jxjx - jyjy) - c12 * ((gx[3] * gx[3] + gy[3] * gy[3]) - (gx[4] * gx[4] + gy[4] * gy[4]));
+  k.m78 = -3.0f * (jxjx + jyjy);
+  k.e = cr * ((hx[0] * hx[3] + hy[0] * hy[3]) - (hx[1] * hx[2] + hy[1] * hy[2]));
+  return k;
+}
+
+// Adjoint of kin_terms: from the adjoints b of the four terms, the adjoints of
+// the gradients (gxb, gyb) and of the site's moments (vb).
+__device__ __forceinline__ void kin_terms_adjoint(const float (&gx)[5], const float (&gy)[5],
+                                                  const float (&v)[5], float c12,
+                                                  const KinTerms& b, float (&gxb)[5],
+                                                  float (&gyb)[5], float (&vb)[5]) {
+  const float ir = frcp(1.0f + v[0]);
+  const float grx = gx[0] * ir, gry = gy[0] * ir;
+  float hx[4], hy[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    hx[k] = gx[k + 1] - v[k + 1] * grx;
+    hy[k] = gy[k + 1] - v[k + 1] * gry;
+  }
+  const float cr = c12 * ir;
+  // jxjx enters m4 and m78, jyjy enters m4 (with a minus) and m78
+  const float jxjxb = b.m4 - 3.0f * b.m78, jyjyb = -b.m4 - 3.0f * b.m78;
+  const float crb = b.m3 * (hx[0] * hx[1] + hy[0] * hy[1]) +
+                    b.e * ((hx[0] * hx[3] + hy[0] * hy[3]) - (hx[1] * hx[2] + hy[1] * hy[2])) +
+                    jxjxb * (hx[0] * hx[0] + hy[0] * hy[0]) +
+                    jyjyb * (hx[1] * hx[1] + hy[1] * hy[1]);
+  const float hxb[4] = {cr * (b.m3 * hx[1] + b.e * hx[3] + 2.0f * jxjxb * hx[0]),
+                        cr * (b.m3 * hx[0] - b.e * hx[2] + 2.0f * jyjyb * hx[1]),
+                        -cr * b.e * hx[1], cr * b.e * hx[0]};
+  const float hyb[4] = {cr * (b.m3 * hy[1] + b.e * hy[3] + 2.0f * jxjxb * hy[0]),
+                        cr * (b.m3 * hy[0] - b.e * hy[2] + 2.0f * jyjyb * hy[1]),
+                        -cr * b.e * hy[1], cr * b.e * hy[0]};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) gxb[k] = gyb[k] = vb[k] = 0.0f;
+  // the product terms B B use the plain gradients
+  gxb[3] = -c12 * (b.m3 * gx[4] + 2.0f * b.m4 * gx[3]);
+  gxb[4] = -c12 * (b.m3 * gx[3] - 2.0f * b.m4 * gx[4]);
+  gyb[3] = -c12 * (b.m3 * gy[4] + 2.0f * b.m4 * gy[3]);
+  gyb[4] = -c12 * (b.m3 * gy[3] - 2.0f * b.m4 * gy[4]);
+  // h_k = g_(k+1) - v_(k+1) g_0 ir
+  float grxb = 0.0f, gryb = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    gxb[k + 1] += hxb[k];
+    gyb[k + 1] += hyb[k];
+    vb[k + 1] -= hxb[k] * grx + hyb[k] * gry;
+    grxb -= hxb[k] * v[k + 1];
+    gryb -= hyb[k] * v[k + 1];
+  }
+  gxb[0] += grxb * ir;
+  gyb[0] += gryb * ir;
+  const float irb = grxb * gx[0] + gryb * gy[0] + c12 * crb;
+  vb[0] -= irb * ir * ir;
+}
+
+// Adjoints of (rho - 1, j_x, j_y, B_x, B_y) added to the populations they are
+// sums of.
+__device__ __forceinline__ void add_moment_adjoints(const float (&m)[5], float (&lf)[9],
+                                                    float (&lg)[10]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lf[i] += m[0] + kCx[i] * m[1] + kCy[i] * m[2];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    lg[k] += m[3];
+    lg[5 + k] += m[4];
+  }
+}
+
+// Pass A.  Block: kAdjKinThreads columns x a strip of kAdjKinRows rows.
+// gb: ten planes (adjoint layout) for d/d(d_x X), then d/d(d_y X), X = rho - 1,
+// j_x, j_y, B_x, B_y.  nslots: the stride between the two slot arrays of acc.
+template <int ST, bool LES>
+__global__ __launch_bounds__(kAdjKinThreads) void k_adj_kin_a(
+    const typename Dec<ST>::T* __restrict__ st, const float* __restrict__ lam_next,
+    float* __restrict__ lam_prev, float* __restrict__ gb, double* __restrict__ acc, Geom geo,
+    Geom ga, Rates rt, AdjConsts ac, float c12, int tiles_x, int nslots) {
+  using D = Dec<ST>;
+  __shared__ float mac[3][5][kAdjKinCols];
+  const int tx = int(threadIdx.x);
+  const int xt = (int(blockIdx.x) % tiles_x) * kAdjKinThreads;
+  const int y0 = (int(blockIdx.x) / tiles_x) * kAdjKinRows;
+  const int y1 = min(y0 + kAdjKinRows, geo.ny);
+  const int x = xt + tx;
+  const bool active = x < geo.nx;
+  const int xc = x % geo.nx;
+  const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1) : (xt + kAdjKinThreads) % geo.nx;
+  const int ch = tx == 0 ? 0 : kAdjKinCols - 1;
+  const long long P = geo.plane, PA = ga.plane;
+  // gathered pre-collision populations of site (xx, yy): x_n(. - c_q)
+  auto gather = [&](int xx, int yy, float (&p)[19]) {
+    yy = yy < 0 ? yy + geo.ny : (yy >= geo.ny ? yy - geo.ny : yy);
+    const int xm = xx == 0 ? geo.nx - 1 : xx - 1, xp = xx == geo.nx - 1 ? 0 : xx + 1;
+    const int ym = yy == 0 ? geo.ny - 1 : yy - 1, yp = yy == geo.ny - 1 ? 0 : yy + 1;
+    const unsigned r0 = unsigned(yy) * geo.pitch, rm = unsigned(ym) * geo.pitch,
+                   rp = unsigned(yp) * geo.pitch;
+    const unsigned o[9] = {r0 + xx, r0 + xm, rm + xx, r0 + xp, rp + xx,
+                           rm + xm, rm + xp, rp + xp, rp + xm};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) p[i] = D::dec(ld_plane(st + i * P, o[i]));
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      p[9 + k] = D::dec(ld_plane(st + (9 + k) * P, o[k]));
+      p[14 + k] = D::dec(ld_plane(st + (14 + k) * P, o[k]));
+    }
+  };
+  auto moments = [&](const float (&p)[19], int slot, int col) {
+    mac[slot][0][col] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])) + p[8];
+    mac[slot][1][col] = (p[1] - p[3]) + (p[5] - p[7]) - (p[6] - p[8]);
+    mac[slot][2][col] = (p[2] - p[4]) + (p[5] - p[7]) + (p[6] - p[8]);
+    mac[slot][3][col] = (p[9] + p[10]) + (p[11] + p[12]) + p[13];
+    mac[slot][4][col] = (p[14] + p[15]) + (p[16] + p[17]) + p[18];
+  };
+  auto stage = [&](int yy, int slot, float (&p)[19]) {
+    gather(xc, yy, p);
+    moments(p, slot, tx + 1);
+    if (tx < 2) {
+      float q[19];
+      gather(xh, yy, q);
+      moments(q, slot, ch);
+    }
+  };
+  CsGrad dcs{0.0f, 0.0f};
+  float cur[19], nxt[19];
+  stage(y0 - 1, 0, nxt);
+  stage(y0, 1, cur);
+  for (int y = y0; y < y1; ++y) {
+    const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
+    stage(y + 1, sp, nxt);
+    __syncthreads();
+    if (active) {
+      const int c = tx + 1;
+      float gx[5], gy[5], v[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const float e = mac[s0][k][c + 1], w = mac[s0][k][c - 1];
+        const float nn = mac[sp][k][c], ss = mac[sm][k][c];
+        const float ne = mac[sp][k][c + 1], nw = mac[sp][k][c - 1];
+        const float se = mac[sm][k][c + 1], sw = mac[sm][k][c - 1];
+        gx[k] = (1.0f / 3.0f) * (e - w) + (1.0f / 12.0f) * ((ne - nw) + (se - sw));
+        gy[k] = (1.0f / 3.0f) * (nn - ss) + (1.0f / 12.0f) * ((ne + nw) - (se + sw));
+        v[k] = mac[s0][k][c];
+      }
+      const KinTerms kc = kin_terms(gx, gy, v, c12);
+      // lam_{n+1} of this site's populations, kept at x + c_i
+      const int xm = x == 0 ? geo.nx - 1 : x - 1, xp = x == geo.nx - 1 ? 0 : x + 1;
+      const int ym = y == 0 ? geo.ny - 1 : y - 1, yp = y == geo.ny - 1 ? 0 : y + 1;
+      const unsigned a0 = unsigned(y) * ga.pitch, am = unsigned(ym) * ga.pitch,
+                     ap = unsigned(yp) * ga.pitch;
+      const unsigned on[9] = {a0 + x, a0 + xp, ap + x, a0 + xm, am + x,
+                              ap + xp, ap + xm, am + xm, am + xp};
+      float lf[9], lg[10], f[9], g[10];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam_next + i * PA, on[i]);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        lg[k] = ld_plane(lam_next + (9 + k) * PA, on[k]);
+        lg[5 + k] = ld_plane(lam_next + (14 + k) * PA, on[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = cur[i];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) g[q] = cur[9 + q];
+      KinTerms kcb;
+      const CsGrad d = collide_adjoint<LES, true>(f, g, lf, lg, rt, ac, kc, &kcb);
+      dcs.v += d.v;
+      dcs.b += d.b;
+      float gxb[5], gyb[5], vb[5];
+      kin_terms_adjoint(gx, gy, v, c12, kcb, gxb, gyb, vb);
+      add_moment_adjoints(vb, lf, lg);
+      const unsigned oc = a0 + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st_plane_nt(lam_prev + i * PA, oc, lf[i]);
+#pragma unroll
+      for (int q = 0; q < 10; ++q) st_plane_nt(lam_prev + (9 + q) * PA, oc, lg[q]);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        st_plane_nt(gb + k * PA, oc, gxb[k]);
+        st_plane_nt(gb + (5 + k) * PA, oc, gyb[k]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 19; ++q) cur[q] = nxt[q];
+  }
+  if (LES) {
+    // the block's sums into acc[b] (C_Sv) and acc[nslots + b] (C_Sb), reduced
+    // in the (now idle) moment buffer
+    float* red = &mac[0][0][0];
+    static_assert(3 * 5 * kAdjKinCols >= 2 * kAdjKinThreads, "moment buffer too small");
+    red[tx] = dcs.v;
+    red[kAdjKinThreads + tx] = dcs.b;
+    __syncthreads();
+    if (tx == 0) {
+      double sv = 0.0, sb = 0.0;
+      for (int t = 0; t < kAdjKinThreads; ++t) {
+        sv += double(red[t]);
+        sb += double(red[kAdjKinThreads + t]);
+      }
+      acc[blockIdx.x] += sv;
+      acc[nslots + blockIdx.x] += sb;
+    }
+  }
+}
+
+// Pass B.  One thread per site: the transposed gradient stencil over the
+// neighbours' gradient adjoints, added to the site's moment adjoints.
+__global__ __launch_bounds__(256) void k_adj_kin_b(const float* __restrict__ gb,
+                                                   float* __restrict__ lam, Geom ga, int tiles_x) {
+  const int x = (int(blockIdx.x) % tiles_x) * 256 + int(threadIdx.x);
+  const int y = int(blockIdx.x) / tiles_x;
+  if (x >= ga.nx) return;
+  const int xm = x == 0 ? ga.nx - 1 : x - 1, xp = x == ga.nx - 1 ? 0 : x + 1;
+  const unsigned r0 = unsigned(y) * ga.pitch,
+                 rm = unsigned(y == 0 ? ga.ny - 1 : y - 1) * ga.pitch,
+                 rp = unsigned(y == ga.ny - 1 ? 0 : y + 1) * ga.pitch;
+  const long long PA = ga.plane;
+  float eta[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const float* bx = gb + k * PA;
+    const float* by = gb + (5 + k) * PA;
+    eta[k] = (1.0f / 3.0f) * ((ld_plane(bx, r0 + xm) - ld_plane(bx, r0 + xp)) +
+                              (ld_plane(by, rm + x) - ld_plane(by, rp + x))) +
+             (1.0f / 12.0f) * ((ld_plane(bx, rm + xm) + ld_plane(by, rm + xm)) +
+                               (ld_plane(by, rm + xp) - ld_plane(bx, rm + xp)) +
+                               (ld_plane(bx, rp + xm) - ld_plane(by, rp + xm)) -
+                               (ld_plane(bx, rp + xp) + ld_plane(by, rp + xp)));
+  }
+  const unsigned oc = r0 + x;
+  float lf[9], lg[10];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam + i * PA, oc);
+#pragma unroll
+  for (int q = 0; q < 10; ++q) lg[q] = ld_plane(lam + (9 + q) * PA, oc);
+  add_moment_adjoints(eta, lf, lg);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) st_plane_nt(lam + i * PA, oc, lf[i]);
+#pragma unroll
+  for (int q = 0; q < 10; ++q) st_plane_nt(lam + (9 + q) * PA, oc, lg[q]);
+}
+
 }  // namespace
 
 int adj_step_blocks(const Geom& g) {
@@ -475,6 +775,38 @@ hipError_t launch_adj_step(int storage, bool les, const void* state, const float
       hipLaunchKernelGGL((k_adj_step<LBMHD_FP16, false>), grid, block, 0, s, st, lam_next,
                          lam_prev, acc, g, ga, r, ac, tiles_x);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_step_kin(int storage, bool les, const void* state, const float* lam_next,
+                               float* lam_prev, float* gb, double* acc, const Geom& g,
+                               const Geom& ga, const Rates& r, double delta2, hipStream_t s) {
+  const int tiles_x = (g.nx + kAdjKinThreads - 1) / kAdjKinThreads;
+  const int strips = (g.ny + kAdjKinRows - 1) / kAdjKinRows;
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kAdjKinThreads);
+  const AdjConsts ac{float(18.0 * delta2), float(36.0 * delta2)};
+  const float c12 = float(delta2 / 12.0);
+  const int nslots = adj_step_blocks(g);
+  if (storage == LBMHD_FP32) {
+    auto* st = static_cast<const float*>(state);
+    if (les)
+      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP32, true>), grid, block, 0, s, st, lam_next,
+                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
+    else
+      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP32, false>), grid, block, 0, s, st, lam_next,
+                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
+  } else {
+    auto* st = static_cast<const _Float16*>(state);
+    if (les)
+      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP16, true>), grid, block, 0, s, st, lam_next,
+                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
+    else
+      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP16, false>), grid, block, 0, s, st, lam_next,
+                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
+  }
+  const int tb = (ga.nx + 255) / 256;
+  hipLaunchKernelGGL(k_adj_kin_b, dim3(unsigned(tb) * unsigned(ga.ny)), dim3(256), 0, s, gb,
+                     lam_prev, ga, tb);
   return hipGetLastError();
 }
 

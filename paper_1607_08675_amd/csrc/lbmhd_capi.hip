@@ -70,9 +70,14 @@ bool rate_ok(double s) { return s > 0.0 && s < 2.0; }
 
 // Workspace (doubles): per-block partials of the reductions, then 32 result
 // slots ([0, 16) diagnostics, [16] the C_Sv sum, [17] the mismatch, [18] the
-// C_Sb sum).  Its size does not depend on the lattice.
+// C_Sb sum); with the kinetic closure, ten FP32 planes in the adjoint layout
+// follow (the reverse step's gradient adjoints).
 size_t workspace_doubles() { return size_t(lbk::kDiagBlocks) * lbk::kDiagSlots + 32; }
 double* ws_out(lbmhd_t* h) { return h->ws + size_t(lbk::kDiagBlocks) * lbk::kDiagSlots; }
+float* ws_kin(lbmhd_t* h) {
+  return reinterpret_cast<float*>(reinterpret_cast<char*>(h->ws) +
+                                  round_up(workspace_doubles() * sizeof(double), kAlign));
+}
 
 int need_bound(lbmhd_t* h) {
   if (!h) return LBMHD_ERR_INVALID_ARG;
@@ -110,6 +115,18 @@ int natural(lbmhd_t* h, const void* state) {
     return current(h, &st);
   }
   return LBMHD_OK;
+}
+
+// One reverse step (state x, lam_next -> lam_prev) with the kernels of the
+// handle's closure.
+hipError_t adj_one(lbmhd_t* h, const void* x, const float* from, float* to, double* acc) {
+  const double d2 = h->p.delta * h->p.delta;
+  const bool smag = (h->p.les & 1) != 0;
+  if (h->p.les & 2)
+    return lbk::launch_adj_step_kin(h->p.storage, smag, x, from, to, ws_kin(h), acc, h->geo,
+                                    h->geoa, h->rates, d2, h->stream);
+  return lbk::launch_adj_step(h->p.storage, smag, x, from, to, acc, h->geo, h->geoa, h->rates,
+                              d2, h->stream);
 }
 
 // Run the diagnostics kernels on `lat` and copy the 16 results to host.
@@ -197,6 +214,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   h->lattice_bytes = size_t(lbk::kNPop) * size_t(g.plane) * esize;
   h->adj_lattice_bytes = size_t(lbk::kNPop) * size_t(ga.plane) * 4;
   h->workspace_bytes = round_up(workspace_doubles() * sizeof(double), kAlign);
+  if (p->les & 2) h->workspace_bytes += round_up(10 * size_t(ga.plane) * 4, kAlign);
   h->adj_acc_bytes = round_up(2 * size_t(lbk::adj_step_blocks(g)) * sizeof(double), kAlign);
   *out = h;
   return LBMHD_OK;
@@ -484,17 +502,15 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
 int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float* lam_prev,
                    double* acc) {
   if (int rc = need_bound(h)) return rc;
-  if (h->p.les & 6)
+  if (h->p.les & 4)
     return fail(h, LBMHD_ERR_UNSUPPORTED,
-                "the adjoint of the kinetic and cross-helicity closures is not provided");
+                "the adjoint of the cross-helicity closure is not provided");
   if (!state_n || !lam_next || !lam_prev || !acc)
     return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
   if (overlap(lam_next, h->adj_lattice_bytes, lam_prev, h->adj_lattice_bytes))
     return fail(h, LBMHD_ERR_INVALID_ARG, "lam_prev overlaps lam_next");
   if (int rc = natural(h, state_n)) return rc;
-  hipError_t e = lbk::launch_adj_step(h->p.storage, (h->p.les & 1) != 0, state_n, lam_next, lam_prev,
-                                        acc, h->geo, h->geoa, h->rates,
-                                        h->p.delta * h->p.delta, h->stream);
+  hipError_t e = adj_one(h, state_n, lam_next, lam_prev, acc);
   if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
   return LBMHD_OK;
 }
@@ -502,9 +518,9 @@ int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float
 int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t stride, int64_t n,
                     float* lam, float* tmp, double* acc) {
   if (int rc = need_bound(h)) return rc;
-  if (h->p.les & 6)
+  if (h->p.les & 4)
     return fail(h, LBMHD_ERR_UNSUPPORTED,
-                "the adjoint of the kinetic and cross-helicity closures is not provided");
+                "the adjoint of the cross-helicity closure is not provided");
   if (n < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
   if (n == 0) return LBMHD_OK;
   if (!src || !lam || !tmp || !acc || (n > 1 && !store))
@@ -514,8 +530,6 @@ int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t strid
   if (overlap(lam, h->adj_lattice_bytes, tmp, h->adj_lattice_bytes))
     return fail(h, LBMHD_ERR_INVALID_ARG, "tmp overlaps lam");
   if (int rc = natural(h, src)) return rc;
-  const bool les = (h->p.les & 1) != 0;
-  const double d2 = h->p.delta * h->p.delta;
   // the last step must write lam: with an odd count the sweep starts from tmp
   float* from = lam;
   float* to = tmp;
@@ -527,8 +541,7 @@ int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t strid
   }
   for (int64_t t = n - 1; t >= 0; --t) {
     const void* x = t == 0 ? src : static_cast<const char*>(store) + size_t(t - 1) * stride;
-    hipError_t e = lbk::launch_adj_step(h->p.storage, les, x, from, to, acc, h->geo, h->geoa,
-                                        h->rates, d2, h->stream);
+    hipError_t e = adj_one(h, x, from, to, acc);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
     std::swap(from, to);
   }

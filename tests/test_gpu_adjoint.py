@@ -364,3 +364,72 @@ def test_store_and_sweep_reject_bad_layouts(lb):
                                p(lam.data_ptr()), p(lam.data_ptr()),
                                p(acc.data_ptr())) == C.LBMHD_ERR_INVALID_ARG
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------ kinetic closure (les = 2, 3)
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("les", [2, 3])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (100, 36), (300, 5), (520, 7), (2, 2)])
+def test_kinetic_adjoint_step_dot_product(lb, orc, nx, ny, les, storage):
+    """<a, J b> = <J^T a, b> for one step with the kinetic closure (its
+    equilibrium terms depend on the neighbours' moments), alone and with the
+    Smagorinsky-MHD closure; J b from the oracle's dual numbers, filter width
+    1.3.  With les = 3 also the derivatives with respect to C_Sv and C_Sb."""
+    cfg = lb.LBMHDConfig(nx=nx, ny=ny, nu=0.01, eta=0.02, s5=1.2, s7=1.5, s8=0.8, les=les,
+                         cs=0.15, cs_b=0.1, delta=1.3, storage=storage)
+    L = lb.Lattice(cfg)
+    x = random_state(nx, ny, seed=3 * nx + ny)
+    L.set_populations(x)
+    x = stored(x, storage)
+    state = L.save_state()
+    rng = np.random.default_rng(nx * ny + les)
+    a = rng.standard_normal((19, ny, nx))
+    b = rng.standard_normal((19, ny, nx))
+    lam_next = _to_adj(L, a)
+    lam_prev = L.new_adj_buffer().fill_(float("nan"))
+    acc = L.new_adj_acc()
+    L.adj_step(state, lam_next, lam_prev, acc)
+    JTa = _from_adj(L, lam_prev)
+    assert np.isfinite(JTa).all()
+    op = orc.Params(nx, ny, nu=cfg.nu, eta=cfg.eta, s5=cfg.s5, s6=cfg.s5, s7=cfg.s7, s8=cfg.s8,
+                    les=les, cs=cfg.cs, csb=cfg.cs_b, delta=cfg.delta)
+    sx = orc.stream(op, x)
+    _, Jb = orc.tl_collide(op, sx, orc.stream(op, b)[None], np.zeros(1))
+    lhs, rhs = float(np.sum(a * Jb[0])), float(np.sum(JTa * b))
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(a * a) * np.sum(b * b)), (lhs, rhs)
+    dcs_gpu = L.adj_acc_total(acc)
+    _, Jc = orc.tl_collide(op, sx, np.zeros((2, 19, ny, nx)), np.eye(2))
+    for k in range(2):
+        want = float(np.sum(a * Jc[k]))
+        if les == 3:
+            assert abs(dcs_gpu[k] - want) <= 1e-5 * (abs(want) + np.sqrt(np.sum(a * a))), \
+                (k, dcs_gpu[k], want)
+        else:
+            assert dcs_gpu[k] == 0.0 and want == 0.0
+
+
+@pytest.mark.parametrize("les", [2, 3])
+def test_kinetic_energy_gradient_matches_oracle_tangent(lb, orc, les):
+    """dJ/d(u0, B0) (and dJ/dC_S with les = 3) through 50 steps with the
+    kinetic closure, several checkpoint segments (every 16), four seeded
+    directions, against the oracle's tangent within 1e-3."""
+    from paper_1607_08675_amd.adjoint import LBMHDFunction
+    nx, ny, steps = 48, 40, 50
+    cfg = lb.LBMHDConfig(nx=nx, ny=ny, nu=0.005, eta=0.005, les=les, cs=0.1, delta=1.0)
+    fields = perturbed_orszag_tang(nx, ny, u0=0.08, b0=0.08)
+    dev = torch.device("cuda")
+    t = [torch.tensor(f, dtype=torch.float64, device=dev, requires_grad=True) for f in fields[1:]]
+    cs = torch.tensor(cfg.cs, dtype=torch.float64, device=dev, requires_grad=True)
+    J = LBMHDFunction.apply(*t, cs, cfg, steps, 16)
+    J.backward()
+    d, dcs = directions(4, nx, ny, 200, 0.05, 0.05, 0.1)
+    op = orc.Params(nx, ny, nu=cfg.nu, eta=cfg.eta, les=les, cs=cfg.cs, delta=cfg.delta)
+    J_o, dJ = orc.tl_energy(op, fields, d, dcs, steps)
+    assert abs(float(J.detach()) - J_o) < 1e-6 * abs(J_o)
+    grads = [ti.grad.cpu().numpy() for ti in t]
+    for k in range(4):
+        g = sum(float(np.sum(grads[c] * d[k, c])) for c in range(4))
+        g += float(cs.grad) * dcs[k] if les == 3 else 0.0
+        assert abs(g - dJ[k]) <= 1e-3 * abs(dJ[k]) + 1e-9, (k, g, dJ[k])
+    if les == 2:
+        assert float(cs.grad) == 0.0

@@ -152,14 +152,3 @@ def test_conservation(lb, orc, les, nu):
     for key in ("mom_x", "mom_y", "flux_x", "flux_y"):
         assert abs(d1[key] - d0[key]) < 1e-7 * n * n, key
     assert d1["nonfinite"] == 0
-
-
-def test_adjoint_refuses_kinetic_closure(lb, orc):
-    from paper_1607_08675_amd._capi import LBMHD_ERR_UNSUPPORTED, LbmhdError
-    L, _ = make(lb, orc, 16, 16)
-    L.init_fields(*orszag_tang(16, 16))
-    st = L.save_state()
-    lam, lam2, acc = L.new_adj_buffer().zero_(), L.new_adj_buffer(), L.new_adj_acc()
-    with pytest.raises(LbmhdError) as e:
-        L.adj_step(st, lam, lam2, acc)
-    assert e.value.code == LBMHD_ERR_UNSUPPORTED
