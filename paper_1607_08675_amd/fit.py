@@ -10,8 +10,8 @@ state.  Each iteration runs the coarse model forward with checkpoints and
 returns L and dL/dC_Sv, dL/dC_Sb from one adjoint sweep; the constants are
 updated on their logs with sign-based steps (step x1.2 while the sign of the
 derivative holds, x0.5 when it flips), either tied (C_Sv = C_Sb) or jointly,
-one step size per constant.  The model is the Smagorinsky-MHD closure (the one
-the adjoint covers).  The arithmetic runs in the library's kernels; this module
+one step size per constant.  The model is the Smagorinsky-MHD closure, on its
+own or on top of the kinetic closure's filtered equilibria.  The arithmetic runs in the library's kernels; this module
 orders the calls and updates the constants.
 """
 from __future__ import annotations
@@ -49,7 +49,13 @@ def fit_cs(coarse_fields, targets, cfg: LBMHDConfig, steps: int, iters: int = 20
            every="auto", step0: float = 0.5, joint: bool = False, log=None) -> FitResult:
     """Minimise the relative mismatch over the closure constants, starting from
     cfg.cs (and cfg.cs_b).  joint=False fits one constant C_Sv = C_Sb; joint=True
-    fits C_Sv and C_Sb together, each with its own sign-based step on its log."""
+    fits C_Sv and C_Sb together, each with its own sign-based step on its log.
+    The model carries the Smagorinsky-MHD closure: alone (cfg.les = 0 or 1) or
+    measured from the kinetic closure's filtered equilibria (cfg.les = 2 or
+    3)."""
+    if cfg.les & 4:
+        raise ValueError("the cross-helicity closure has no adjoint to fit with")
+    les = 3 if cfg.les & 2 else 1
     norm = float(sum(torch.sum(torch.as_tensor(t) ** 2).item() for t in targets))
     res = FitResult()
     theta = [math.log(cfg.cs), math.log(cfg.csb)] if joint else [math.log(cfg.cs)]
@@ -58,7 +64,7 @@ def fit_cs(coarse_fields, targets, cfg: LBMHDConfig, steps: int, iters: int = 20
     t0 = time.perf_counter()
     for it in range(iters):
         csv, csb = math.exp(theta[0]), math.exp(theta[-1])
-        lat = Lattice(LBMHDConfig(**{**cfg.__dict__, "les": 1, "cs": csv, "cs_b": csb}))
+        lat = Lattice(LBMHDConfig(**{**cfg.__dict__, "les": les, "cs": csv, "cs_b": csb}))
         run = Checkpointed(lat, every)
         L = run.forward(coarse_fields, steps, targets=targets) / norm
         dv, db = run.backward(scale=1.0 / norm)[4:]

@@ -128,3 +128,21 @@ def test_joint_fit_recovers_both_constants(lb, orc):
     res = fit_cs(fields, targets, start, steps, iters=24, every=16, joint=True)
     assert res.loss[-1] < 1e-2 * res.loss[0], res.loss
     assert abs(res.cs[-1] - 0.2) < 0.02 and abs(res.cs_b[-1] - 0.1) < 0.01, (res.cs, res.cs_b)
+
+
+def test_fit_with_kinetic_closure_recovers_cs(lb, orc):
+    """Twin experiment with the Smagorinsky estimate on top of the kinetic
+    closure (les = 3, Delta = 1): targets at C_S = 0.2, the fit started at 0.05
+    returns to it through the two-pass kinetic reverse step."""
+    from paper_1607_08675_amd.fit import fit_cs
+    n, steps = 32, 60
+    fields = decaying_turbulence(n, n, u_rms=0.08, b_rms=0.08)
+    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-4, eta=1e-4, les=3, cs=0.2, delta=1.0)
+    L = lb.Lattice(cfg)
+    L.init_fields(*fields).step(steps)
+    m = L.macro()
+    targets = (m["ux"], m["uy"], m["bx"], m["by"])
+    start = lb.LBMHDConfig(**{**cfg.__dict__, "cs": 0.05})
+    res = fit_cs(fields, targets, start, steps, iters=14, every=16)
+    assert res.loss[-1] < 1e-2 * res.loss[0], res.loss
+    assert abs(res.cs[-1] - 0.2) < 0.01, res.cs
