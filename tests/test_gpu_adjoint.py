@@ -433,3 +433,50 @@ def test_kinetic_energy_gradient_matches_oracle_tangent(lb, orc, les):
         assert abs(g - dJ[k]) <= 1e-3 * abs(dJ[k]) + 1e-9, (k, g, dJ[k])
     if les == 2:
         assert float(cs.grad) == 0.0
+
+
+def test_kinetic_adjoint_full_size_patches(lb, orc):
+    """The kinetic-closure reverse step (les = 3) in its production launch
+    configuration, 4096^2: a on a 7x7 window, b on a 5x5 window around sampled
+    centres (corners included); the oracle evaluates J b on 13x13 patches of
+    the decoded GPU state after 3 steps (one step of this update reaches two
+    sites: the gather, then the neighbours' gradients)."""
+    n = 4096
+    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=3, cs=0.1, delta=1.0)
+    L = lb.Lattice(cfg)
+    L.init_fields(*perturbed_orszag_tang(n, n)).step(3)
+    state = L.save_state()
+    pops = L.populations()
+    op = orc.Params(13, 13, nu=cfg.nu, eta=cfg.eta, les=3, cs=cfg.cs, delta=cfg.delta)
+    rng = np.random.default_rng(11)
+    centres = [(0, 0), (n - 1, n - 1), (n - 1, 0), (513, 17)] + \
+        [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(4)]
+    R, ra, rb = 6, 3, 2
+    ti = torch.as_tensor
+    for (cx, cy) in centres:
+        ys = (np.arange(cy - R, cy + R + 1)) % n
+        xs = (np.arange(cx - R, cx + R + 1)) % n
+        d = np.maximum(np.abs(np.arange(-R, R + 1))[:, None], np.abs(np.arange(-R, R + 1))[None, :])
+        a = rng.standard_normal((19, 2 * R + 1, 2 * R + 1)) * (d <= ra)
+        b = rng.standard_normal((19, 2 * R + 1, 2 * R + 1)) * (d <= rb)
+        lam = L.new_adj_buffer().zero_()
+        L.adj_view(lam)[:, ti(ys).cuda()[:, None], ti(xs).cuda()[None, :]] = \
+            ti(streamed(a), dtype=torch.float32).cuda()
+        out = L.new_adj_buffer().zero_()
+        acc = L.new_adj_acc()
+        L.adj_step(state, lam, out, acc)
+        JTa = unstreamed(L.adj_view(out)[:, ti(ys).cuda()[:, None],
+                                          ti(xs).cuda()[None, :]].double().cpu().numpy())
+        rhs = float(np.sum(JTa * b))
+        x = pops[:, ti(ys).cuda()[:, None], ti(xs).cuda()[None, :]].cpu().numpy()
+        sx = orc.stream(op, x)
+        _, Jb = orc.tl_collide(op, sx, orc.stream(op, b)[None], np.zeros(1))
+        lhs = float(np.sum(a * Jb[0]))
+        scale = np.sqrt(np.sum(a * a) * np.sum(b * b))
+        assert abs(lhs - rhs) <= 2e-5 * scale, ((cx, cy), lhs, rhs)
+        _, Jc = orc.tl_collide(op, sx, np.zeros((1, 19, 2 * R + 1, 2 * R + 1)), np.ones(1))
+        want = float(np.sum(a * Jc[0]))
+        got = sum(L.adj_acc_total(acc))
+        assert abs(got - want) <= 2e-4 * abs(want) + 1e-5 * np.sqrt(np.sum(a * a)), ((cx, cy), got, want)
+    del pops, L
+    torch.cuda.empty_cache()
