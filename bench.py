@@ -434,7 +434,12 @@ def main():
         },
         "cpu_baseline": cpu,
         "error_bound": {
-            "fp32_rel_l2_uB": 1e-5, "fp16_rel_l2_uB": 1e-3,
+            "fp32_rel_l2_uB": 1e-5,
+            "fp32_workloads": "64^2 Orszag-Tang (nu = eta = 0.01) to step 1000, 256^2 "
+                              "turbulence (nu = eta = 1e-6) to step 1000",
+            "fp16_rel_l2_uB": {"step_100": 1.5e-3, "step_1000": 1.2e-2},
+            "fp16_workload": "256^2 turbulence, nu = eta = 1e-6 (FP16 rounding of the stored "
+                             "deviations; measured 8.4e-4 / 7.7e-3)",
             "checked_by": "tests/test_gpu_forward.py (oracle parity, 64^2/256^2 trajectories, "
                           "full-size sampled sites)",
         },
