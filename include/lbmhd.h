@@ -10,7 +10,12 @@
  * time step and the collide/stream split of Sec. 1.2 and Sec. 3.  Optionally
  * the relaxation times carry the Smagorinsky-MHD eddy viscosity and eddy
  * resistivity (Sec. 1.1, eqs. SmagorinskyClosure, SmagorinskyMHDClosureV/B),
- * computed per site from the site's own non-equilibrium moments.
+ * computed per site from the site's own non-equilibrium moments; the paper's
+ * kinetic closure (Sec. 4.1, filtered equilibria) and the cross-helicity
+ * closure (eqs. CHClosureV/B) are selected the same way (lbmhd_params.les).
+ * The library also runs the update in place on one lattice, and provides its
+ * discrete adjoint (reverse step, seeds, pull-back to the initial fields) for
+ * the gradients of a final-time functional.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
