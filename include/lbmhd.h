@@ -116,6 +116,17 @@ typedef struct {
                              that read the state, or take a state argument
                              that is the bound lattice itself, first return
                              a reversed lattice to the natural layout. */
+  int32_t steps_per_pass; /* How lbmhd_step covers pairs of steps when two
+                             lattices are bound and the closure reads no
+                             neighbours (les = 0 or 1): 0 (automatic) takes
+                             two steps per pass over the lattice, keeping the
+                             intermediate state on chip, when the lattice is
+                             large enough for that to pay (at least 512 tiles
+                             of 8 rows by 256 FP32 or 512 FP16 columns, e.g.
+                             1024^2 FP32, 2048^2 FP16); 2 always does; 1
+                             never does.  Either way the result is bit for bit
+                             that of single steps.  Other values are
+                             rejected. */
 } lbmhd_params;
 
 /* Global diagnostics of the current state, accumulated in FP64.
@@ -180,10 +191,18 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
                       const double* bx, const double* by);
 
 /* Advance nsteps >= 0 steps of stream + collide (Sec. 1.2 update with the
- * moment-space collision of Sec. 3; closures as selected by les).  One
- * fused kernel launch per step, ping-ponging the two bound lattices.
- * Asynchronous. */
+ * moment-space collision of Sec. 3; closures as selected by les), ping-ponging
+ * the two bound lattices (or updating the one lattice in place).  Each kernel
+ * launch fuses streaming and collision of one step, or, for pairs of steps
+ * as steps_per_pass selects, of two steps (the result is the same bit for
+ * bit).  Asynchronous. */
 int lbmhd_step(lbmhd_t* h, int64_t nsteps);
+
+/* Steps that one pass over the lattice covers when lbmhd_step advances an
+ * even number of steps on this handle: 2 where steps_per_pass (and, for 0,
+ * the lattice size) selects the two-step kernel for this closure and layout,
+ * else 1.  Host only.  Errors: LBMHD_ERR_INVALID_ARG for NULL arguments. */
+int lbmhd_steps_per_pass(const lbmhd_t* h, int32_t* out);
 
 /* One step from the encoded lattice src into dst (device, `lattice` bytes
  * each, 256-byte aligned; dst overlaps neither src nor the bound buffers, src

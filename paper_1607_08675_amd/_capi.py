@@ -27,7 +27,8 @@ LBMHD_FP16 = 1
 # Every function declared in include/lbmhd.h, in declaration order.
 EXPORTS = (
     "lbmhd_strerror", "lbmhd_last_error", "lbmhd_create", "lbmhd_destroy", "lbmhd_sizes",
-    "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_step_between", "lbmhd_step_store",
+    "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_steps_per_pass",
+    "lbmhd_step_between", "lbmhd_step_store",
     "lbmhd_macro",
     "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_get_populations",
     "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state", "lbmhd_get_step",
@@ -51,6 +52,7 @@ class Params(ctypes.Structure):
         ("les", ctypes.c_int32),
         ("cs", ctypes.c_double), ("cs_b", ctypes.c_double), ("delta", ctypes.c_double),
         ("storage", ctypes.c_int32), ("inplace", ctypes.c_int32),
+        ("steps_per_pass", ctypes.c_int32),
     ]
 
 
@@ -127,6 +129,7 @@ def lib():
             "lbmhd_save_state": [vp, vp],
             "lbmhd_load_state": [vp, vp, i64],
             "lbmhd_get_step": [vp, P(i64)],
+            "lbmhd_steps_per_pass": [vp, P(ctypes.c_int32)],
             "lbmhd_energy": [vp, vp, P(ctypes.c_double)],
             "lbmhd_adj_seed_energy": [vp, vp, vp],
             "lbmhd_adj_step": [vp, vp, vp, vp, vp],

@@ -46,6 +46,13 @@ hipError_t launch_one_step(const lbmhd_t* h, const void* src, void* dst) {
   return lbk::launch_step(h->p.storage, eddy == 1, src, dst, h->geo, h->rates, h->stream);
 }
 
+// Whether lbmhd_step covers pairs of steps with the two-step kernel.
+bool two_steps_per_pass(const lbmhd_t* h) {
+  const int spp = h->p.steps_per_pass;
+  return !h->p.inplace && !(h->p.les & 6) &&
+         (spp == 2 || (spp == 0 && lbk::step2_pays(h->p.storage, h->geo)));
+}
+
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int fail(lbmhd_t* h, int code, const std::string& msg) {
@@ -177,6 +184,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   // locations; closures that read the neighbours' populations cannot
   if (p->inplace != 0 && p->inplace != 1) return LBMHD_ERR_INVALID_ARG;
   if (p->inplace && (p->les & 6)) return LBMHD_ERR_INVALID_ARG;
+  if (p->steps_per_pass < 0 || p->steps_per_pass > 2) return LBMHD_ERR_INVALID_ARG;
   const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
   lbk::Geom g = make_geom(p->nx, p->ny, esize);
   lbk::Geom ga = make_geom(p->nx, p->ny, 4);
@@ -278,11 +286,27 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
   return LBMHD_OK;
 }
 
+int lbmhd_steps_per_pass(const lbmhd_t* h, int32_t* out) {
+  if (!h || !out) return LBMHD_ERR_INVALID_ARG;
+  *out = two_steps_per_pass(h) ? 2 : 1;
+  return LBMHD_OK;
+}
+
 int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   if (int rc = need_bound(h)) return rc;
   if (nsteps < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
   const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
-  for (int64_t t = 0; t < nsteps; ++t) {
+  int64_t t = 0;
+  if (two_steps_per_pass(h)) {
+    for (; t + 2 <= nsteps; t += 2) {
+      hipError_t e = lbk::launch_step2(h->p.storage, les, h->lat[h->cur], h->lat[1 - h->cur],
+                                       h->geo, h->rates, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "step launch");
+      h->cur = 1 - h->cur;
+      h->step += 2;
+    }
+  }
+  for (; t < nsteps; ++t) {
     hipError_t e;
     if (h->p.inplace) {
       e = lbk::launch_step_aa(h->p.storage, les, h->reversed ? 1 : 0, h->lat[0], h->geo,

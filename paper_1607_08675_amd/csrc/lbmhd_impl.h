@@ -47,6 +47,13 @@ constexpr int kDiagBlocks = 4096; // partials in the workspace (one per reducing
 // Forward step: dst = C(S(src)).
 hipError_t launch_step(int storage, bool les, const void* src, void* dst, const Geom& g,
                        const Rates& r, hipStream_t s);
+// Two forward steps in one pass: dst = C(S(C(S(src)))), equal to two
+// launch_step calls; src and dst must not overlap.
+hipError_t launch_step2(int storage, bool les, const void* src, void* dst, const Geom& g,
+                        const Rates& r, hipStream_t s);
+// Whether launch_step2 beats two launch_step calls on this lattice: it needs
+// enough blocks to fill the chip (measured crossover: 1024^2 FP32, 2048^2 FP16).
+bool step2_pays(int storage, const Geom& g);
 // In-place step on one lattice (AA pattern): phase 0 takes the natural
 // layout to the reversed one, phase 1 back; launch_unswap_aa turns a
 // reversed layout into the natural one in place.

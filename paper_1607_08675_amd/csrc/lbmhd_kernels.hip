@@ -40,11 +40,18 @@ struct Codec<LBMHD_FP16> {
   using T = _Float16;
   // deviation = half * 2^-10; scaling by a power of two is exact, the only
   // rounding is the RNE conversion of the FP32 value to half.  The empty asm
-  // keeps that FP32 value: without it the compiler may fuse the conversion
-  // with the multiply-add that produced v (v_fma_mix*), rounding straight to
-  // half, and kernels storing the same value would then differ in rare
-  // last bits.
-  __device__ static __forceinline__ float dec(_Float16 v) { return float(v) * 0x1p-10f; }
+  // statements pin the FP32 values on both sides.  Without them the compiler
+  // may fuse the conversion with the multiply-add that produced v
+  // (v_fma_mix*), rounding straight to half; and on decoding, it may fuse the
+  // exact scale of a decoded value into the add that consumes it, where
+  // a * b + dec(h) could otherwise have fused a * b, a choice that depends
+  // on the surrounding code.  Either way two kernels computing the same
+  // update would differ in rare last bits.
+  __device__ static __forceinline__ float dec(_Float16 v) {
+    float f = float(v) * 0x1p-10f;
+    asm("" : "+v"(f));
+    return f;
+  }
   __device__ static __forceinline__ _Float16 enc(float v) {
     asm("" : "+v"(v));
     return _Float16(v * 0x1p10f);
@@ -242,35 +249,24 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
 }
 
 // --------------------------------------------------------------- the step
-// dst(x) = C(pre(x)),  pre_i(x) = src_i(x - c_i) (periodic pull; Sec. 1.2
-// streaming written as a gather).  Thread t of block b updates sites
-// x0 .. x0 + V - 1 of row y, x0 = (b mod tiles_x) * 256 V + t V, y = b / tiles_x.
-// V > 1 requires nx % V == 0.
-template <int ST, int V, bool LES>
-__global__ __launch_bounds__(kStepThreads) void k_step(
-    const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
-    Geom geo, Rates rt, int tiles_x) {
+// Pre-collision values of the V consecutive sites x .. x + V - 1 of one row:
+// pre_q(x) = src_q(x - c_q), periodic.  xl and xr are the columns left of x
+// and right of x + V - 1 (wrapped); row[c_y + 1] is the source row of a plane
+// with velocity c_y.  A plane that streams along x is read as the aligned
+// vector of the sites plus one edge element.  V > 1 requires nx % V == 0.
+template <int ST, int V>
+__device__ __forceinline__ void gather_row(const typename Codec<ST>::T* __restrict__ src,
+                                           long long P, int x, int xl, int xr,
+                                           const unsigned (&row)[3], float (&v)[kNPop][V]) {
   using C = Codec<ST>;
   using T = typename C::T;
   using VT = typename Vec<T, V>::type;
-  const int x0 = ((int(blockIdx.x) % tiles_x) * kStepThreads + int(threadIdx.x)) * V;
-  const int y = int(blockIdx.x) / tiles_x;
-  if (x0 >= geo.nx) return;
-  const int xl = x0 == 0 ? geo.nx - 1 : x0 - 1;       // source of c_x = +1 planes
-  const int xr = x0 + V == geo.nx ? 0 : x0 + V;       // source of c_x = -1 planes
-  const int ym = y == 0 ? geo.ny - 1 : y - 1;
-  const int yp = y == geo.ny - 1 ? 0 : y + 1;
-  // source row of a plane with velocity c_y: y - c_y, indexed by c_y + 1
-  const unsigned row[3] = {unsigned(yp) * geo.pitch, unsigned(y) * geo.pitch,
-                           unsigned(ym) * geo.pitch};
-  const long long P = geo.plane;
-  float v[kNPop][V];
 #pragma unroll
   for (int q = 0; q < kNPop; ++q) {
     const T* __restrict__ base = src + q * P;
     const unsigned r = row[kPlaneCy[q] + 1];
     if (V == 1 || kPlaneCx[q] == 0) {
-      const int xs = kPlaneCx[q] == 0 ? x0 : (kPlaneCx[q] == 1 ? xl : xr);
+      const int xs = kPlaneCx[q] == 0 ? x : (kPlaneCx[q] == 1 ? xl : xr);
       const VT a = ld_plane<VT>(base, r + unsigned(xs));
       if constexpr (V == 1) {
         v[q][0] = C::dec(a);
@@ -279,7 +275,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
         for (int j = 0; j < V; ++j) v[q][j] = C::dec(a[j]);
       }
     } else if constexpr (V > 1) {
-      const VT a = ld_plane<VT>(base, r + unsigned(x0));
+      const VT a = ld_plane<VT>(base, r + unsigned(x));
       const float e = C::dec(ld_plane<T>(base, r + unsigned(kPlaneCx[q] == 1 ? xl : xr)));
 #pragma unroll
       for (int j = 0; j < V; ++j) {
@@ -290,7 +286,11 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
       }
     }
   }
-  float out[kNPop][V];
+}
+
+// One collision of each of the V sites in v (planes in the storage order).
+template <int V, bool LES>
+__device__ __forceinline__ void collide_sites(float (&v)[kNPop][V], const Rates& rt) {
 #pragma unroll
   for (int j = 0; j < V; ++j) {
     float f[9], g[10];
@@ -300,21 +300,210 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
     for (int k = 0; k < 10; ++k) g[k] = v[9 + k][j];
     collide<LES ? 1 : 0>(f, g, rt);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[i][j] = f[i];
+    for (int i = 0; i < 9; ++i) v[i][j] = f[i];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) out[9 + k][j] = g[k];
+    for (int k = 0; k < 10; ++k) v[9 + k][j] = g[k];
   }
-  const unsigned od = row[1] + unsigned(x0);
+}
+
+// Encode and store the V sites of v at element `off` of every plane.
+template <int ST, int V>
+__device__ __forceinline__ void store_row(typename Codec<ST>::T* __restrict__ dst, long long P,
+                                          unsigned off, const float (&v)[kNPop][V]) {
+  using C = Codec<ST>;
+  using VT = typename Vec<typename C::T, V>::type;
 #pragma unroll
   for (int q = 0; q < kNPop; ++q) {
     VT w;
     if constexpr (V == 1) {
-      w = C::enc(out[q][0]);
+      w = C::enc(v[q][0]);
     } else {
 #pragma unroll
-      for (int j = 0; j < V; ++j) w[j] = C::enc(out[q][j]);
+      for (int j = 0; j < V; ++j) w[j] = C::enc(v[q][j]);
     }
-    st_plane_nt<VT>(dst + q * P, od, w);
+    st_plane_nt<VT>(dst + q * P, off, w);
+  }
+}
+
+// dst(x) = C(pre(x)),  pre_i(x) = src_i(x - c_i) (periodic pull; Sec. 1.2
+// streaming written as a gather).  Thread t of block b updates sites
+// x0 .. x0 + V - 1 of row y, x0 = (b mod tiles_x) * 256 V + t V, y = b / tiles_x.
+// V > 1 requires nx % V == 0.
+template <int ST, int V, bool LES>
+__global__ __launch_bounds__(kStepThreads) void k_step(
+    const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
+    Geom geo, Rates rt, int tiles_x) {
+  const int x0 = ((int(blockIdx.x) % tiles_x) * kStepThreads + int(threadIdx.x)) * V;
+  const int y = int(blockIdx.x) / tiles_x;
+  if (x0 >= geo.nx) return;
+  const int xl = x0 == 0 ? geo.nx - 1 : x0 - 1;       // source of c_x = +1 planes
+  const int xr = x0 + V == geo.nx ? 0 : x0 + V;       // source of c_x = -1 planes
+  const int ym = y == 0 ? geo.ny - 1 : y - 1;
+  const int yp = y == geo.ny - 1 ? 0 : y + 1;
+  // source row of a plane with velocity c_y: y - c_y, indexed by c_y + 1
+  const unsigned row[3] = {unsigned(yp) * geo.pitch, unsigned(y) * geo.pitch,
+                           unsigned(ym) * geo.pitch};
+  float v[kNPop][V];
+  gather_row<ST, V>(src, geo.plane, x0, xl, xr, row, v);
+  collide_sites<V, LES>(v, rt);
+  store_row<ST, V>(dst, geo.plane, row[1] + unsigned(x0), v);
+}
+
+// ------------------------------------------- two steps in one pass over HBM
+// dst = C(S(C(S(src)))) for the closures that read no neighbours (plain and
+// Smagorinsky-MHD): temporal blocking.  A block of kT2Threads threads owns a
+// tile of W = kT2Threads V columns and a strip of `rows` rows of the output
+// and walks the strip upward.  Pass t first updates row r = y0 - 1 + t from
+// src (gathered as in k_step) on the tile's columns and on one halo column on
+// each side, then updates row r - 1 a second time from those results: its
+// pre-collision value of plane q is the first update's post-collision value
+// at x - c_q.  The intermediate state never reaches HBM.  Planes that move
+// along x are handed to the neighbouring columns through LDS, grouped by c_y:
+// a plane with c_y = +1 is read two passes after it is written, c_y = 0 one
+// pass after, c_y = -1 in the same pass, hence rings of 4, 3 and 2 row slots,
+// which lets one barrier per pass order every write before its reads and
+// every read before the slot is written again.  Planes with c_x = 0 stay in
+// the thread's registers for the same number of passes.  The intermediate
+// values pass through the storage codec, so that the result equals two
+// k_step launches.  HBM bytes per site for two steps: one read and one write
+// of the lattice, plus halo re-reads of 2 / rows of the rows and 4 / W of
+// the columns.
+constexpr int kT2Threads = 256;
+constexpr int kT2Slots = 30;   // 2 planes x 4 slots + 6 x 3 + 2 x 2
+// LDS group of each plane with c_x != 0 (0: c_y = +1, 1: c_y = 0, 2: c_y = -1)
+// and its index in the group; -1 for the register-held planes (c_x = 0).
+__device__ constexpr int kT2Group[kNPop] = {-1, 1, -1, 1, -1, 0, 0, 2, 2, -1,
+                                            1, -1, 1, -1, -1, 1, -1, 1, -1};
+__device__ constexpr int kT2Index[kNPop] = {0, 0, 0, 1, 0, 0, 1, 0, 1, 0,
+                                            2, 0, 3, 0, 0, 4, 0, 5, 0};
+// index of a c_x = 0 plane among the three of its c_y: {0, 9, 14} (c_y = 0),
+// {2, 11, 16} (c_y = +1), {4, 13, 18} (c_y = -1)
+__device__ constexpr int kT2Reg[kNPop] = {0, -1, 0, -1, 0, -1, -1, -1, -1, 1,
+                                          -1, 1, -1, 1, 2, -1, 2, -1, 2};
+
+template <int ST, int V, bool LES>
+__global__ __launch_bounds__(kT2Threads) void k_step2(
+    const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
+    Geom geo, Rates rt, int tiles_x, int rows) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  constexpr int W = kT2Threads * V;
+  __shared__ T lds[kT2Slots][W + 2];   // LDS column s holds local column s - 1
+  const int nx = geo.nx, ny = geo.ny;
+  const long long P = geo.plane;
+  const int x0 = (int(blockIdx.x) % tiles_x) * W;
+  const int y0 = (int(blockIdx.x) / tiles_x) * rows;
+  const int wt = min(W, nx - x0);          // columns of this tile
+  const int h = min(rows, ny - y0);        // output rows of this strip
+  const int lc = int(threadIdx.x) * V;     // first local column of the thread
+  const bool active = lc < wt;
+  const int x = x0 + lc;
+  const int xl = x == 0 ? nx - 1 : x - 1;
+  const int xr = x + V >= nx ? x + V - nx : x + V;
+  // threads 0 and 1 also update the halo columns x0 - 1 and x0 + wt (wrapped)
+  const bool halo = threadIdx.x < 2;
+  const int hx = threadIdx.x == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + wt == nx ? 0 : x0 + wt);
+  const int hs = threadIdx.x == 0 ? 0 : wt + 1;
+  const int hxl = hx == 0 ? nx - 1 : hx - 1;
+  const int hxr = hx == nx - 1 ? 0 : hx + 1;
+
+  // c_x = 0 planes of earlier passes: c_y = 0 from the last pass (zc), c_y = +1
+  // from the last two (zu1, zu2)
+  float zc[3][V], zu1[3][V], zu2[3][V];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < V; ++j) zc[k][j] = zu1[k][j] = zu2[k][j] = 0.0f;
+  int sB = 0;   // t mod 3
+  for (int t = 0; t < h + 2; ++t) {
+    const int sA = t & 3, sC = t & 1;
+    int r = y0 - 1 + t;
+    r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+    const int rm = r == 0 ? ny - 1 : r - 1;
+    const int rp = r == ny - 1 ? 0 : r + 1;
+    const unsigned row[3] = {unsigned(rp) * geo.pitch, unsigned(r) * geo.pitch,
+                             unsigned(rm) * geo.pitch};
+    // first update of row r; c_x = 0 planes kept by c_y (nc: 0, nu: +1, nd: -1)
+    float nc[3][V], nu[3][V], nd[3][V];
+    if (active) {
+      float v[kNPop][V];
+      gather_row<ST, V>(src, P, x, xl, xr, row, v);
+      collide_sites<V, LES>(v, rt);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          const T e = C::enc(v[q][j]);
+          const int g = kT2Group[q], i = kT2Index[q], k = kT2Reg[q];
+          if (g == 0)
+            lds[sA * 2 + i][lc + j + 1] = e;
+          else if (g == 1)
+            lds[8 + sB * 6 + i][lc + j + 1] = e;
+          else if (g == 2)
+            lds[26 + sC * 2 + i][lc + j + 1] = e;
+          else if (kPlaneCy[q] == 0)
+            nc[k][j] = C::dec(e);
+          else if (kPlaneCy[q] == 1)
+            nu[k][j] = C::dec(e);
+          else
+            nd[k][j] = C::dec(e);
+        }
+      }
+    }
+    if (halo) {
+      float v[kNPop][1];
+      gather_row<ST, 1>(src, P, hx, hxl, hxr, row, v);
+      collide_sites<1, LES>(v, rt);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const T e = C::enc(v[q][0]);
+        const int g = kT2Group[q], i = kT2Index[q];
+        if (g == 0)
+          lds[sA * 2 + i][hs] = e;
+        else if (g == 1)
+          lds[8 + sB * 6 + i][hs] = e;
+        else if (g == 2)
+          lds[26 + sC * 2 + i][hs] = e;
+      }
+    }
+    __syncthreads();
+    // second update of row r - 1 (from pass 2 on)
+    if (t >= 2 && active) {
+      const int sB1 = sB == 0 ? 2 : sB - 1;   // (t - 1) mod 3
+      const int sA2 = (t - 2) & 3;
+      float v[kNPop][V];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          const int g = kT2Group[q], i = kT2Index[q], k = kT2Reg[q];
+          const int sx = lc + j - kPlaneCx[q] + 1;
+          if (g == 0)
+            v[q][j] = C::dec(lds[sA2 * 2 + i][sx]);
+          else if (g == 1)
+            v[q][j] = C::dec(lds[8 + sB1 * 6 + i][sx]);
+          else if (g == 2)
+            v[q][j] = C::dec(lds[26 + sC * 2 + i][sx]);
+          else if (kPlaneCy[q] == 0)
+            v[q][j] = zc[k][j];
+          else if (kPlaneCy[q] == 1)
+            v[q][j] = zu2[k][j];
+          else
+            v[q][j] = nd[k][j];
+        }
+      }
+      collide_sites<V, LES>(v, rt);
+      store_row<ST, V>(dst, P, unsigned(y0 + t - 2) * geo.pitch + unsigned(x), v);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        zu2[k][j] = zu1[k][j];
+        zu1[k][j] = active ? nu[k][j] : 0.0f;
+        zc[k][j] = active ? nc[k][j] : 0.0f;
+      }
+    sB = sB == 2 ? 0 : sB + 1;
   }
 }
 
@@ -1012,6 +1201,30 @@ void launch_step_v(bool les, const void* src, void* dst, const Geom& g, const Ra
     hipLaunchKernelGGL((k_step<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x);
 }
 
+// Strip height of the two-step kernel: the tallest strip (at most 64 rows,
+// a 2 / rows halo overhead) that still gives about 1024 blocks, at least 8.
+static int step2_rows(const Geom& g, int V) {
+  const long long tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
+  const long long rows = tiles_x * g.ny / 1024;
+  return int(rows < 8 ? 8 : (rows > 64 ? 64 : rows));
+}
+
+template <int ST, int V>
+void launch_step2_v(bool les, const void* src, void* dst, const Geom& g, const Rates& r,
+                    hipStream_t s) {
+  using T = typename Codec<ST>::T;
+  const int rows = step2_rows(g, V);
+  const int tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
+  const int strips = (g.ny + rows - 1) / rows;
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kT2Threads);
+  auto* a = static_cast<const T*>(src);
+  auto* b = static_cast<T*>(dst);
+  if (les)
+    hipLaunchKernelGGL((k_step2<ST, V, true>), grid, block, 0, s, a, b, g, r, tiles_x, rows);
+  else
+    hipLaunchKernelGGL((k_step2<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x, rows);
+}
+
 template <int ST, int EDDY, bool KIN>
 void launch_step_nb_t(const void* src, void* dst, const Geom& g, const Rates& r, float c12,
                       hipStream_t s) {
@@ -1054,6 +1267,23 @@ hipError_t launch_step(int storage, bool les, const void* src, void* dst, const 
     launch_step_v<LBMHD_FP16, 2>(les, src, dst, g, r, s);
   else
     launch_step_v<LBMHD_FP16, 1>(les, src, dst, g, r, s);
+  return hipGetLastError();
+}
+
+bool step2_pays(int storage, const Geom& g) {
+  const int V = storage == LBMHD_FP16 && g.nx % 2 == 0 ? 2 : 1;
+  const long long tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
+  return tiles_x * ((g.ny + 7) / 8) >= 512;
+}
+
+hipError_t launch_step2(int storage, bool les, const void* src, void* dst, const Geom& g,
+                        const Rates& r, hipStream_t s) {
+  if (storage == LBMHD_FP32)
+    launch_step2_v<LBMHD_FP32, 1>(les, src, dst, g, r, s);
+  else if (g.nx % 2 == 0)
+    launch_step2_v<LBMHD_FP16, 2>(les, src, dst, g, r, s);
+  else
+    launch_step2_v<LBMHD_FP16, 1>(les, src, dst, g, r, s);
   return hipGetLastError();
 }
 

@@ -33,6 +33,10 @@ class LBMHDConfig:
     storage: "fp32" or "fp16" (deviation from the rest state, FP16 scaled by 2^10).
     inplace: one lattice updated in place (AA pattern) instead of two; not with
     the closures that read neighbours (les = 2, 3, 4, 6).
+    steps_per_pass: with two lattices and les = 0 or 1, step() can advance two
+    steps per pass over the lattice with the intermediate state kept on chip,
+    bit for bit equal to single steps: 0 (default) where the lattice is large
+    enough for it to pay, 2 always, 1 never.
     """
     nx: int
     ny: int
@@ -47,6 +51,7 @@ class LBMHDConfig:
     storage: str = "fp32"
     cs_b: float | None = None
     inplace: bool = False
+    steps_per_pass: int = 0
 
     @property
     def csb(self) -> float:
@@ -56,7 +61,7 @@ class LBMHDConfig:
         st = {"fp32": C.LBMHD_FP32, "fp16": C.LBMHD_FP16}[self.storage]
         return C.Params(self.nx, self.ny, self.nu, self.eta, self.s5, self.s5, self.s7,
                         self.s8, int(self.les), self.cs, self.csb, self.delta, st,
-                        int(self.inplace))
+                        int(self.inplace), int(self.steps_per_pass))
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
@@ -210,6 +215,14 @@ class Lattice:
     def step_count(self) -> int:
         v = ctypes.c_int64()
         self._check(self._L.lbmhd_get_step(self._h, ctypes.byref(v)), "lbmhd_get_step")
+        return v.value
+
+    @property
+    def steps_per_pass(self) -> int:
+        """Steps one kernel pass covers in step() for pairs of steps (1 or 2)."""
+        v = ctypes.c_int32()
+        self._check(self._L.lbmhd_steps_per_pass(self._h, ctypes.byref(v)),
+                    "lbmhd_steps_per_pass")
         return v.value
 
     def energy(self, state: torch.Tensor | None = None) -> float:

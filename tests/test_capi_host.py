@@ -45,7 +45,8 @@ def test_every_declared_function_is_exported(capi):
 
 def _params(capi, **kw):
     base = dict(nx=64, ny=48, nu=0.01, eta=0.02, s5=1.0, s6=1.0, s7=1.1, s8=0.9, les=1,
-                cs=0.1, cs_b=0.1, delta=1.0, storage=capi.LBMHD_FP32, inplace=0)
+                cs=0.1, cs_b=0.1, delta=1.0, storage=capi.LBMHD_FP32, inplace=0,
+                steps_per_pass=0)
     base.update(kw)
     return capi.Params(*[base[n] for n, _ in capi.Params._fields_])
 
@@ -60,7 +61,7 @@ def _create(capi, p):
     dict(nx=1), dict(ny=0), dict(nu=0.0), dict(eta=-1.0), dict(nu=float("nan")),
     dict(s5=2.0), dict(s7=0.0), dict(s8=-0.5), dict(s5=1.1, s6=1.2), dict(les=5), dict(les=7), dict(les=-1),
     dict(cs=-0.1), dict(cs_b=-0.1), dict(cs_b=float("inf")), dict(delta=0.0),
-    dict(inplace=2), dict(inplace=1, les=2), dict(inplace=1, les=4), dict(inplace=1, les=6), dict(storage=7), dict(nx=70000, ny=70000),
+    dict(inplace=2), dict(steps_per_pass=3), dict(steps_per_pass=-1), dict(inplace=1, les=2), dict(inplace=1, les=4), dict(inplace=1, les=6), dict(storage=7), dict(nx=70000, ny=70000),
 ])
 def test_create_rejects_invalid_parameters(capi, bad):
     rc, h = _create(capi, _params(capi, **bad))
@@ -82,6 +83,29 @@ def test_sizes_and_layout(capi):
         assert ws >= 16 * 8 and ws % 256 == 0   # reduction partials and results only
         assert acc % 256 == 0 and acc >= 2 * 8 * 36   # two slot arrays, >= 1 block per row
         assert L.lbmhd_destroy(h) == 0
+
+
+@pytest.mark.parametrize("kw,want", [
+    (dict(nx=4096, ny=4096), 2), (dict(nx=1024, ny=1024), 2), (dict(nx=512, ny=512), 1),
+    (dict(nx=2048, ny=2048, storage=1), 2), (dict(nx=1024, ny=1024, storage=1), 1),
+    (dict(nx=1023, ny=1024, storage=1), 2), (dict(nx=64, ny=48, steps_per_pass=2), 2),
+    (dict(nx=4096, ny=4096, steps_per_pass=1), 1), (dict(nx=4096, ny=4096, les=0), 2),
+    (dict(nx=4096, ny=4096, les=2), 1), (dict(nx=4096, ny=4096, les=4), 1),
+    (dict(nx=4096, ny=4096, inplace=1), 1), (dict(nx=64, ny=48, inplace=1, steps_per_pass=2), 1),
+])
+def test_steps_per_pass_selection(capi, kw, want):
+    """Two steps per pass only for two lattices and a closure without
+    neighbour terms; automatically from 512 tiles of 8 rows (256 FP32 or
+    FP16-odd-nx columns, 512 FP16 columns) up, always with 2, never with 1."""
+    rc, h = _create(capi, _params(capi, **kw))
+    assert rc == 0
+    try:
+        v = ctypes.c_int32()
+        assert capi.lib().lbmhd_steps_per_pass(h, ctypes.byref(v)) == 0
+        assert v.value == want
+        assert capi.lib().lbmhd_steps_per_pass(h, None) == capi.LBMHD_ERR_INVALID_ARG
+    finally:
+        capi.lib().lbmhd_destroy(h)
 
 
 def test_calls_before_bind_are_refused(capi):

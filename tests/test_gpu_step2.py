@@ -1,0 +1,108 @@
+"""Two steps per pass over the lattice (temporal blocking) against single steps
+and against the oracle (GPU).
+
+A fused pass keeps the intermediate state on chip in the storage encoding, so
+n steps taken two per pass must reproduce n single steps bit for bit: full and
+ragged tiles (256 columns FP32, 512 FP16 with nx even, 256 FP16 with nx odd),
+ragged strips, tiny periodic lattices where the halo columns and rows wrap onto
+the tile itself, odd step counts, and the largest headline lattice.  The
+oracle comparison repeats the forward parity bound on the fused path itself.
+"""
+import numpy as np
+import pytest
+import torch
+
+from lbmhd_inputs import decaying_turbulence, orszag_tang, random_fields
+from state_words import stored_words
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_08675_amd import lattice
+    return lattice
+
+
+def stored(L):
+    return stored_words(L)
+
+
+def pair(lb, fields, n, **kw):
+    out = []
+    for spp in (1, 2):
+        L = lb.Lattice(lb.LBMHDConfig(steps_per_pass=spp, **kw))
+        L.init_fields(*fields).step(n)
+        assert L.step_count == n
+        out.append(stored(L))
+    return out
+
+
+CASES = [
+    ("fp32", 256, 64), ("fp32", 300, 70), ("fp32", 2, 2), ("fp32", 3, 5), ("fp32", 513, 9),
+    ("fp16", 512, 40), ("fp16", 600, 70), ("fp16", 2, 2), ("fp16", 1030, 17),
+    ("fp16", 301, 33), ("fp16", 3, 3),
+]
+
+
+@pytest.mark.parametrize("storage,nx,ny", CASES)
+@pytest.mark.parametrize("les", [0, 1])
+@pytest.mark.parametrize("n", [5, 6])
+def test_fused_equals_single_steps(lb, storage, nx, ny, les, n):
+    fields = random_fields(nx, ny, 7 + nx + ny)
+    a, b = pair(lb, fields, n, nx=nx, ny=ny, nu=1e-3, eta=2e-3, les=les, cs=0.15,
+                storage=storage)
+    assert torch.equal(a, b), int((a != b).sum())
+
+
+@pytest.mark.parametrize("storage,nx,ny", [("fp32", 1061, 2000), ("fp16", 2048, 3000)])
+def test_fused_equals_single_steps_mid_strips(lb, storage, nx, ny):
+    """Strip heights between the bounds (9 and 11 rows here), ragged last strip."""
+    fields = decaying_turbulence(nx, ny, u_rms=0.05, b_rms=0.05)
+    a, b = pair(lb, fields, 4, nx=nx, ny=ny, nu=1e-4, eta=1e-4, les=1, cs=0.1,
+                storage=storage)
+    assert torch.equal(a, b), int((a != b).sum())
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_fused_equals_single_steps_headline_size(lb, storage):
+    """4096^2 Orszag-Tang with the Smagorinsky-MHD closure: 64-row strips."""
+    n = 4096
+    fields = orszag_tang(n, n)
+    a, b = pair(lb, fields, 4, nx=n, ny=n, nu=1e-5, eta=1e-5, les=1, cs=0.1, storage=storage)
+    assert torch.equal(a, b), int((a != b).sum())
+
+
+def test_fused_interleaved_with_stored_steps(lb):
+    """Fused steps, single steps into a store, and fused steps again, against
+    single steps throughout."""
+    nx, ny = 300, 70
+    fields = random_fields(nx, ny, 11)
+    kw = dict(nx=nx, ny=ny, nu=1e-3, eta=2e-3, les=1, cs=0.15)
+    ref = lb.Lattice(lb.LBMHDConfig(steps_per_pass=1, **kw))
+    ref.init_fields(*fields).step(9)
+    L = lb.Lattice(lb.LBMHDConfig(**kw))
+    L.init_fields(*fields).step(4)
+    store = torch.empty(3, L.lattice_bytes, dtype=torch.uint8, device="cuda")
+    L.step_store(L.save_state(), store, 3)
+    L.load_state(store[2], 7).step(2)
+    assert L.step_count == 9
+    assert torch.equal(stored(L), stored(ref))
+
+
+@pytest.mark.parametrize("storage,nx,ny", [("fp32", 300, 70), ("fp16", 600, 34), ("fp16", 77, 41)])
+def test_fused_path_matches_oracle(lb, orc, storage, nx, ny):
+    steps = 12
+    fields = decaying_turbulence(nx, ny, u_rms=0.05, b_rms=0.05)
+    cfg = lb.LBMHDConfig(nx=nx, ny=ny, nu=1e-3, eta=1e-3, les=1, cs=0.15, storage=storage)
+    L = lb.Lattice(cfg)
+    L.init_fields(*fields).step(steps)
+    got = {k: v.cpu().numpy() for k, v in L.macro().items()}
+    op = orc.Params(nx, ny, nu=1e-3, eta=1e-3, les=True, cs=0.15)
+    want = orc.macro(op, orc.run(op, orc.init(op, *fields), steps))
+    bound = 1e-5 if storage == "fp32" else 1.5e-3
+    for k in ("ux", "uy", "bx", "by"):
+        err = np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k])
+        assert err < bound, (k, err)
