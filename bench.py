@@ -6,9 +6,9 @@ stream-collide update on a 4096 x 4096 periodic Orszag-Tang vortex
 (nu = eta = 1e-5, Smagorinsky-MHD closure with C_S = 0.1), inputs resident in
 HBM, K timed steps with the FP64 diagnostics reduction run every 100 steps
 inside the timed region.  Steps go two per pass over the lattice (the
-intermediate state stays on chip; results equal single steps bit for bit), so
-the dominant kernel moves 152 B per site per launch for two updates; the
-single-step kernel is timed beside it.  The same JSON line also reports the FP16-storage
+intermediate state stays on chip; in FP32 the results equal single steps bit
+for bit), so the dominant kernel moves 152 B per site per launch for two
+updates; the single-step kernel is timed beside it.  The same JSON line also reports the FP16-storage
 step on 8192 x 8192 decaying turbulence (nu = eta = 1e-6), the adjoint
 (gradient of the final total energy after 2000 steps of a perturbed 1024 x 1024
 Orszag-Tang run, checkpoint interval from the free HBM), the adjoint-driven fit of C_S

@@ -124,9 +124,13 @@ typedef struct {
                              large enough for that to pay (at least 512 tiles
                              of 8 rows by 256 FP32 or 512 FP16 columns, e.g.
                              1024^2 FP32, 2048^2 FP16); 2 always does; 1
-                             never does.  Either way the result is bit for bit
-                             that of single steps.  Other values are
-                             rejected. */
+                             never does.  Other values are rejected.  The
+                             result is bit for bit that of single steps, with
+                             one measured exception: FP16 storage with even
+                             nx, where a few stored halves in ten million,
+                             next to the 512-column tile edges, differ in
+                             their last bits (the tile's halo sites run a
+                             separately compiled collision). */
 } lbmhd_params;
 
 /* Global diagnostics of the current state, accumulated in FP64.
@@ -194,8 +198,8 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
  * moment-space collision of Sec. 3; closures as selected by les), ping-ponging
  * the two bound lattices (or updating the one lattice in place).  Each kernel
  * launch fuses streaming and collision of one step, or, for pairs of steps
- * as steps_per_pass selects, of two steps (the result is the same bit for
- * bit).  Asynchronous. */
+ * as steps_per_pass selects, of two steps (the same result; see
+ * steps_per_pass for the one FP16 exception).  Asynchronous. */
 int lbmhd_step(lbmhd_t* h, int64_t nsteps);
 
 /* Steps that one pass over the lattice covers when lbmhd_step advances an

@@ -365,11 +365,16 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
 // every read before the slot is written again.  Planes with c_x = 0 stay in
 // the thread's registers for the same number of passes.  The intermediate
 // values pass through the storage codec, so that the result equals two
-// k_step launches.  HBM bytes per site for two steps: one read and one write
-// of the lattice, plus halo re-reads of 2 / rows of the rows and 4 / W of
-// the columns.
+// k_step launches (FP32 bit for bit; with FP16 and V = 2 the halo sites,
+// computed by a separate single-site copy of the collision, round a few
+// values in ten million differently).  HBM bytes per site for two steps: one
+// read and one write of the lattice, plus halo re-reads of 2 / rows of the
+// rows and 4 / W of the columns.
 constexpr int kT2Threads = 256;
-constexpr int kT2Slots = 30;   // 2 planes x 4 slots + 6 x 3 + 2 x 2
+// LDS rings: 2 planes x 4 slots + 6 x 3 + 2 x 2 plane-rows
+constexpr int kT2SlotsA = 4, kT2SlotsB = 3, kT2SlotsC = 2;
+constexpr int kT2Slots = 2 * kT2SlotsA + 6 * kT2SlotsB + 2 * kT2SlotsC;
+constexpr int kT2BaseB = 2 * kT2SlotsA, kT2BaseC = kT2BaseB + 6 * kT2SlotsB;
 // LDS group of each plane with c_x != 0 (0: c_y = +1, 1: c_y = 0, 2: c_y = -1)
 // and its index in the group; -1 for the register-held planes (c_x = 0).
 __device__ constexpr int kT2Group[kNPop] = {-1, 1, -1, 1, -1, 0, 0, 2, 2, -1,
@@ -381,18 +386,41 @@ __device__ constexpr int kT2Index[kNPop] = {0, 0, 0, 1, 0, 0, 1, 0, 1, 0,
 __device__ constexpr int kT2Reg[kNPop] = {0, -1, 0, -1, 0, -1, -1, -1, -1, 1,
                                           -1, 1, -1, 1, 2, -1, 2, -1, 2};
 
+// Row offsets of the gather for row r (-1 <= r <= ny, wrapped): the source
+// row of a plane with velocity c_y is r - c_y, indexed by c_y + 1.
+__device__ __forceinline__ void t2_rows(int r, const Geom& geo, unsigned (&row)[3]) {
+  r = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
+  const int rm = r == 0 ? geo.ny - 1 : r - 1;
+  const int rp = r == geo.ny - 1 ? 0 : r + 1;
+  row[0] = unsigned(rp) * geo.pitch;
+  row[1] = unsigned(r) * geo.pitch;
+  row[2] = unsigned(rm) * geo.pitch;
+}
+
 template <int ST, int V, bool LES>
 __global__ __launch_bounds__(kT2Threads) void k_step2(
     const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
-    Geom geo, Rates rt, int tiles_x, int rows) {
+    Geom geo, Rates rt, int tiles_x, int rows, bool xcd_map) {
   using C = Codec<ST>;
   using T = typename C::T;
   constexpr int W = kT2Threads * V;
   __shared__ T lds[kT2Slots][W + 2];   // LDS column s holds local column s - 1
   const int nx = geo.nx, ny = geo.ny;
   const long long P = geo.plane;
-  const int x0 = (int(blockIdx.x) % tiles_x) * W;
-  const int y0 = (int(blockIdx.x) / tiles_x) * rows;
+  // blocks go round-robin to the eight XCDs: with xcd_map (strips % 8 == 0)
+  // each XCD gets whole strips, so that the halo lines that neighbouring
+  // tiles share meet in one L2
+  int tile, strip;
+  if (xcd_map) {
+    const int k = int(blockIdx.x) >> 3;
+    strip = (int(blockIdx.x) & 7) + 8 * (k / tiles_x);
+    tile = k % tiles_x;
+  } else {
+    tile = int(blockIdx.x) % tiles_x;
+    strip = int(blockIdx.x) / tiles_x;
+  }
+  const int x0 = tile * W;
+  const int y0 = strip * rows;
   const int wt = min(W, nx - x0);          // columns of this tile
   const int h = min(rows, ny - y0);        // output rows of this strip
   const int lc = int(threadIdx.x) * V;     // first local column of the thread
@@ -414,17 +442,13 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int j = 0; j < V; ++j) zc[k][j] = zu1[k][j] = zu2[k][j] = 0.0f;
-  int sB = 0;   // t mod 3
+  int sA = 0, sB = 0;   // t mod kT2SlotsA, t mod kT2SlotsB
   for (int t = 0; t < h + 2; ++t) {
-    const int sA = t & 3, sC = t & 1;
-    int r = y0 - 1 + t;
-    r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
-    const int rm = r == 0 ? ny - 1 : r - 1;
-    const int rp = r == ny - 1 ? 0 : r + 1;
-    const unsigned row[3] = {unsigned(rp) * geo.pitch, unsigned(r) * geo.pitch,
-                             unsigned(rm) * geo.pitch};
-    // first update of row r; c_x = 0 planes kept by c_y (nc: 0, nu: +1, nd: -1)
+    const int sC = t & 1;
+    // first update of row y0 - 1 + t; c_x = 0 planes kept by c_y (nc: 0, nu: +1, nd: -1)
     float nc[3][V], nu[3][V], nd[3][V];
+    unsigned row[3];
+    t2_rows(y0 - 1 + t, geo, row);
     if (active) {
       float v[kNPop][V];
       gather_row<ST, V>(src, P, x, xl, xr, row, v);
@@ -438,9 +462,9 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
           if (g == 0)
             lds[sA * 2 + i][lc + j + 1] = e;
           else if (g == 1)
-            lds[8 + sB * 6 + i][lc + j + 1] = e;
+            lds[kT2BaseB + sB * 6 + i][lc + j + 1] = e;
           else if (g == 2)
-            lds[26 + sC * 2 + i][lc + j + 1] = e;
+            lds[kT2BaseC + sC * 2 + i][lc + j + 1] = e;
           else if (kPlaneCy[q] == 0)
             nc[k][j] = C::dec(e);
           else if (kPlaneCy[q] == 1)
@@ -461,16 +485,16 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
         if (g == 0)
           lds[sA * 2 + i][hs] = e;
         else if (g == 1)
-          lds[8 + sB * 6 + i][hs] = e;
+          lds[kT2BaseB + sB * 6 + i][hs] = e;
         else if (g == 2)
-          lds[26 + sC * 2 + i][hs] = e;
+          lds[kT2BaseC + sC * 2 + i][hs] = e;
       }
     }
     __syncthreads();
-    // second update of row r - 1 (from pass 2 on)
+    // second update of row y0 - 2 + t (from pass 2 on)
     if (t >= 2 && active) {
-      const int sB1 = sB == 0 ? 2 : sB - 1;   // (t - 1) mod 3
-      const int sA2 = (t - 2) & 3;
+      const int sB1 = sB == 0 ? kT2SlotsB - 1 : sB - 1;            // (t - 1) mod slots
+      const int sA2 = sA >= 2 ? sA - 2 : sA + kT2SlotsA - 2;       // (t - 2) mod slots
       float v[kNPop][V];
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
@@ -481,9 +505,9 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
           if (g == 0)
             v[q][j] = C::dec(lds[sA2 * 2 + i][sx]);
           else if (g == 1)
-            v[q][j] = C::dec(lds[8 + sB1 * 6 + i][sx]);
+            v[q][j] = C::dec(lds[kT2BaseB + sB1 * 6 + i][sx]);
           else if (g == 2)
-            v[q][j] = C::dec(lds[26 + sC * 2 + i][sx]);
+            v[q][j] = C::dec(lds[kT2BaseC + sC * 2 + i][sx]);
           else if (kPlaneCy[q] == 0)
             v[q][j] = zc[k][j];
           else if (kPlaneCy[q] == 1)
@@ -503,7 +527,8 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
         zu1[k][j] = active ? nu[k][j] : 0.0f;
         zc[k][j] = active ? nc[k][j] : 0.0f;
       }
-    sB = sB == 2 ? 0 : sB + 1;
+    sA = sA == kT2SlotsA - 1 ? 0 : sA + 1;
+    sB = sB == kT2SlotsB - 1 ? 0 : sB + 1;
   }
 }
 
@@ -1201,28 +1226,34 @@ void launch_step_v(bool les, const void* src, void* dst, const Geom& g, const Ra
     hipLaunchKernelGGL((k_step<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x);
 }
 
-// Strip height of the two-step kernel: the tallest strip (at most 64 rows,
-// a 2 / rows halo overhead) that still gives about 1024 blocks, at least 8.
-static int step2_rows(const Geom& g, int V) {
+// Strip height of the two-step kernel, measured on MI355X: FP32 runs best
+// with about 512 blocks (2048^2: 32 rows, 4096^2: 128), FP16 with about 4096
+// (8192^2: 32 rows, 4096^2 and 2048^2: 8); halo overhead 2 / rows.
+static int step2_rows(const Geom& g, int storage, int V) {
+  const bool fp16 = storage == LBMHD_FP16;
   const long long tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
-  const long long rows = tiles_x * g.ny / 1024;
-  return int(rows < 8 ? 8 : (rows > 64 ? 64 : rows));
+  const long long rows = tiles_x * g.ny / (fp16 ? 4096 : 512);
+  const long long hi = fp16 ? 32 : 128;
+  return int(rows < 8 ? 8 : (rows > hi ? hi : rows));
 }
 
 template <int ST, int V>
 void launch_step2_v(bool les, const void* src, void* dst, const Geom& g, const Rates& r,
                     hipStream_t s) {
   using T = typename Codec<ST>::T;
-  const int rows = step2_rows(g, V);
+  const int rows = step2_rows(g, ST, V);
   const int tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
   const int strips = (g.ny + rows - 1) / rows;
   const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kT2Threads);
+  const bool xcd_map = strips % 8 == 0;
   auto* a = static_cast<const T*>(src);
   auto* b = static_cast<T*>(dst);
   if (les)
-    hipLaunchKernelGGL((k_step2<ST, V, true>), grid, block, 0, s, a, b, g, r, tiles_x, rows);
+    hipLaunchKernelGGL((k_step2<ST, V, true>), grid, block, 0, s, a, b, g, r, tiles_x, rows,
+                       xcd_map);
   else
-    hipLaunchKernelGGL((k_step2<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x, rows);
+    hipLaunchKernelGGL((k_step2<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x, rows,
+                       xcd_map);
 }
 
 template <int ST, int EDDY, bool KIN>

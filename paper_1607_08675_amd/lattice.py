@@ -35,8 +35,9 @@ class LBMHDConfig:
     the closures that read neighbours (les = 2, 3, 4, 6).
     steps_per_pass: with two lattices and les = 0 or 1, step() can advance two
     steps per pass over the lattice with the intermediate state kept on chip,
-    bit for bit equal to single steps: 0 (default) where the lattice is large
-    enough for it to pay, 2 always, 1 never.
+    equal to single steps bit for bit (FP16 with even nx: but for a few halves
+    in ten million at tile edges, in their last bits): 0 (default) where the
+    lattice is large enough for it to pay, 2 always, 1 never.
     """
     nx: int
     ny: int
