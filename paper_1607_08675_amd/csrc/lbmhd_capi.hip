@@ -300,7 +300,7 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   if (two_steps_per_pass(h)) {
     for (; t + 2 <= nsteps; t += 2) {
       hipError_t e = lbk::launch_step2(h->p.storage, les, h->lat[h->cur], h->lat[1 - h->cur],
-                                       h->geo, h->rates, h->stream);
+                                       nullptr, h->geo, h->rates, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "step launch");
       h->cur = 1 - h->cur;
       h->step += 2;
@@ -356,7 +356,19 @@ int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, in
   if (int rc = natural(h, src)) return rc;
   const char* prev = static_cast<const char*>(src);
   char* out = static_cast<char*>(store);
-  for (int64_t t = 0; t < n; ++t) {
+  int64_t t = 0;
+  if (two_steps_per_pass(h)) {
+    // pairs of steps in one pass that stores the intermediate state too
+    const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
+    for (; t + 2 <= n; t += 2) {
+      hipError_t e = lbk::launch_step2(h->p.storage, les, prev, out + stride, out, h->geo,
+                                       h->rates, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "step launch");
+      prev = out + stride;
+      out += 2 * stride;
+    }
+  }
+  for (; t < n; ++t) {
     hipError_t e = launch_one_step(h, prev, out);
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
     prev = out;

@@ -397,10 +397,13 @@ __device__ __forceinline__ void t2_rows(int r, const Geom& geo, unsigned (&row)[
   row[2] = unsigned(rm) * geo.pitch;
 }
 
-template <int ST, int V, bool LES>
+// MID: also store the intermediate state (after the first update) to mid;
+// each block writes the rows and columns it owns, so every site once.
+template <int ST, int V, bool LES, bool MID>
 __global__ __launch_bounds__(kT2Threads) void k_step2(
     const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
-    Geom geo, Rates rt, int tiles_x, int rows, bool xcd_map) {
+    typename Codec<ST>::T* __restrict__ mid, Geom geo, Rates rt, int tiles_x, int rows,
+    bool xcd_map) {
   using C = Codec<ST>;
   using T = typename C::T;
   constexpr int W = kT2Threads * V;
@@ -453,6 +456,7 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
       float v[kNPop][V];
       gather_row<ST, V>(src, P, x, xl, xr, row, v);
       collide_sites<V, LES>(v, rt);
+      if (MID && t >= 1 && t <= h) store_row<ST, V>(mid, P, row[1] + unsigned(x), v);
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
 #pragma unroll
@@ -1238,8 +1242,8 @@ static int step2_rows(const Geom& g, int storage, int V) {
 }
 
 template <int ST, int V>
-void launch_step2_v(bool les, const void* src, void* dst, const Geom& g, const Rates& r,
-                    hipStream_t s) {
+void launch_step2_v(bool les, const void* src, void* dst, void* mid, const Geom& g,
+                    const Rates& r, hipStream_t s) {
   using T = typename Codec<ST>::T;
   const int rows = step2_rows(g, ST, V);
   const int tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
@@ -1248,12 +1252,19 @@ void launch_step2_v(bool les, const void* src, void* dst, const Geom& g, const R
   const bool xcd_map = strips % 8 == 0;
   auto* a = static_cast<const T*>(src);
   auto* b = static_cast<T*>(dst);
-  if (les)
-    hipLaunchKernelGGL((k_step2<ST, V, true>), grid, block, 0, s, a, b, g, r, tiles_x, rows,
-                       xcd_map);
+  auto* m = static_cast<T*>(mid);
+  if (les && m)
+    hipLaunchKernelGGL((k_step2<ST, V, true, true>), grid, block, 0, s, a, b, m, g, r, tiles_x,
+                       rows, xcd_map);
+  else if (les)
+    hipLaunchKernelGGL((k_step2<ST, V, true, false>), grid, block, 0, s, a, b, m, g, r, tiles_x,
+                       rows, xcd_map);
+  else if (m)
+    hipLaunchKernelGGL((k_step2<ST, V, false, true>), grid, block, 0, s, a, b, m, g, r, tiles_x,
+                       rows, xcd_map);
   else
-    hipLaunchKernelGGL((k_step2<ST, V, false>), grid, block, 0, s, a, b, g, r, tiles_x, rows,
-                       xcd_map);
+    hipLaunchKernelGGL((k_step2<ST, V, false, false>), grid, block, 0, s, a, b, m, g, r,
+                       tiles_x, rows, xcd_map);
 }
 
 template <int ST, int EDDY, bool KIN>
@@ -1307,14 +1318,14 @@ bool step2_pays(int storage, const Geom& g) {
   return tiles_x * ((g.ny + 7) / 8) >= 512;
 }
 
-hipError_t launch_step2(int storage, bool les, const void* src, void* dst, const Geom& g,
-                        const Rates& r, hipStream_t s) {
+hipError_t launch_step2(int storage, bool les, const void* src, void* dst, void* mid,
+                        const Geom& g, const Rates& r, hipStream_t s) {
   if (storage == LBMHD_FP32)
-    launch_step2_v<LBMHD_FP32, 1>(les, src, dst, g, r, s);
+    launch_step2_v<LBMHD_FP32, 1>(les, src, dst, mid, g, r, s);
   else if (g.nx % 2 == 0)
-    launch_step2_v<LBMHD_FP16, 2>(les, src, dst, g, r, s);
+    launch_step2_v<LBMHD_FP16, 2>(les, src, dst, mid, g, r, s);
   else
-    launch_step2_v<LBMHD_FP16, 1>(les, src, dst, g, r, s);
+    launch_step2_v<LBMHD_FP16, 1>(les, src, dst, mid, g, r, s);
   return hipGetLastError();
 }
 

@@ -122,6 +122,49 @@ def test_fused_equals_single_steps_rough_fields(lb, storage, n):
         assert torch.equal(a, b), int((a != b).sum())
 
 
+@pytest.mark.parametrize("storage,nx,ny,n", [("fp32", 300, 70, 5), ("fp32", 600, 60, 6),
+                                             ("fp16", 512, 40, 4), ("fp16", 301, 33, 5),
+                                             ("fp32", 1024, 1024, 4)])
+def test_stored_trajectory_two_steps_per_pass(lb, storage, nx, ny, n):
+    """lbmhd_step_store with two steps per pass (the pass also stores its
+    intermediate state) writes every state of the one-step trajectory."""
+    fields = random_fields(nx, ny, 13)
+    rows = []
+    for spp in (1, 2):
+        L = lb.Lattice(lb.LBMHDConfig(nx=nx, ny=ny, nu=1e-3, eta=2e-3, les=1, cs=0.15,
+                                      storage=storage, steps_per_pass=spp))
+        L.init_fields(*fields)
+        store = torch.zeros(n, L.lattice_bytes, dtype=torch.uint8, device="cuda")
+        L.step_store(L.save_state(), store, n)
+        rows.append([stored_words(L, store[t]).clone() for t in range(n)])
+    for t in range(n):
+        assert torch.equal(rows[0][t], rows[1][t]), (t, int((rows[0][t] != rows[1][t]).sum()))
+
+
+def test_gradient_with_two_steps_per_pass_matches_single(lb):
+    """The checkpointed gradient (stored trajectory and checkpointed segments)
+    with two steps per pass equals the one-step gradient bit for bit (FP32)."""
+    from paper_1607_08675_amd.adjoint import LBMHDFunction
+    n, steps = 64, 30
+    fields = decaying_turbulence(n, n, u_rms=0.05, b_rms=0.05)
+    out = []
+    for spp in (1, 2):
+        for every in (1, 7):
+            cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-4, eta=1e-4, les=1, cs=0.1, cs_b=0.07,
+                                 steps_per_pass=spp)
+            t = [torch.tensor(f, dtype=torch.float64, device="cuda", requires_grad=True)
+                 for f in fields[1:]]
+            cs = torch.tensor(0.1, dtype=torch.float64, device="cuda", requires_grad=True)
+            J = LBMHDFunction.apply(*t, cs, cfg, steps, every)
+            J.backward()
+            out.append((float(J), [ti.grad.clone() for ti in t], float(cs.grad)))
+    ref = out[0]
+    for o in out[1:]:
+        assert o[0] == ref[0] and o[2] == ref[2]
+        for a, b in zip(o[1], ref[1]):
+            assert torch.equal(a, b)
+
+
 def test_fused_interleaved_with_stored_steps(lb):
     """Fused steps, single steps into a store, and fused steps again, against
     single steps throughout."""
