@@ -219,10 +219,10 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst);
  * (t = 1 .. n) is written to store + (t - 1) * stride bytes (device; stride a
  * multiple of 256 and >= `lattice` bytes).  The same update as lbmhd_step,
  * launched from the library in one call: pairs of steps that lbmhd_step
- * takes in one pass go in one pass here too, which reads state t - 1 once
- * and writes states t and t + 1 (three lattice transfers for two steps
- * instead of four).  The handle's current state and step count are
- * untouched.  The store range overlaps neither src nor the bound
+ * takes in one pass go in one pass here too (with FP16 storage only when
+ * steps_per_pass is 2), which reads state t - 1 once and writes states t
+ * and t + 1 (three lattice transfers for two steps instead of four).  The
+ * handle's current state and step count are untouched.  The store range overlaps neither src nor the bound
  * buffers.  Used to keep the whole trajectory for the adjoint when it fits
  * in device memory.  Asynchronous. */
 int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, int64_t n);

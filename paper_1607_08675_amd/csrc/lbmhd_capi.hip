@@ -357,8 +357,10 @@ int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, in
   const char* prev = static_cast<const char*>(src);
   char* out = static_cast<char*>(store);
   int64_t t = 0;
-  if (two_steps_per_pass(h)) {
-    // pairs of steps in one pass that stores the intermediate state too
+  // pairs of steps in one pass that stores the intermediate state too; in
+  // automatic mode for FP32 only (with FP16 the extra store made the pass
+  // slower than two single steps: 75 against 64 us per step at 2048^2)
+  if (two_steps_per_pass(h) && (h->p.storage == LBMHD_FP32 || h->p.steps_per_pass == 2)) {
     const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
     for (; t + 2 <= n; t += 2) {
       hipError_t e = lbk::launch_step2(h->p.storage, les, prev, out + stride, out, h->geo,
