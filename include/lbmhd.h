@@ -116,15 +116,19 @@ typedef struct {
                              that read the state, or take a state argument
                              that is the bound lattice itself, first return
                              a reversed lattice to the natural layout. */
-  int32_t steps_per_pass; /* How lbmhd_step covers pairs of steps when two
-                             lattices are bound and the closure reads no
-                             neighbours (les = 0 or 1): 0 (automatic) takes
-                             two steps per pass over the lattice, keeping the
-                             intermediate state on chip, when the lattice is
+  int32_t steps_per_pass; /* How many steps lbmhd_step takes per pass over
+                             the lattice when two lattices are bound and the
+                             closure reads no neighbours (les = 0 or 1), the
+                             intermediate states staying on chip: 0
+                             (automatic) takes triples of steps with FP32
+                             storage and pairs with FP16 when the lattice is
                              large enough for that to pay (at least 512 tiles
                              of 8 rows by 256 FP32 or 512 FP16 columns, e.g.
-                             1024^2 FP32, 2048^2 FP16); 2 always does; 1
-                             never does.  Other values are rejected.  The
+                             1024^2 FP32, 2048^2 FP16); 3 always takes
+                             triples with FP32 (pairs with FP16); 2 always
+                             takes pairs; 1 takes single steps.  A remainder
+                             goes in pairs and single steps.  Other values
+                             are rejected.  The
                              result is bit for bit that of single steps, with
                              one measured exception: FP16 storage with even
                              nx, where a few stored halves in ten million,
@@ -202,10 +206,11 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
  * steps_per_pass for the one FP16 exception).  Asynchronous. */
 int lbmhd_step(lbmhd_t* h, int64_t nsteps);
 
-/* Steps that one pass over the lattice covers when lbmhd_step advances an
- * even number of steps on this handle: 2 where steps_per_pass (and, for 0,
- * the lattice size) selects the two-step kernel for this closure and layout,
- * else 1.  Host only.  Errors: LBMHD_ERR_INVALID_ARG for NULL arguments. */
+/* Steps that one pass over the lattice covers when lbmhd_step advances a
+ * multiple of that many steps on this handle: 3 or 2 where steps_per_pass
+ * (and, for 0, the lattice size) selects the three- or two-step kernel for
+ * this storage, closure and layout, else 1.  Host only.  Errors:
+ * LBMHD_ERR_INVALID_ARG for NULL arguments. */
 int lbmhd_steps_per_pass(const lbmhd_t* h, int32_t* out);
 
 /* One step from the encoded lattice src into dst (device, `lattice` bytes

@@ -46,11 +46,17 @@ hipError_t launch_one_step(const lbmhd_t* h, const void* src, void* dst) {
   return lbk::launch_step(h->p.storage, eddy == 1, src, dst, h->geo, h->rates, h->stream);
 }
 
-// Whether lbmhd_step covers pairs of steps with the two-step kernel.
-bool two_steps_per_pass(const lbmhd_t* h) {
+// Steps that one kernel pass of lbmhd_step covers: 3 (FP32 only), 2 or 1.
+// Automatic: where the multi-step kernels fill the chip, triples for FP32
+// (measured faster than pairs from 1024^2 to 8192^2) and pairs for FP16.
+int pass_steps(const lbmhd_t* h) {
   const int spp = h->p.steps_per_pass;
-  return !h->p.inplace && !(h->p.les & 6) &&
-         (spp == 2 || (spp == 0 && lbk::step2_pays(h->p.storage, h->geo)));
+  if (h->p.inplace || (h->p.les & 6) || spp == 1) return 1;
+  const bool fp32 = h->p.storage == LBMHD_FP32;
+  if (spp == 3) return fp32 ? 3 : 2;
+  if (spp == 2) return 2;
+  if (!lbk::step2_pays(h->p.storage, h->geo)) return 1;
+  return fp32 ? 3 : 2;
 }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -184,7 +190,7 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   // locations; closures that read the neighbours' populations cannot
   if (p->inplace != 0 && p->inplace != 1) return LBMHD_ERR_INVALID_ARG;
   if (p->inplace && (p->les & 6)) return LBMHD_ERR_INVALID_ARG;
-  if (p->steps_per_pass < 0 || p->steps_per_pass > 2) return LBMHD_ERR_INVALID_ARG;
+  if (p->steps_per_pass < 0 || p->steps_per_pass > 3) return LBMHD_ERR_INVALID_ARG;
   const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
   lbk::Geom g = make_geom(p->nx, p->ny, esize);
   lbk::Geom ga = make_geom(p->nx, p->ny, 4);
@@ -288,7 +294,7 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
 
 int lbmhd_steps_per_pass(const lbmhd_t* h, int32_t* out) {
   if (!h || !out) return LBMHD_ERR_INVALID_ARG;
-  *out = two_steps_per_pass(h) ? 2 : 1;
+  *out = pass_steps(h);
   return LBMHD_OK;
 }
 
@@ -297,7 +303,20 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   if (nsteps < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
   const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
   int64_t t = 0;
-  if (two_steps_per_pass(h)) {
+  const int ps = pass_steps(h);
+  if (ps == 3) {
+    // a remainder of one step goes with the last triple as two pairs
+    int64_t triples = nsteps / 3;
+    if (nsteps % 3 == 1 && triples > 0) --triples;
+    for (; t < 3 * triples; t += 3) {
+      hipError_t e = lbk::launch_step_t3(les, h->lat[h->cur], h->lat[1 - h->cur], h->geo,
+                                         h->rates, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "step launch");
+      h->cur = 1 - h->cur;
+      h->step += 3;
+    }
+  }
+  if (ps >= 2) {
     for (; t + 2 <= nsteps; t += 2) {
       hipError_t e = lbk::launch_step2(h->p.storage, les, h->lat[h->cur], h->lat[1 - h->cur],
                                        nullptr, h->geo, h->rates, h->stream);
@@ -360,7 +379,7 @@ int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, in
   // pairs of steps in one pass that stores the intermediate state too; in
   // automatic mode for FP32 only (with FP16 the extra store made the pass
   // slower than two single steps: 75 against 64 us per step at 2048^2)
-  if (two_steps_per_pass(h) && (h->p.storage == LBMHD_FP32 || h->p.steps_per_pass == 2)) {
+  if (pass_steps(h) >= 2 && (h->p.storage == LBMHD_FP32 || h->p.steps_per_pass >= 2)) {
     const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
     for (; t + 2 <= n; t += 2) {
       hipError_t e = lbk::launch_step2(h->p.storage, les, prev, out + stride, out, h->geo,

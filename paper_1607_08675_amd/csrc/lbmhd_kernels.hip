@@ -536,6 +536,164 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
   }
 }
 
+// ----------------------------------------- three steps in one pass (FP32)
+// The two-step scheme one level deeper: dst = (C S)^3 src for FP32 storage
+// and the closures without neighbour terms.  A block owns a tile of kT3Cols
+// columns and a strip of `rows` output rows; pass t takes row y0 - 2 + t
+// through the first update (from HBM), row y0 - 3 + t through the second
+// (from level 1) and row y0 - 4 + t through the third (from level 2, to
+// HBM).  The first update also covers two halo columns on each side and the
+// second one on each side; a fifth wave owns those four halo columns, so
+// that every thread keeps the c_x = 0 planes of its own column in registers
+// and no wave collides more than three times per pass.  Planes with c_x != 0
+// pass through one LDS level per update, grouped by c_y as in k_step2; two
+// barriers per pass (after the first and after the second update) order
+// every ring access, so rings of 3, 2 and 1 slots suffice (20 plane-rows per
+// level).  HBM bytes per site for three steps: one read and one write of the
+// lattice, plus halo re-reads of 4 / rows of the rows and 8 / kT3Cols of the
+// columns.
+constexpr int kT3Cols = 256;
+constexpr int kT3Threads = kT3Cols + 64;
+constexpr int kT3SlotsA = 3, kT3SlotsB = 2;   // c_y = +1 and c_y = 0 groups; c_y = -1: 1
+constexpr int kT3Slots = 2 * kT3SlotsA + 6 * kT3SlotsB + 2;
+constexpr int kT3BaseB = 2 * kT3SlotsA, kT3BaseC = kT3BaseB + 6 * kT3SlotsB;
+
+// One level's ring row of plane q (c_x != 0) written on pass slot (sA, sB).
+__device__ __forceinline__ int t3_row(int q, int sA, int sB) {
+  const int g = kT2Group[q], i = kT2Index[q];
+  return g == 0 ? sA * 2 + i : (g == 1 ? kT3BaseB + sB * 6 + i : kT3BaseC + i);
+}
+
+template <bool LES>
+__global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict__ src,
+                                                        float* __restrict__ dst, Geom geo,
+                                                        Rates rt, int tiles_x, int rows,
+                                                        bool xcd_map) {
+  __shared__ float l1[kT3Slots][kT3Cols + 4];   // first update: column lc + 2
+  __shared__ float l2[kT3Slots][kT3Cols + 2];   // second update: column lc + 1
+  const int nx = geo.nx, ny = geo.ny;
+  const long long P = geo.plane;
+  int tile, strip;
+  if (xcd_map) {   // whole strips per XCD, as in k_step2
+    const int k = int(blockIdx.x) >> 3;
+    strip = (int(blockIdx.x) & 7) + 8 * (k / tiles_x);
+    tile = k % tiles_x;
+  } else {
+    tile = int(blockIdx.x) % tiles_x;
+    strip = int(blockIdx.x) / tiles_x;
+  }
+  const int x0 = tile * kT3Cols, y0 = strip * rows;
+  const int wt = min(kT3Cols, nx - x0), h = min(rows, ny - y0);
+  // the thread's column: its own (threads 0 .. kT3Cols - 1) or a halo column
+  // (lanes 0 .. 3 of the fifth wave: x0 - 2, x0 - 1, x0 + wt, x0 + wt + 1)
+  const int tid = int(threadIdx.x);
+  int lc = tid;
+  bool has = tid < wt;
+  if (tid >= kT3Cols) {
+    const int k = tid - kT3Cols;
+    has = k < 4;
+    lc = k == 0 ? -2 : (k == 1 ? -1 : (k == 2 ? wt : wt + 1));
+  }
+  const bool up2 = has && lc >= -1 && lc <= wt;   // takes the second update
+  const bool up3 = has && lc >= 0 && lc < wt;     // takes the third update
+  int xc = (x0 + lc) % nx;
+  if (xc < 0) xc += nx;
+  const int xl = xc == 0 ? nx - 1 : xc - 1;
+  const int xr = xc == nx - 1 ? 0 : xc + 1;
+
+  // c_x = 0 planes of earlier passes, per level: c_y = 0 from the last pass,
+  // c_y = +1 from the last two
+  float z1c[3], z1u1[3], z1u2[3], z2c[3], z2u1[3], z2u2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) z1c[k] = z1u1[k] = z1u2[k] = z2c[k] = z2u1[k] = z2u2[k] = 0.0f;
+  int sA = 0;   // t mod 3; t mod 2 is t & 1
+  for (int t = 0; t < h + 4; ++t) {
+    const int sB = t & 1;
+    const int sA1 = sA == 0 ? kT3SlotsA - 1 : sA - 1;   // (t - 1) mod 3 ...
+    const int sA2 = sA1 == 0 ? kT3SlotsA - 1 : sA1 - 1;  // ... and (t - 2) mod 3
+    const int sB1 = sB ^ 1;                               // (t - 1) mod 2
+    // first update of row y0 - 2 + t
+    float n1c[3], n1u[3], n1d[3];
+    if (has) {
+      unsigned row[3];
+      t2_rows(y0 - 2 + t, geo, row);
+      float v[kNPop][1];
+      gather_row<LBMHD_FP32, 1>(src, P, xc, xl, xr, row, v);
+      collide_sites<1, LES>(v, rt);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const int k = kT2Reg[q];
+        if (kT2Group[q] >= 0)
+          l1[t3_row(q, sA, sB)][lc + 2] = v[q][0];
+        else if (kPlaneCy[q] == 0)
+          n1c[k] = v[q][0];
+        else if (kPlaneCy[q] == 1)
+          n1u[k] = v[q][0];
+        else
+          n1d[k] = v[q][0];
+      }
+    }
+    __syncthreads();
+    // second update of row y0 - 3 + t (from pass 2 on)
+    float n2c[3], n2u[3], n2d[3];
+    const bool do2 = t >= 2 && up2;
+    if (do2) {
+      float v[kNPop][1];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const int g = kT2Group[q], k = kT2Reg[q];
+        if (g >= 0) {
+          // c_y = +1 planes were written two passes ago, c_y = 0 one, c_y = -1 now
+          const int r = g == 0 ? t3_row(q, sA2, 0) : (g == 1 ? t3_row(q, 0, sB1) : t3_row(q, 0, 0));
+          v[q][0] = l1[r][lc - kPlaneCx[q] + 2];
+        } else {
+          v[q][0] = kPlaneCy[q] == 0 ? z1c[k] : (kPlaneCy[q] == 1 ? z1u2[k] : n1d[k]);
+        }
+      }
+      collide_sites<1, LES>(v, rt);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const int k = kT2Reg[q];
+        if (kT2Group[q] >= 0)
+          l2[t3_row(q, sA, sB)][lc + 1] = v[q][0];
+        else if (kPlaneCy[q] == 0)
+          n2c[k] = v[q][0];
+        else if (kPlaneCy[q] == 1)
+          n2u[k] = v[q][0];
+        else
+          n2d[k] = v[q][0];
+      }
+    }
+    __syncthreads();
+    // third update of row y0 - 4 + t (from pass 4 on), stored
+    if (t >= 4 && up3) {
+      float v[kNPop][1];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const int g = kT2Group[q], k = kT2Reg[q];
+        if (g >= 0) {
+          const int r = g == 0 ? t3_row(q, sA2, 0) : (g == 1 ? t3_row(q, 0, sB1) : t3_row(q, 0, 0));
+          v[q][0] = l2[r][lc - kPlaneCx[q] + 1];
+        } else {
+          v[q][0] = kPlaneCy[q] == 0 ? z2c[k] : (kPlaneCy[q] == 1 ? z2u2[k] : n2d[k]);
+        }
+      }
+      collide_sites<1, LES>(v, rt);
+      store_row<LBMHD_FP32, 1>(dst, P, unsigned(y0 - 4 + t) * geo.pitch + unsigned(xc), v);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      z1u2[k] = z1u1[k];
+      z1u1[k] = has ? n1u[k] : 0.0f;
+      z1c[k] = has ? n1c[k] : 0.0f;
+      z2u2[k] = z2u1[k];
+      z2u1[k] = do2 ? n2u[k] : 0.0f;
+      z2c[k] = do2 ? n2c[k] : 0.0f;
+    }
+    sA = sA == kT3SlotsA - 1 ? 0 : sA + 1;
+  }
+}
+
 // --------------------------------------------- steps with lattice gradients
 // Same update as k_step for the closures that need the neighbours: the
 // kinetic closure (KIN) relaxes toward the filtered equilibria, whose Delta^2
@@ -1316,6 +1474,30 @@ bool step2_pays(int storage, const Geom& g) {
   const int V = storage == LBMHD_FP16 && g.nx % 2 == 0 ? 2 : 1;
   const long long tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
   return tiles_x * ((g.ny + 7) / 8) >= 512;
+}
+
+// Strip height of the three-step kernel: about 512 blocks, 8 to 128 rows
+// (halo overhead 4 / rows).
+static int step_t3_rows(const Geom& g) {
+  const long long tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
+  const long long rows = tiles_x * g.ny / 512;
+  return int(rows < 8 ? 8 : (rows > 128 ? 128 : rows));
+}
+
+hipError_t launch_step_t3(bool les, const void* src, void* dst, const Geom& g, const Rates& r,
+                          hipStream_t s) {
+  const int rows = step_t3_rows(g);
+  const int tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
+  const int strips = (g.ny + rows - 1) / rows;
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kT3Threads);
+  const bool xcd_map = strips % 8 == 0;
+  auto* a = static_cast<const float*>(src);
+  auto* b = static_cast<float*>(dst);
+  if (les)
+    hipLaunchKernelGGL((k_step_t3<true>), grid, block, 0, s, a, b, g, r, tiles_x, rows, xcd_map);
+  else
+    hipLaunchKernelGGL((k_step_t3<false>), grid, block, 0, s, a, b, g, r, tiles_x, rows, xcd_map);
+  return hipGetLastError();
 }
 
 hipError_t launch_step2(int storage, bool les, const void* src, void* dst, void* mid,

@@ -61,7 +61,7 @@ def _create(capi, p):
     dict(nx=1), dict(ny=0), dict(nu=0.0), dict(eta=-1.0), dict(nu=float("nan")),
     dict(s5=2.0), dict(s7=0.0), dict(s8=-0.5), dict(s5=1.1, s6=1.2), dict(les=5), dict(les=7), dict(les=-1),
     dict(cs=-0.1), dict(cs_b=-0.1), dict(cs_b=float("inf")), dict(delta=0.0),
-    dict(inplace=2), dict(steps_per_pass=3), dict(steps_per_pass=-1), dict(inplace=1, les=2), dict(inplace=1, les=4), dict(inplace=1, les=6), dict(storage=7), dict(nx=70000, ny=70000),
+    dict(inplace=2), dict(steps_per_pass=4), dict(steps_per_pass=-1), dict(inplace=1, les=2), dict(inplace=1, les=4), dict(inplace=1, les=6), dict(storage=7), dict(nx=70000, ny=70000),
 ])
 def test_create_rejects_invalid_parameters(capi, bad):
     rc, h = _create(capi, _params(capi, **bad))
@@ -86,17 +86,22 @@ def test_sizes_and_layout(capi):
 
 
 @pytest.mark.parametrize("kw,want", [
-    (dict(nx=4096, ny=4096), 2), (dict(nx=1024, ny=1024), 2), (dict(nx=512, ny=512), 1),
+    (dict(nx=4096, ny=4096), 3), (dict(nx=1024, ny=1024), 3), (dict(nx=512, ny=512), 1),
     (dict(nx=2048, ny=2048, storage=1), 2), (dict(nx=1024, ny=1024, storage=1), 1),
     (dict(nx=1023, ny=1024, storage=1), 2), (dict(nx=64, ny=48, steps_per_pass=2), 2),
-    (dict(nx=4096, ny=4096, steps_per_pass=1), 1), (dict(nx=4096, ny=4096, les=0), 2),
+    (dict(nx=4096, ny=4096, steps_per_pass=2), 2),
+    (dict(nx=4096, ny=4096, steps_per_pass=1), 1), (dict(nx=4096, ny=4096, les=0), 3),
     (dict(nx=4096, ny=4096, les=2), 1), (dict(nx=4096, ny=4096, les=4), 1),
     (dict(nx=4096, ny=4096, inplace=1), 1), (dict(nx=64, ny=48, inplace=1, steps_per_pass=2), 1),
+    (dict(nx=64, ny=48, steps_per_pass=3), 3), (dict(nx=64, ny=48, steps_per_pass=3, storage=1), 2),
+    (dict(nx=64, ny=48, steps_per_pass=3, les=2), 1),
 ])
 def test_steps_per_pass_selection(capi, kw, want):
-    """Two steps per pass only for two lattices and a closure without
-    neighbour terms; automatically from 512 tiles of 8 rows (256 FP32 or
-    FP16-odd-nx columns, 512 FP16 columns) up, always with 2, never with 1."""
+    """Several steps per pass only for two lattices and a closure without
+    neighbour terms: automatically from 512 tiles of 8 rows (256 FP32 or
+    FP16-odd-nx columns, 512 FP16 columns) up, triples for FP32 and pairs for
+    FP16; triples with 3 for FP32 (pairs for FP16), pairs with 2, single steps
+    with 1."""
     rc, h = _create(capi, _params(capi, **kw))
     assert rc == 0
     try:

@@ -165,6 +165,60 @@ def test_gradient_with_two_steps_per_pass_matches_single(lb):
             assert torch.equal(a, b)
 
 
+T3_CASES = [(256, 64), (300, 70), (2, 2), (3, 5), (513, 9), (600, 60), (5, 3), (77, 41)]
+
+
+@pytest.mark.parametrize("nx,ny", T3_CASES)
+@pytest.mark.parametrize("les", [0, 1])
+@pytest.mark.parametrize("n", [3, 4, 5, 7])
+def test_three_steps_per_pass_equal_single_steps(lb, nx, ny, les, n):
+    """Three steps per pass (FP32): triples, the remainder in pairs (a
+    remainder of one takes the last triple along as two pairs), bit for bit
+    equal to single steps; full and ragged tiles and strips, halos wrapping
+    onto tiny lattices."""
+    fields = random_fields(nx, ny, 23 + nx + ny)
+    out = []
+    for spp in (1, 3):
+        L = lb.Lattice(lb.LBMHDConfig(nx=nx, ny=ny, nu=1e-3, eta=2e-3, les=les, cs=0.15,
+                                      steps_per_pass=spp))
+        assert L.steps_per_pass == spp
+        L.init_fields(*fields).step(n)
+        assert L.step_count == n
+        out.append(stored_words(L))
+    assert torch.equal(out[0], out[1]), int((out[0] != out[1]).sum())
+
+
+@pytest.mark.parametrize("nx,ny,gen", [(4096, 4096, "ot"), (4096, 4096, "rough"),
+                                       (1061, 2000, "turb"), (2048, 1536, "turb")])
+def test_three_steps_per_pass_large(lb, nx, ny, gen):
+    """The headline lattice (128-row strips, XCD-grouped), rough fields and
+    strip heights between the bounds (ragged and XCD-grouped)."""
+    f = {"ot": lambda: orszag_tang(nx, ny), "rough": lambda: random_fields(nx, ny, 3),
+         "turb": lambda: decaying_turbulence(nx, ny, u_rms=0.05, b_rms=0.05)}[gen]()
+    out = []
+    for spp in (1, 3):
+        L = lb.Lattice(lb.LBMHDConfig(nx=nx, ny=ny, nu=1e-5, eta=1e-5, les=1, cs=0.1,
+                                      steps_per_pass=spp))
+        L.init_fields(*f).step(6)
+        out.append(stored_words(L))
+        del L
+    assert torch.equal(out[0], out[1]), int((out[0] != out[1]).sum())
+
+
+def test_three_steps_per_pass_matches_oracle(lb, orc):
+    nx, ny, steps = 300, 70, 12
+    fields = decaying_turbulence(nx, ny, u_rms=0.05, b_rms=0.05)
+    L = lb.Lattice(lb.LBMHDConfig(nx=nx, ny=ny, nu=1e-3, eta=1e-3, les=1, cs=0.15,
+                                  steps_per_pass=3))
+    L.init_fields(*fields).step(steps)
+    got = {k: v.cpu().numpy() for k, v in L.macro().items()}
+    op = orc.Params(nx, ny, nu=1e-3, eta=1e-3, les=True, cs=0.15)
+    want = orc.macro(op, orc.run(op, orc.init(op, *fields), steps))
+    for k in ("ux", "uy", "bx", "by"):
+        err = np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k])
+        assert err < 1e-5, (k, err)
+
+
 def test_fused_interleaved_with_stored_steps(lb):
     """Fused steps, single steps into a store, and fused steps again, against
     single steps throughout."""
