@@ -1,0 +1,188 @@
+"""Index arithmetic of the multi-step forward kernels, modelled on the CPU.
+
+The two- and three-step kernels (two or three stream-collide updates per pass
+over HBM) hand intermediate populations between threads through LDS rings and
+registers.  These tests restate the kernels' index formulas (block -> tile and
+strip with the XCD-grouped order, thread -> column including the halo
+columns, ring row of each plane and pass slot, register pipelines by c_y) and
+check, for every block, thread and pass, what the kernels rely on:
+
+* every LDS index is inside its array and no cell is written twice in a pass;
+* every read of an update gets plane q of site (x - c_qx, y - c_qy) of the
+  previous update's output, written in the pass the ring scheme says;
+* every output site is written exactly once.
+
+Read/write order within a pass follows the barriers (writes of an update
+before the reads of the next one).  The tests do not run GPU code; the GPU
+tests compare the kernels with single steps bit for bit.
+"""
+import pytest
+
+# plane velocities in storage order (D2Q9, then the D2Q5 x and y components)
+CX = (0, 1, 0, -1, 0, 1, -1, -1, 1, 0, 1, 0, -1, 0, 0, 1, 0, -1, 0)
+CY = (0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 0, 1, 0, -1, 0, 0, 1, 0, -1)
+# LDS group of the c_x != 0 planes (0: c_y = +1, 1: c_y = 0, 2: c_y = -1), -1 for c_x = 0
+GROUP = (-1, 1, -1, 1, -1, 0, 0, 2, 2, -1, 1, -1, 1, -1, -1, 1, -1, 1, -1)
+INDEX = (0, 0, 0, 1, 0, 0, 1, 0, 1, 0, 2, 0, 3, 0, 0, 4, 0, 5, 0)
+NPLANES = {0: 2, 1: 6, 2: 2}
+# a c_y = +1 plane is read two passes after it is written, c_y = 0 one, c_y = -1 the same
+DELAY = {0: 2, 1: 1, 2: 0}
+REG_DELAY = {1: 2, 0: 1, -1: 0}
+
+
+def block_origin(b, tiles, strips, rows, width):
+    if strips % 8 == 0:   # whole strips per XCD
+        k = b >> 3
+        strip, tile = (b & 7) + 8 * (k // tiles), k % tiles
+    else:
+        tile, strip = b % tiles, b // tiles
+    return tile * width, strip * rows
+
+
+def ring_row(q, t, slots):
+    g = GROUP[q]
+    base = {0: 0, 1: 2 * slots[0], 2: 2 * slots[0] + 6 * slots[1]}[g]
+    return base + (t % slots[g]) * NPLANES[g] + INDEX[q]
+
+
+def two_step(nx, ny, V, fp16):
+    """k_step2: 256 threads of V sites, one halo column per side taken by
+    threads 0 and 1, rings of 4 / 3 / 2 slots, one barrier per pass."""
+    W = 256 * V
+    tiles = (nx + W - 1) // W
+    rows = max(8, min(32 if fp16 else 128, tiles * ny // (4096 if fp16 else 512)))
+    strips = (ny + rows - 1) // rows
+    slots = (4, 3, 2)
+    nrows = 2 * 4 + 6 * 3 + 2 * 2
+    written = set()
+    for b in range(tiles * strips):
+        x0, y0 = block_origin(b, tiles, strips, rows, W)
+        wt, h = min(W, nx - x0), min(rows, ny - y0)
+        lds, reg = {}, {}
+        for t in range(h + 2):
+            r = (y0 - 1 + t) % ny
+            sites = []
+            for tid in range(256):
+                if tid * V < wt:
+                    sites += [(tid, j, x0 + tid * V + j, tid * V + j + 1, True) for j in range(V)]
+                if tid < 2:
+                    hx = ((x0 - 1) % nx) if tid == 0 else ((x0 + wt) % nx)
+                    sites.append((tid, -1, hx, 0 if tid == 0 else wt + 1, False))
+            cells = set()
+            for tid, j, xc, col, own in sites:
+                for q in range(19):
+                    if GROUP[q] >= 0:
+                        row = ring_row(q, t, slots)
+                        assert 0 <= row < nrows and 0 <= col < W + 2
+                        assert (row, col) not in cells
+                        cells.add((row, col))
+                        lds[(row, col)] = (q, xc, r, t)
+                    elif own:
+                        reg[(tid, j, q, t)] = (xc, r)
+            if t < 2:
+                continue
+            r2 = y0 + t - 2
+            for tid in range(256):
+                for j in range(V):
+                    lc = tid * V + j
+                    if tid * V >= wt:
+                        continue
+                    x = x0 + lc
+                    assert (x, r2) not in written
+                    written.add((x, r2))
+                    for q in range(19):
+                        want = ((x - CX[q]) % nx, (r2 - CY[q]) % ny)
+                        if GROUP[q] >= 0:
+                            tt = t - DELAY[GROUP[q]]
+                            got = lds[(ring_row(q, tt, slots), lc - CX[q] + 1)]
+                            assert got == (q, *want, tt)
+                            # the slot is not written again in the next pass
+                            assert ring_row(q, t + 1, slots) != ring_row(q, tt, slots)
+                        else:
+                            assert reg[(tid, j, q, t - REG_DELAY[CY[q]])] == want
+    assert len(written) == nx * ny
+
+
+def three_step(nx, ny):
+    """k_step_t3: 256 threads plus a fifth wave for the four halo columns,
+    two LDS levels with rings of 3 / 2 / 1 slots, two barriers per pass."""
+    W, H = 256, 2
+    tiles = (nx + W - 1) // W
+    rows = max(8, min(128, tiles * ny // 512))
+    strips = (ny + rows - 1) // rows
+    slots = (3, 2, 1)
+    written = set()
+    for b in range(tiles * strips):
+        x0, y0 = block_origin(b, tiles, strips, rows, W)
+        wt, h = min(W, nx - x0), min(rows, ny - y0)
+        cols = []
+        for tid in range(W + 64):
+            if tid < W:
+                cols.append((tid, tid < wt))
+            else:
+                k = tid - W
+                cols.append(((-2, -1, wt, wt + 1)[k] if k < 4 else 0, k < 4))
+        levels = [{}, {}]
+        regs = [{}, {}]
+        for t in range(h + 2 * H):
+            for s in range(3):
+                cells = set()
+                r = y0 - H + t - s
+                for tid, (lc, has) in enumerate(cols):
+                    if not (has and t >= 2 * s and s - H <= lc <= wt - 1 + H - s):
+                        continue
+                    xc = (x0 + lc) % nx
+                    if s > 0:
+                        for q in range(19):
+                            want = ((xc - CX[q]) % nx, (r - CY[q]) % ny)
+                            if GROUP[q] >= 0:
+                                tt = t - DELAY[GROUP[q]]
+                                col = lc - CX[q] + H - (s - 1)
+                                assert 0 <= col < W + 4
+                                assert levels[s - 1][(ring_row(q, tt, slots), col)] == (q, *want, tt)
+                            else:
+                                assert regs[s - 1][(tid, q, t - REG_DELAY[CY[q]])] == want
+                    if s < 2:
+                        for q in range(19):
+                            if GROUP[q] >= 0:
+                                key = (ring_row(q, t, slots), lc + H - s)
+                                assert 0 <= key[0] < 20 and 0 <= key[1] < W + 4 - 2 * s
+                                assert key not in cells
+                                cells.add(key)
+                                levels[s][key] = (q, xc, r % ny, t)
+                            else:
+                                regs[s][(tid, q, t)] = (xc, r % ny)
+                    else:
+                        assert y0 <= r < y0 + h and 0 <= lc < wt
+                        assert (xc, r) not in written
+                        written.add((xc, r))
+    assert len(written) == nx * ny
+
+
+SIZES = [(256, 64), (300, 70), (2, 2), (3, 5), (513, 9), (600, 60), (77, 41), (4, 600)]
+
+
+@pytest.mark.parametrize("nx,ny", SIZES)
+def test_two_step_fp32_index_model(nx, ny):
+    two_step(nx, ny, 1, False)
+
+
+@pytest.mark.parametrize("nx,ny", [(512, 40), (600, 70), (2, 2), (1030, 124), (600, 34)])
+def test_two_step_fp16_pairs_index_model(nx, ny):
+    two_step(nx, ny, 2, True)
+
+
+@pytest.mark.parametrize("nx,ny", [(301, 33), (3, 3), (77, 41)])
+def test_two_step_fp16_odd_index_model(nx, ny):
+    two_step(nx, ny, 1, True)
+
+
+@pytest.mark.parametrize("nx,ny", SIZES + [(5, 3)])
+def test_three_step_index_model(nx, ny):
+    three_step(nx, ny)
+
+
+@pytest.mark.parametrize("tiles,strips", [(1, 8), (3, 8), (16, 32), (5, 64), (32, 64)])
+def test_xcd_order_is_a_bijection(tiles, strips):
+    seen = {block_origin(b, tiles, strips, 1, 1) for b in range(tiles * strips)}
+    assert seen == {(x, y) for x in range(tiles) for y in range(strips)}
