@@ -127,7 +127,9 @@ typedef struct {
                              1024^2 FP32, 2048^2 FP16); 3 always takes
                              triples with FP32 (pairs with FP16); 2 always
                              takes pairs; 1 takes single steps.  A remainder
-                             goes in pairs and single steps.  Other values
+                             goes in pairs (a remainder of one takes the
+                             last triple along as two pairs), so a single
+                             step runs only when one is left.  Other values
                              are rejected.  The
                              result is bit for bit that of single steps, with
                              one measured exception: FP16 storage with even
@@ -201,9 +203,9 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
 /* Advance nsteps >= 0 steps of stream + collide (Sec. 1.2 update with the
  * moment-space collision of Sec. 3; closures as selected by les), ping-ponging
  * the two bound lattices (or updating the one lattice in place).  Each kernel
- * launch fuses streaming and collision of one step, or, for pairs of steps
- * as steps_per_pass selects, of two steps (the same result; see
- * steps_per_pass for the one FP16 exception).  Asynchronous. */
+ * launch fuses streaming and collision of one, two or three steps as
+ * steps_per_pass selects (the same result; see steps_per_pass for the one
+ * FP16 exception).  Asynchronous. */
 int lbmhd_step(lbmhd_t* h, int64_t nsteps);
 
 /* Steps that one pass over the lattice covers when lbmhd_step advances a
@@ -223,13 +225,14 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst);
 /* n >= 0 steps from the encoded lattice src, keeping every state: state t
  * (t = 1 .. n) is written to store + (t - 1) * stride bytes (device; stride a
  * multiple of 256 and >= `lattice` bytes).  The same update as lbmhd_step,
- * launched from the library in one call: pairs of steps that lbmhd_step
- * takes in one pass go in one pass here too (with FP16 storage only when
- * steps_per_pass is 2), which reads state t - 1 once and writes states t
- * and t + 1 (three lattice transfers for two steps instead of four).  The
- * handle's current state and step count are untouched.  The store range overlaps neither src nor the bound
- * buffers.  Used to keep the whole trajectory for the adjoint when it fits
- * in device memory.  Asynchronous. */
+ * launched from the library in one call: where lbmhd_step takes several
+ * steps per pass, consecutive steps go in pairs here (with FP16 storage only
+ * when steps_per_pass is 2 or more), a pass that reads state t - 1 once and
+ * writes states t and t + 1 (three lattice transfers for two steps instead
+ * of four).  The handle's current state and step count are untouched.  The
+ * store range overlaps neither src nor the bound buffers.  Used to keep the
+ * whole trajectory for the adjoint when it fits in device memory.
+ * Asynchronous. */
 int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, int64_t n);
 
 /* Macroscopic fields of the current state: rho = sum f, u = (sum c f) / rho,
