@@ -189,10 +189,12 @@ def test_three_steps_per_pass_equal_single_steps(lb, nx, ny, les, n):
 
 
 @pytest.mark.parametrize("nx,ny,gen", [(4096, 4096, "ot"), (4096, 4096, "rough"),
-                                       (1061, 2000, "turb"), (2048, 1536, "turb")])
+                                       (1061, 2000, "turb"), (2048, 1536, "turb"),
+                                       (8192, 4096, "rough")])
 def test_three_steps_per_pass_large(lb, nx, ny, gen):
-    """The headline lattice (128-row strips, XCD-grouped), rough fields and
-    strip heights between the bounds (ragged and XCD-grouped)."""
+    """The headline lattice (128-row strips, XCD-grouped), rough fields, strip
+    heights between the bounds (ragged and XCD-grouped) and a lattice past
+    the 128-row bound (32-row strips)."""
     f = {"ot": lambda: orszag_tang(nx, ny), "rough": lambda: random_fields(nx, ny, 3),
          "turb": lambda: decaying_turbulence(nx, ny, u_rms=0.05, b_rms=0.05)}[gen]()
     out = []

@@ -108,7 +108,8 @@ def three_step(nx, ny):
     two LDS levels with rings of 3 / 2 / 1 slots, two barriers per pass."""
     W, H = 256, 2
     tiles = (nx + W - 1) // W
-    rows = max(8, min(128, tiles * ny // 512))
+    rows = tiles * ny // 512
+    rows = 8 if rows < 8 else (32 if rows > 128 else rows)
     strips = (ny + rows - 1) // rows
     slots = (3, 2, 1)
     written = set()
