@@ -277,6 +277,14 @@ int lbmhd_load_state(lbmhd_t* h, const void* src, int64_t step);
 /* Steps taken since the last (re)initialisation (host value). */
 int lbmhd_get_step(const lbmhd_t* h, int64_t* step);
 
+/* Device address of the bound lattice that holds the current state (which of
+ * the two lattices depends on how many kernel passes the steps took; the one
+ * lattice in place, whose layout is reversed after an odd step count until a
+ * call that reads the state restores it).  For reading the state in place
+ * without a copy; the library owns what it writes there.  Host only.
+ * Errors: LBMHD_ERR_NOT_BOUND, LBMHD_ERR_INVALID_ARG for NULL arguments. */
+int lbmhd_current_state(const lbmhd_t* h, const void** out);
+
 /* Total energy J = sum (|rho u|^2 / (2 rho) + |B|^2 / 2) of an encoded
  * lattice `state` (device, `lattice` bytes; NULL = current state), in FP64,
  * written to *J (host).  Synchronises the bound stream. */

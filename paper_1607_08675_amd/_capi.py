@@ -32,6 +32,7 @@ EXPORTS = (
     "lbmhd_macro",
     "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_get_populations",
     "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state", "lbmhd_get_step",
+    "lbmhd_current_state",
     "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_seed_mismatch", "lbmhd_adj_step",
     "lbmhd_adj_sweep", "lbmhd_adj_acc_total", "lbmhd_adj_fields",
 )
@@ -129,6 +130,7 @@ def lib():
             "lbmhd_save_state": [vp, vp],
             "lbmhd_load_state": [vp, vp, i64],
             "lbmhd_get_step": [vp, P(i64)],
+            "lbmhd_current_state": [vp, P(vp)],
             "lbmhd_steps_per_pass": [vp, P(ctypes.c_int32)],
             "lbmhd_energy": [vp, vp, P(ctypes.c_double)],
             "lbmhd_adj_seed_energy": [vp, vp, vp],

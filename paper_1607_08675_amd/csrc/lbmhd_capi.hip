@@ -520,6 +520,13 @@ int lbmhd_get_step(const lbmhd_t* h, int64_t* step) {
   return LBMHD_OK;
 }
 
+int lbmhd_current_state(const lbmhd_t* h, const void** out) {
+  if (!h || !out) return LBMHD_ERR_INVALID_ARG;
+  if (!h->lat[0]) return LBMHD_ERR_NOT_BOUND;
+  *out = h->p.inplace ? h->lat[0] : h->lat[h->cur];
+  return LBMHD_OK;
+}
+
 int lbmhd_energy(lbmhd_t* h, const void* state, double* J) {
   if (int rc = need_bound(h)) return rc;
   if (!J) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");

@@ -220,6 +220,17 @@ class Lattice:
         self._check(self._L.lbmhd_get_step(self._h, ctypes.byref(v)), "lbmhd_get_step")
         return v.value
 
+    def current_state(self) -> torch.Tensor:
+        """The bound lattice buffer (uint8, lattice_bytes) that holds the current
+        state; in place, read it after a call that restores the natural layout
+        (diag, macro, save_state)."""
+        p = ctypes.c_void_p()
+        self._check(self._L.lbmhd_current_state(self._h, ctypes.byref(p)), "lbmhd_current_state")
+        for t in (self._a, self._b):
+            if t is not None and t.data_ptr() == p.value:
+                return t
+        raise RuntimeError("the library reports a state outside the bound lattices")
+
     @property
     def steps_per_pass(self) -> int:
         """Steps one kernel pass covers in step() for pairs of steps (1 or 2)."""

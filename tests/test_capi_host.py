@@ -124,6 +124,9 @@ def test_calls_before_bind_are_refused(capi):
     assert L.lbmhd_bind(h, None, 0, None, 0, None, 0, None) == capi.LBMHD_ERR_INVALID_ARG
     step = ctypes.c_int64(-1)
     assert L.lbmhd_get_step(h, ctypes.byref(step)) == 0 and step.value == 0
+    ptr = ctypes.c_void_p()
+    assert L.lbmhd_current_state(h, ctypes.byref(ptr)) == capi.LBMHD_ERR_NOT_BOUND
+    assert L.lbmhd_current_state(h, None) == capi.LBMHD_ERR_INVALID_ARG
     assert L.lbmhd_destroy(h) == 0
     assert L.lbmhd_destroy(None) == 0
 

@@ -3,12 +3,16 @@
 In-plane byte offsets are 32-bit, so lbmhd_create takes a lattice only while
 one FP32 plane stays below 4 GiB: 32768 x 32767 sites is the largest square-
 ish one (its last site sits 131,076 bytes below 2^32 in every plane).  The
-Orszag-Tang vortex runs k = 2 steps with the Smagorinsky-MHD closure, in FP32
-on two lattices (163 GB), in place on one, and in FP16; the oracle then
-recomputes sampled sites, the four corners and the last row and column among
-them, on (2k + 5)^2 patches, and the FP64 diagnostics of the initial state
-are checked against their closed forms (sum over the nodes of sin^2 is N / 2).
-Skipped when the GPU has too little free memory.
+Orszag-Tang vortex runs k = 3 steps with the Smagorinsky-MHD closure, in FP32
+on two lattices (163 GB; one three-step pass), in place on one, and in FP16
+(a two-step pass and a single step); the oracle then recomputes sampled
+sites, the four corners and the last row and column among them, on
+(2k + 5)^2 patches, and the FP64 diagnostics of the initial state are checked
+against their closed forms (sum over the nodes of sin^2 is N / 2).  The flow
+on this lattice is so smooth that three steps move a population by only
+1e-6 to 3e-6, so the FP32 bound is 2e-7 and the test also requires the
+sampled sites to have moved by more than it.  Skipped when the GPU has too
+little free memory.
 """
 import math
 
@@ -48,7 +52,7 @@ def oracle_after(orc, op, x0, k):
     return orc.collide(op, st)
 
 
-@pytest.mark.parametrize("storage,inplace,tol", [("fp32", False, 1e-6), ("fp32", True, 1e-6),
+@pytest.mark.parametrize("storage,inplace,tol", [("fp32", False, 2e-7), ("fp32", True, 2e-7),
                                                  ("fp16", False, 1e-4)])
 def test_largest_lattice(lb, orc, storage, inplace, tol):
     n = NX * NY
@@ -74,11 +78,11 @@ def test_largest_lattice(lb, orc, storage, inplace, tol):
     assert abs(d["mass"] - n) <= 1e-8 * n
     assert abs(d["e_kin"] - U0 ** 2 * n / 2) <= 1e-6 * U0 ** 2 * n
     assert abs(d["e_mag"] - B0 ** 2 * n / 2) <= 1e-6 * B0 ** 2 * n
-    k = 2
+    k = 3
     L.step(k)
     d = L.diag()                      # also returns an in-place lattice to its natural layout
     assert d["nonfinite"] == 0 and abs(d["mass"] - n) <= 1e-6 * n
-    cur = L._a if (inplace or k % 2 == 0) else L._b
+    cur = L.current_state()
     plane = L.lattice_bytes // esize // 19
     pitch = plane // NY
     raw = cur.view(torch.float32 if storage == "fp32" else torch.float16)
@@ -87,14 +91,19 @@ def test_largest_lattice(lb, orc, storage, inplace, tol):
     sites += [(int(a), int(b)) for a, b in zip(rng.integers(0, NX, 10), rng.integers(0, NY, 10))]
     r = k + 2
     op = orc.Params(2 * r + 1, 2 * r + 1, nu=cfg.nu, eta=cfg.eta, les=1, cs=cfg.cs)
+    moved = 0
     for (sx, sy_) in sites:
         idx = torch.tensor([q * plane + sy_ * pitch + sx for q in range(19)], device=dev)
         v = raw[idx].double().cpu().numpy()
         got = W19 + (v if storage == "fp32" else v / 1024.0)
         xs = (np.arange(sx - r, sx + r + 1)) % NX
         ys = (np.arange(sy_ - r, sy_ + r + 1)) % NY
-        want = oracle_after(orc, op, orc.init(op, *ot_patch(xs, ys)), k)[:, r, r]
+        x0 = orc.init(op, *ot_patch(xs, ys))
+        want = oracle_after(orc, op, x0, k)[:, r, r]
         err = float(np.abs(got - want).max())
         assert err < tol, ((sx, sy_), err)
+        moved += float(np.abs(want - x0[:, r, r]).max()) > 2 * tol
+    if storage == "fp32":
+        assert moved >= len(sites) // 2, moved
     del raw, cur, L
     torch.cuda.empty_cache()

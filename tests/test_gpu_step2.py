@@ -221,6 +221,17 @@ def test_three_steps_per_pass_matches_oracle(lb, orc):
         assert err < 1e-5, (k, err)
 
 
+@pytest.mark.parametrize("spp,n", [(1, 3), (2, 3), (2, 4), (3, 3), (3, 4), (3, 7)])
+def test_current_state_follows_the_passes(lb, spp, n):
+    """lbmhd_current_state names the lattice that holds the state, whatever
+    the number of kernel passes the steps took."""
+    nx, ny = 300, 70
+    L = lb.Lattice(lb.LBMHDConfig(nx=nx, ny=ny, steps_per_pass=spp))
+    L.init_fields(*random_fields(nx, ny, 3)).step(n)
+    cur = L.current_state()
+    assert torch.equal(stored_words(L, cur), stored_words(L))
+
+
 def test_fused_interleaved_with_stored_steps(lb):
     """Fused steps, single steps into a store, and fused steps again, against
     single steps throughout."""
