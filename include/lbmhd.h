@@ -226,10 +226,10 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst);
  * (t = 1 .. n) is written to store + (t - 1) * stride bytes (device; stride a
  * multiple of 256 and >= `lattice` bytes).  The same update as lbmhd_step,
  * launched from the library in one call: where lbmhd_step takes several
- * steps per pass, consecutive steps go in pairs here (with FP16 storage only
- * when steps_per_pass is 2 or more), a pass that reads state t - 1 once and
- * writes states t and t + 1 (three lattice transfers for two steps instead
- * of four).  The handle's current state and step count are untouched.  The
+ * steps per pass, consecutive steps go in triples (FP32) or pairs here (with
+ * FP16 storage only when steps_per_pass is 2 or more), a pass that reads
+ * state t - 1 once and writes all the states it computes (four lattice
+ * transfers for three steps, three for two, instead of two per step).  The handle's current state and step count are untouched.  The
  * store range overlaps neither src nor the bound buffers.  Used to keep the
  * whole trajectory for the adjoint when it fits in device memory.
  * Asynchronous. */

@@ -309,8 +309,8 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
     int64_t triples = nsteps / 3;
     if (nsteps % 3 == 1 && triples > 0) --triples;
     for (; t < 3 * triples; t += 3) {
-      hipError_t e = lbk::launch_step_t3(les, h->lat[h->cur], h->lat[1 - h->cur], h->geo,
-                                         h->rates, h->stream);
+      hipError_t e = lbk::launch_step_t3(les, h->lat[h->cur], h->lat[1 - h->cur], nullptr,
+                                         nullptr, h->geo, h->rates, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "step launch");
       h->cur = 1 - h->cur;
       h->step += 3;
@@ -376,11 +376,24 @@ int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, in
   const char* prev = static_cast<const char*>(src);
   char* out = static_cast<char*>(store);
   int64_t t = 0;
+  const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
+  // triples (FP32) that also store both intermediate states; a remainder of
+  // one step goes with the last triple as two pairs
+  if (pass_steps(h) == 3) {
+    int64_t triples = n / 3;
+    if (n % 3 == 1 && triples > 0) --triples;
+    for (; t < 3 * triples; t += 3) {
+      hipError_t e = lbk::launch_step_t3(les, prev, out + 2 * stride, out, out + stride, h->geo,
+                                         h->rates, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "step launch");
+      prev = out + 2 * stride;
+      out += 3 * stride;
+    }
+  }
   // pairs of steps in one pass that stores the intermediate state too; in
   // automatic mode for FP32 only (with FP16 the extra store made the pass
   // slower than two single steps: 75 against 64 us per step at 2048^2)
   if (pass_steps(h) >= 2 && (h->p.storage == LBMHD_FP32 || h->p.steps_per_pass >= 2)) {
-    const bool les = (h->p.les & 1) && (h->p.cs > 0.0 || h->p.cs_b > 0.0);
     for (; t + 2 <= n; t += 2) {
       hipError_t e = lbk::launch_step2(h->p.storage, les, prev, out + stride, out, h->geo,
                                        h->rates, h->stream);

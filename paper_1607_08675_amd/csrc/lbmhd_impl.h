@@ -53,9 +53,10 @@ hipError_t launch_step(int storage, bool les, const void* src, void* dst, const 
 hipError_t launch_step2(int storage, bool les, const void* src, void* dst, void* mid,
                         const Geom& g, const Rates& r, hipStream_t s);
 // Three forward steps in one pass, FP32 storage only: dst = (C S)^3 src,
-// equal to three launch_step calls; src and dst must not overlap.
-hipError_t launch_step_t3(bool les, const void* src, void* dst, const Geom& g, const Rates& r,
-                          hipStream_t s);
+// equal to three launch_step calls; with mid1, mid2 != nullptr the states
+// after one and two steps are stored there too.  The buffers do not overlap.
+hipError_t launch_step_t3(bool les, const void* src, void* dst, void* mid1, void* mid2,
+                          const Geom& g, const Rates& r, hipStream_t s);
 // Whether launch_step2 beats two launch_step calls on this lattice: it needs
 // enough blocks to fill the chip (measured crossover: 1024^2 FP32, 2048^2 FP16).
 bool step2_pays(int storage, const Geom& g);

@@ -564,9 +564,13 @@ __device__ __forceinline__ int t3_row(int q, int sA, int sB) {
   return g == 0 ? sA * 2 + i : (g == 1 ? kT3BaseB + sB * 6 + i : kT3BaseC + i);
 }
 
-template <bool LES>
+// MID: also store the states after the first and the second update to mid1
+// and mid2 (each block the rows and columns it owns, so every site once).
+template <bool LES, bool MID>
 __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict__ src,
-                                                        float* __restrict__ dst, Geom geo,
+                                                        float* __restrict__ dst,
+                                                        float* __restrict__ mid1,
+                                                        float* __restrict__ mid2, Geom geo,
                                                         Rates rt, int tiles_x, int rows,
                                                         bool xcd_map) {
   __shared__ float l1[kT3Slots][kT3Cols + 4];   // first update: column lc + 2
@@ -620,6 +624,8 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
       float v[kNPop][1];
       gather_row<LBMHD_FP32, 1>(src, P, xc, xl, xr, row, v);
       collide_sites<1, LES>(v, rt);
+      if (MID && up3 && t >= 2 && t <= h + 1)
+        store_row<LBMHD_FP32, 1>(mid1, P, row[1] + unsigned(xc), v);
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
         const int k = kT2Reg[q];
@@ -651,6 +657,8 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
         }
       }
       collide_sites<1, LES>(v, rt);
+      if (MID && up3 && t >= 3 && t <= h + 2)
+        store_row<LBMHD_FP32, 1>(mid2, P, unsigned(y0 - 3 + t) * geo.pitch + unsigned(xc), v);
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
         const int k = kT2Reg[q];
@@ -1487,8 +1495,8 @@ static int step_t3_rows(const Geom& g) {
   return int(rows < 8 ? 8 : (rows > 128 ? 32 : rows));
 }
 
-hipError_t launch_step_t3(bool les, const void* src, void* dst, const Geom& g, const Rates& r,
-                          hipStream_t s) {
+hipError_t launch_step_t3(bool les, const void* src, void* dst, void* mid1, void* mid2,
+                          const Geom& g, const Rates& r, hipStream_t s) {
   const int rows = step_t3_rows(g);
   const int tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
   const int strips = (g.ny + rows - 1) / rows;
@@ -1496,10 +1504,20 @@ hipError_t launch_step_t3(bool les, const void* src, void* dst, const Geom& g, c
   const bool xcd_map = strips % 8 == 0;
   auto* a = static_cast<const float*>(src);
   auto* b = static_cast<float*>(dst);
-  if (les)
-    hipLaunchKernelGGL((k_step_t3<true>), grid, block, 0, s, a, b, g, r, tiles_x, rows, xcd_map);
+  auto* m1 = static_cast<float*>(mid1);
+  auto* m2 = static_cast<float*>(mid2);
+  if (m1 && les)
+    hipLaunchKernelGGL((k_step_t3<true, true>), grid, block, 0, s, a, b, m1, m2, g, r, tiles_x,
+                       rows, xcd_map);
+  else if (m1)
+    hipLaunchKernelGGL((k_step_t3<false, true>), grid, block, 0, s, a, b, m1, m2, g, r, tiles_x,
+                       rows, xcd_map);
+  else if (les)
+    hipLaunchKernelGGL((k_step_t3<true, false>), grid, block, 0, s, a, b, m1, m2, g, r, tiles_x,
+                       rows, xcd_map);
   else
-    hipLaunchKernelGGL((k_step_t3<false>), grid, block, 0, s, a, b, g, r, tiles_x, rows, xcd_map);
+    hipLaunchKernelGGL((k_step_t3<false, false>), grid, block, 0, s, a, b, m1, m2, g, r,
+                       tiles_x, rows, xcd_map);
   return hipGetLastError();
 }
 

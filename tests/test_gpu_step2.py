@@ -122,15 +122,17 @@ def test_fused_equals_single_steps_rough_fields(lb, storage, n):
         assert torch.equal(a, b), int((a != b).sum())
 
 
-@pytest.mark.parametrize("storage,nx,ny,n", [("fp32", 300, 70, 5), ("fp32", 600, 60, 6),
-                                             ("fp16", 512, 40, 4), ("fp16", 301, 33, 5),
-                                             ("fp32", 1024, 1024, 4)])
-def test_stored_trajectory_two_steps_per_pass(lb, storage, nx, ny, n):
-    """lbmhd_step_store with two steps per pass (the pass also stores its
-    intermediate state) writes every state of the one-step trajectory."""
+@pytest.mark.parametrize("storage,nx,ny,n,deep", [
+    ("fp32", 300, 70, 5, 2), ("fp32", 600, 60, 6, 2), ("fp16", 512, 40, 4, 2),
+    ("fp16", 301, 33, 5, 2), ("fp32", 1024, 1024, 4, 2), ("fp32", 300, 70, 3, 3),
+    ("fp32", 300, 70, 7, 3), ("fp32", 600, 60, 8, 3), ("fp32", 5, 3, 4, 3),
+    ("fp32", 1024, 1024, 6, 3)])
+def test_stored_trajectory_two_steps_per_pass(lb, storage, nx, ny, n, deep):
+    """lbmhd_step_store with two or three steps per pass (the pass also stores
+    its intermediate states) writes every state of the one-step trajectory."""
     fields = random_fields(nx, ny, 13)
     rows = []
-    for spp in (1, 2):
+    for spp in (1, deep):
         L = lb.Lattice(lb.LBMHDConfig(nx=nx, ny=ny, nu=1e-3, eta=2e-3, les=1, cs=0.15,
                                       storage=storage, steps_per_pass=spp))
         L.init_fields(*fields)
@@ -143,12 +145,13 @@ def test_stored_trajectory_two_steps_per_pass(lb, storage, nx, ny, n):
 
 def test_gradient_with_two_steps_per_pass_matches_single(lb):
     """The checkpointed gradient (stored trajectory and checkpointed segments)
-    with two steps per pass equals the one-step gradient bit for bit (FP32)."""
+    with two or three steps per pass equals the one-step gradient bit for bit
+    (FP32)."""
     from paper_1607_08675_amd.adjoint import LBMHDFunction
     n, steps = 64, 30
     fields = decaying_turbulence(n, n, u_rms=0.05, b_rms=0.05)
     out = []
-    for spp in (1, 2):
+    for spp in (1, 2, 3):
         for every in (1, 7):
             cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-4, eta=1e-4, les=1, cs=0.1, cs_b=0.07,
                                  steps_per_pass=spp)

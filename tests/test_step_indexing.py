@@ -105,7 +105,8 @@ def two_step(nx, ny, V, fp16):
 
 def three_step(nx, ny):
     """k_step_t3: 256 threads plus a fifth wave for the four halo columns,
-    two LDS levels with rings of 3 / 2 / 1 slots, two barriers per pass."""
+    two LDS levels with rings of 3 / 2 / 1 slots, two barriers per pass; the
+    trajectory-storing variant writes each intermediate site once."""
     W, H = 256, 2
     tiles = (nx + W - 1) // W
     rows = tiles * ny // 512
@@ -113,6 +114,7 @@ def three_step(nx, ny):
     strips = (ny + rows - 1) // rows
     slots = (3, 2, 1)
     written = set()
+    mids = [set(), set()]   # intermediate states stored by a trajectory-storing pass
     for b in range(tiles * strips):
         x0, y0 = block_origin(b, tiles, strips, rows, W)
         wt, h = min(W, nx - x0), min(rows, ny - y0)
@@ -143,6 +145,9 @@ def three_step(nx, ny):
                                 assert levels[s - 1][(ring_row(q, tt, slots), col)] == (q, *want, tt)
                             else:
                                 assert regs[s - 1][(tid, q, t - REG_DELAY[CY[q]])] == want
+                    if s < 2 and 0 <= lc < wt and 2 + s <= t <= h + 1 + s:
+                        assert y0 <= r < y0 + h and (xc, r) not in mids[s]
+                        mids[s].add((xc, r))
                     if s < 2:
                         for q in range(19):
                             if GROUP[q] >= 0:
@@ -158,6 +163,7 @@ def three_step(nx, ny):
                         assert (xc, r) not in written
                         written.add((xc, r))
     assert len(written) == nx * ny
+    assert len(mids[0]) == len(mids[1]) == nx * ny
 
 
 SIZES = [(256, 64), (300, 70), (2, 2), (3, 5), (513, 9), (600, 60), (77, 41), (4, 600)]
