@@ -235,6 +235,25 @@ def test_current_state_follows_the_passes(lb, spp, n):
     assert torch.equal(stored_words(L, cur), stored_words(L))
 
 
+@pytest.mark.parametrize("deep", [2, 3])
+def test_multi_step_long_run_equals_single_steps(lb, deep):
+    """301 steps of 1024^2 Orszag-Tang (FP32, LES) two or three per pass,
+    remainders included, against 301 single steps, bit for bit: any
+    difference would have been amplified by the flow over that many steps."""
+    n = 1024
+    fields = orszag_tang(n, n)
+    out = []
+    for spp in (1, deep):
+        L = lb.Lattice(lb.LBMHDConfig(nx=n, ny=n, nu=1e-5, eta=1e-5, les=1, cs=0.1,
+                                      steps_per_pass=spp))
+        L.init_fields(*fields)
+        for chunk in (100, 100, 100, 1):
+            L.step(chunk)
+        assert L.step_count == 301
+        out.append(stored_words(L))
+    assert torch.equal(out[0], out[1]), int((out[0] != out[1]).sum())
+
+
 def test_fused_interleaved_with_stored_steps(lb):
     """Fused steps, single steps into a store, and fused steps again, against
     single steps throughout."""
