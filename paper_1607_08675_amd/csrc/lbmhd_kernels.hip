@@ -544,24 +544,24 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
 // (from level 1) and row y0 - 4 + t through the third (from level 2, to
 // HBM).  The first update also covers two halo columns on each side and the
 // second one on each side; a fifth wave owns those four halo columns, so
-// that every thread keeps the c_x = 0 planes of its own column in registers
-// and no wave collides more than three times per pass.  Planes with c_x != 0
-// pass through one LDS level per update, grouped by c_y as in k_step2; two
-// barriers per pass (after the first and after the second update) order
-// every ring access, so rings of 3, 2 and 1 slots suffice (20 plane-rows per
-// level).  HBM bytes per site for three steps: one read and one write of the
-// lattice, plus halo re-reads of 4 / rows of the rows and 8 / kT3Cols of the
-// columns.
+// that every thread keeps the values of its own column in registers and no
+// wave collides more than three times per pass.  Planes with c_x != 0 cross
+// to the neighbouring column through one LDS row per plane and level: the
+// consumer reads it right after the barrier that publishes it (two barriers
+// per pass, after the first and after the second update), and carries the
+// c_y = 0 values one pass and the c_y = +1 values two passes in registers,
+// as it does for its own c_x = 0 planes.  So each LDS row is rewritten on
+// the next pass and a level is 10 plane-rows.  HBM bytes per site for three
+// steps: one read and one write of the lattice, plus halo re-reads of
+// 4 / rows of the rows and 8 / kT3Cols of the columns.
 constexpr int kT3Cols = 256;
 constexpr int kT3Threads = kT3Cols + 64;
-constexpr int kT3SlotsA = 3, kT3SlotsB = 2;   // c_y = +1 and c_y = 0 groups; c_y = -1: 1
-constexpr int kT3Slots = 2 * kT3SlotsA + 6 * kT3SlotsB + 2;
-constexpr int kT3BaseB = 2 * kT3SlotsA, kT3BaseC = kT3BaseB + 6 * kT3SlotsB;
+constexpr int kT3Rows = 10;   // planes with c_x != 0
 
-// One level's ring row of plane q (c_x != 0) written on pass slot (sA, sB).
-__device__ __forceinline__ int t3_row(int q, int sA, int sB) {
+// LDS row of plane q (c_x != 0): the c_y = +1 planes, then c_y = 0, then c_y = -1.
+__device__ __forceinline__ int t3_row(int q) {
   const int g = kT2Group[q], i = kT2Index[q];
-  return g == 0 ? sA * 2 + i : (g == 1 ? kT3BaseB + sB * 6 + i : kT3BaseC + i);
+  return g == 0 ? i : (g == 1 ? 2 + i : 8 + i);
 }
 
 // MID: also store the states after the first and the second update to mid1
@@ -573,8 +573,8 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
                                                         float* __restrict__ mid2, Geom geo,
                                                         Rates rt, int tiles_x, int rows,
                                                         bool xcd_map) {
-  __shared__ float l1[kT3Slots][kT3Cols + 4];   // first update: column lc + 2
-  __shared__ float l2[kT3Slots][kT3Cols + 2];   // second update: column lc + 1
+  __shared__ float l1[kT3Rows][kT3Cols + 4];   // first update: column lc + 2
+  __shared__ float l2[kT3Rows][kT3Cols + 2];   // second update: column lc + 1
   const int nx = geo.nx, ny = geo.ny;
   const long long P = geo.plane;
   int tile, strip;
@@ -605,17 +605,19 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
   const int xl = xc == 0 ? nx - 1 : xc - 1;
   const int xr = xc == nx - 1 ? 0 : xc + 1;
 
-  // c_x = 0 planes of earlier passes, per level: c_y = 0 from the last pass,
-  // c_y = +1 from the last two
+  // Inputs of earlier passes, per level, for this thread's column: c_y = 0
+  // planes from the last pass, c_y = +1 planes from the last two; z: the
+  // c_x = 0 planes (3 per c_y), x: the c_x != 0 ones (6 with c_y = 0, 2 with
+  // c_y = +1), already taken from column lc - c_x.
   float z1c[3], z1u1[3], z1u2[3], z2c[3], z2u1[3], z2u2[3];
+  float x1c[6], x1u1[2], x1u2[2], x2c[6], x2u1[2], x2u2[2];
 #pragma unroll
   for (int k = 0; k < 3; ++k) z1c[k] = z1u1[k] = z1u2[k] = z2c[k] = z2u1[k] = z2u2[k] = 0.0f;
-  int sA = 0;   // t mod 3; t mod 2 is t & 1
+#pragma unroll
+  for (int k = 0; k < 6; ++k) x1c[k] = x2c[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) x1u1[k] = x1u2[k] = x2u1[k] = x2u2[k] = 0.0f;
   for (int t = 0; t < h + 4; ++t) {
-    const int sB = t & 1;
-    const int sA1 = sA == 0 ? kT3SlotsA - 1 : sA - 1;   // (t - 1) mod 3 ...
-    const int sA2 = sA1 == 0 ? kT3SlotsA - 1 : sA1 - 1;  // ... and (t - 2) mod 3
-    const int sB1 = sB ^ 1;                               // (t - 1) mod 2
     // first update of row y0 - 2 + t
     float n1c[3], n1u[3], n1d[3];
     if (has) {
@@ -630,7 +632,7 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
       for (int q = 0; q < kNPop; ++q) {
         const int k = kT2Reg[q];
         if (kT2Group[q] >= 0)
-          l1[t3_row(q, sA, sB)][lc + 2] = v[q][0];
+          l1[t3_row(q)][lc + 2] = v[q][0];
         else if (kPlaneCy[q] == 0)
           n1c[k] = v[q][0];
         else if (kPlaneCy[q] == 1)
@@ -640,54 +642,77 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
       }
     }
     __syncthreads();
-    // second update of row y0 - 3 + t (from pass 2 on)
+    // second update of row y0 - 3 + t (from pass 2 on); the level-1 row of
+    // this pass is read in every pass, before the next one overwrites it
     float n2c[3], n2u[3], n2d[3];
     const bool do2 = t >= 2 && up2;
-    if (do2) {
+    {
+      float e[kT3Rows];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q)
+        if (kT2Group[q] >= 0) e[t3_row(q)] = up2 ? l1[t3_row(q)][lc - kPlaneCx[q] + 2] : 0.0f;
       float v[kNPop][1];
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
-        const int g = kT2Group[q], k = kT2Reg[q];
-        if (g >= 0) {
-          // c_y = +1 planes were written two passes ago, c_y = 0 one, c_y = -1 now
-          const int r = g == 0 ? t3_row(q, sA2, 0) : (g == 1 ? t3_row(q, 0, sB1) : t3_row(q, 0, 0));
-          v[q][0] = l1[r][lc - kPlaneCx[q] + 2];
-        } else {
-          v[q][0] = kPlaneCy[q] == 0 ? z1c[k] : (kPlaneCy[q] == 1 ? z1u2[k] : n1d[k]);
-        }
-      }
-      collide_sites<1, LES>(v, rt);
-      if (MID && up3 && t >= 3 && t <= h + 2)
-        store_row<LBMHD_FP32, 1>(mid2, P, unsigned(y0 - 3 + t) * geo.pitch + unsigned(xc), v);
-#pragma unroll
-      for (int q = 0; q < kNPop; ++q) {
-        const int k = kT2Reg[q];
-        if (kT2Group[q] >= 0)
-          l2[t3_row(q, sA, sB)][lc + 1] = v[q][0];
-        else if (kPlaneCy[q] == 0)
-          n2c[k] = v[q][0];
-        else if (kPlaneCy[q] == 1)
-          n2u[k] = v[q][0];
+        const int g = kT2Group[q], i = kT2Index[q], k = kT2Reg[q];
+        if (g >= 0)
+          v[q][0] = g == 0 ? x1u2[i] : (g == 1 ? x1c[i] : e[t3_row(q)]);
         else
-          n2d[k] = v[q][0];
+          v[q][0] = kPlaneCy[q] == 0 ? z1c[k] : (kPlaneCy[q] == 1 ? z1u2[k] : n1d[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        x1u2[i] = x1u1[i];
+        x1u1[i] = e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) x1c[i] = e[2 + i];
+      if (do2) {
+        collide_sites<1, LES>(v, rt);
+        if (MID && up3 && t >= 3 && t <= h + 2)
+          store_row<LBMHD_FP32, 1>(mid2, P, unsigned(y0 - 3 + t) * geo.pitch + unsigned(xc), v);
+#pragma unroll
+        for (int q = 0; q < kNPop; ++q) {
+          const int k = kT2Reg[q];
+          if (kT2Group[q] >= 0)
+            l2[t3_row(q)][lc + 1] = v[q][0];
+          else if (kPlaneCy[q] == 0)
+            n2c[k] = v[q][0];
+          else if (kPlaneCy[q] == 1)
+            n2u[k] = v[q][0];
+          else
+            n2d[k] = v[q][0];
+        }
       }
     }
     __syncthreads();
-    // third update of row y0 - 4 + t (from pass 4 on), stored
-    if (t >= 4 && up3) {
-      float v[kNPop][1];
+    // third update of row y0 - 4 + t (from pass 4 on), stored; the level-2
+    // row of this pass is read in every pass, as above
+    {
+      float e[kT3Rows];
 #pragma unroll
-      for (int q = 0; q < kNPop; ++q) {
-        const int g = kT2Group[q], k = kT2Reg[q];
-        if (g >= 0) {
-          const int r = g == 0 ? t3_row(q, sA2, 0) : (g == 1 ? t3_row(q, 0, sB1) : t3_row(q, 0, 0));
-          v[q][0] = l2[r][lc - kPlaneCx[q] + 1];
-        } else {
-          v[q][0] = kPlaneCy[q] == 0 ? z2c[k] : (kPlaneCy[q] == 1 ? z2u2[k] : n2d[k]);
+      for (int q = 0; q < kNPop; ++q)
+        if (kT2Group[q] >= 0) e[t3_row(q)] = up3 ? l2[t3_row(q)][lc - kPlaneCx[q] + 1] : 0.0f;
+      if (t >= 4 && up3) {
+        float v[kNPop][1];
+#pragma unroll
+        for (int q = 0; q < kNPop; ++q) {
+          const int g = kT2Group[q], i = kT2Index[q], k = kT2Reg[q];
+          if (g >= 0)
+            v[q][0] = g == 0 ? x2u2[i] : (g == 1 ? x2c[i] : e[t3_row(q)]);
+          else
+            v[q][0] = kPlaneCy[q] == 0 ? z2c[k] : (kPlaneCy[q] == 1 ? z2u2[k] : n2d[k]);
         }
+        collide_sites<1, LES>(v, rt);
+        store_row<LBMHD_FP32, 1>(dst, P, unsigned(y0 - 4 + t) * geo.pitch + unsigned(xc), v);
       }
-      collide_sites<1, LES>(v, rt);
-      store_row<LBMHD_FP32, 1>(dst, P, unsigned(y0 - 4 + t) * geo.pitch + unsigned(xc), v);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        x2u2[i] = x2u1[i];
+        x2u1[i] = e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) x2c[i] = e[2 + i];
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -698,7 +723,6 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
       z2u1[k] = do2 ? n2u[k] : 0.0f;
       z2c[k] = do2 ? n2c[k] : 0.0f;
     }
-    sA = sA == kT3SlotsA - 1 ? 0 : sA + 1;
   }
 }
 
@@ -1485,10 +1509,10 @@ bool step2_pays(int storage, const Geom& g) {
 }
 
 // Strip height of the three-step kernel (halo overhead 4 / rows), measured:
-// about 512 blocks, which all run at once (LDS admits three per CU), up to
-// 128-row strips (2048^2: 32 rows, 4096^2: 128); on larger lattices, where
-// 128-row strips would leave a last round of blocks partly empty, 32-row
-// strips (8192^2: 80.7k MLUPS against 75.5k at 128 rows).
+// about 512 blocks, which all run at once (registers admit four per CU), up
+// to 128-row strips (2048^2: 32 rows, 4096^2: 128; 64-row strips there, 1024
+// blocks, were slower); on larger lattices 32-row strips (8192^2: 16-row
+// strips as fast, 64 and 8 rows 3% and 8% slower).
 static int step_t3_rows(const Geom& g) {
   const long long tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
   const long long rows = tiles_x * g.ny / 512;

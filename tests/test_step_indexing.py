@@ -103,16 +103,22 @@ def two_step(nx, ny, V, fp16):
     assert len(written) == nx * ny
 
 
+def t3_row(q):
+    g, i = GROUP[q], INDEX[q]
+    return i if g == 0 else (2 + i if g == 1 else 8 + i)
+
+
 def three_step(nx, ny):
     """k_step_t3: 256 threads plus a fifth wave for the four halo columns,
-    two LDS levels with rings of 3 / 2 / 1 slots, two barriers per pass; the
-    trajectory-storing variant writes each intermediate site once."""
+    one LDS row per c_x != 0 plane and level, read by the consumer in the
+    pass that writes it (right after the barrier) and carried on in its
+    registers; two barriers per pass; the trajectory-storing variant writes
+    each intermediate site once."""
     W, H = 256, 2
     tiles = (nx + W - 1) // W
     rows = tiles * ny // 512
     rows = 8 if rows < 8 else (32 if rows > 128 else rows)
     strips = (ny + rows - 1) // rows
-    slots = (3, 2, 1)
     written = set()
     mids = [set(), set()]   # intermediate states stored by a trajectory-storing pass
     for b in range(tiles * strips):
@@ -126,11 +132,25 @@ def three_step(nx, ny):
                 k = tid - W
                 cols.append(((-2, -1, wt, wt + 1)[k] if k < 4 else 0, k < 4))
         levels = [{}, {}]
-        regs = [{}, {}]
+        regs = [{}, {}]   # (thread, plane, pass) -> site whose level-s value the thread holds
         for t in range(h + 2 * H):
             for s in range(3):
-                cells = set()
                 r = y0 - H + t - s
+                if s > 0:
+                    # every pass, each thread of the update's columns takes the
+                    # c_x != 0 planes of the row just published at lc - c_x
+                    for tid, (lc, has) in enumerate(cols):
+                        if not (has and s - H <= lc <= wt - 1 + H - s):
+                            continue
+                        for q in range(19):
+                            if GROUP[q] >= 0:
+                                col = lc - CX[q] + H - (s - 1)
+                                assert 0 <= col < W + 2 * (H - s + 1)
+                                cell = levels[s - 1].get((t3_row(q), col))
+                                if t >= 2 * (s - 1):
+                                    assert cell is not None and cell[0] == q and cell[3] == t
+                                    regs[s - 1][(tid, q, t)] = cell[1:3]
+                cells = set()
                 for tid, (lc, has) in enumerate(cols):
                     if not (has and t >= 2 * s and s - H <= lc <= wt - 1 + H - s):
                         continue
@@ -138,21 +158,15 @@ def three_step(nx, ny):
                     if s > 0:
                         for q in range(19):
                             want = ((xc - CX[q]) % nx, (r - CY[q]) % ny)
-                            if GROUP[q] >= 0:
-                                tt = t - DELAY[GROUP[q]]
-                                col = lc - CX[q] + H - (s - 1)
-                                assert 0 <= col < W + 4
-                                assert levels[s - 1][(ring_row(q, tt, slots), col)] == (q, *want, tt)
-                            else:
-                                assert regs[s - 1][(tid, q, t - REG_DELAY[CY[q]])] == want
+                            assert regs[s - 1][(tid, q, t - REG_DELAY[CY[q]])] == want
                     if s < 2 and 0 <= lc < wt and 2 + s <= t <= h + 1 + s:
                         assert y0 <= r < y0 + h and (xc, r) not in mids[s]
                         mids[s].add((xc, r))
                     if s < 2:
                         for q in range(19):
                             if GROUP[q] >= 0:
-                                key = (ring_row(q, t, slots), lc + H - s)
-                                assert 0 <= key[0] < 20 and 0 <= key[1] < W + 4 - 2 * s
+                                key = (t3_row(q), lc + H - s)
+                                assert 0 <= key[0] < 10 and 0 <= key[1] < W + 4 - 2 * s
                                 assert key not in cells
                                 cells.add(key)
                                 levels[s][key] = (q, xc, r % ny, t)
