@@ -600,6 +600,11 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
   }
   const bool up2 = has && lc >= -1 && lc <= wt;   // takes the second update
   const bool up3 = has && lc >= 0 && lc < wt;     // takes the third update
+  // LDS columns read for the second and third updates: lc - c_x + c1 and
+  // lc - c_x + c2.  Threads that take no such update read columns 1 .. 3 or
+  // 0 .. 2 instead (in bounds, never used), so the reads need no branch.
+  const int c1 = up2 ? lc + 2 : 2;
+  const int c2 = up3 ? lc + 1 : 1;
   int xc = (x0 + lc) % nx;
   if (xc < 0) xc += nx;
   const int xl = xc == 0 ? nx - 1 : xc - 1;
@@ -650,7 +655,7 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
       float e[kT3Rows];
 #pragma unroll
       for (int q = 0; q < kNPop; ++q)
-        if (kT2Group[q] >= 0) e[t3_row(q)] = up2 ? l1[t3_row(q)][lc - kPlaneCx[q] + 2] : 0.0f;
+        if (kT2Group[q] >= 0) e[t3_row(q)] = l1[t3_row(q)][c1 - kPlaneCx[q]];
       float v[kNPop][1];
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
@@ -692,7 +697,7 @@ __global__ __launch_bounds__(kT3Threads) void k_step_t3(const float* __restrict_
       float e[kT3Rows];
 #pragma unroll
       for (int q = 0; q < kNPop; ++q)
-        if (kT2Group[q] >= 0) e[t3_row(q)] = up3 ? l2[t3_row(q)][lc - kPlaneCx[q] + 1] : 0.0f;
+        if (kT2Group[q] >= 0) e[t3_row(q)] = l2[t3_row(q)][c2 - kPlaneCx[q]];
       if (t >= 4 && up3) {
         float v[kNPop][1];
 #pragma unroll
