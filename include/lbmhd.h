@@ -100,7 +100,11 @@ typedef struct {
                                 moments, the vorticity w from the neighbours;
                                 self-consistent tau, tau_m (cubic roots);
                              6: kinetic and cross-helicity closures together.
-                             Bits 0 and 2 exclude each other. */
+                             Bits 0 and 2 exclude each other.  Bit 2 needs
+                             tau_m0 <= 5/4 (eta <= 1/4): as tau_m0 nears 3/2
+                             the clip of tau_m nears a double root of its
+                             cubic, where the kernel's Newton solution
+                             converges only linearly. */
   double cs, cs_b;        /* closure constants C_Sv >= 0 of the eddy viscosity
                              and C_Sb >= 0 of the eddy resistivity (eqs.
                              SmagorinskyMHDClosureV/B, CHClosureV/B) */
@@ -167,7 +171,8 @@ const char* lbmhd_last_error(const lbmhd_t* h);
  * Errors: LBMHD_ERR_INVALID_ARG if p is out of range (nx, ny < 2; nu, eta
  * <= 0; a rate outside (0, 2); s5 != s6; cs < 0; delta <= 0; unknown
  * storage; one FP32 plane of ny rows of padded nx reaching 4 GiB, since
- * in-plane byte offsets are 32-bit). */
+ * in-plane byte offsets are 32-bit); LBMHD_ERR_UNSUPPORTED for the
+ * cross-helicity closure (les bit 2) with eta > 1/4. */
 int lbmhd_create(const lbmhd_params* p, lbmhd_t** out);
 
 /* Release the handle (not the caller's buffers).  NULL is accepted. */
@@ -269,8 +274,11 @@ int lbmhd_get_populations(lbmhd_t* h, double* out);
 int lbmhd_set_populations(lbmhd_t* h, const double* in, int64_t step);
 
 /* Copy the current encoded lattice (`lattice` bytes) to / from caller device
- * memory, bit-exact; used for checkpoints.  load sets the step count.
- * Asynchronous. */
+ * memory, bit-exact; used for checkpoints.  load sets the step count.  src may
+ * be the state buffer the handle reports (lbmhd_current_state), also of an
+ * in-place lattice left in the reversed layout, which load turns back first;
+ * a src that partly overlaps the first bound lattice is refused
+ * (LBMHD_ERR_INVALID_ARG).  Asynchronous. */
 int lbmhd_save_state(lbmhd_t* h, void* dst);
 int lbmhd_load_state(lbmhd_t* h, const void* src, int64_t step);
 

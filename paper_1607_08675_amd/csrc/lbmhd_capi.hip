@@ -142,15 +142,45 @@ hipError_t adj_one(lbmhd_t* h, const void* x, const float* from, float* to, doub
                               d2, h->stream);
 }
 
-// Run the diagnostics kernels on `lat` and copy the 16 results to host.
-int run_diag(lbmhd_t* h, const void* lat, double out[lbk::kDiagSlots]) {
-  hipError_t e = lbk::launch_diag(h->p.storage, lat, h->ws, ws_out(h), h->geo, h->stream);
+// Run the diagnostics kernels on `lat` with the block partials at `part` and
+// the results at `res` (the workspace unless given), and copy the 16 results
+// to host.
+int run_diag(lbmhd_t* h, const void* lat, double out[lbk::kDiagSlots],
+             double* part = nullptr, double* res = nullptr) {
+  if (!part) {
+    part = h->ws;
+    res = ws_out(h);
+  }
+  hipError_t e = lbk::launch_diag(h->p.storage, lat, part, res, h->geo, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "diagnostics launch");
-  e = hipMemcpyAsync(out, ws_out(h), sizeof(double) * lbk::kDiagSlots, hipMemcpyDeviceToHost,
+  e = hipMemcpyAsync(out, res, sizeof(double) * lbk::kDiagSlots, hipMemcpyDeviceToHost,
                      h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "diagnostics copy");
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "diagnostics synchronise");
+  return LBMHD_OK;
+}
+
+// Diagnostics results (16 doubles) into the public struct; nonzero
+// non-finite count -> LBMHD_ERR_NONFINITE.
+int fill_diag(lbmhd_t* h, const double v[lbk::kDiagSlots], lbmhd_diag_t* out) {
+  out->mass = v[0];
+  out->mom_x = v[1];
+  out->mom_y = v[2];
+  out->flux_x = v[3];
+  out->flux_y = v[4];
+  out->e_kin = v[5];
+  out->e_mag = v[6];
+  out->cross_helicity = v[7];
+  out->enstrophy = v[8];
+  out->current_sq = v[9];
+  out->nonfinite = int64_t(v[10]);
+  out->max_abs_divB = v[11];
+  out->max_u = v[12];
+  out->step = h->step;
+  if (out->nonfinite > 0)
+    return fail(h, LBMHD_ERR_NONFINITE,
+                std::to_string(out->nonfinite) + " sites hold non-finite populations");
   return LBMHD_OK;
 }
 
@@ -191,6 +221,11 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   if (p->inplace != 0 && p->inplace != 1) return LBMHD_ERR_INVALID_ARG;
   if (p->inplace && (p->les & 6)) return LBMHD_ERR_INVALID_ARG;
   if (p->steps_per_pass < 0 || p->steps_per_pass > 3) return LBMHD_ERR_INVALID_ARG;
+  // cross-helicity closure: as tau_m0 = 3 eta + 1/2 approaches 3/2, the clip
+  // of the magnetic relaxation time approaches a double root of its cubic,
+  // where the kernel's Newton steps converge only linearly; up to
+  // tau_m0 = 5/4 six steps land within 1e-6 of the root (measured)
+  if ((p->les & 4) && 3.0 * p->eta + 0.5 > 1.25) return LBMHD_ERR_UNSUPPORTED;
   const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
   lbk::Geom g = make_geom(p->nx, p->ny, esize);
   lbk::Geom ga = make_geom(p->nx, p->ny, 4);
@@ -464,24 +499,7 @@ int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out) {
   const void* st = nullptr;
   if (int rc = current(h, &st)) return rc;
   if (int rc = run_diag(h, st, v)) return rc;
-  out->mass = v[0];
-  out->mom_x = v[1];
-  out->mom_y = v[2];
-  out->flux_x = v[3];
-  out->flux_y = v[4];
-  out->e_kin = v[5];
-  out->e_mag = v[6];
-  out->cross_helicity = v[7];
-  out->enstrophy = v[8];
-  out->current_sq = v[9];
-  out->nonfinite = int64_t(v[10]);
-  out->max_abs_divB = v[11];
-  out->max_u = v[12];
-  out->step = h->step;
-  if (out->nonfinite > 0)
-    return fail(h, LBMHD_ERR_NONFINITE,
-                std::to_string(out->nonfinite) + " sites hold non-finite populations");
-  return LBMHD_OK;
+  return fill_diag(h, v, out);
 }
 
 int lbmhd_get_populations(lbmhd_t* h, double* out) {
@@ -519,8 +537,16 @@ int lbmhd_load_state(lbmhd_t* h, const void* src, int64_t step) {
   if (int rc = need_bound(h)) return rc;
   if (!src || !aligned(src) || step < 0)
     return fail(h, LBMHD_ERR_INVALID_ARG, "null or unaligned src, or negative step");
-  hipError_t e = lbk::launch_copy(src, h->lat[0], h->lattice_bytes, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "copy launch");
+  // src may be the bound lattice itself (then nothing moves) but not a range
+  // that partly overlaps it
+  if (src != h->lat[0] && overlap(src, h->lattice_bytes, h->lat[0], h->lattice_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "src partly overlaps the bound lattice");
+  // an in-place lattice left reversed by an odd step count is read naturally
+  if (int rc = natural(h, src)) return rc;
+  if (src != h->lat[0]) {
+    hipError_t e = lbk::launch_copy(src, h->lat[0], h->lattice_bytes, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copy launch");
+  }
   h->cur = 0;
   h->reversed = false;
   h->step = step;

@@ -83,12 +83,12 @@ hipError_t launch_macro(int storage, const void* lat, double* rho, double* ux, d
                         double* bx, double* by, const Geom& g, hipStream_t s);
 // Byte copy (vector loads/stores) for checkpoints.
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
-// Diagnostics: macro planes (5 x nx*ny doubles at ws), partials, final 16
-// doubles at out_dev.
 // Diagnostics in one pass over the lattice: per-block partials (at most
 // kDiagBlocks x kDiagSlots doubles at part) folded into out_dev[0 .. 12].
 hipError_t launch_diag(int storage, const void* lat, double* part, double* out_dev,
                        const Geom& g, hipStream_t s);
+// Number of block partials launch_diag writes for this lattice (<= kDiagBlocks).
+int diag_partials(const Geom& g);
 
 // Box-averaged macroscopic fields (w x w blocks).
 hipError_t launch_macro_box(int storage, const void* lat, int w, double* rho, double* ux,

@@ -141,8 +141,13 @@ struct NbTerms {
 // t^2 = p + d (2 sp + d), d = t - sp: Newton steps on the convex, increasing
 // h(d) = d (2 p + 3 sp d + d^2) - q from an upper bound of the root
 // (min(q / (2 p), q^(1/3)) for q > 0, 0 otherwise), so the iterates fall
-// monotonically; six steps reach FP32 resolution for p <= 0.8 and all q
-// down to the clip.  For q < 0 the caller guarantees a root >= sqrt(p / 3).
+// monotonically.  For q >= 0 six steps reach FP32 resolution at every p
+// (measured to p = 20).  For q < 0 the caller clips first, so the root is at
+// least t* = max(sqrt(1/2), sqrt(p / 3)), a simple root for p < 3/2; but as p
+// nears 3/2 the clip nears the cubic's double root at sqrt(p / 3), where
+// Newton converges only linearly.  Six steps land within 1e-6 of the root
+// up to p = 5/4 (measured: 8.8e-4 at p = 1.4), and lbmhd_create refuses the
+// closure beyond.
 __device__ __forceinline__ float cubic_root_sq(float p, float sp, float q) {
   float d = q > 0.0f ? fminf(q * (0.5f * frcp(p)), cbrtf(q)) : 0.0f;
 #pragma unroll
@@ -1665,11 +1670,17 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
   return hipGetLastError();
 }
 
+int diag_partials(const Geom& g) {
+  const int tiles_x = (g.nx + kDiagThreads - 1) / kDiagThreads;
+  const long long units = (long long)tiles_x * ((g.ny + kDiagRows - 1) / kDiagRows);
+  return int(std::min<long long>(kDiagBlocks, units));
+}
+
 hipError_t launch_diag(int storage, const void* lat, double* part, double* out_dev,
                        const Geom& g, hipStream_t s) {
   const int tiles_x = (g.nx + kDiagThreads - 1) / kDiagThreads;
   const long long units = (long long)tiles_x * ((g.ny + kDiagRows - 1) / kDiagRows);
-  const int nparts = int(std::min<long long>(kDiagBlocks, units));
+  const int nparts = diag_partials(g);
   if (storage == LBMHD_FP32)
     hipLaunchKernelGGL(k_diag<LBMHD_FP32>, dim3(nparts), dim3(kDiagThreads), 0, s,
                        static_cast<const float*>(lat), part, g, tiles_x, int(units));

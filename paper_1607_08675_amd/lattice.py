@@ -233,7 +233,9 @@ class Lattice:
 
     @property
     def steps_per_pass(self) -> int:
-        """Steps one kernel pass covers in step() for pairs of steps (1 or 2)."""
+        """Steps one kernel pass covers in step(): 3 (FP32 triples), 2 or 1.
+        With 3, a remainder of two steps is one pair, and a remainder of one
+        step takes the last triple along as two pairs."""
         v = ctypes.c_int32()
         self._check(self._L.lbmhd_steps_per_pass(self._h, ctypes.byref(v)),
                     "lbmhd_steps_per_pass")

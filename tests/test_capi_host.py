@@ -69,6 +69,19 @@ def test_create_rejects_invalid_parameters(capi, bad):
     assert not h.value
 
 
+@pytest.mark.parametrize("les", [4, 6])
+def test_create_refuses_crosshelicity_beyond_eta_one_quarter(capi, les):
+    """The clip of the cross-helicity closure's magnetic relaxation time
+    nears a double root of its cubic as tau_m0 = 3 eta + 1/2 nears 3/2; the
+    library refuses the closure beyond tau_m0 = 5/4 and accepts it up to
+    there (any nu)."""
+    rc, h = _create(capi, _params(capi, les=les, eta=0.2501))
+    assert rc == capi.LBMHD_ERR_UNSUPPORTED and not h.value
+    rc, h = _create(capi, _params(capi, les=les, eta=0.25, nu=2.0))
+    assert rc == 0
+    assert capi.lib().lbmhd_destroy(h) == 0
+
+
 def test_sizes_and_layout(capi):
     L = capi.lib()
     for storage, esize in ((capi.LBMHD_FP32, 4), (capi.LBMHD_FP16, 2)):

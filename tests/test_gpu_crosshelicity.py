@@ -61,6 +61,34 @@ def test_one_step_fp32(lb, orc, nx, ny, les):
     assert err < 5e-7, err
 
 
+@pytest.mark.parametrize("nu,eta", [(0.3, 0.25), (1.0, 0.25), (1.0, 0.05), (0.02, 0.25)])
+def test_one_step_at_large_transport_coefficients(lb, orc, nu, eta):
+    """The Newton solution of the two cubics against the oracle's closed-form
+    roots where the relaxation times are far from 1/2: tau0 = 3 nu + 1/2 up to
+    3.5, tau_m0 = 3 eta + 1/2 up to 5/4, the largest the library accepts for
+    this closure (beyond it the clip nears a double root of the magnetic
+    cubic).  A closure constant of 2 and a large filter width make
+    the eddy terms comparable to the molecular ones and push sites into
+    backscatter."""
+    nx, ny = 100, 36
+    L, op = make(lb, orc, nx, ny, nu=nu, eta=eta, delta=3.0, cs=2.0)
+    x0 = random_state(nx, ny, seed=17, famp=0.05, gamp=0.03)
+    pre = orc.stream(op, x0)
+    want, tau, taum = orc.collide(op, pre, return_tau=True)
+    assert np.abs(tau - (3 * nu + 0.5)).max() > 0.05 * (3 * nu + 0.5)   # the closure acts
+    assert np.any(taum < 3 * eta + 0.5)                                  # backscatter occurs
+    L.set_populations(x0).step(1)
+    err = np.abs(L.populations().cpu().numpy() - want).max()
+    assert err < 5e-7, err
+
+
+def test_refused_where_the_clip_nears_the_double_root(lb):
+    from paper_1607_08675_amd._capi import LbmhdError
+    with pytest.raises(LbmhdError):
+        lb.Lattice(lb.LBMHDConfig(nx=16, ny=16, nu=0.01, eta=0.2501, les=4, cs=0.1))
+    lb.Lattice(lb.LBMHDConfig(nx=16, ny=16, nu=1.0, eta=0.25, les=4, cs=0.1))
+
+
 def test_closure_matters_and_backscatter_occurs(lb, orc):
     """On the parity states the closure moves the populations well beyond
     the tolerance, and a good share of the sites backscatters (tau_m < tau_m0),

@@ -152,3 +152,24 @@ def test_bound_lattice_passed_as_explicit_state(lb, storage):
     one.adj_seed_energy(one._a, lam1)
     two.adj_seed_energy(two.save_state(), lam2)
     assert torch.equal(one.adj_view(lam1), two.adj_view(lam2))
+
+
+def test_load_state_of_the_reversed_lattice_itself(lb):
+    """load_state(current_state()) on an in-place lattice left reversed by an
+    odd step count turns the layout back before taking it as the state, and a
+    buffer that partly overlaps the bound lattice is refused."""
+    import ctypes
+    n = 64
+    two, one = pair(lb, nx=n, ny=n, nu=0.002, eta=0.002, les=1, cs=0.2)
+    f = perturbed_orszag_tang(n, n, u0=0.1, b0=0.1)
+    one.init_fields(*f).step(7)
+    one.load_state(one.current_state(), 7)
+    two.init_fields(*f).step(7)
+    assert_same(one.populations(), two.populations(), "after load")
+    one.step(4)
+    two.step(4)
+    assert_same(one.populations(), two.populations(), "four steps on")
+    # through the C ABI: a source 256 bytes into the bound lattice
+    p = ctypes.c_void_p(one.current_state().data_ptr() + 256)
+    assert one._L.lbmhd_load_state(one._h, p, ctypes.c_int64(11)) == -1   # LBMHD_ERR_INVALID_ARG
+    assert one.step_count == 11

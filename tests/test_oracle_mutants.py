@@ -11,6 +11,7 @@ unmodified source must pass.  Everything runs on the CPU.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -107,10 +108,10 @@ MUTANTS3 = {
 
 
 def _run_pins(lib_path, pins=PINS, var="LBMHD_ORACLE_LIB"):
-    env = dict(os.environ, OMP_NUM_THREADS="4")
+    env = dict(os.environ, OMP_NUM_THREADS="2")
     env[var] = lib_path
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                           *pins], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+                           *pins], cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
 
 
 def _build(tmp_path, text, name):
@@ -120,33 +121,51 @@ def _build(tmp_path, text, name):
     return oracle.compile_source(str(src), str(tmp_path / f"lib{name}.so"))
 
 
-def test_unmodified_oracle_passes_pins(tmp_path):
-    lib = _build(tmp_path, open(SRC).read(), "orig")
-    r = _run_pins(lib)
-    assert r.returncode == 0, r.stdout[-2000:]
+def _case(d, key):
+    """Build one oracle variant in directory d and run its pin suite:
+    (return code, output tail)."""
+    kind, name = key
+    src, pins, var = (SRC3, PINS3, "LBMHD3_ORACLE_LIB") if kind.endswith("3") else \
+        (SRC, PINS, "LBMHD_ORACLE_LIB")
+    text = open(src).read()
+    if kind.startswith("mut"):
+        old, new = (MUTANTS3 if kind.endswith("3") else MUTANTS)[name]
+        assert text.count(old) >= 1, f"mutation site not found: {old}"
+        text = text.replace(old, new, 1)
+    d.mkdir()
+    r = _run_pins(_build(d, text, "v"), pins, var)
+    return r.returncode, r.stdout[-2000:]
+
+
+@pytest.fixture(scope="module")
+def outcomes(tmp_path_factory):
+    """Every variant built and checked once, four at a time (each pin run uses
+    two threads): the unmodified sources and every mutant."""
+    keys = [("orig", ""), ("orig3", "")] + [("mut", k) for k in sorted(MUTANTS)] + \
+        [("mut3", k) for k in sorted(MUTANTS3)]
+    tmp = tmp_path_factory.mktemp("mutants")
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        futs = {k: ex.submit(_case, tmp / f"v{i}", k) for i, k in enumerate(keys)}
+        return {k: f.result() for k, f in futs.items()}
+
+
+def test_unmodified_oracle_passes_pins(outcomes):
+    rc, out = outcomes[("orig", "")]
+    assert rc == 0, out
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_mutant_is_caught(tmp_path, name):
-    old, new = MUTANTS[name]
-    text = open(SRC).read()
-    assert text.count(old) >= 1, f"mutation site not found: {old}"
-    lib = _build(tmp_path, text.replace(old, new, 1), "mut")
-    r = _run_pins(lib)
-    assert r.returncode != 0, f"mutant '{name}' passed every pin"
+def test_mutant_is_caught(outcomes, name):
+    rc, _ = outcomes[("mut", name)]
+    assert rc != 0, f"mutant '{name}' passed every pin"
 
 
-def test_unmodified_3d_oracle_passes_pins(tmp_path):
-    lib = _build(tmp_path, open(SRC3).read(), "orig3")
-    r = _run_pins(lib, PINS3, "LBMHD3_ORACLE_LIB")
-    assert r.returncode == 0, r.stdout[-2000:]
+def test_unmodified_3d_oracle_passes_pins(outcomes):
+    rc, out = outcomes[("orig3", "")]
+    assert rc == 0, out
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS3))
-def test_3d_mutant_is_caught(tmp_path, name):
-    old, new = MUTANTS3[name]
-    text = open(SRC3).read()
-    assert text.count(old) >= 1, f"mutation site not found: {old}"
-    lib = _build(tmp_path, text.replace(old, new, 1), "mut3")
-    r = _run_pins(lib, PINS3, "LBMHD3_ORACLE_LIB")
-    assert r.returncode != 0, f"mutant '{name}' passed every pin"
+def test_3d_mutant_is_caught(outcomes, name):
+    rc, _ = outcomes[("mut3", name)]
+    assert rc != 0, f"mutant '{name}' passed every pin"
