@@ -361,6 +361,20 @@ int lbmhd_adj_fields(lbmhd_t* h, const float* lam0, const double* rho0, const do
                      const double* uy0, const double* bx0, const double* by0, double* g_ux,
                      double* g_uy, double* g_bx, double* g_by);
 
+/* lbmhd_diag without the bound workspace, for callers that cannot allocate
+ * device memory at the point of the call (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same kernels, same
+ * results, same return codes and synchronisation as lbmhd_diag; the
+ * reductions' block partials and result slots live instead in a static
+ * device array of the library, 524,416 bytes on each GPU it runs on, held
+ * until the process ends (at most 4096 partials of 16 doubles plus 16
+ * result doubles, which every lattice size fits: the reducing blocks stride
+ * over the lattice).  Its device address is looked up once per GPU, for the
+ * device of the bound stream.  Calls on one GPU share that array: calls
+ * that overlap in time on one GPU (on different streams or threads) race
+ * and must be ordered by the caller.  Allocates nothing. */
+int lbmhd_diag_noalloc(lbmhd_t* h, lbmhd_diag_t* out);
+
 #ifdef __cplusplus
 }
 #endif

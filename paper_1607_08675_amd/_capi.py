@@ -34,7 +34,7 @@ EXPORTS = (
     "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state", "lbmhd_get_step",
     "lbmhd_current_state",
     "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_seed_mismatch", "lbmhd_adj_step",
-    "lbmhd_adj_sweep", "lbmhd_adj_acc_total", "lbmhd_adj_fields",
+    "lbmhd_adj_sweep", "lbmhd_adj_acc_total", "lbmhd_adj_fields", "lbmhd_diag_noalloc",
 )
 # Every function declared in include/lbmhd3.h.
 EXPORTS3 = (
@@ -125,6 +125,7 @@ def lib():
             "lbmhd_mismatch": [vp] * 6 + [P(ctypes.c_double)],
             "lbmhd_adj_seed_mismatch": [vp] * 6 + [ctypes.c_double, vp],
             "lbmhd_diag": [vp, P(Diag)],
+            "lbmhd_diag_noalloc": [vp, P(Diag)],
             "lbmhd_get_populations": [vp, vp],
             "lbmhd_set_populations": [vp, vp, i64],
             "lbmhd_save_state": [vp, vp],

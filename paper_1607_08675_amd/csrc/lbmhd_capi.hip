@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -181,6 +182,48 @@ int fill_diag(lbmhd_t* h, const double v[lbk::kDiagSlots], lbmhd_diag_t* out) {
   if (out->nonfinite > 0)
     return fail(h, LBMHD_ERR_NONFINITE,
                 std::to_string(out->nonfinite) + " sites hold non-finite populations");
+  return LBMHD_OK;
+}
+
+// ------------------------------------------------ static diagnostics scratch
+// lbmhd_diag_noalloc keeps the reductions' block partials (at most
+// kDiagBlocks x kDiagSlots doubles) and the result slots (kDiagSlots doubles)
+// here instead of in the bound workspace.  Each GPU holds its own copy; host
+// code never uses the array's name as an address, only the per-device
+// address from hipGetSymbolAddress.
+constexpr size_t kScratchParts = size_t(lbk::kDiagBlocks);
+constexpr size_t kScratchDoubles = kScratchParts * lbk::kDiagSlots + lbk::kDiagSlots;
+static_assert(kScratchDoubles * sizeof(double) == 524416, "documented scratch size");
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the GPU of the handle's stream, looked up
+// (with that GPU current) on the first call for that GPU.
+int scratch_address(lbmhd_t* h, double** out) {
+  int dev = -1;
+  // the null stream belongs to the current device
+  hipError_t e = h->stream ? hipStreamGetDevice(h->stream, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(h, e, "stream device query");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(h, LBMHD_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    int cur = -1;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(h, e, "current device query");
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess)
+      return hip_fail(h, e, "device switch");
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    hipError_t e2 = cur != dev ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(h, e, "scratch address lookup");
+    if (e2 != hipSuccess) return hip_fail(h, e2, "device switch back");
+    g_scratch_addr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_addr[dev];
   return LBMHD_OK;
 }
 
@@ -499,6 +542,20 @@ int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out) {
   const void* st = nullptr;
   if (int rc = current(h, &st)) return rc;
   if (int rc = run_diag(h, st, v)) return rc;
+  return fill_diag(h, v, out);
+}
+
+int lbmhd_diag_noalloc(lbmhd_t* h, lbmhd_diag_t* out) {
+  if (int rc = need_bound(h)) return rc;
+  if (!out) return fail(h, LBMHD_ERR_INVALID_ARG, "null output");
+  if (size_t(lbk::diag_partials(h->geo)) > kScratchParts)
+    return fail(h, LBMHD_ERR_UNSUPPORTED, "more reduction partials than the static scratch holds");
+  double* s = nullptr;
+  if (int rc = scratch_address(h, &s)) return rc;
+  double v[lbk::kDiagSlots];
+  const void* st = nullptr;
+  if (int rc = current(h, &st)) return rc;
+  if (int rc = run_diag(h, st, v, s, s + kScratchParts * lbk::kDiagSlots)) return rc;
   return fill_diag(h, v, out);
 }
 

@@ -184,6 +184,15 @@ class Lattice:
             self._check(rc, "lbmhd_diag")
         return d.as_dict()
 
+    def diag_noalloc(self, raise_nonfinite: bool = False) -> dict:
+        """diag() through lbmhd_diag_noalloc: the reductions' scratch is the
+        library's static device array, not the bound workspace."""
+        d = C.Diag()
+        rc = self._L.lbmhd_diag_noalloc(self._h, ctypes.byref(d))
+        if rc != C.LBMHD_ERR_NONFINITE or raise_nonfinite:
+            self._check(rc, "lbmhd_diag_noalloc")
+        return d.as_dict()
+
     def populations(self) -> torch.Tensor:
         out = torch.empty(19, self.cfg.ny, self.cfg.nx, dtype=torch.float64, device=self.device)
         self._check(self._L.lbmhd_get_populations(self._h, _ptr(out)), "lbmhd_get_populations")
