@@ -69,7 +69,9 @@ def test_one_step_at_large_transport_coefficients(lb, orc, nu, eta):
     this closure (beyond it the clip nears a double root of the magnetic
     cubic).  A closure constant of 2 and a large filter width make
     the eddy terms comparable to the molecular ones and push sites into
-    backscatter."""
+    backscatter.  The states are drawn 2.5 times as far from the rest state
+    as in the other one-step tests, and the FP32 rounding of the result
+    scales with them: 2.5 x 5e-7."""
     nx, ny = 100, 36
     L, op = make(lb, orc, nx, ny, nu=nu, eta=eta, delta=3.0, cs=2.0)
     x0 = random_state(nx, ny, seed=17, famp=0.05, gamp=0.03)
@@ -79,7 +81,7 @@ def test_one_step_at_large_transport_coefficients(lb, orc, nu, eta):
     assert np.any(taum < 3 * eta + 0.5)                                  # backscatter occurs
     L.set_populations(x0).step(1)
     err = np.abs(L.populations().cpu().numpy() - want).max()
-    assert err < 5e-7, err
+    assert err < 1.25e-6, err
 
 
 def test_refused_where_the_clip_nears_the_double_root(lb):
