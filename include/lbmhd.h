@@ -135,12 +135,11 @@ typedef struct {
                              last triple along as two pairs), so a single
                              step runs only when one is left.  Other values
                              are rejected.  The
-                             result is bit for bit that of single steps, with
-                             one measured exception: FP16 storage with even
-                             nx, where a few stored halves in ten million,
-                             next to the 512-column tile edges, differ in
-                             their last bits (the tile's halo sites run a
-                             separately compiled collision). */
+                             result is bit for bit that of single steps, in
+                             FP32 and FP16 storage (every kernel rounds the
+                             collision identically: its fused multiply-adds
+                             are spelled out and no other contraction is
+                             allowed). */
 } lbmhd_params;
 
 /* Global diagnostics of the current state, accumulated in FP64.
@@ -209,8 +208,7 @@ int lbmhd_init_fields(lbmhd_t* h, const double* rho, const double* ux, const dou
  * moment-space collision of Sec. 3; closures as selected by les), ping-ponging
  * the two bound lattices (or updating the one lattice in place).  Each kernel
  * launch fuses streaming and collision of one, two or three steps as
- * steps_per_pass selects (the same result; see steps_per_pass for the one
- * FP16 exception).  Asynchronous. */
+ * steps_per_pass selects (the same result, bit for bit).  Asynchronous. */
 int lbmhd_step(lbmhd_t* h, int64_t nsteps);
 
 /* Steps that one pass over the lattice covers when lbmhd_step advances a

@@ -295,6 +295,12 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   r.taum0sq = float(taum0 * taum0);
   r.cf = float(18.0 * p->cs * d2);
   r.cm = float(36.0 * p->cs_b * d2);
+  r.tau0d = 2.0f * r.tau0;
+  r.tau0dsq = 4.0f * r.tau0sq;
+  r.cf4 = 4.0f * r.cf;
+  r.taum0h = 0.5f * r.taum0;
+  r.taum0hsq = 0.25f * r.taum0sq;
+  r.cmq = 0.25f * r.cm;
   r.stau0 = float(std::sqrt(tau0));
   r.staum0 = float(std::sqrt(taum0));
   r.kv = float(4.5 * p->cs * d2);

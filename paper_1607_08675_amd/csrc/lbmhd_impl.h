@@ -31,6 +31,15 @@ struct Rates {
   float taum0sq;  // tau_m0^2
   float cf;       // 18 C_S Delta^2
   float cm;       // 36 C_S Delta^2
+  // the same constants scaled by powers of two (exact), as the forward
+  // collision uses them: 1 / (4 tau) = 1 / (tau0d + sqrt(tau0dsq + cf4 Q / rho)),
+  // 1 / tau_m = 1 / (taum0h + sqrt(taum0hsq + cmq |A|))
+  float tau0d;    // 2 tau0
+  float tau0dsq;  // 4 tau0^2
+  float cf4;      // 4 cf
+  float taum0h;   // tau_m0 / 2
+  float taum0hsq; // tau_m0^2 / 4
+  float cmq;      // cm / 4
   // cross-helicity closure: sqrt(tau) and sqrt(tau_m) are the largest roots
   // of t^3 - p t - q = 0 (p = tau0, tau_m0)
   float stau0;    // sqrt(tau0)

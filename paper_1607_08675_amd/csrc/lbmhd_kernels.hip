@@ -149,48 +149,58 @@ struct NbTerms {
 // up to p = 5/4 (measured: 8.8e-4 at p = 1.4), and lbmhd_create refuses the
 // closure beyond.
 __device__ __forceinline__ float cubic_root_sq(float p, float sp, float q) {
+#pragma clang fp contract(off)
   float d = q > 0.0f ? fminf(q * (0.5f * frcp(p)), cbrtf(q)) : 0.0f;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float h = d * (2.0f * p + d * (3.0f * sp + d)) - q;
-    const float hp = 2.0f * p + d * (6.0f * sp + 3.0f * d);
-    d -= h * frcp(hp);
+    const float h = fmaf(d, fmaf(d, 3.0f * sp + d, 2.0f * p), -q);
+    const float hp = fmaf(d, fmaf(3.0f, d, 6.0f * sp), 2.0f * p);
+    d = fmaf(-h, frcp(hp), d);
   }
-  return p + d * (2.0f * sp + d);
+  return fmaf(d, 2.0f * sp + d, p);
 }
 
+// Every multiply-add of the collision is written out: fmaf where one
+// rounding is wanted, a separate product where two.  The compiler may not
+// contract anything else (fp contract off), so each kernel that inlines the
+// collision -- one or two sites per thread, halo columns, several steps per
+// pass, in place -- rounds it identically and their results agree bit for bit.
 template <int EDDY, bool KIN = false>
 __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rates& r,
                                         const NbTerms& kc = NbTerms{0.f, 0.f, 0.f, 0.f, 0.f}) {
+#pragma clang fp contract(off)
   const float a13 = f[1] + f[3], a24 = f[2] + f[4];
   const float d13 = f[1] - f[3], d24 = f[2] - f[4];
   const float s57 = f[5] + f[7], s68 = f[6] + f[8];
   const float d57 = f[5] - f[7], d68 = f[6] - f[8];
   const float dd = s57 + s68;
-  const float drho = f[0] + a13 + a24 + dd;
+  const float sa = a13 + a24;
+  const float f0dd = f[0] + dd;
+  const float drho = f0dd + sa;
   const float rho = 1.0f + drho;
-  const float jx = d13 + d57 - d68;
-  const float jy = d24 + d57 + d68;
+  const float jx = (d13 + d57) - d68;
+  const float jy = (d24 + d57) + d68;
   const float M3 = s57 - s68;
   const float M4 = a13 - a24;
-  const float M5 = jx - 3.0f * d13;
-  const float M6 = jy - 3.0f * d24;
-  const float M7 = 4.0f * f[0] - 5.0f * (a13 + a24) + 4.0f * dd;
-  const float M8 = 4.0f * f[0] - dd;
+  const float M5 = fmaf(-3.0f, d13, jx);
+  const float M6 = fmaf(-3.0f, d24, jy);
+  const float M7 = fmaf(-5.0f, sa, 4.0f * f0dd);   // 4 f0 - 5 (a13 + a24) + 4 dd
+  const float M8 = fmaf(4.0f, f[0], -dd);
 
   const float ir = frcp(rho);
   const float ux = jx * ir, uy = jy * ir;
-  const float Bx = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
-  const float By = (g[5] + g[6]) + (g[7] + g[8]) + g[9];
-  const float jxux = jx * ux, jyuy = jy * uy;
-  const float jj = jxux + jyuy;
-  float n3 = M3 - (jx * uy - Bx * By);
-  float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
+  const float Bx = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+  const float By = ((g[5] + g[6]) + (g[7] + g[8])) + g[9];
+  const float jyuy = jy * uy;
+  const float jj = fmaf(jx, ux, jyuy);                       // |j|^2 / rho
+  const float Byy = By * By;
+  float n3 = M3 - fmaf(-Bx, By, jx * uy);                    // M3 - (jx uy - Bx By)
+  float n4 = M4 - (fmaf(jx, ux, -jyuy) - fmaf(Bx, Bx, -Byy));
   const float n5 = M5 + jx;
   const float n6 = M6 + jy;
-  float n7 = M7 + 3.0f * jj;
-  float n8 = M8 - (5.0f / 3.0f) * drho + 3.0f * jj;
-  float E = ux * By - uy * Bx;
+  float n7 = fmaf(3.0f, jj, M7);
+  float n8 = fmaf(3.0f, jj, fmaf(-5.0f / 3.0f, drho, M8));
+  float E = fmaf(ux, By, -(uy * Bx));
   if (KIN) {
     // relax toward the filtered equilibria; with the Smagorinsky closure as
     // well, Q and A below are then measured from the filtered equilibria
@@ -203,16 +213,17 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
 
   float s3q, sm;
   if (EDDY == 1) {
-    const float Q = fsqrt(n4 * n4 + 4.0f * (n3 * n3));
-    const float tau = 0.5f * (r.tau0 + fsqrt(r.tau0sq + r.cf * Q * ir));
-    s3q = 0.25f * frcp(tau);
-    const float A = (g[6] - g[8]) - (g[2] - g[4]) - 2.0f * E;
-    const float taum = 0.5f * (r.taum0 + fsqrt(r.taum0sq + r.cm * fabsf(A)));
-    sm = frcp(taum);
+    // s3q = 1 / (4 tau) = 1 / (2 tau0 + sqrt(4 tau0^2 + 4 cf Q / rho)) with
+    // the powers of two folded into the constants (exact)
+    const float Q = fsqrt(fmaf(n4, n4, 4.0f * (n3 * n3)));
+    s3q = frcp(r.tau0d + fsqrt(fmaf(r.cf4 * Q, ir, r.tau0dsq)));
+    const float A = fmaf(-2.0f, E, (g[6] - g[8]) - (g[2] - g[4]));
+    // sm = 1 / tau_m = 1 / (tau_m0 / 2 + sqrt(tau_m0^2 / 4 + cm |A| / 4))
+    sm = frcp(r.taum0h + fsqrt(fmaf(r.cmq, fabsf(A), r.taum0hsq)));
   } else if (EDDY == 2) {
     const float lxy = g[6] - g[8], lyx = g[2] - g[4];
-    const float P = n4 * ((g[1] - g[3]) - (g[7] - g[9])) + 2.0f * (n3 * (lxy + lyx));
-    const float X = ((lxy - lyx) - 2.0f * E) * kc.w;
+    const float P = fmaf(n4, (g[1] - g[3]) - (g[7] - g[9]), 2.0f * (n3 * (lxy + lyx)));
+    const float X = fmaf(-2.0f, E, lxy - lyx) * kc.w;
     const float qb = -r.kb * copysignf(fsqrt(fabsf(X)), X);
     const float taum = qb < r.qclip ? 0.5f : fmaxf(0.5f, cubic_root_sq(r.taum0, r.staum0, qb));
     const float qv = r.kv * fsqrt(fabsf(P) * ir * frcp(taum));
@@ -225,32 +236,33 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
   const float r3 = s3q * n3, r4 = s3q * n4;
   const float r5 = r.s5q * n5, r6 = r.s5q * n6;
   const float r7 = r.s7q * n7, r8 = r.s8q * n8;
-  const float c58 = 4.0f * r7 - r8;
-  const float c14 = 5.0f * r7;
-  f[0] -= 4.0f * (r7 + r8);
-  f[1] -= r4 - 2.0f * r5 - c14;
-  f[2] -= -r4 - 2.0f * r6 - c14;
-  f[3] -= r4 + 2.0f * r5 - c14;
-  f[4] -= -r4 + 2.0f * r6 - c14;
-  f[5] -= r3 + r5 + r6 + c58;
-  f[6] -= -r3 - r5 + r6 + c58;
-  f[7] -= r3 - r5 - r6 + c58;
-  f[8] -= -r3 + r5 - r6 + c58;
+  const float c58 = fmaf(4.0f, r7, -r8);
+  f[0] = fmaf(-4.0f, r7 + r8, f[0]);
+  f[1] -= fmaf(-5.0f, r7, fmaf(-2.0f, r5, r4));
+  f[2] -= fmaf(-5.0f, r7, fmaf(-2.0f, r6, -r4));
+  f[3] -= fmaf(-5.0f, r7, fmaf(2.0f, r5, r4));
+  f[4] -= fmaf(-5.0f, r7, fmaf(2.0f, r6, -r4));
+  const float p56 = r5 + r6, m56 = r5 - r6;
+  f[5] -= (r3 + p56) + c58;
+  f[6] -= c58 - (r3 + m56);
+  f[7] -= (r3 - p56) + c58;
+  f[8] -= (m56 - r3) + c58;
 
   // g^eq of the four moving directions is B/6 +- E/2; the rest direction takes
   // the remainder B - 4 (B/6) so that sum_k g^eq = B holds in FP32 as well
   // (6 * fl(1/6) != 1 would otherwise feed a systematic drift into B).
-  const float bx6 = Bx * (1.0f / 6.0f), by6 = By * (1.0f / 6.0f), he = 0.5f * E;
-  g[0] -= sm * (g[0] - (Bx - 4.0f * bx6));
-  g[1] -= sm * (g[1] - bx6);
-  g[2] -= sm * (g[2] - (bx6 - he));
-  g[3] -= sm * (g[3] - bx6);
-  g[4] -= sm * (g[4] - (bx6 + he));
-  g[5] -= sm * (g[5] - (By - 4.0f * by6));
-  g[6] -= sm * (g[6] - (by6 + he));
-  g[7] -= sm * (g[7] - by6);
-  g[8] -= sm * (g[8] - (by6 - he));
-  g[9] -= sm * (g[9] - by6);
+  const float bx6 = Bx * (1.0f / 6.0f), by6 = By * (1.0f / 6.0f);
+  const float msm = -sm;
+  g[0] = fmaf(msm, g[0] - fmaf(-4.0f, bx6, Bx), g[0]);
+  g[1] = fmaf(msm, g[1] - bx6, g[1]);
+  g[2] = fmaf(msm, g[2] - fmaf(-0.5f, E, bx6), g[2]);
+  g[3] = fmaf(msm, g[3] - bx6, g[3]);
+  g[4] = fmaf(msm, g[4] - fmaf(0.5f, E, bx6), g[4]);
+  g[5] = fmaf(msm, g[5] - fmaf(-4.0f, by6, By), g[5]);
+  g[6] = fmaf(msm, g[6] - fmaf(0.5f, E, by6), g[6]);
+  g[7] = fmaf(msm, g[7] - by6, g[7]);
+  g[8] = fmaf(msm, g[8] - fmaf(-0.5f, E, by6), g[8]);
+  g[9] = fmaf(msm, g[9] - by6, g[9]);
 }
 
 // --------------------------------------------------------------- the step

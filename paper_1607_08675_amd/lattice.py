@@ -35,8 +35,7 @@ class LBMHDConfig:
     the closures that read neighbours (les = 2, 3, 4, 6).
     steps_per_pass: with two lattices and les = 0 or 1, step() can advance
     several steps per pass over the lattice with the intermediate states kept
-    on chip, equal to single steps bit for bit (FP16 with even nx: but for a
-    few halves in ten million at tile edges, in their last bits).  0 (default):
+    on chip, equal to single steps bit for bit in both storages.  0 (default):
     three per pass with FP32 storage and two with FP16 where the lattice is
     large enough for it to pay; 3: three with FP32, two with FP16; 2: two;
     1: one.
