@@ -58,6 +58,27 @@ struct Codec<LBMHD_FP16> {
   }
 };
 
+// FP16 storage as the plain and Smagorinsky-MHD kernels hold it: the
+// collision runs on the stored values themselves, i.e. on deviations in units
+// of 2^-10 (collide<..., SC = true> folds the scale into its constants), so
+// decoding and encoding are bare conversions.  Every operand is then 2^10
+// (products of two: 2^20) times its unscaled counterpart, exactly, and the
+// stored halves are the same as with the scale applied around the collision.
+constexpr int kFP16S = 2;
+template <>
+struct Codec<kFP16S> {
+  using T = _Float16;
+  __device__ static __forceinline__ float dec(_Float16 v) {
+    float f = float(v);
+    asm("" : "+v"(f));
+    return f;
+  }
+  __device__ static __forceinline__ _Float16 enc(float v) {
+    asm("" : "+v"(v));
+    return _Float16(v);
+  }
+};
+
 // V consecutive stored elements moved as one vector access.
 template <typename T, int V>
 struct Vec;
@@ -165,10 +186,16 @@ __device__ __forceinline__ float cubic_root_sq(float p, float sp, float q) {
 // contract anything else (fp contract off), so each kernel that inlines the
 // collision -- one or two sites per thread, halo columns, several steps per
 // pass, in place -- rounds it identically and their results agree bit for bit.
-template <int EDDY, bool KIN = false>
+// With SC the populations are in units of 2^-10 (scaled FP16 storage): each
+// product of two scaled quantities carries an extra 2^10, taken out by the
+// factor kS = 2^-10 folded into the constant of the operation that consumes it
+// (exact), so the result is 2^10 times the unscaled one bit for bit.
+template <int EDDY, bool KIN = false, bool SC = false>
 __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rates& r,
                                         const NbTerms& kc = NbTerms{0.f, 0.f, 0.f, 0.f, 0.f}) {
 #pragma clang fp contract(off)
+  static_assert(!SC || (!KIN && EDDY < 2), "scaled populations: plain and Smagorinsky only");
+  constexpr float kS = SC ? 0x1p-10f : 1.0f;
   const float a13 = f[1] + f[3], a24 = f[2] + f[4];
   const float d13 = f[1] - f[3], d24 = f[2] - f[4];
   const float s57 = f[5] + f[7], s68 = f[6] + f[8];
@@ -177,7 +204,7 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
   const float sa = a13 + a24;
   const float f0dd = f[0] + dd;
   const float drho = f0dd + sa;
-  const float rho = 1.0f + drho;
+  const float rho = SC ? fmaf(kS, drho, 1.0f) : 1.0f + drho;
   const float jx = (d13 + d57) - d68;
   const float jy = (d24 + d57) + d68;
   const float M3 = s57 - s68;
@@ -194,13 +221,13 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
   const float jyuy = jy * uy;
   const float jj = fmaf(jx, ux, jyuy);                       // |j|^2 / rho
   const float Byy = By * By;
-  float n3 = M3 - fmaf(-Bx, By, jx * uy);                    // M3 - (jx uy - Bx By)
-  float n4 = M4 - (fmaf(jx, ux, -jyuy) - fmaf(Bx, Bx, -Byy));
+  float n3 = fmaf(-kS, fmaf(-Bx, By, jx * uy), M3);          // M3 - (jx uy - Bx By)
+  float n4 = fmaf(-kS, fmaf(jx, ux, -jyuy) - fmaf(Bx, Bx, -Byy), M4);
   const float n5 = M5 + jx;
   const float n6 = M6 + jy;
-  float n7 = fmaf(3.0f, jj, M7);
-  float n8 = fmaf(3.0f, jj, fmaf(-5.0f / 3.0f, drho, M8));
-  float E = fmaf(ux, By, -(uy * Bx));
+  float n7 = fmaf(3.0f * kS, jj, M7);
+  float n8 = fmaf(3.0f * kS, jj, fmaf(-5.0f / 3.0f, drho, M8));
+  float E = fmaf(ux, By, -(uy * Bx));                          // scaled: 2^20 E
   if (KIN) {
     // relax toward the filtered equilibria; with the Smagorinsky closure as
     // well, Q and A below are then measured from the filtered equilibria
@@ -216,10 +243,10 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
     // s3q = 1 / (4 tau) = 1 / (2 tau0 + sqrt(4 tau0^2 + 4 cf Q / rho)) with
     // the powers of two folded into the constants (exact)
     const float Q = fsqrt(fmaf(n4, n4, 4.0f * (n3 * n3)));
-    s3q = frcp(r.tau0d + fsqrt(fmaf(r.cf4 * Q, ir, r.tau0dsq)));
-    const float A = fmaf(-2.0f, E, (g[6] - g[8]) - (g[2] - g[4]));
+    s3q = frcp(r.tau0d + fsqrt(fmaf((r.cf4 * kS) * Q, ir, r.tau0dsq)));
+    const float A = fmaf(-2.0f * kS, E, (g[6] - g[8]) - (g[2] - g[4]));
     // sm = 1 / tau_m = 1 / (tau_m0 / 2 + sqrt(tau_m0^2 / 4 + cm |A| / 4))
-    sm = frcp(r.taum0h + fsqrt(fmaf(r.cmq, fabsf(A), r.taum0hsq)));
+    sm = frcp(r.taum0h + fsqrt(fmaf(r.cmq * kS, fabsf(A), r.taum0hsq)));
   } else if (EDDY == 2) {
     const float lxy = g[6] - g[8], lyx = g[2] - g[4];
     const float P = fmaf(n4, (g[1] - g[3]) - (g[7] - g[9]), 2.0f * (n3 * (lxy + lyx)));
@@ -255,13 +282,13 @@ __device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rat
   const float msm = -sm;
   g[0] = fmaf(msm, g[0] - fmaf(-4.0f, bx6, Bx), g[0]);
   g[1] = fmaf(msm, g[1] - bx6, g[1]);
-  g[2] = fmaf(msm, g[2] - fmaf(-0.5f, E, bx6), g[2]);
+  g[2] = fmaf(msm, g[2] - fmaf(-0.5f * kS, E, bx6), g[2]);
   g[3] = fmaf(msm, g[3] - bx6, g[3]);
-  g[4] = fmaf(msm, g[4] - fmaf(0.5f, E, bx6), g[4]);
+  g[4] = fmaf(msm, g[4] - fmaf(0.5f * kS, E, bx6), g[4]);
   g[5] = fmaf(msm, g[5] - fmaf(-4.0f, by6, By), g[5]);
-  g[6] = fmaf(msm, g[6] - fmaf(0.5f, E, by6), g[6]);
+  g[6] = fmaf(msm, g[6] - fmaf(0.5f * kS, E, by6), g[6]);
   g[7] = fmaf(msm, g[7] - by6, g[7]);
-  g[8] = fmaf(msm, g[8] - fmaf(-0.5f, E, by6), g[8]);
+  g[8] = fmaf(msm, g[8] - fmaf(-0.5f * kS, E, by6), g[8]);
   g[9] = fmaf(msm, g[9] - by6, g[9]);
 }
 
@@ -306,7 +333,7 @@ __device__ __forceinline__ void gather_row(const typename Codec<ST>::T* __restri
 }
 
 // One collision of each of the V sites in v (planes in the storage order).
-template <int V, bool LES>
+template <int V, bool LES, bool SC = false>
 __device__ __forceinline__ void collide_sites(float (&v)[kNPop][V], const Rates& rt) {
 #pragma unroll
   for (int j = 0; j < V; ++j) {
@@ -315,7 +342,7 @@ __device__ __forceinline__ void collide_sites(float (&v)[kNPop][V], const Rates&
     for (int i = 0; i < 9; ++i) f[i] = v[i][j];
 #pragma unroll
     for (int k = 0; k < 10; ++k) g[k] = v[9 + k][j];
-    collide<LES ? 1 : 0>(f, g, rt);
+    collide<LES ? 1 : 0, false, SC>(f, g, rt);
 #pragma unroll
     for (int i = 0; i < 9; ++i) v[i][j] = f[i];
 #pragma unroll
@@ -362,7 +389,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
                            unsigned(ym) * geo.pitch};
   float v[kNPop][V];
   gather_row<ST, V>(src, geo.plane, x0, xl, xr, row, v);
-  collide_sites<V, LES>(v, rt);
+  collide_sites<V, LES, ST == kFP16S>(v, rt);
   store_row<ST, V>(dst, geo.plane, row[1] + unsigned(x0), v);
 }
 
@@ -472,7 +499,7 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
     if (active) {
       float v[kNPop][V];
       gather_row<ST, V>(src, P, x, xl, xr, row, v);
-      collide_sites<V, LES>(v, rt);
+      collide_sites<V, LES, ST == kFP16S>(v, rt);
       if (MID && t >= 1 && t <= h) store_row<ST, V>(mid, P, row[1] + unsigned(x), v);
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
@@ -498,7 +525,7 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
     if (halo) {
       float v[kNPop][1];
       gather_row<ST, 1>(src, P, hx, hxl, hxr, row, v);
-      collide_sites<1, LES>(v, rt);
+      collide_sites<1, LES, ST == kFP16S>(v, rt);
 #pragma unroll
       for (int q = 0; q < kNPop; ++q) {
         const T e = C::enc(v[q][0]);
@@ -537,7 +564,7 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
             v[q][j] = nd[k][j];
         }
       }
-      collide_sites<V, LES>(v, rt);
+      collide_sites<V, LES, ST == kFP16S>(v, rt);
       store_row<ST, V>(dst, P, unsigned(y0 + t - 2) * geo.pitch + unsigned(x), v);
     }
 #pragma unroll
@@ -990,7 +1017,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_aa(typename Codec<ST>::T*
     for (int i = 0; i < 9; ++i) f[i] = v[i][j];
 #pragma unroll
     for (int k = 0; k < 10; ++k) g[k] = v[9 + k][j];
-    collide<LES ? 1 : 0>(f, g, rt);
+    collide<LES ? 1 : 0, false, ST == kFP16S>(f, g, rt);
 #pragma unroll
     for (int i = 0; i < 9; ++i) out[i][j] = f[i];
 #pragma unroll
@@ -1446,7 +1473,7 @@ void launch_step_v(bool les, const void* src, void* dst, const Geom& g, const Ra
 // with about 512 blocks (2048^2: 32 rows, 4096^2: 128), FP16 with about 4096
 // (8192^2: 32 rows, 4096^2 and 2048^2: 8); halo overhead 2 / rows.
 static int step2_rows(const Geom& g, int storage, int V) {
-  const bool fp16 = storage == LBMHD_FP16;
+  const bool fp16 = storage != LBMHD_FP32;   // LBMHD_FP16 or its scaled tag
   const long long tiles_x = (g.nx + kT2Threads * V - 1) / (kT2Threads * V);
   const long long rows = tiles_x * g.ny / (fp16 ? 4096 : 512);
   const long long hi = fp16 ? 32 : 128;
@@ -1518,9 +1545,9 @@ hipError_t launch_step(int storage, bool les, const void* src, void* dst, const 
   if (storage == LBMHD_FP32)
     launch_step_v<LBMHD_FP32, 1>(les, src, dst, g, r, s);
   else if (g.nx % 2 == 0)
-    launch_step_v<LBMHD_FP16, 2>(les, src, dst, g, r, s);
+    launch_step_v<kFP16S, 2>(les, src, dst, g, r, s);
   else
-    launch_step_v<LBMHD_FP16, 1>(les, src, dst, g, r, s);
+    launch_step_v<kFP16S, 1>(les, src, dst, g, r, s);
   return hipGetLastError();
 }
 
@@ -1572,9 +1599,9 @@ hipError_t launch_step2(int storage, bool les, const void* src, void* dst, void*
   if (storage == LBMHD_FP32)
     launch_step2_v<LBMHD_FP32, 1>(les, src, dst, mid, g, r, s);
   else if (g.nx % 2 == 0)
-    launch_step2_v<LBMHD_FP16, 2>(les, src, dst, mid, g, r, s);
+    launch_step2_v<kFP16S, 2>(les, src, dst, mid, g, r, s);
   else
-    launch_step2_v<LBMHD_FP16, 1>(les, src, dst, mid, g, r, s);
+    launch_step2_v<kFP16S, 1>(les, src, dst, mid, g, r, s);
   return hipGetLastError();
 }
 
@@ -1607,9 +1634,9 @@ hipError_t launch_step_aa(int storage, bool les, int phase, void* lat, const Geo
   if (storage == LBMHD_FP32)
     launch_step_aa_p<LBMHD_FP32, 1>(les, phase, lat, g, r, s);
   else if (g.nx % 2 == 0)
-    launch_step_aa_p<LBMHD_FP16, 2>(les, phase, lat, g, r, s);
+    launch_step_aa_p<kFP16S, 2>(les, phase, lat, g, r, s);
   else
-    launch_step_aa_p<LBMHD_FP16, 1>(les, phase, lat, g, r, s);
+    launch_step_aa_p<kFP16S, 1>(les, phase, lat, g, r, s);
   return hipGetLastError();
 }
 
