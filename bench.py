@@ -38,7 +38,10 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 FP32_BYTES_PER_SITE = 19 * 4 * 2
 FP16_BYTES_PER_SITE = 19 * 2 * 2
 ADJ_BYTES_PER_SITE = 19 * 4 * 2 + 3 * 19 * 4  # recompute step + (lam in, state gather, lam out)
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_step_fp32_4096.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_kernels.json")
+# VALU issue: 256 CUs x 4 SIMDs x 16 lanes, one lane-operation per lane and cycle, 2.4 GHz
+# (an FMA counted once; the 78.6 TFLOP/s FP32 figure counts it twice)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(msg: str):
@@ -55,17 +58,47 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP32 step from the committed counter
-    summary, or None if the kernel sources changed since it was taken."""
+def counters():
+    """The committed counter summary, or None if the kernel sources changed
+    since it was taken."""
     try:
         with open(COUNTERS_FILE) as fh:
             c = json.load(fh)
     except (OSError, ValueError):
         return None
-    if c.get("kernel_source_hash") != kernel_source_hash():
+    return c if c.get("kernel_source_hash") == kernel_source_hash() else None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counters."""
+    c = counters()
+    return c.get("headline_bytes_per_launch") if c else None
+
+
+def valu_frac(key, ms_per_launch):
+    """VALU issue time per launch at the chip's peak (from the committed SQ
+    counters of kernel `key`) over the launch time measured here."""
+    c = counters()
+    if not c or key not in c["kernels"]:
         return None
-    return c.get("bytes_per_launch")
+    return round(c["kernels"][key]["valu_time_at_peak_us"] * 1e-3 / ms_per_launch, 4)
+
+
+def valu_roofline(key, ms_per_launch):
+    """Roofline object of a kernel bound by its VALU issue rate: achieved lane
+    operations per second (counted instructions x 64 lanes, transcendentals
+    at four issue slots) against VALU_PEAK_TOPS."""
+    c = counters()
+    if not c or key not in c["kernels"]:
+        return None
+    k = c["kernels"][key]
+    ops = (k["valu_insts"] + 3 * k["trans_insts"]) * 64
+    achieved = ops / (ms_per_launch * 1e-3) / 1e12
+    return {"kernel": k["kernel"], "bound": "alu", "achieved": round(achieved, 2),
+            "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s (VALU lane operations)",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "hbm_frac": round(
+                k["algorithmic_bytes"] / (ms_per_launch * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "ms_per_launch": round(ms_per_launch, 5)}
 
 
 def timed_steps(torch, lat, steps, diag_every):
@@ -530,6 +563,10 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "valu_frac": valu_frac("step_t3_fp32_4096", r32["per_launch"]),
+            "binding": "neither HBM nor VALU saturated (VALU ceiling 0.86x the HBM ceiling): "
+                       "9.5 waves per CU, each pass a chain of loads, three collisions and two "
+                       "barriers",
             "bytes_per_site": FP32_BYTES_PER_SITE,
             "steps_per_launch": spp,
             "ms_per_launch": round(r32["per_launch"], 5),
@@ -625,6 +662,7 @@ def main():
                 "bytes_per_site": FP32_BYTES_PER_SITE, "steps_per_launch": f32["steps_per_pass"],
                 "nonfinite": f32["nonfinite"],
             },
+            "roofline": valu_roofline("step2_fp16_8192", f16["per_launch"]),
             "speedup_vs_fp32_same_workload": round(m16 / m32, 3),
             "speedup_vs_fp32_headline": round(m16 / value, 3),
             "rel_l2_vs_fp32": {"step": args.fp16_compare_steps,
