@@ -236,12 +236,14 @@ def closure_leg(torch, args, les):
     lat.init_fields(*orszag_tang(n, n))
     lat.step(args.warmup)
     torch.cuda.synchronize()
-    per_launch = burst_ms_per_step(torch, lat, 200)
+    spp = lat.steps_per_pass
+    per_step = burst_ms_per_step(torch, lat, 200)
     d = lat.diag()
-    log(f"{CLOSURES[les]} 4096^2 FP32: {per_launch:.4f} ms/launch, nonfinite={d['nonfinite']}")
+    log(f"{CLOSURES[les]} 4096^2 FP32: {per_step:.4f} ms/step, {spp} per pass, "
+        f"nonfinite={d['nonfinite']}")
     del lat
     torch.cuda.empty_cache()
-    return dict(per_launch=per_launch, sites=n * n, nonfinite=d["nonfinite"])
+    return dict(per_step=per_step, spp=spp, sites=n * n, nonfinite=d["nonfinite"])
 
 
 def fp16_leg(torch, args):
@@ -292,8 +294,10 @@ def adjoint_leg(torch, args):
     """Gradient of the final total energy after args.adj_steps steps of the
     perturbed 1024^2 Orszag-Tang run: end to end with checkpoints every 100
     steps (the stated workload: recompute each segment, then sweep back), and
-    with the interval chosen from the free HBM (every state kept, nothing
-    recomputed); then the reverse kernels alone at 4096^2."""
+    with the interval chosen from the free HBM (every state the sweep reads
+    kept, nothing recomputed); then at 4096^2 one 100-step segment, the
+    reverse kernels alone, and a run of args.adj_steps steps with the interval
+    chosen from the free HBM."""
     from lbmhd_inputs import perturbed_orszag_tang
     from paper_1607_08675_amd.adjoint import Checkpointed
     from paper_1607_08675_amd.lattice import Lattice, LBMHDConfig
@@ -352,31 +356,75 @@ def adjoint_leg(torch, args):
     del lat, st, lam, lam2, acc
     torch.cuda.empty_cache()
     # one checkpoint segment of 100 steps at 4096^2, where the working set is
-    # far above the caches: recompute of 99 states into one stored block (as
-    # the checkpointed backward does), then 100 reverse steps
+    # far above the caches, as the checkpointed backward takes it: recompute
+    # of the 49 even states 2 .. 98 into one stored block (a pass per pair),
+    # then 100 reverse steps two per pass; and the reverse step alone, single
+    # and paired
     from lbmhd_inputs import orszag_tang
     nb = 4096
     lat = Lattice(LBMHDConfig(nx=nb, ny=nb, nu=1e-5, eta=1e-5, les=True, cs=0.1, storage="fp32"))
-    lat.init_fields(*orszag_tang(nb, nb)).step(10)
+    f4096 = orszag_tang(nb, nb)
+    lat.init_fields(*f4096).step(10)
     st = lat.save_state()
-    seg = torch.empty(99, lat.lattice_bytes, dtype=torch.uint8, device=lat.device)
+    seg = torch.empty(49, lat.lattice_bytes, dtype=torch.uint8, device=lat.device)
     lam, lam2, acc = lat.new_adj_buffer(), lat.new_adj_buffer(), lat.new_adj_acc()
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     for _ in range(2):   # the first round warms up
         lat.adj_seed_energy(st, lam)
         torch.cuda.synchronize()
         e0.record(lat.stream)
-        lat.step_store(st, seg, 99)
+        lat.step_store_pairs(st, seg, 49)
         e1.record(lat.stream)
-        lat.adj_sweep(st, seg, 100, lam, lam2, acc)
+        lat.adj_sweep_pairs(st, seg, 100, lam, lam2, acc)
         e2.record(lat.stream)
         torch.cuda.synchronize()
     out["recompute_ms_4096"] = e0.elapsed_time(e1) / 100
     out["adj_ms_4096"] = e1.elapsed_time(e2) / 100
     out["fwd_ms_4096"] = burst_ms_per_step(torch, lat, 198)
+    x1 = lat.new_state_buffer()
+    lat.step_between(st, x1)
+    torch.cuda.synchronize()
+    e0.record(lat.stream)
+    for _ in range(10):
+        lat.adj_step(x1, lam, lam2, acc)
+        lat.adj_step(st, lam2, lam, acc)
+    e1.record(lat.stream)
+    for _ in range(10):
+        lat.adj_step2(st, lam, lam2, acc)
+        lam, lam2 = lam2, lam
+    e2.record(lat.stream)
+    torch.cuda.synchronize()
+    out["adj_single_ms_4096"] = e0.elapsed_time(e1) / 20
+    out["adj_pair_ms_4096"] = e1.elapsed_time(e2) / 20
     log(f"4096^2 segment of 100: recompute {out['recompute_ms_4096']:.4f} ms/step, adjoint "
-        f"{out['adj_ms_4096']:.4f} ms/step, forward {out['fwd_ms_4096']:.4f} ms/step")
-    del lat, st, seg, lam, lam2, acc
+        f"{out['adj_ms_4096']:.4f} ms/step, forward {out['fwd_ms_4096']:.4f} ms/step; reverse "
+        f"step single {out['adj_single_ms_4096']:.4f}, paired {out['adj_pair_ms_4096']:.4f} "
+        f"ms/step")
+    del st, seg, lam, lam2, acc, x1
+    torch.cuda.empty_cache()
+    # the stated run length at 4096^2: 2000 steps forward and backward with the
+    # interval chosen from the free HBM (a warm-up run allocates the buffers)
+    for rnd in range(2):
+        run = Checkpointed(lat, "auto")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = run.forward(f4096, args.adj_steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = run.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rnd == 0:
+            del run, g
+            continue
+        out["run_4096"] = dict(nsteps=args.adj_steps, interval=run.interval, J=J,
+                               fwd_ms=1e3 * (t1 - t0) / args.adj_steps,
+                               bwd_ms=1e3 * (t2 - t1) / args.adj_steps, dJ_dcsv=g[4])
+        log(f"4096^2 run of {args.adj_steps} steps, interval {run.interval}: forward "
+            f"{out['run_4096']['fwd_ms']:.4f} ms/step, backward {out['run_4096']['bwd_ms']:.4f} "
+            f"ms/step")
+        del run, g
+    del lat
     torch.cuda.empty_cache()
     # the reverse step of the kinetic closure (two passes) at the same size
     lat = Lattice(LBMHDConfig(nx=nb, ny=nb, nu=1e-5, eta=1e-5, les=2, cs=0.1, delta=1.0,
@@ -633,13 +681,16 @@ def main():
              "cross-helicity LES closure with backscatter (C_S = 0.1, Delta = 1)")):
         if not res:
             continue
-        mk = res["sites"] / (res["per_launch"] * 1e-3) / 1e6
-        ak = FP32_BYTES_PER_SITE * res["sites"] / (res["per_launch"] * 1e-3) / 1e9
+        # one launch reads and writes the lattice once for its steps_per_pass steps
+        ms_launch = res["per_step"] * res["spp"]
+        mk = res["sites"] / (res["per_step"] * 1e-3) / 1e6
+        ak = FP32_BYTES_PER_SITE * res["sites"] / (ms_launch * 1e-3) / 1e9
         line[key] = {
             "workload": f"Orszag-Tang 4096x4096, FP32, {what}, nu=eta=1e-5",
-            "mlups": round(mk, 1), "ms_per_step": round(res["per_launch"], 5),
+            "mlups": round(mk, 1), "ms_per_step": round(res["per_step"], 5),
+            "steps_per_pass": res["spp"], "ms_per_launch": round(ms_launch, 5),
             "achieved_gbs": round(ak, 1), "frac": round(ak / HBM_PEAK_GBS, 4),
-            "bytes_per_site": FP32_BYTES_PER_SITE, "nonfinite": res["nonfinite"],
+            "bytes_per_site_per_launch": FP32_BYTES_PER_SITE, "nonfinite": res["nonfinite"],
         }
     if r16:
         f16, f32 = r16["fp16"], r16["fp32"]
@@ -706,15 +757,28 @@ def main():
             "adj_kernel_gbs": round(3 * 19 * 4 * s / (radj["adj_kernel_ms"] * 1e-3) / 1e9, 1),
             "segment_4096": {
                 "workload": "Orszag-Tang 4096x4096, FP32, LES: one 100-step checkpoint segment "
-                            "(99 states recomputed into one block, then 100 reverse steps)",
+                            "(the 49 even states recomputed into one block, a pass per pair, "
+                            "then 100 reverse steps two per pass)",
                 "recompute_ms_per_step": round(radj["recompute_ms_4096"], 5),
                 "adjoint_ms_per_step": round(radj["adj_ms_4096"], 5),
                 "forward_ms_per_step": round(radj["fwd_ms_4096"], 5),
                 "adjoint_over_forward_step": round(radj["adj_ms_4096"] / radj["fwd_ms_4096"], 3),
                 "recompute_plus_adjoint_over_forward_step": round(
                     (radj["recompute_ms_4096"] + radj["adj_ms_4096"]) / radj["fwd_ms_4096"], 3),
-                "adj_kernel_gbs": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9, 1),
-                "adj_kernel_frac": round(3 * 19 * 4 * 4096 * 4096 / (radj["adj_ms_4096"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                # x_t, lam_{t+2} and lam_t once per pair of reverse steps
+                "adj_pair_kernel_gbs": round(3 * 19 * 4 * 4096 * 4096 / (2 * radj["adj_ms_4096"] * 1e-3) / 1e9, 1),
+                "adj_pair_kernel_frac": round(3 * 19 * 4 * 4096 * 4096 / (2 * radj["adj_ms_4096"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "reverse_step_single_ms": round(radj["adj_single_ms_4096"], 5),
+                "reverse_step_paired_ms": round(radj["adj_pair_ms_4096"], 5),
+            },
+            "run_4096": {
+                "workload": f"Orszag-Tang 4096x4096, FP32, LES, {radj['run_4096']['nsteps']} steps, "
+                            "checkpoint interval from the free HBM, reverse steps in pairs",
+                "interval": radj["run_4096"]["interval"],
+                "forward_ms_per_step": round(radj["run_4096"]["fwd_ms"], 5),
+                "backward_ms_per_step": round(radj["run_4096"]["bwd_ms"], 5),
+                "backward_over_forward_step": round(radj["run_4096"]["bwd_ms"] / radj["fwd_ms_4096"], 3),
+                "J": radj["run_4096"]["J"], "dJ_dcsv": radj["run_4096"]["dJ_dcsv"],
             },
             "kinetic_closure_adj_ms_4096": round(radj["adj_kin_ms_4096"], 5),
             "kinetic_closure_adj_gbs_4096": round(460 * 4096 * 4096 / (radj["adj_kin_ms_4096"] * 1e-3) / 1e9, 1),

@@ -121,25 +121,30 @@ typedef struct {
                              that is the bound lattice itself, first return
                              a reversed lattice to the natural layout. */
   int32_t steps_per_pass; /* How many steps lbmhd_step takes per pass over
-                             the lattice when two lattices are bound and the
-                             closure reads no neighbours (les = 0 or 1), the
-                             intermediate states staying on chip: 0
+                             the lattice when two lattices are bound, the
+                             intermediate states staying on chip.  Closures
+                             that read no neighbours (les = 0 or 1): 0
                              (automatic) takes triples of steps with FP32
                              storage and pairs with FP16 when the lattice is
                              large enough for that to pay (at least 512 tiles
                              of 8 rows by 256 FP32 or 512 FP16 columns, e.g.
                              1024^2 FP32, 2048^2 FP16); 3 always takes
                              triples with FP32 (pairs with FP16); 2 always
-                             takes pairs; 1 takes single steps.  A remainder
-                             goes in pairs (a remainder of one takes the
-                             last triple along as two pairs), so a single
+                             takes pairs.  Closures that read the neighbours'
+                             moments (les = 2, 3, 4, 6): 0 takes pairs with
+                             FP32 storage and les = 2, 3 or 4 from 512 tiles
+                             of 8 rows by 256 columns on (else single steps),
+                             2 and 3 always take pairs.  1 takes single
+                             steps.  A
+                             remainder goes in pairs (a remainder of one takes
+                             the last triple along as two pairs), so a single
                              step runs only when one is left.  Other values
                              are rejected.  The
                              result is bit for bit that of single steps, in
                              FP32 and FP16 storage (every kernel rounds the
-                             collision identically: its fused multiply-adds
-                             are spelled out and no other contraction is
-                             allowed). */
+                             collision and the gradient terms identically:
+                             their fused multiply-adds are spelled out and
+                             no other contraction is allowed). */
 } lbmhd_params;
 
 /* Global diagnostics of the current state, accumulated in FP64.
@@ -237,6 +242,18 @@ int lbmhd_step_between(lbmhd_t* h, const void* src, void* dst);
  * whole trajectory for the adjoint when it fits in device memory.
  * Asynchronous. */
 int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, int64_t n);
+
+/* npairs >= 0 pairs of steps from the encoded lattice src, keeping every
+ * other state: state 2k (k = 1 .. npairs) is written to store + (k - 1) *
+ * stride bytes (device; stride a multiple of 256 and >= `lattice` bytes), the
+ * odd states are never written.  Each pair is one pass over the lattice (the
+ * two-step kernels of lbmhd_step), so the result equals 2 npairs single
+ * steps bit for bit.  The handle's current state and step count are
+ * untouched; the store range overlaps neither src nor the bound buffers.
+ * Used to recompute a checkpoint segment for lbmhd_adj_sweep_pairs, which
+ * needs only these states.  Asynchronous.  Errors as lbmhd_step_store. */
+int lbmhd_step_store_pairs(lbmhd_t* h, const void* src, void* store, size_t stride,
+                           int64_t npairs);
 
 /* Macroscopic fields of the current state: rho = sum f, u = (sum c f) / rho,
  * B = sum g (Sec. 3).  Outputs: device fields.  Asynchronous. */
@@ -342,10 +359,33 @@ int lbmhd_adj_step(lbmhd_t* h, const void* state_n, const float* lam_next, float
  * writes), and lam holding lam_n (streamed position) on entry, apply
  * lbmhd_adj_step for t = n - 1 down to 0 and leave lam_0 in lam.  tmp is a
  * second adjoint lattice used as scratch (not overlapping lam); acc gains the
- * closure-constant sums as in lbmhd_adj_step.  Asynchronous.  Errors as
- * lbmhd_adj_step. */
+ * closure-constant sums as in lbmhd_adj_step.  Without neighbour terms
+ * (les = 0, 1) and from 512 tiles of 8 rows by 256 columns on, the steps go
+ * in pairs as in lbmhd_adj_sweep_pairs (the same lam_0 bit for bit, reading
+ * the even states only).  Asynchronous.  Errors as lbmhd_adj_step. */
 int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t stride, int64_t n,
                     float* lam, float* tmp, double* acc);
+
+/* Two reverse steps in one pass over the lattice: lam_prev = (dx_{t+2} /
+ * dx_t)^T lam_next from the encoded state_t = x_t alone; x_{t+1} =
+ * C(S(x_t)) is recomputed on the device with the collision lbmhd_step
+ * applies, so lam_prev equals lbmhd_adj_step(x_{t+1}, lam_next, tmp)
+ * followed by lbmhd_adj_step(x_t, tmp, lam_prev) bit for bit, and acc gains
+ * the same closure-constant sums up to the order of their additions.
+ * Closures without neighbour terms (les = 0, 1); LBMHD_ERR_UNSUPPORTED for
+ * les = 2, 3, 4, 6.  Other errors as lbmhd_adj_step.  Asynchronous. */
+int lbmhd_adj_step2(lbmhd_t* h, const void* state_t, const float* lam_next, float* lam_prev,
+                    double* acc);
+
+/* Reverse sweep over n >= 0 steps of a trajectory kept every other state
+ * (the layout lbmhd_step_store_pairs writes): x_0 = src and x_t at store +
+ * (t / 2 - 1) * stride for the even t = 2 .. n - 1.  The reverse steps go in
+ * pairs (lbmhd_adj_step2 from x_t for t = n - 2, n - 4, ...), after a single
+ * lbmhd_adj_step from x_{n-1} first when n is odd; lam holds lam_n on entry
+ * and lam_0 on return, tmp is scratch, acc gains the closure-constant sums.
+ * Errors as lbmhd_adj_step2.  Asynchronous. */
+int lbmhd_adj_sweep_pairs(lbmhd_t* h, const void* src, const void* store, size_t stride,
+                          int64_t n, float* lam, float* tmp, double* acc);
 
 /* Sum the two slot arrays of acc into out[0] (C_Sv) and out[1] (C_Sb), host,
  * in FP64.  Synchronises. */

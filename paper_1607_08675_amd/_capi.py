@@ -28,13 +28,14 @@ LBMHD_FP16 = 1
 EXPORTS = (
     "lbmhd_strerror", "lbmhd_last_error", "lbmhd_create", "lbmhd_destroy", "lbmhd_sizes",
     "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_steps_per_pass",
-    "lbmhd_step_between", "lbmhd_step_store",
+    "lbmhd_step_between", "lbmhd_step_store", "lbmhd_step_store_pairs",
     "lbmhd_macro",
     "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_get_populations",
     "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state", "lbmhd_get_step",
     "lbmhd_current_state",
     "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_seed_mismatch", "lbmhd_adj_step",
-    "lbmhd_adj_sweep", "lbmhd_adj_acc_total", "lbmhd_adj_fields", "lbmhd_diag_noalloc",
+    "lbmhd_adj_sweep", "lbmhd_adj_step2", "lbmhd_adj_sweep_pairs", "lbmhd_adj_acc_total",
+    "lbmhd_adj_fields", "lbmhd_diag_noalloc",
 )
 # Every function declared in include/lbmhd3.h.
 EXPORTS3 = (
@@ -137,6 +138,9 @@ def lib():
             "lbmhd_adj_seed_energy": [vp, vp, vp],
             "lbmhd_adj_step": [vp, vp, vp, vp, vp],
             "lbmhd_adj_sweep": [vp, vp, vp, sz, i64, vp, vp, vp],
+            "lbmhd_step_store_pairs": [vp, vp, vp, sz, i64],
+            "lbmhd_adj_step2": [vp, vp, vp, vp, vp],
+            "lbmhd_adj_sweep_pairs": [vp, vp, vp, sz, i64, vp, vp, vp],
             "lbmhd_adj_acc_total": [vp, vp, P(ctypes.c_double)],
             "lbmhd_adj_fields": [vp] * 11,
             "lbmhd3_create": [P(Params3), P(vp)],

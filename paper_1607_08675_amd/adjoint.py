@@ -6,9 +6,12 @@ J = sum |rho u|^2 / (2 rho) + |B|^2 / 2 of the final state (FP64).  Its backward
 pass is the discrete adjoint: checkpoints of the encoded lattice are kept every
 ``every`` steps during the forward run (every state when they fit in device
 memory); the backward sweep recomputes each segment's states from its
-checkpoint straight into one stored block (``lbmhd_step_store``, one step
-kernel per state, no copies) and walks them in reverse (``lbmhd_adj_sweep``),
-each a single library call.  The result holds the exact
+checkpoint straight into one stored block and walks them in reverse, each a
+single library call.  Without neighbour terms in the closure (les = 0, 1) the
+reverse steps go two per pass from one state (``lbmhd_adj_sweep_pairs``), so
+only every other state is kept or recomputed (``lbmhd_step_store_pairs``, one
+pass per pair); with the kinetic closure every state is
+(``lbmhd_step_store``, ``lbmhd_adj_sweep``).  The result holds the exact
 derivative of the FP32 update map (storage rounding counted as the identity)
 with respect to the initial fields and the closure constants: ``cs`` is a
 scalar (C_Sv = C_Sb = cs) or a pair (C_Sv, C_Sb), and its gradient has the
@@ -21,23 +24,31 @@ import torch
 from .lattice import LBMHDConfig, Lattice
 
 
-def states_needed(nsteps: int, every: int) -> int:
+def states_needed(nsteps: int, every: int, pairs: bool = False) -> int:
     """Lattice-sized buffers a run of nsteps with checkpoints every `every`
     steps holds at once: every state when every == 1; otherwise the
     checkpoints, the final state and the every - 1 recomputed states of one
-    segment."""
+    segment.  With pairs (reverse steps two per pass, each from one state)
+    only the even states of a segment are kept: at every == 1 the initial
+    state, the states 2, 4, .. <= nsteps - 1 and the final one; otherwise
+    (every - 1) // 2 segment states."""
     if every == 1:
-        return nsteps + 1
-    return -(-nsteps // every) + 1 + (every - 1)
+        return (nsteps - 1) // 2 + 2 if pairs and nsteps > 1 else nsteps + 1
+    seg = (every - 1) // 2 if pairs else every - 1
+    return -(-nsteps // every) + 1 + seg
 
 
-def choose_interval(nsteps: int, state_bytes: int, budget_bytes: int) -> int:
+def choose_interval(nsteps: int, state_bytes: int, budget_bytes: int,
+                    pairs: bool = False) -> int:
     """The smallest checkpoint interval whose buffers fit the budget (1 keeps
-    every state and makes the backward sweep recompute nothing)."""
+    every state and makes the backward sweep recompute nothing).  With pairs an
+    odd interval k > 1 becomes k + 1: that holds no more buffers (the same
+    (k - 1) // 2 segment states, fewer checkpoints) and takes every reverse
+    step in a pair, where k leaves one single step per segment."""
     fit = budget_bytes // max(state_bytes, 1)
     for k in range(1, max(nsteps, 1) + 1):
-        if states_needed(nsteps, k) <= fit:
-            return k
+        if states_needed(nsteps, k, pairs) <= fit:
+            return k + 1 if pairs and k > 1 and k % 2 else k
     raise MemoryError("not even one checkpoint segment fits the memory budget")
 
 
@@ -47,10 +58,11 @@ class Checkpointed:
 
     every = "auto" picks the smallest interval whose state buffers fit
     ``budget_bytes`` (default: 70% of the device memory free when the forward
-    run starts).  With interval 1 every state is kept: the forward steps write
-    straight into the stored buffers and the backward sweep recomputes
-    nothing, which is the case whenever the run fits in HBM (2000 steps of a
-    1024^2 FP32 lattice take 160 GB)."""
+    run starts).  With interval 1 every state the sweep reads is kept (every
+    other one with paired reverse steps): the forward steps write straight
+    into the stored buffers and the backward sweep recomputes nothing, which
+    is the case whenever the run fits in HBM (the 1001 states of 2000 steps
+    of a 1024^2 FP32 lattice take 80 GB)."""
 
     def __init__(self, lat: Lattice, every="auto", budget_bytes: int | None = None):
         if every != "auto" and (not isinstance(every, int) or every < 1):
@@ -60,6 +72,9 @@ class Checkpointed:
         self.budget_bytes = budget_bytes
         self.interval = None
         self.ckpts: list[torch.Tensor] = []
+        # reverse steps in pairs, from every other state (closures without
+        # neighbour terms)
+        self.pairs = lat is not None and (int(lat.cfg.les) & 6) == 0
 
     def _interval(self, nsteps: int) -> int:
         if self.every != "auto":
@@ -70,7 +85,7 @@ class Checkpointed:
             cached = (torch.cuda.memory_reserved(self.lat.device)
                       - torch.cuda.memory_allocated(self.lat.device))
             budget = int(0.7 * (free + cached))
-        return choose_interval(nsteps, self.lat.lattice_bytes, budget)
+        return choose_interval(nsteps, self.lat.lattice_bytes, budget, self.pairs)
 
     def forward(self, fields, nsteps: int, targets=None) -> float:
         """Run nsteps from equilibrium at `fields` (rho, ux, uy, bx, by) keeping
@@ -86,15 +101,28 @@ class Checkpointed:
         store = None
         if k == 1:
             try:
-                store = torch.empty(nsteps + 1, lat.lattice_bytes, dtype=torch.uint8,
-                                    device=lat.device)
+                store = torch.empty(states_needed(nsteps, 1, self.pairs), lat.lattice_bytes,
+                                    dtype=torch.uint8, device=lat.device)
             except torch.OutOfMemoryError:
                 # the free memory was not in one piece: fall back to checkpoints
                 # within half of what every state would have taken
                 k = choose_interval(nsteps, lat.lattice_bytes,
-                                    (nsteps + 1) * lat.lattice_bytes // 2)
+                                    states_needed(nsteps, 1, self.pairs) * lat.lattice_bytes // 2,
+                                    self.pairs)
         self.interval = k
-        if k == 1:
+        if k == 1 and self.pairs and nsteps > 1:
+            # the initial state, the even states 2 .. 2m (m = (nsteps - 1) // 2,
+            # one library call) and the final state, reached from state 2m by
+            # the one or two steps left; the lattice ends on the final state
+            m = (nsteps - 1) // 2
+            self.store = store
+            self.ckpts = [store[0]]
+            lat.save_state(store[0])
+            lat.step_store_pairs(store[0], store[1:m + 1], m)
+            lat.load_state(store[m], lat.step_count + 2 * m)
+            lat.step(nsteps - 2 * m)
+            self.final = lat.save_state(store[m + 1])
+        elif k == 1:
             # every state kept, in one allocation, written by one library call;
             # the lattice ends on the final state
             self.store = store
@@ -127,8 +155,20 @@ class Checkpointed:
         else:
             lat.adj_seed_mismatch(self.final, self.targets, scale, lam)
         k = self.interval
-        if k == 1:
+        if k == 1 and self.pairs and self.nsteps > 1:
+            m = (self.nsteps - 1) // 2
+            lat.adj_sweep_pairs(self.ckpts[0], self.store[1:m + 1], self.nsteps, lam, lam2, acc)
+        elif k == 1:
             lat.adj_sweep(self.ckpts[0], self.store[1:], self.nsteps, lam, lam2, acc)
+        elif self.pairs:
+            # per segment, from the last: recompute its even states into one
+            # block (one pass per pair), then sweep back over it in pairs
+            seg = torch.empty(max((k - 1) // 2, 1), lat.lattice_bytes, dtype=torch.uint8,
+                              device=lat.device)
+            for s in reversed(range(len(self.ckpts))):
+                n = min(k, self.nsteps - s * k)
+                lat.step_store_pairs(self.ckpts[s], seg, (n - 1) // 2)
+                lat.adj_sweep_pairs(self.ckpts[s], seg, n, lam, lam2, acc)
         else:
             # per segment, from the last: recompute its states into one block,
             # then sweep back over them (lambda stays in lam)

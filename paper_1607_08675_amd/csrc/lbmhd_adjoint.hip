@@ -21,7 +21,10 @@
 // the kinks of |A| and of the norm Q take derivative 0 at exactly 0.
 #include <math.h>
 
+#include <type_traits>
+
 #include "lbmhd_impl.h"
+#include "lbmhd_step_dev.h"
 
 #ifndef LBMHD_ADJ_TX
 #define LBMHD_ADJ_TX 256
@@ -30,38 +33,15 @@
 namespace lbk {
 namespace {
 
+// Decoded deviations of a stored state, as the forward step decodes them
+// (FP16: the stored half times 2^-10).
 template <int ST>
-struct Dec;
-template <>
-struct Dec<LBMHD_FP32> {
-  using T = float;
-  __device__ static __forceinline__ float dec(float v) { return v; }
-};
-template <>
-struct Dec<LBMHD_FP16> {
-  using T = _Float16;
-  __device__ static __forceinline__ float dec(_Float16 v) { return float(v) * 0x1p-10f; }
-};
+using Dec = Codec<ST>;
 
-__device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__device__ constexpr int kMx[5] = {0, 1, 0, -1, 0};
-__device__ constexpr int kMy[5] = {0, 0, 1, 0, -1};
-__device__ constexpr double kW[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
-                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-__device__ constexpr double kWm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
-
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-// Plane element access with a uniform base and a 32-bit byte offset (the byte
-// size of a plane is below 2^32, checked at lbmhd_create).
+// One element of a plane with a uniform base and a 32-bit element offset.
 template <typename T>
-__device__ __forceinline__ T ld_plane(const T* __restrict__ base, unsigned off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off * unsigned(sizeof(T)));
-}
-__device__ __forceinline__ void st_plane_nt(float* __restrict__ base, unsigned off, float v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off * 4u));
+__device__ __forceinline__ T ld_elem(const T* __restrict__ base, unsigned off) {
+  return ld_plane<T>(base, off);
 }
 
 struct AdjConsts {
@@ -94,8 +74,12 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
                                                  const Rates& r, const AdjConsts& ac,
                                                  const KinTerms& kc = KinTerms{0.f, 0.f, 0.f, 0.f},
                                                  KinTerms* kcb = nullptr) {
-  // ---- forward recompute of what the reverse sweep needs (same operations
-  // as the forward collision)
+  // Every multiply-add is written out and no other contraction is allowed,
+  // so each kernel that inlines this function rounds it identically (two
+  // reverse steps in one pass equal two single ones bit for bit).
+#pragma clang fp contract(off)
+  // ---- forward recompute of what the reverse sweep needs (the forward
+  // collision's quantities)
   const float a13 = f[1] + f[3], a24 = f[2] + f[4];
   const float d13 = f[1] - f[3], d24 = f[2] - f[4];
   const float s57 = f[5] + f[7], s68 = f[6] + f[8];
@@ -111,10 +95,9 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
   const float ux = jx * ir, uy = jy * ir;
   const float Bx = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
   const float By = (g[5] + g[6]) + (g[7] + g[8]) + g[9];
-  const float jxux = jx * ux, jyuy = jy * uy;
-  float n3 = M3 - (jx * uy - Bx * By);
-  float n4 = M4 - ((jxux - jyuy) - (Bx * Bx - By * By));
-  float E = ux * By - uy * Bx;
+  float n3 = M3 - fmaf(jx, uy, -(Bx * By));
+  float n4 = M4 - (fmaf(jx, ux, -(jy * uy)) - fmaf(Bx, Bx, -(By * By)));
+  float E = fmaf(ux, By, -(uy * Bx));
   if (KIN) {
     n3 -= kc.m3;
     n4 -= kc.m4;
@@ -122,12 +105,12 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
   }
   float s3q, sm, Q = 0.0f, Rr = 1.0f, tau = 1.0f, A = 0.0f, Rm = 1.0f, taum = 1.0f;
   if (LES) {
-    Q = fsqrt(n4 * n4 + 4.0f * (n3 * n3));
-    Rr = fsqrt(r.tau0sq + r.cf * Q * ir);
+    Q = fsqrt(fmaf(n4, n4, 4.0f * (n3 * n3)));
+    Rr = fsqrt(fmaf(r.cf * Q, ir, r.tau0sq));
     tau = 0.5f * (r.tau0 + Rr);
     s3q = 0.25f * frcp(tau);
-    A = (g[6] - g[8]) - (g[2] - g[4]) - 2.0f * E;
-    Rm = fsqrt(r.taum0sq + r.cm * fabsf(A));
+    A = fmaf(-2.0f, E, (g[6] - g[8]) - (g[2] - g[4]));
+    Rm = fsqrt(fmaf(r.cm, fabsf(A), r.taum0sq));
     taum = 0.5f * (r.taum0 + Rm);
     sm = frcp(taum);
   } else {
@@ -135,8 +118,8 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
     sm = r.sm;
   }
   const float bx6 = Bx * (1.0f / 6.0f), by6 = By * (1.0f / 6.0f), he = 0.5f * E;
-  const float geq[10] = {Bx - 4.0f * bx6, bx6, bx6 - he, bx6, bx6 + he,
-                         By - 4.0f * by6, by6 + he, by6, by6 - he, by6};
+  const float geq[10] = {fmaf(-4.0f, bx6, Bx), bx6, bx6 - he, bx6, bx6 + he,
+                         fmaf(-4.0f, by6, By), by6 + he, by6, by6 - he, by6};
 
   // ---- reverse
   // f* = f - K r, K_ij = T_ji:  rbar_j = -(T lam*_f)_j, j = 3..8.
@@ -148,25 +131,25 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
   const float ljx = ld13 + ld57 - ld68, ljy = ld24 + ld57 + ld68;
   const float rb3 = -(ls57 - ls68);
   const float rb4 = -(la13 - la24);
-  const float rb5 = -(ljx - 3.0f * ld13);
-  const float rb6 = -(ljy - 3.0f * ld24);
-  const float rb7 = -(4.0f * lf[0] - 5.0f * (la13 + la24) + 4.0f * ldd);
-  const float rb8 = -(4.0f * lf[0] - ldd);
+  const float rb5 = -fmaf(-3.0f, ld13, ljx);
+  const float rb6 = -fmaf(-3.0f, ld24, ljy);
+  const float rb7 = -fmaf(4.0f, lf[0], fmaf(-5.0f, la13 + la24, 4.0f * ldd));
+  const float rb8 = -fmaf(4.0f, lf[0], -ldd);
   float nb3 = s3q * rb3, nb4 = s3q * rb4;
   const float nb5 = r.s5q * rb5, nb6 = r.s5q * rb6;
   const float nb7 = r.s7q * rb7, nb8 = r.s8q * rb8;
-  const float s3qb = n3 * rb3 + n4 * rb4;
+  const float s3qb = fmaf(n3, rb3, n4 * rb4);
 
   // g* = g - sm (g - geq)
   float smb = 0.0f, geqb[10], lgo[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) {
-    smb -= lg[q] * (g[q] - geq[q]);
+    smb = fmaf(-lg[q], g[q] - geq[q], smb);
     geqb[q] = sm * lg[q];
-    lgo[q] = (1.0f - sm) * lg[q];
+    lgo[q] = fmaf(-sm, lg[q], lg[q]);
   }
-  float Bxb = (1.0f / 3.0f) * geqb[0] + (1.0f / 6.0f) * (geqb[1] + geqb[2] + geqb[3] + geqb[4]);
-  float Byb = (1.0f / 3.0f) * geqb[5] + (1.0f / 6.0f) * (geqb[6] + geqb[7] + geqb[8] + geqb[9]);
+  float Bxb = fmaf(1.0f / 3.0f, geqb[0], (1.0f / 6.0f) * (geqb[1] + geqb[2] + geqb[3] + geqb[4]));
+  float Byb = fmaf(1.0f / 3.0f, geqb[5], (1.0f / 6.0f) * (geqb[6] + geqb[7] + geqb[8] + geqb[9]));
   float Eb = 0.5f * (-geqb[2] + geqb[4] + geqb[6] - geqb[8]);
 
   CsGrad dcs{0.0f, 0.0f};
@@ -177,23 +160,23 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
     const float amb = 0.5f * taumb * 0.5f * frcp(Rm);
     const float absAb = r.cm * amb;
     const float Ab = A > 0.0f ? absAb : (A < 0.0f ? -absAb : 0.0f);
-    dcs.b += ac.dcm * fabsf(A) * amb;
+    dcs.b = fmaf(ac.dcm * fabsf(A), amb, dcs.b);
     lgo[6] += Ab;
     lgo[8] -= Ab;
     lgo[2] -= Ab;
     lgo[4] += Ab;
-    Eb -= 2.0f * Ab;
+    Eb = fmaf(-2.0f, Ab, Eb);
     // s3q = 1 / (4 tau), tau = (tau0 + Rr) / 2, Rr = sqrt(tau0^2 + cf Q ir)
     const float itau = frcp(tau);
     const float taub = -0.25f * s3qb * itau * itau;
     const float ab = 0.5f * taub * 0.5f * frcp(Rr);
     const float Qb = r.cf * ir * ab;
-    irb += r.cf * Q * ab;
-    dcs.v += ac.dcf * Q * ir * ab;
+    irb = fmaf(r.cf * Q, ab, irb);
+    dcs.v = fmaf(ac.dcf * Q * ir, ab, dcs.v);
     if (Q > 0.0f) {
       const float iQ = frcp(Q);
-      nb4 += Qb * n4 * iQ;
-      nb3 += 4.0f * Qb * n3 * iQ;
+      nb4 = fmaf(Qb * n4, iQ, nb4);
+      nb3 = fmaf(4.0f * Qb * n3, iQ, nb3);
     }
   }
   if (KIN) {
@@ -204,42 +187,42 @@ __device__ __forceinline__ CsGrad collide_adjoint(const float (&f)[9], const flo
   }
   // E = ux By - uy Bx (+ e)
   float uxb = Eb * By, uyb = -Eb * Bx;
-  Byb += Eb * ux;
-  Bxb -= Eb * uy;
+  Byb = fmaf(Eb, ux, Byb);
+  Bxb = fmaf(-Eb, uy, Bxb);
   // n3 = M3 - jx jy ir + Bx By
   float jxb = -nb3 * jy * ir, jyb = -nb3 * jx * ir;
-  irb -= nb3 * jx * jy;
-  Bxb += nb3 * By;
-  Byb += nb3 * Bx;
+  irb = fmaf(-nb3 * jx, jy, irb);
+  Bxb = fmaf(nb3, By, Bxb);
+  Byb = fmaf(nb3, Bx, Byb);
   // n4 = M4 - (jx^2 - jy^2) ir + Bx^2 - By^2
-  jxb -= 2.0f * nb4 * jx * ir;
-  jyb += 2.0f * nb4 * jy * ir;
-  irb -= nb4 * (jx * jx - jy * jy);
-  Bxb += 2.0f * nb4 * Bx;
-  Byb -= 2.0f * nb4 * By;
+  jxb = fmaf(-2.0f * nb4 * jx, ir, jxb);
+  jyb = fmaf(2.0f * nb4 * jy, ir, jyb);
+  irb = fmaf(-nb4, fmaf(jx, jx, -(jy * jy)), irb);
+  Bxb = fmaf(2.0f * nb4, Bx, Bxb);
+  Byb = fmaf(-2.0f * nb4, By, Byb);
   // n5 = M5 + jx, n6 = M6 + jy
   jxb += nb5;
   jyb += nb6;
   // n7, n8 through jj = (jx^2 + jy^2) ir and drho
   const float jjb = 3.0f * (nb7 + nb8);
   float drhob = -(5.0f / 3.0f) * nb8;
-  jxb += 2.0f * jjb * jx * ir;
-  jyb += 2.0f * jjb * jy * ir;
-  irb += jjb * (jx * jx + jy * jy);
+  jxb = fmaf(2.0f * jjb * jx, ir, jxb);
+  jyb = fmaf(2.0f * jjb * jy, ir, jyb);
+  irb = fmaf(jjb, fmaf(jx, jx, jy * jy), irb);
   // ux = jx ir, uy = jy ir
-  jxb += uxb * ir;
-  jyb += uyb * ir;
-  irb += uxb * jx + uyb * jy;
+  jxb = fmaf(uxb, ir, jxb);
+  jyb = fmaf(uyb, ir, jyb);
+  irb = fmaf(uxb, jx, fmaf(uyb, jy, irb));
   // ir = 1 / (1 + drho)
-  drhob -= irb * ir * ir;
+  drhob = fmaf(-irb * ir, ir, drhob);
   // moments M3..M8 = T_r f; drho = sum f; j = sum c f
   const float Mb3 = nb3, Mb4 = nb4, Mb5 = nb5, Mb6 = nb6, Mb7 = nb7, Mb8 = nb8;
-  lf[0] += drhob + 4.0f * Mb7 + 4.0f * Mb8;
-  lf[1] += drhob + jxb + Mb4 - 2.0f * Mb5 - 5.0f * Mb7;
-  lf[2] += drhob + jyb - Mb4 - 2.0f * Mb6 - 5.0f * Mb7;
-  lf[3] += drhob - jxb + Mb4 + 2.0f * Mb5 - 5.0f * Mb7;
-  lf[4] += drhob - jyb - Mb4 + 2.0f * Mb6 - 5.0f * Mb7;
-  const float c58 = 4.0f * Mb7 - Mb8;
+  lf[0] += fmaf(4.0f, Mb7 + Mb8, drhob);
+  lf[1] += fmaf(-5.0f, Mb7, fmaf(-2.0f, Mb5, drhob + jxb + Mb4));
+  lf[2] += fmaf(-5.0f, Mb7, fmaf(-2.0f, Mb6, drhob + jyb - Mb4));
+  lf[3] += fmaf(-5.0f, Mb7, fmaf(2.0f, Mb5, drhob - jxb + Mb4));
+  lf[4] += fmaf(-5.0f, Mb7, fmaf(2.0f, Mb6, drhob - jyb - Mb4));
+  const float c58 = fmaf(4.0f, Mb7, -Mb8);
   lf[5] += drhob + jxb + jyb + Mb3 + Mb5 + Mb6 + c58;
   lf[6] += drhob - jxb + jyb - Mb3 - Mb5 + Mb6 + c58;
   lf[7] += drhob - jxb - jyb + Mb3 - Mb5 - Mb6 + c58;
@@ -280,18 +263,18 @@ __global__ __launch_bounds__(LBMHD_ADJ_TX) void k_adj_step(
     const long long P = geo.plane, PA = ga.plane;
     float f[9], g[10], lf[9], lg[10];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = D::dec(ld_plane(st + i * P, o[i]));
+    for (int i = 0; i < 9; ++i) f[i] = D::dec(ld_elem(st + i * P, o[i]));
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      g[k] = D::dec(ld_plane(st + (9 + k) * P, o[k]));
-      g[5 + k] = D::dec(ld_plane(st + (14 + k) * P, o[k]));
+      g[k] = D::dec(ld_elem(st + (9 + k) * P, o[k]));
+      g[5 + k] = D::dec(ld_elem(st + (14 + k) * P, o[k]));
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam_next + i * PA, on[i]);
+    for (int i = 0; i < 9; ++i) lf[i] = ld_elem(lam_next + i * PA, on[i]);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      lg[k] = ld_plane(lam_next + (9 + k) * PA, on[k]);
-      lg[5 + k] = ld_plane(lam_next + (14 + k) * PA, on[k]);
+      lg[k] = ld_elem(lam_next + (9 + k) * PA, on[k]);
+      lg[5 + k] = ld_elem(lam_next + (14 + k) * PA, on[k]);
     }
     dcs = collide_adjoint<LES>(f, g, lf, lg, rt, ac);
     const unsigned oc = a0 + x;
@@ -602,11 +585,11 @@ __global__ __launch_bounds__(kAdjKinThreads) void k_adj_kin_a(
     const unsigned o[9] = {r0 + xx, r0 + xm, rm + xx, r0 + xp, rp + xx,
                            rm + xm, rm + xp, rp + xp, rp + xm};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) p[i] = D::dec(ld_plane(st + i * P, o[i]));
+    for (int i = 0; i < 9; ++i) p[i] = D::dec(ld_elem(st + i * P, o[i]));
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      p[9 + k] = D::dec(ld_plane(st + (9 + k) * P, o[k]));
-      p[14 + k] = D::dec(ld_plane(st + (14 + k) * P, o[k]));
+      p[9 + k] = D::dec(ld_elem(st + (9 + k) * P, o[k]));
+      p[14 + k] = D::dec(ld_elem(st + (14 + k) * P, o[k]));
     }
   };
   auto moments = [&](const float (&p)[19], int slot, int col) {
@@ -656,11 +639,11 @@ __global__ __launch_bounds__(kAdjKinThreads) void k_adj_kin_a(
                               ap + xp, ap + xm, am + xm, am + xp};
       float lf[9], lg[10], f[9], g[10];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam_next + i * PA, on[i]);
+      for (int i = 0; i < 9; ++i) lf[i] = ld_elem(lam_next + i * PA, on[i]);
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
-        lg[k] = ld_plane(lam_next + (9 + k) * PA, on[k]);
-        lg[5 + k] = ld_plane(lam_next + (14 + k) * PA, on[k]);
+        lg[k] = ld_elem(lam_next + (9 + k) * PA, on[k]);
+        lg[5 + k] = ld_elem(lam_next + (14 + k) * PA, on[k]);
       }
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = cur[i];
@@ -725,24 +708,289 @@ __global__ __launch_bounds__(256) void k_adj_kin_b(const float* __restrict__ gb,
   for (int k = 0; k < 5; ++k) {
     const float* bx = gb + k * PA;
     const float* by = gb + (5 + k) * PA;
-    eta[k] = (1.0f / 3.0f) * ((ld_plane(bx, r0 + xm) - ld_plane(bx, r0 + xp)) +
-                              (ld_plane(by, rm + x) - ld_plane(by, rp + x))) +
-             (1.0f / 12.0f) * ((ld_plane(bx, rm + xm) + ld_plane(by, rm + xm)) +
-                               (ld_plane(by, rm + xp) - ld_plane(bx, rm + xp)) +
-                               (ld_plane(bx, rp + xm) - ld_plane(by, rp + xm)) -
-                               (ld_plane(bx, rp + xp) + ld_plane(by, rp + xp)));
+    eta[k] = (1.0f / 3.0f) * ((ld_elem(bx, r0 + xm) - ld_elem(bx, r0 + xp)) +
+                              (ld_elem(by, rm + x) - ld_elem(by, rp + x))) +
+             (1.0f / 12.0f) * ((ld_elem(bx, rm + xm) + ld_elem(by, rm + xm)) +
+                               (ld_elem(by, rm + xp) - ld_elem(bx, rm + xp)) +
+                               (ld_elem(bx, rp + xm) - ld_elem(by, rp + xm)) -
+                               (ld_elem(bx, rp + xp) + ld_elem(by, rp + xp)));
   }
   const unsigned oc = r0 + x;
   float lf[9], lg[10];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) lf[i] = ld_plane(lam + i * PA, oc);
+  for (int i = 0; i < 9; ++i) lf[i] = ld_elem(lam + i * PA, oc);
 #pragma unroll
-  for (int q = 0; q < 10; ++q) lg[q] = ld_plane(lam + (9 + q) * PA, oc);
+  for (int q = 0; q < 10; ++q) lg[q] = ld_elem(lam + (9 + q) * PA, oc);
   add_moment_adjoints(eta, lf, lg);
 #pragma unroll
   for (int i = 0; i < 9; ++i) st_plane_nt(lam + i * PA, oc, lf[i]);
 #pragma unroll
   for (int q = 0; q < 10; ++q) st_plane_nt(lam + (9 + q) * PA, oc, lg[q]);
+}
+
+// ------------------------------------------- two reverse steps in one pass
+// lam_t = R_t(R_{t+1}(lam_{t+2})) in the streamed placement, R_n being the
+// reverse step at state x_n (k_adj_step), with x_{t+1} = C(S(x_t)) recomputed
+// on chip from the stored x_t: one stored state serves two reverse steps, so
+// a sweep needs every other state only.  R_n at site x reads x_n at x - c_i
+// (its pre-collision gather) and lam_{n+1} at x + c_i, so lam_t at x needs
+// lam_{t+1} one site out, hence x_{t+1} and lam_{t+2} two sites out and x_t
+// three.  A block owns a tile of kT3Cols columns and a strip of `rows` rows
+// and walks upward; pass t, with a = y0 - 2 + t:
+//   A. gathers row a of x_t (columns x0 - 2 .. x0 + wt + 1) and collides it
+//      with the forward collision: row a of x_{t+1}, passed through the
+//      storage codec as the forward step stores it; the planes that move along
+//      x go to the LDS row l1, the others stay in registers;
+//   B. reverse step t + 1 at row a - 1 (columns x0 - 1 .. x0 + wt): the
+//      pre-collision values of x_{t+1} from l1 and the registers, as in the
+//      forward three-step kernel, and lam_{t+2} at x + c_i from HBM; the
+//      result goes to l2 and the registers;
+//   C. reverse step t at row a - 2 (the tile's own columns): x_t gathered
+//      again (rows read in the last three passes, served by the caches) and
+//      lam_{t+1} at x + c_i from l2 and the registers -- the hand-over runs
+//      the other way than the forward one: a plane with c_y = +1 is read in
+//      the pass that writes it, c_y = 0 one pass later, c_y = -1 two; the
+//      result is stored.
+// Two barriers per pass; a fifth wave owns the four halo columns.  Both
+// reverse steps apply collide_adjoint to the values k_adj_step would read
+// (the recomputed state equals the stored one bit for bit), and the
+// closure-constant derivatives of both steps are summed per block over the
+// sites the block owns (slots b and nslots + b of acc).  LESF: the forward
+// step's collision takes the Smagorinsky-MHD closure (as lbmhd_step chooses
+// it: not with C_S = 0); LESA: the reverse steps differentiate it.  HBM bytes per site
+// for two reverse steps: x_t, lam_{t+2} and lam_t once each, plus the
+// strips' halo rows and the tiles' halo columns.
+template <int ST, bool LESF, bool LESA>
+__global__ __launch_bounds__(kT3Threads) void k_adj_step2(
+    const typename Codec<ST>::T* __restrict__ st, const float* __restrict__ lam_next,
+    float* __restrict__ lam_prev, double* __restrict__ acc, Geom geo, Geom ga, Rates rt,
+    AdjConsts ac, int tiles_x, int rows, int nslots) {
+  // the forward recompute runs on the stored values as the forward step
+  // does (FP16: in units of 2^-10); the reverse steps see deviations
+  constexpr int SF = ST == LBMHD_FP32 ? LBMHD_FP32 : kFP16S;
+  using CF = Codec<SF>;
+  using CA = Codec<ST>;
+  __shared__ float l1[kT3Rows][kT3Cols + 4];   // x_{t+1}: column lc + 2
+  __shared__ float l2[kT3Rows][kT3Cols + 2];   // lam_{t+1}: column lc + 1
+  __shared__ double red[2][kT3Threads];
+  const int nx = geo.nx, ny = geo.ny;
+  const long long P = geo.plane, PA = ga.plane;
+  const int tile = int(blockIdx.x) % tiles_x, strip = int(blockIdx.x) / tiles_x;
+  const int x0 = tile * kT3Cols, y0 = strip * rows;
+  const int wt = min(kT3Cols, nx - x0), h = min(rows, ny - y0);
+  // the thread's column: its own (threads 0 .. kT3Cols - 1) or a halo column
+  // (lanes 0 .. 3 of the fifth wave: x0 - 2, x0 - 1, x0 + wt, x0 + wt + 1)
+  const int tid = int(threadIdx.x);
+  int lc = tid;
+  bool has = tid < wt;
+  if (tid >= kT3Cols) {
+    const int k = tid - kT3Cols;
+    has = k < 4;
+    lc = k == 0 ? -2 : (k == 1 ? -1 : (k == 2 ? wt : wt + 1));
+  }
+  const bool up2 = has && lc >= -1 && lc <= wt;   // takes reverse step t + 1
+  const bool up3 = has && lc >= 0 && lc < wt;     // takes reverse step t
+  // LDS columns read in stages B and C: lc - c_x + c1 and lc + c_x + c2 (fixed
+  // in-bounds columns for the threads that take no such step)
+  const int c1 = up2 ? lc + 2 : 2;
+  const int c2 = up3 ? lc + 1 : 1;
+  int xc = (x0 + lc) % nx;
+  if (xc < 0) xc += nx;
+  const int xl = xc == 0 ? nx - 1 : xc - 1;
+  const int xr = xc == nx - 1 ? 0 : xc + 1;
+
+  // x_{t+1} of earlier passes for this thread's column (as in k_step_t3's
+  // first level): z, the c_x = 0 planes by c_y; x, the c_x != 0 planes
+  // already taken from column lc - c_x (6 with c_y = 0, 2 with c_y = +1)
+  float z1c[3], z1u1[3], z1u2[3], x1c[6], x1u1[2], x1u2[2];
+  // lam_{t+1} of earlier passes: w, the c_x = 0 planes (c_y = 0 one pass
+  // back, c_y = -1 two); y, the c_x != 0 planes taken from column lc + c_x
+  float w2c[3], w2d1[3], w2d2[3], y2c[6], y2d1[2], y2d2[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) z1c[k] = z1u1[k] = z1u2[k] = w2c[k] = w2d1[k] = w2d2[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) x1c[k] = y2c[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) x1u1[k] = x1u2[k] = y2d1[k] = y2d2[k] = 0.0f;
+  double dv = 0.0, db = 0.0;
+  for (int t = 0; t < h + 4; ++t) {
+    // A. row a = y0 - 2 + t of x_{t+1}
+    float n1c[3], n1u[3], n1d[3];
+    if (has) {
+      unsigned row[3];
+      t2_rows(y0 - 2 + t, geo, row);
+      float v[kNPop][1];
+      gather_row<SF, 1>(st, P, xc, xl, xr, row, v);
+      collide_sites<1, LESF, SF == kFP16S>(v, rt);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const float e = CA::dec(CF::enc(v[q][0]));
+        const int k = kT2Reg[q];
+        if (kT2Group[q] >= 0)
+          l1[t3_row(q)][lc + 2] = e;
+        else if (kPlaneCy[q] == 0)
+          n1c[k] = e;
+        else if (kPlaneCy[q] == 1)
+          n1u[k] = e;
+        else
+          n1d[k] = e;
+      }
+    }
+    __syncthreads();
+    // B. reverse step t + 1 at row b = y0 - 3 + t (from pass 2 on); the l1 row
+    // of this pass is read in every pass, before the next one overwrites it
+    float n2c[3], n2u[3], n2d[3];
+    const bool do2 = t >= 2 && up2;
+    {
+      float e[kT3Rows];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q)
+        if (kT2Group[q] >= 0) e[t3_row(q)] = l1[t3_row(q)][c1 - kPlaneCx[q]];
+      float pre[kNPop];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const int g = kT2Group[q], i = kT2Index[q], k = kT2Reg[q];
+        if (g >= 0)
+          pre[q] = g == 0 ? x1u2[i] : (g == 1 ? x1c[i] : e[t3_row(q)]);
+        else
+          pre[q] = kPlaneCy[q] == 0 ? z1c[k] : (kPlaneCy[q] == 1 ? z1u2[k] : n1d[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        x1u2[i] = x1u1[i];
+        x1u1[i] = e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) x1c[i] = e[2 + i];
+      if (do2) {
+        const int b = y0 - 3 + t;
+        unsigned ra[3];
+        t2_rows(b, ga, ra);
+        // lam_{t+2} at x + c_i: row b + c_y is ra[1 - c_y]
+        float lam[kNPop];
+#pragma unroll
+        for (int q = 0; q < kNPop; ++q) {
+          const int cx = kPlaneCx[q];
+          const unsigned col = unsigned(cx == 0 ? xc : (cx == 1 ? xr : xl));
+          lam[q] = ld_elem(lam_next + q * PA, ra[1 - kPlaneCy[q]] + col);
+        }
+        float f[9], g[10], lf[9], lg[10];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          f[i] = pre[i];
+          lf[i] = lam[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+          g[k] = pre[9 + k];
+          lg[k] = lam[9 + k];
+        }
+        const CsGrad d = collide_adjoint<LESA>(f, g, lf, lg, rt, ac);
+        if (LESA && up3 && b >= y0 && b < y0 + h) {
+          dv += double(d.v);
+          db += double(d.b);
+        }
+#pragma unroll
+        for (int q = 0; q < kNPop; ++q) {
+          const float val = q < 9 ? lf[q] : lg[q - 9];
+          const int k = kT2Reg[q];
+          if (kT2Group[q] >= 0)
+            l2[t3_row(q)][lc + 1] = val;
+          else if (kPlaneCy[q] == 0)
+            n2c[k] = val;
+          else if (kPlaneCy[q] == 1)
+            n2u[k] = val;
+          else
+            n2d[k] = val;
+        }
+      }
+    }
+    __syncthreads();
+    // C. reverse step t at row c = y0 - 4 + t (from pass 4 on), stored; the
+    // l2 row of this pass is read in every pass, as above
+    {
+      float e[kT3Rows];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q)
+        if (kT2Group[q] >= 0) e[t3_row(q)] = l2[t3_row(q)][c2 + kPlaneCx[q]];
+      if (t >= 4 && up3) {
+        const int c = y0 - 4 + t;
+        float lam[kNPop];
+#pragma unroll
+        for (int q = 0; q < kNPop; ++q) {
+          const int g = kT2Group[q], i = kT2Index[q], k = kT2Reg[q];
+          if (g >= 0)
+            lam[q] = g == 0 ? e[t3_row(q)] : (g == 1 ? y2c[i] : y2d2[i]);
+          else
+            lam[q] = kPlaneCy[q] == 1 ? n2u[k] : (kPlaneCy[q] == 0 ? w2c[k] : w2d2[k]);
+        }
+        unsigned row[3];
+        t2_rows(c, geo, row);
+        float v[kNPop][1];
+        gather_row<ST, 1>(st, P, xc, xl, xr, row, v);
+        float f[9], g[10], lf[9], lg[10];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          f[i] = v[i][0];
+          lf[i] = lam[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+          g[k] = v[9 + k][0];
+          lg[k] = lam[9 + k];
+        }
+        const CsGrad d = collide_adjoint<LESA>(f, g, lf, lg, rt, ac);
+        if (LESA) {
+          dv += double(d.v);
+          db += double(d.b);
+        }
+        const unsigned oc = unsigned(c) * ga.pitch + unsigned(xc);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_plane_nt(lam_prev + i * PA, oc, lf[i]);
+#pragma unroll
+        for (int q = 0; q < 10; ++q) st_plane_nt(lam_prev + (9 + q) * PA, oc, lg[q]);
+      }
+      // group 0 (c_y = +1) was used above from this pass; keep group 1 one
+      // pass and group 2 two
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        y2d2[i] = y2d1[i];
+        y2d1[i] = e[8 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) y2c[i] = e[2 + i];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      z1u2[k] = z1u1[k];
+      z1u1[k] = has ? n1u[k] : 0.0f;
+      z1c[k] = has ? n1c[k] : 0.0f;
+      w2d2[k] = w2d1[k];
+      w2d1[k] = do2 ? n2d[k] : 0.0f;
+      w2c[k] = do2 ? n2c[k] : 0.0f;
+    }
+  }
+  if (LESA) {
+    red[0][tid] = dv;
+    red[1][tid] = db;
+    __syncthreads();
+    if (tid < kT3Threads - kT3Cols) {
+      red[0][tid] += red[0][kT3Cols + tid];
+      red[1][tid] += red[1][kT3Cols + tid];
+    }
+    __syncthreads();
+    for (int w = kT3Cols / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[0][tid] += red[0][tid + w];
+        red[1][tid] += red[1][tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      acc[blockIdx.x] += red[0][0];
+      acc[nslots + blockIdx.x] += red[1][0];
+    }
+  }
 }
 
 }  // namespace
@@ -776,6 +1024,54 @@ hipError_t launch_adj_step(int storage, bool les, const void* state, const float
                          lam_prev, acc, g, ga, r, ac, tiles_x);
   }
   return hipGetLastError();
+}
+
+// Strip height of the two-reverse-step kernel (halo overhead 4 / rows): as
+// for the forward three-step kernel, about 512 blocks up to 128-row strips,
+// 32-row strips beyond.
+static int adj_step2_rows(const Geom& g) {
+  const long long tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
+  const long long rows = tiles_x * g.ny / 512;
+  return int(rows < 8 ? 8 : (rows > 128 ? 32 : rows));
+}
+
+template <int ST, bool LESF, bool LESA>
+void launch_adj_step2_t(const void* state, const float* lam_next, float* lam_prev, double* acc,
+                        const Geom& g, const Geom& ga, const Rates& r, const AdjConsts& ac,
+                        hipStream_t s) {
+  const int rows = adj_step2_rows(g);
+  const int tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
+  const int strips = (g.ny + rows - 1) / rows;
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kT3Threads);
+  hipLaunchKernelGGL((k_adj_step2<ST, LESF, LESA>), grid, block, 0, s,
+                     static_cast<const typename Codec<ST>::T*>(state), lam_next, lam_prev, acc, g,
+                     ga, r, ac, tiles_x, rows, adj_step_blocks(g));
+}
+
+hipError_t launch_adj_step2(int storage, bool les_fwd, bool les, const void* state,
+                            const float* lam_next, float* lam_prev, double* acc, const Geom& g,
+                            const Geom& ga, const Rates& r, double delta2, hipStream_t s) {
+  if (les_fwd && !les) return hipErrorInvalidValue;
+  const AdjConsts ac{float(18.0 * delta2), float(36.0 * delta2)};
+  auto go = [&](auto fp32) {
+    constexpr int ST = decltype(fp32)::value ? LBMHD_FP32 : LBMHD_FP16;
+    if (les_fwd)
+      launch_adj_step2_t<ST, true, true>(state, lam_next, lam_prev, acc, g, ga, r, ac, s);
+    else if (les)
+      launch_adj_step2_t<ST, false, true>(state, lam_next, lam_prev, acc, g, ga, r, ac, s);
+    else
+      launch_adj_step2_t<ST, false, false>(state, lam_next, lam_prev, acc, g, ga, r, ac, s);
+  };
+  if (storage == LBMHD_FP32)
+    go(std::true_type{});
+  else
+    go(std::false_type{});
+  return hipGetLastError();
+}
+
+bool adj_step2_pays(const Geom& g) {
+  const long long tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
+  return tiles_x * ((g.ny + 7) / 8) >= 512;
 }
 
 hipError_t launch_adj_step_kin(int storage, bool les, const void* state, const float* lam_next,

@@ -35,24 +35,51 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
-// One step src -> dst with the handle's closure.
-hipError_t launch_one_step(const lbmhd_t* h, const void* src, void* dst) {
-  // C_S = 0 makes the eddy closures the identity (tau = tau0): skip them.
+// The eddy closure in effect: 0 none, 1 Smagorinsky-MHD, 2 cross-helicity
+// (C_S = 0 makes the eddy closures the identity, tau = tau0: skip them).
+int eddy_of(const lbmhd_t* h) {
   const int les = h->p.les;
   const bool on = h->p.cs > 0.0 || h->p.cs_b > 0.0;
-  const int eddy = (les & 1) && on ? 1 : ((les & 4) && on ? 2 : 0);
-  if ((les & 2) || eddy == 2)
-    return lbk::launch_step_nb(h->p.storage, eddy, (les & 2) != 0, src, dst, h->geo, h->rates,
-                               h->p.delta, h->stream);
+  return (les & 1) && on ? 1 : ((les & 4) && on ? 2 : 0);
+}
+
+// Whether the update reads the neighbours' moments (kinetic closure, or the
+// cross-helicity closure's vorticity).
+bool reads_neighbours(const lbmhd_t* h) { return (h->p.les & 2) || eddy_of(h) == 2; }
+
+// One step src -> dst with the handle's closure.
+hipError_t launch_one_step(const lbmhd_t* h, const void* src, void* dst) {
+  const int eddy = eddy_of(h);
+  if (reads_neighbours(h))
+    return lbk::launch_step_nb(h->p.storage, eddy, (h->p.les & 2) != 0, src, dst, h->geo,
+                               h->rates, h->p.delta, h->stream);
   return lbk::launch_step(h->p.storage, eddy == 1, src, dst, h->geo, h->rates, h->stream);
+}
+
+// Two steps src -> dst in one pass (mid: also the state between them).
+hipError_t launch_two_steps(const lbmhd_t* h, const void* src, void* dst, void* mid) {
+  const int eddy = eddy_of(h);
+  if (reads_neighbours(h))
+    return lbk::launch_step_nb2(h->p.storage, eddy, (h->p.les & 2) != 0, src, dst, mid, h->geo,
+                                h->rates, h->p.delta, h->stream);
+  return lbk::launch_step2(h->p.storage, eddy == 1, src, dst, mid, h->geo, h->rates, h->stream);
 }
 
 // Steps that one kernel pass of lbmhd_step covers: 3 (FP32 only), 2 or 1.
 // Automatic: where the multi-step kernels fill the chip, triples for FP32
-// (measured faster than pairs from 1024^2 to 8192^2) and pairs for FP16.
+// (measured faster than pairs from 1024^2 to 8192^2) and pairs for FP16; the
+// closures that read the neighbours' moments take pairs with FP32 storage and
+// one of the two closures (at 4096^2, 1.6x single steps for the kinetic
+// closure, 1.4x for the cross-helicity one; with FP16 storage, and with both
+// closures together, pairs measured slower than single steps).
 int pass_steps(const lbmhd_t* h) {
   const int spp = h->p.steps_per_pass;
-  if (h->p.inplace || (h->p.les & 6) || spp == 1) return 1;
+  if (h->p.inplace || spp == 1) return 1;
+  if (reads_neighbours(h)) {
+    if (spp >= 2) return 2;
+    const bool both = (h->p.les & 2) && eddy_of(h) == 2;
+    return h->p.storage == LBMHD_FP32 && !both && lbk::step_nb2_pays(h->geo) ? 2 : 1;
+  }
   const bool fp32 = h->p.storage == LBMHD_FP32;
   if (spp == 3) return fp32 ? 3 : 2;
   if (spp == 2) return 2;
@@ -141,6 +168,47 @@ hipError_t adj_one(lbmhd_t* h, const void* x, const float* from, float* to, doub
                                     h->geoa, h->rates, d2, h->stream);
   return lbk::launch_adj_step(h->p.storage, smag, x, from, to, acc, h->geo, h->geoa, h->rates,
                               d2, h->stream);
+}
+
+// Whether reverse steps can go in pairs from one stored state (closures that
+// read no neighbours).
+bool adj_pairs_ok(const lbmhd_t* h) { return (h->p.les & 6) == 0; }
+
+// Two reverse steps (state x_t, lam_{t+2} -> lam_t); x_{t+1} is recomputed with
+// the forward collision lbmhd_step uses.
+hipError_t adj_two(lbmhd_t* h, const void* x, const float* from, float* to, double* acc) {
+  const double d2 = h->p.delta * h->p.delta;
+  return lbk::launch_adj_step2(h->p.storage, eddy_of(h) == 1, (h->p.les & 1) != 0, x, from, to,
+                               acc, h->geo, h->geoa, h->rates, d2, h->stream);
+}
+
+// Reverse sweep over n steps taken in pairs: state(t) is x_t for the even t
+// (and for t = n - 1 when n is odd, whose reverse step goes first, alone).
+// lam holds lam_n on entry and lam_0 on return.
+template <class StateAt>
+int sweep_pairs(lbmhd_t* h, int64_t n, StateAt state, float* lam, float* tmp, double* acc) {
+  // the last launch must write lam
+  float* from = lam;
+  float* to = tmp;
+  if ((n / 2 + n % 2) % 2) {
+    hipError_t e = lbk::launch_copy(lam, tmp, h->adj_lattice_bytes, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copy launch");
+    from = tmp;
+    to = lam;
+  }
+  int64_t t = n;
+  if (n % 2) {
+    hipError_t e = adj_one(h, state(n - 1), from, to, acc);
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
+    std::swap(from, to);
+    --t;
+  }
+  for (; t >= 2; t -= 2) {
+    hipError_t e = adj_two(h, state(t - 2), from, to, acc);
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
+    std::swap(from, to);
+  }
+  return LBMHD_OK;
 }
 
 // Run the diagnostics kernels on `lat` with the block partials at `part` and
@@ -402,8 +470,7 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   }
   if (ps >= 2) {
     for (; t + 2 <= nsteps; t += 2) {
-      hipError_t e = lbk::launch_step2(h->p.storage, les, h->lat[h->cur], h->lat[1 - h->cur],
-                                       nullptr, h->geo, h->rates, h->stream);
+      hipError_t e = launch_two_steps(h, h->lat[h->cur], h->lat[1 - h->cur], nullptr);
       if (e != hipSuccess) return hip_fail(h, e, "step launch");
       h->cur = 1 - h->cur;
       h->step += 2;
@@ -479,8 +546,7 @@ int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, in
   // slower than two single steps: 75 against 64 us per step at 2048^2)
   if (pass_steps(h) >= 2 && (h->p.storage == LBMHD_FP32 || h->p.steps_per_pass >= 2)) {
     for (; t + 2 <= n; t += 2) {
-      hipError_t e = lbk::launch_step2(h->p.storage, les, prev, out + stride, out, h->geo,
-                                       h->rates, h->stream);
+      hipError_t e = launch_two_steps(h, prev, out + stride, out);
       if (e != hipSuccess) return hip_fail(h, e, "step launch");
       prev = out + stride;
       out += 2 * stride;
@@ -488,6 +554,35 @@ int lbmhd_step_store(lbmhd_t* h, const void* src, void* store, size_t stride, in
   }
   for (; t < n; ++t) {
     hipError_t e = launch_one_step(h, prev, out);
+    if (e != hipSuccess) return hip_fail(h, e, "step launch");
+    prev = out;
+    out += stride;
+  }
+  return LBMHD_OK;
+}
+
+int lbmhd_step_store_pairs(lbmhd_t* h, const void* src, void* store, size_t stride,
+                           int64_t npairs) {
+  if (int rc = need_bound(h)) return rc;
+  if (npairs < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative pair count");
+  if (npairs == 0) return LBMHD_OK;
+  if (!src || !store || !aligned(src) || !aligned(store))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null or unaligned lattice");
+  if (stride < h->lattice_bytes || stride % kAlign != 0)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "stride below the lattice size or not 256-aligned");
+  if (size_t(npairs - 1) > (SIZE_MAX - h->lattice_bytes) / stride)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "store range overflows");
+  const size_t span = size_t(npairs - 1) * stride + h->lattice_bytes;
+  if (overlap(src, h->lattice_bytes, store, span))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "store overlaps src");
+  for (const void* b : {(const void*)h->lat[0], (const void*)h->lat[1], (const void*)h->ws})
+    if (b && overlap(store, span, b, b == h->ws ? h->workspace_bytes : h->lattice_bytes))
+      return fail(h, LBMHD_ERR_INVALID_ARG, "store overlaps a bound buffer");
+  if (int rc = natural(h, src)) return rc;
+  const char* prev = static_cast<const char*>(src);
+  char* out = static_cast<char*>(store);
+  for (int64_t k = 0; k < npairs; ++k) {
+    hipError_t e = launch_two_steps(h, prev, out, nullptr);
     if (e != hipSuccess) return hip_fail(h, e, "step launch");
     prev = out;
     out += stride;
@@ -696,6 +791,12 @@ int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t strid
   if (overlap(lam, h->adj_lattice_bytes, tmp, h->adj_lattice_bytes))
     return fail(h, LBMHD_ERR_INVALID_ARG, "tmp overlaps lam");
   if (int rc = natural(h, src)) return rc;
+  if (adj_pairs_ok(h) && lbk::adj_step2_pays(h->geo)) {
+    const char* base = static_cast<const char*>(store);
+    return sweep_pairs(h, n, [&](int64_t t) -> const void* {
+      return t == 0 ? src : base + size_t(t - 1) * stride;
+    }, lam, tmp, acc);
+  }
   // the last step must write lam: with an odd count the sweep starts from tmp
   float* from = lam;
   float* to = tmp;
@@ -712,6 +813,43 @@ int lbmhd_adj_sweep(lbmhd_t* h, const void* src, const void* store, size_t strid
     std::swap(from, to);
   }
   return LBMHD_OK;
+}
+
+int lbmhd_adj_step2(lbmhd_t* h, const void* state_t, const float* lam_next, float* lam_prev,
+                    double* acc) {
+  if (int rc = need_bound(h)) return rc;
+  if (!adj_pairs_ok(h))
+    return fail(h, LBMHD_ERR_UNSUPPORTED,
+                "paired reverse steps are provided for les = 0 and 1 only");
+  if (!state_t || !lam_next || !lam_prev || !acc)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
+  if (overlap(lam_next, h->adj_lattice_bytes, lam_prev, h->adj_lattice_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "lam_prev overlaps lam_next");
+  if (int rc = natural(h, state_t)) return rc;
+  hipError_t e = adj_two(h, state_t, lam_next, lam_prev, acc);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint step launch");
+  return LBMHD_OK;
+}
+
+int lbmhd_adj_sweep_pairs(lbmhd_t* h, const void* src, const void* store, size_t stride,
+                          int64_t n, float* lam, float* tmp, double* acc) {
+  if (int rc = need_bound(h)) return rc;
+  if (!adj_pairs_ok(h))
+    return fail(h, LBMHD_ERR_UNSUPPORTED,
+                "paired reverse steps are provided for les = 0 and 1 only");
+  if (n < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
+  if (n == 0) return LBMHD_OK;
+  if (!src || !lam || !tmp || !acc || (n > 2 && !store))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "null adjoint argument");
+  if (n > 2 && (stride < h->lattice_bytes || stride % kAlign != 0))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "stride below the lattice size or not 256-aligned");
+  if (overlap(lam, h->adj_lattice_bytes, tmp, h->adj_lattice_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "tmp overlaps lam");
+  if (int rc = natural(h, src)) return rc;
+  const char* base = static_cast<const char*>(store);
+  return sweep_pairs(h, n, [&](int64_t t) -> const void* {
+    return t == 0 ? src : base + size_t(t / 2 - 1) * stride;
+  }, lam, tmp, acc);
 }
 
 int lbmhd_adj_acc_total(lbmhd_t* h, const double* acc, double* out) {

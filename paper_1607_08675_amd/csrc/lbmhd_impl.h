@@ -80,6 +80,13 @@ hipError_t launch_unswap_aa(int storage, void* lat, const Geom& g, hipStream_t s
 // the eddy closure `eddy` (0 none, 1 Smagorinsky, 2 cross-helicity).
 hipError_t launch_step_nb(int storage, int eddy, bool kin, const void* src, void* dst,
                           const Geom& g, const Rates& r, double delta, hipStream_t s);
+// Two such steps in one pass: dst = C(S(C(S(src)))), equal to two
+// launch_step_nb calls bit for bit; with mid != nullptr the intermediate state
+// is stored there as well.  src, dst and mid must not overlap.
+hipError_t launch_step_nb2(int storage, int eddy, bool kin, const void* src, void* dst,
+                           void* mid, const Geom& g, const Rates& r, double delta, hipStream_t s);
+// Whether launch_step_nb2 beats two launch_step_nb calls on this lattice.
+bool step_nb2_pays(const Geom& g);
 // Equilibrium initialisation from FP64 fields.
 hipError_t launch_init(int storage, const double* rho, const double* ux, const double* uy,
                        const double* bx, const double* by, void* lat, const Geom& g,
@@ -119,6 +126,18 @@ hipError_t launch_adj_step(int storage, bool les, const void* state, const float
                            float* lam_prev, double* acc, const Geom& g, const Geom& ga,
                            const Rates& r, double delta2, hipStream_t s);
 int adj_step_blocks(const Geom& g);
+// Two reverse steps in one pass: lam_prev = R_t(R_{t+1}(lam_next)) from the
+// state x_t alone (x_{t+1} is recomputed on chip), equal to two
+// launch_adj_step calls with the stored x_{t+1} and x_t; the closure-constant
+// derivatives of both steps are added to acc (block slots b and
+// adj_step_blocks(g) + b).  Closures that read no neighbours: les_fwd, the
+// forward step takes the Smagorinsky-MHD collision (as launch_step's les);
+// les, the reverse steps differentiate it (les_fwd implies les).
+hipError_t launch_adj_step2(int storage, bool les_fwd, bool les, const void* state,
+                            const float* lam_next, float* lam_prev, double* acc, const Geom& g,
+                            const Geom& ga, const Rates& r, double delta2, hipStream_t s);
+// Whether launch_adj_step2 fills the chip on this lattice.
+bool adj_step2_pays(const Geom& g);
 // The same reverse step for the kinetic closure (les = 2, or 3 with the
 // Smagorinsky-MHD closure): two passes, gb = ten scratch planes in the
 // adjoint layout.

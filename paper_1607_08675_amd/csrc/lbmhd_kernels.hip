@@ -21,353 +21,10 @@
 #include <math.h>
 
 #include "lbmhd_impl.h"
-
+#include "lbmhd_step_dev.h"
 
 namespace lbk {
 namespace {
-
-// ------------------------------------------------------------ storage codec
-template <int ST>
-struct Codec;
-template <>
-struct Codec<LBMHD_FP32> {
-  using T = float;
-  __device__ static __forceinline__ float dec(float v) { return v; }
-  __device__ static __forceinline__ float enc(float v) { return v; }
-};
-template <>
-struct Codec<LBMHD_FP16> {
-  using T = _Float16;
-  // deviation = half * 2^-10; scaling by a power of two is exact, the only
-  // rounding is the RNE conversion of the FP32 value to half.  The empty asm
-  // statements pin the FP32 values on both sides.  Without them the compiler
-  // may fuse the conversion with the multiply-add that produced v
-  // (v_fma_mix*), rounding straight to half; and on decoding, it may fuse the
-  // exact scale of a decoded value into the add that consumes it, where
-  // a * b + dec(h) could otherwise have fused a * b, a choice that depends
-  // on the surrounding code.  Either way two kernels computing the same
-  // update would differ in rare last bits.
-  __device__ static __forceinline__ float dec(_Float16 v) {
-    float f = float(v) * 0x1p-10f;
-    asm("" : "+v"(f));
-    return f;
-  }
-  __device__ static __forceinline__ _Float16 enc(float v) {
-    asm("" : "+v"(v));
-    return _Float16(v * 0x1p10f);
-  }
-};
-
-// FP16 storage as the plain and Smagorinsky-MHD kernels hold it: the
-// collision runs on the stored values themselves, i.e. on deviations in units
-// of 2^-10 (collide<..., SC = true> folds the scale into its constants), so
-// decoding and encoding are bare conversions.  Every operand is then 2^10
-// (products of two: 2^20) times its unscaled counterpart, exactly, and the
-// stored halves are the same as with the scale applied around the collision.
-constexpr int kFP16S = 2;
-template <>
-struct Codec<kFP16S> {
-  using T = _Float16;
-  __device__ static __forceinline__ float dec(_Float16 v) {
-    float f = float(v);
-    asm("" : "+v"(f));
-    return f;
-  }
-  __device__ static __forceinline__ _Float16 enc(float v) {
-    asm("" : "+v"(v));
-    return _Float16(v);
-  }
-};
-
-// V consecutive stored elements moved as one vector access.
-template <typename T, int V>
-struct Vec;
-template <>
-struct Vec<float, 1> {
-  typedef float type;
-};
-template <>
-struct Vec<_Float16, 1> {
-  typedef _Float16 type;
-};
-template <>
-struct Vec<_Float16, 2> {
-  typedef _Float16 type __attribute__((ext_vector_type(2)));
-};
-
-// D2Q9 / D2Q5 lattice (Sec. 3 velocity lists) and the weights under which the
-// equilibria reproduce the printed moment tables.
-__device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__device__ constexpr int kMx[5] = {0, 1, 0, -1, 0};
-__device__ constexpr int kMy[5] = {0, 0, 1, 0, -1};
-__device__ constexpr double kW[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
-                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-__device__ constexpr double kWm[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
-// Element `off` of a plane: the plane base is uniform across the wavefront and
-// the byte offset fits 32 bits (checked at lbmhd_create), so the compiler emits
-// scalar-base + 32-bit-offset global accesses instead of 64-bit lane addresses.
-template <typename VT, typename T>
-__device__ __forceinline__ VT ld_plane(const T* __restrict__ base, unsigned off) {
-  return *reinterpret_cast<const VT*>(reinterpret_cast<const char*>(base) + off * unsigned(sizeof(T)));
-}
-template <typename VT, typename T>
-__device__ __forceinline__ void st_plane_nt(T* __restrict__ base, unsigned off, VT v) {
-  __builtin_nontemporal_store(
-      v, reinterpret_cast<VT*>(reinterpret_cast<char*>(base) + off * unsigned(sizeof(T))));
-}
-
-// velocity (c_x, c_y) of the population held by each of the 19 planes
-__device__ constexpr int kPlaneCx[kNPop] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 0,
-                                            1, 0, -1, 0, 0, 1,  0, -1, 0};
-__device__ constexpr int kPlaneCy[kNPop] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0,
-                                            0, 1, 0, -1, 0, 0, 1,  0, -1};
-constexpr int kStepThreads = 256;
-
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-// ------------------------------------------------------------ the collision
-// One collision in deviation variables.  f[9] = f_i - w_i and g[10] (g_x,
-// then g_y) in, post-collision values out.
-//  M = T f with the rows of eq. FluidTMatrix; the equilibrium moments of
-//  eq. KinMomentEq (w carries rho = 1, so T(f - w) differs from T f only in
-//  M_0 and M_8, by 1 and 5/3); f* = f - T^-1 diag(s) (M - M^eq) with
-//  T^-1 = T^T diag(1/9, 1/6, 1/6, 1/4, 1/4, 1/12, 1/12, 1/180, 1/20)
-//  expanded by hand; g* = g - s_m (g - g^eq) with g^eq of Sec. 3.
-//  With LES the shear rate and the magnetic rate follow the Smagorinsky-MHD
-//  closure: tau = (tau0 + sqrt(tau0^2 + 18 C_S Delta^2 Q / rho)) / 2 with
-//  Q = sqrt((M4 - M4eq)^2 + 4 (M3 - M3eq)^2) (|S| = 3 Q / (2 rho tau)), and
-//  tau_m = (tau_m0 + sqrt(tau_m0^2 + 36 C_S Delta^2 |A|)) / 2 with A the
-//  antisymmetric non-equilibrium first moment of g (j = -3 A / tau_m).
-//  With EDDY = 2 the cross-helicity closure (eqs. CHClosureV/B) sets them:
-//  nu_t = C_S Delta^2 |S^v : S^b|^(1/2), eta_t = C_S Delta^2 sgn(j w) |j w|^(1/2),
-//  with S^v from M3, M4 as above, S^b and j from the non-equilibrium
-//  first-moment tensor L_ab = sum_k C_ka g_kb ~ -(tau_m / 3) d_a B_b, and the
-//  vorticity w from the neighbours (NbTerms).  For traceless strains
-//  S^v : S^b = 9 P / (4 rho tau tau_m), P = n4 (L_xx - L_yy) + 2 n3 (L_xy + L_yx),
-//  and j w = -3 A w / tau_m, so sqrt(tau_m) and sqrt(tau) are the largest
-//  roots of t^3 - tau_m0 t - q_b and t^3 - tau0 t - q_v with
-//  q_b = -3 sqrt(3) C_S Delta^2 sgn(A w) |A w|^(1/2) and
-//  q_v = (9/2) C_S Delta^2 (|P| / (rho tau_m))^(1/2).  Where backscatter would
-//  make eta + eta_t negative, tau_m = 1/2.
-// Terms that need the neighbours: Delta^2 parts of the filtered equilibrium
-// moments (kinetic closure), added to M3^eq, M4^eq, M7^eq = M8^eq and to the
-// u x B term E of g^eq (N_y1^eq = E, N_x2^eq = -E); the vorticity w.
-struct NbTerms {
-  float m3, m4, m78, e, w;
-};
-
-// Largest root t of t^3 - p t - q = 0 (p > 0, sp = sqrt(p)), returned as
-// t^2 = p + d (2 sp + d), d = t - sp: Newton steps on the convex, increasing
-// h(d) = d (2 p + 3 sp d + d^2) - q from an upper bound of the root
-// (min(q / (2 p), q^(1/3)) for q > 0, 0 otherwise), so the iterates fall
-// monotonically.  For q >= 0 six steps reach FP32 resolution at every p
-// (measured to p = 20).  For q < 0 the caller clips first, so the root is at
-// least t* = max(sqrt(1/2), sqrt(p / 3)), a simple root for p < 3/2; but as p
-// nears 3/2 the clip nears the cubic's double root at sqrt(p / 3), where
-// Newton converges only linearly.  Six steps land within 1e-6 of the root
-// up to p = 5/4 (measured: 8.8e-4 at p = 1.4), and lbmhd_create refuses the
-// closure beyond.
-__device__ __forceinline__ float cubic_root_sq(float p, float sp, float q) {
-#pragma clang fp contract(off)
-  float d = q > 0.0f ? fminf(q * (0.5f * frcp(p)), cbrtf(q)) : 0.0f;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const float h = fmaf(d, fmaf(d, 3.0f * sp + d, 2.0f * p), -q);
-    const float hp = fmaf(d, fmaf(3.0f, d, 6.0f * sp), 2.0f * p);
-    d = fmaf(-h, frcp(hp), d);
-  }
-  return fmaf(d, 2.0f * sp + d, p);
-}
-
-// Every multiply-add of the collision is written out: fmaf where one
-// rounding is wanted, a separate product where two.  The compiler may not
-// contract anything else (fp contract off), so each kernel that inlines the
-// collision -- one or two sites per thread, halo columns, several steps per
-// pass, in place -- rounds it identically and their results agree bit for bit.
-// With SC the populations are in units of 2^-10 (scaled FP16 storage): each
-// product of two scaled quantities carries an extra 2^10, taken out by the
-// factor kS = 2^-10 folded into the constant of the operation that consumes it
-// (exact), so the result is 2^10 times the unscaled one bit for bit.
-template <int EDDY, bool KIN = false, bool SC = false>
-__device__ __forceinline__ void collide(float (&f)[9], float (&g)[10], const Rates& r,
-                                        const NbTerms& kc = NbTerms{0.f, 0.f, 0.f, 0.f, 0.f}) {
-#pragma clang fp contract(off)
-  static_assert(!SC || (!KIN && EDDY < 2), "scaled populations: plain and Smagorinsky only");
-  constexpr float kS = SC ? 0x1p-10f : 1.0f;
-  const float a13 = f[1] + f[3], a24 = f[2] + f[4];
-  const float d13 = f[1] - f[3], d24 = f[2] - f[4];
-  const float s57 = f[5] + f[7], s68 = f[6] + f[8];
-  const float d57 = f[5] - f[7], d68 = f[6] - f[8];
-  const float dd = s57 + s68;
-  const float sa = a13 + a24;
-  const float f0dd = f[0] + dd;
-  const float drho = f0dd + sa;
-  const float rho = SC ? fmaf(kS, drho, 1.0f) : 1.0f + drho;
-  const float jx = (d13 + d57) - d68;
-  const float jy = (d24 + d57) + d68;
-  const float M3 = s57 - s68;
-  const float M4 = a13 - a24;
-  const float M5 = fmaf(-3.0f, d13, jx);
-  const float M6 = fmaf(-3.0f, d24, jy);
-  const float M7 = fmaf(-5.0f, sa, 4.0f * f0dd);   // 4 f0 - 5 (a13 + a24) + 4 dd
-  const float M8 = fmaf(4.0f, f[0], -dd);
-
-  const float ir = frcp(rho);
-  const float ux = jx * ir, uy = jy * ir;
-  const float Bx = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
-  const float By = ((g[5] + g[6]) + (g[7] + g[8])) + g[9];
-  const float jyuy = jy * uy;
-  const float jj = fmaf(jx, ux, jyuy);                       // |j|^2 / rho
-  const float Byy = By * By;
-  float n3 = fmaf(-kS, fmaf(-Bx, By, jx * uy), M3);          // M3 - (jx uy - Bx By)
-  float n4 = fmaf(-kS, fmaf(jx, ux, -jyuy) - fmaf(Bx, Bx, -Byy), M4);
-  const float n5 = M5 + jx;
-  const float n6 = M6 + jy;
-  float n7 = fmaf(3.0f * kS, jj, M7);
-  float n8 = fmaf(3.0f * kS, jj, fmaf(-5.0f / 3.0f, drho, M8));
-  float E = fmaf(ux, By, -(uy * Bx));                          // scaled: 2^20 E
-  if (KIN) {
-    // relax toward the filtered equilibria; with the Smagorinsky closure as
-    // well, Q and A below are then measured from the filtered equilibria
-    n3 -= kc.m3;
-    n4 -= kc.m4;
-    n7 -= kc.m78;
-    n8 -= kc.m78;
-    E += kc.e;
-  }
-
-  float s3q, sm;
-  if (EDDY == 1) {
-    // s3q = 1 / (4 tau) = 1 / (2 tau0 + sqrt(4 tau0^2 + 4 cf Q / rho)) with
-    // the powers of two folded into the constants (exact)
-    const float Q = fsqrt(fmaf(n4, n4, 4.0f * (n3 * n3)));
-    s3q = frcp(r.tau0d + fsqrt(fmaf((r.cf4 * kS) * Q, ir, r.tau0dsq)));
-    const float A = fmaf(-2.0f * kS, E, (g[6] - g[8]) - (g[2] - g[4]));
-    // sm = 1 / tau_m = 1 / (tau_m0 / 2 + sqrt(tau_m0^2 / 4 + cm |A| / 4))
-    sm = frcp(r.taum0h + fsqrt(fmaf(r.cmq * kS, fabsf(A), r.taum0hsq)));
-  } else if (EDDY == 2) {
-    const float lxy = g[6] - g[8], lyx = g[2] - g[4];
-    const float P = fmaf(n4, (g[1] - g[3]) - (g[7] - g[9]), 2.0f * (n3 * (lxy + lyx)));
-    const float X = fmaf(-2.0f, E, lxy - lyx) * kc.w;
-    const float qb = -r.kb * copysignf(fsqrt(fabsf(X)), X);
-    const float taum = qb < r.qclip ? 0.5f : fmaxf(0.5f, cubic_root_sq(r.taum0, r.staum0, qb));
-    const float qv = r.kv * fsqrt(fabsf(P) * ir * frcp(taum));
-    s3q = 0.25f * frcp(cubic_root_sq(r.tau0, r.stau0, qv));
-    sm = frcp(taum);
-  } else {
-    s3q = r.s3q;
-    sm = r.sm;
-  }
-  const float r3 = s3q * n3, r4 = s3q * n4;
-  const float r5 = r.s5q * n5, r6 = r.s5q * n6;
-  const float r7 = r.s7q * n7, r8 = r.s8q * n8;
-  const float c58 = fmaf(4.0f, r7, -r8);
-  f[0] = fmaf(-4.0f, r7 + r8, f[0]);
-  f[1] -= fmaf(-5.0f, r7, fmaf(-2.0f, r5, r4));
-  f[2] -= fmaf(-5.0f, r7, fmaf(-2.0f, r6, -r4));
-  f[3] -= fmaf(-5.0f, r7, fmaf(2.0f, r5, r4));
-  f[4] -= fmaf(-5.0f, r7, fmaf(2.0f, r6, -r4));
-  const float p56 = r5 + r6, m56 = r5 - r6;
-  f[5] -= (r3 + p56) + c58;
-  f[6] -= c58 - (r3 + m56);
-  f[7] -= (r3 - p56) + c58;
-  f[8] -= (m56 - r3) + c58;
-
-  // g^eq of the four moving directions is B/6 +- E/2; the rest direction takes
-  // the remainder B - 4 (B/6) so that sum_k g^eq = B holds in FP32 as well
-  // (6 * fl(1/6) != 1 would otherwise feed a systematic drift into B).
-  const float bx6 = Bx * (1.0f / 6.0f), by6 = By * (1.0f / 6.0f);
-  const float msm = -sm;
-  g[0] = fmaf(msm, g[0] - fmaf(-4.0f, bx6, Bx), g[0]);
-  g[1] = fmaf(msm, g[1] - bx6, g[1]);
-  g[2] = fmaf(msm, g[2] - fmaf(-0.5f * kS, E, bx6), g[2]);
-  g[3] = fmaf(msm, g[3] - bx6, g[3]);
-  g[4] = fmaf(msm, g[4] - fmaf(0.5f * kS, E, bx6), g[4]);
-  g[5] = fmaf(msm, g[5] - fmaf(-4.0f, by6, By), g[5]);
-  g[6] = fmaf(msm, g[6] - fmaf(0.5f * kS, E, by6), g[6]);
-  g[7] = fmaf(msm, g[7] - by6, g[7]);
-  g[8] = fmaf(msm, g[8] - fmaf(-0.5f * kS, E, by6), g[8]);
-  g[9] = fmaf(msm, g[9] - by6, g[9]);
-}
-
-// --------------------------------------------------------------- the step
-// Pre-collision values of the V consecutive sites x .. x + V - 1 of one row:
-// pre_q(x) = src_q(x - c_q), periodic.  xl and xr are the columns left of x
-// and right of x + V - 1 (wrapped); row[c_y + 1] is the source row of a plane
-// with velocity c_y.  A plane that streams along x is read as the aligned
-// vector of the sites plus one edge element.  V > 1 requires nx % V == 0.
-template <int ST, int V>
-__device__ __forceinline__ void gather_row(const typename Codec<ST>::T* __restrict__ src,
-                                           long long P, int x, int xl, int xr,
-                                           const unsigned (&row)[3], float (&v)[kNPop][V]) {
-  using C = Codec<ST>;
-  using T = typename C::T;
-  using VT = typename Vec<T, V>::type;
-#pragma unroll
-  for (int q = 0; q < kNPop; ++q) {
-    const T* __restrict__ base = src + q * P;
-    const unsigned r = row[kPlaneCy[q] + 1];
-    if (V == 1 || kPlaneCx[q] == 0) {
-      const int xs = kPlaneCx[q] == 0 ? x : (kPlaneCx[q] == 1 ? xl : xr);
-      const VT a = ld_plane<VT>(base, r + unsigned(xs));
-      if constexpr (V == 1) {
-        v[q][0] = C::dec(a);
-      } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j) v[q][j] = C::dec(a[j]);
-      }
-    } else if constexpr (V > 1) {
-      const VT a = ld_plane<VT>(base, r + unsigned(x));
-      const float e = C::dec(ld_plane<T>(base, r + unsigned(kPlaneCx[q] == 1 ? xl : xr)));
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        if (kPlaneCx[q] == 1)
-          v[q][j] = j == 0 ? e : C::dec(a[j > 0 ? j - 1 : 0]);
-        else
-          v[q][j] = j == V - 1 ? e : C::dec(a[j < V - 1 ? j + 1 : 0]);
-      }
-    }
-  }
-}
-
-// One collision of each of the V sites in v (planes in the storage order).
-template <int V, bool LES, bool SC = false>
-__device__ __forceinline__ void collide_sites(float (&v)[kNPop][V], const Rates& rt) {
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    float f[9], g[10];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = v[i][j];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) g[k] = v[9 + k][j];
-    collide<LES ? 1 : 0, false, SC>(f, g, rt);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) v[i][j] = f[i];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) v[9 + k][j] = g[k];
-  }
-}
-
-// Encode and store the V sites of v at element `off` of every plane.
-template <int ST, int V>
-__device__ __forceinline__ void store_row(typename Codec<ST>::T* __restrict__ dst, long long P,
-                                          unsigned off, const float (&v)[kNPop][V]) {
-  using C = Codec<ST>;
-  using VT = typename Vec<typename C::T, V>::type;
-#pragma unroll
-  for (int q = 0; q < kNPop; ++q) {
-    VT w;
-    if constexpr (V == 1) {
-      w = C::enc(v[q][0]);
-    } else {
-#pragma unroll
-      for (int j = 0; j < V; ++j) w[j] = C::enc(v[q][j]);
-    }
-    st_plane_nt<VT>(dst + q * P, off, w);
-  }
-}
 
 // dst(x) = C(pre(x)),  pre_i(x) = src_i(x - c_i) (periodic pull; Sec. 1.2
 // streaming written as a gather).  Thread t of block b updates sites
@@ -409,9 +66,9 @@ __global__ __launch_bounds__(kStepThreads) void k_step(
 // every read before the slot is written again.  Planes with c_x = 0 stay in
 // the thread's registers for the same number of passes.  The intermediate
 // values pass through the storage codec, so that the result equals two
-// k_step launches (FP32 bit for bit; with FP16 and V = 2 the halo sites,
-// computed by a separate single-site copy of the collision, round a few
-// values in ten million differently).  HBM bytes per site for two steps: one
+// k_step launches bit for bit (the collision spells out its fused
+// multiply-adds, so the halo sites' single-site copy of it rounds as the
+// paired one does).  HBM bytes per site for two steps: one
 // read and one write of the lattice, plus halo re-reads of 2 / rows of the
 // rows and 4 / W of the columns.
 constexpr int kT2Threads = 256;
@@ -419,28 +76,6 @@ constexpr int kT2Threads = 256;
 constexpr int kT2SlotsA = 4, kT2SlotsB = 3, kT2SlotsC = 2;
 constexpr int kT2Slots = 2 * kT2SlotsA + 6 * kT2SlotsB + 2 * kT2SlotsC;
 constexpr int kT2BaseB = 2 * kT2SlotsA, kT2BaseC = kT2BaseB + 6 * kT2SlotsB;
-// LDS group of each plane with c_x != 0 (0: c_y = +1, 1: c_y = 0, 2: c_y = -1)
-// and its index in the group; -1 for the register-held planes (c_x = 0).
-__device__ constexpr int kT2Group[kNPop] = {-1, 1, -1, 1, -1, 0, 0, 2, 2, -1,
-                                            1, -1, 1, -1, -1, 1, -1, 1, -1};
-__device__ constexpr int kT2Index[kNPop] = {0, 0, 0, 1, 0, 0, 1, 0, 1, 0,
-                                            2, 0, 3, 0, 0, 4, 0, 5, 0};
-// index of a c_x = 0 plane among the three of its c_y: {0, 9, 14} (c_y = 0),
-// {2, 11, 16} (c_y = +1), {4, 13, 18} (c_y = -1)
-__device__ constexpr int kT2Reg[kNPop] = {0, -1, 0, -1, 0, -1, -1, -1, -1, 1,
-                                          -1, 1, -1, 1, 2, -1, 2, -1, 2};
-
-// Row offsets of the gather for row r (-1 <= r <= ny, wrapped): the source
-// row of a plane with velocity c_y is r - c_y, indexed by c_y + 1.
-__device__ __forceinline__ void t2_rows(int r, const Geom& geo, unsigned (&row)[3]) {
-  r = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
-  const int rm = r == 0 ? geo.ny - 1 : r - 1;
-  const int rp = r == geo.ny - 1 ? 0 : r + 1;
-  row[0] = unsigned(rp) * geo.pitch;
-  row[1] = unsigned(r) * geo.pitch;
-  row[2] = unsigned(rm) * geo.pitch;
-}
-
 // MID: also store the intermediate state (after the first update) to mid;
 // each block writes the rows and columns it owns, so every site once.
 template <int ST, int V, bool LES, bool MID>
@@ -598,16 +233,6 @@ __global__ __launch_bounds__(kT2Threads) void k_step2(
 // the next pass and a level is 10 plane-rows.  HBM bytes per site for three
 // steps: one read and one write of the lattice, plus halo re-reads of
 // 4 / rows of the rows and 8 / kT3Cols of the columns.
-constexpr int kT3Cols = 256;
-constexpr int kT3Threads = kT3Cols + 64;
-constexpr int kT3Rows = 10;   // planes with c_x != 0
-
-// LDS row of plane q (c_x != 0): the c_y = +1 planes, then c_y = 0, then c_y = -1.
-__device__ __forceinline__ int t3_row(int q) {
-  const int g = kT2Group[q], i = kT2Index[q];
-  return g == 0 ? i : (g == 1 ? 2 + i : 8 + i);
-}
-
 // MID: also store the states after the first and the second update to mid1
 // and mid2 (each block the rows and columns it owns, so every site once).
 template <bool LES, bool MID>
@@ -827,6 +452,60 @@ __device__ __forceinline__ void site_moments(const float (&p)[kNPop], float (&m)
   m[4] = (p[14] + p[15]) + (p[16] + p[17]) + p[18];
 }
 
+// Terms of the closures with lattice gradients at one site, from the
+// pre-collision rho - 1, j (and B for KIN) of the site and its eight
+// neighbours: rows rm (y - 1), r0 (y) and rp (y + 1) of a moment buffer whose
+// fields lie `fs` floats apart, the site at column c.  Isotropic D2Q9
+// gradient: d_x = (E - W)/3 + (NE - NW + SE - SW)/12, d_y likewise.
+// h_X = grad X - X grad(rho) / rho (= rho grad(X / rho)); ratio terms
+// (X Y / rho) of the kinetic closure use it, product terms (B B) the plain
+// gradients:
+//   R(X, Y) = Delta^2 / (12 rho) h_X . h_Y,  S(X, Y) = Delta^2 / 12 grad X . grad Y;
+// the vorticity is d_x u_y - d_y u_x = (h_jy,x - h_jx,y) / rho.  Every
+// multiply-add is written out (no other contraction), so each kernel that
+// evaluates the terms rounds them identically.
+template <int EDDY, bool KIN>
+__device__ __forceinline__ NbTerms nb_terms(const float* __restrict__ rm,
+                                            const float* __restrict__ r0,
+                                            const float* __restrict__ rp, int fs, int c,
+                                            float c12) {
+#pragma clang fp contract(off)
+  constexpr int NF = KIN ? 5 : 3;
+  float gx[NF], gy[NF], v[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int o = k * fs + c;
+    const float e = r0[o + 1], w = r0[o - 1];
+    const float nn = rp[o], ss = rm[o];
+    const float ne = rp[o + 1], nw = rp[o - 1];
+    const float se = rm[o + 1], sw = rm[o - 1];
+    gx[k] = fmaf(1.0f / 3.0f, e - w, (1.0f / 12.0f) * ((ne - nw) + (se - sw)));
+    gy[k] = fmaf(1.0f / 3.0f, nn - ss, (1.0f / 12.0f) * ((ne + nw) - (se + sw)));
+    v[k] = r0[o];
+  }
+  const float ir = frcp(1.0f + v[0]);
+  const float grx = gx[0] * ir, gry = gy[0] * ir;
+  float hx[NF - 1], hy[NF - 1];
+#pragma unroll
+  for (int k = 0; k < NF - 1; ++k) {
+    hx[k] = fmaf(-v[k + 1], grx, gx[k + 1]);
+    hy[k] = fmaf(-v[k + 1], gry, gy[k + 1]);
+  }
+  NbTerms kc{0.f, 0.f, 0.f, 0.f, 0.f};
+  if constexpr (KIN) {
+    const float cr = c12 * ir;
+    const float jxjx = cr * fmaf(hx[0], hx[0], hy[0] * hy[0]);
+    const float jyjy = cr * fmaf(hx[1], hx[1], hy[1] * hy[1]);
+    kc.m3 = fmaf(cr, fmaf(hx[0], hx[1], hy[0] * hy[1]), -(c12 * fmaf(gx[3], gx[4], gy[3] * gy[4])));
+    kc.m4 = fmaf(-c12, fmaf(gx[3], gx[3], gy[3] * gy[3]) - fmaf(gx[4], gx[4], gy[4] * gy[4]),
+                 jxjx - jyjy);
+    kc.m78 = -3.0f * (jxjx + jyjy);
+    kc.e = cr * (fmaf(hx[0], hx[3], hy[0] * hy[3]) - fmaf(hx[1], hx[2], hy[1] * hy[2]));
+  }
+  if constexpr (EDDY == 2) kc.w = (hx[1] - hy[0]) * ir;
+  return kc;
+}
+
 template <int ST, int EDDY, bool KIN>
 __global__ __launch_bounds__(kKinThreads) void k_step_nb(
     const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
@@ -884,44 +563,8 @@ __global__ __launch_bounds__(kKinThreads) void k_step_nb(
     if (y + 2 <= y1) issue(y + 2);
     __syncthreads();
     if (active) {
-      const int c = tx + 1;
-      // isotropic D2Q9 gradient: d_x = (E - W)/3 + (NE - NW + SE - SW)/12, d_y likewise
-      float gx[NF], gy[NF], v[NF];
-#pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        const float e = mac[s0][k][c + 1], w = mac[s0][k][c - 1];
-        const float nn = mac[sp][k][c], ss = mac[sm][k][c];
-        const float ne = mac[sp][k][c + 1], nw = mac[sp][k][c - 1];
-        const float se = mac[sm][k][c + 1], sw = mac[sm][k][c - 1];
-        gx[k] = (1.0f / 3.0f) * (e - w) + (1.0f / 12.0f) * ((ne - nw) + (se - sw));
-        gy[k] = (1.0f / 3.0f) * (nn - ss) + (1.0f / 12.0f) * ((ne + nw) - (se + sw));
-        v[k] = mac[s0][k][c];
-      }
-      // h_X = grad X - X grad(rho) / rho (= rho grad(X / rho)).  Ratio terms
-      // (X Y / rho) of the kinetic closure use it, product terms (B B) the
-      // plain gradients:
-      //   R(X, Y) = Delta^2 / (12 rho) h_X . h_Y,  S(X, Y) = Delta^2 / 12 grad X . grad Y;
-      // the vorticity is d_x u_y - d_y u_x = (h_jy,x - h_jx,y) / rho.
-      const float ir = frcp(1.0f + v[0]);
-      const float grx = gx[0] * ir, gry = gy[0] * ir;
-      float hx[NF - 1], hy[NF - 1];
-#pragma unroll
-      for (int k = 0; k < NF - 1; ++k) {
-        hx[k] = gx[k + 1] - v[k + 1] * grx;
-        hy[k] = gy[k + 1] - v[k + 1] * gry;
-      }
-      NbTerms kc{0.f, 0.f, 0.f, 0.f, 0.f};
-      if constexpr (KIN) {
-        const float cr = c12 * ir;
-        const float jxjx = cr * (hx[0] * hx[0] + hy[0] * hy[0]);
-        const float jyjy = cr * (hx[1] * hx[1] + hy[1] * hy[1]);
-        kc.m3 = cr * (hx[0] * hx[1] + hy[0] * hy[1]) - c12 * (gx[3] * gx[4] + gy[3] * gy[4]);
-        kc.m4 = (jxjx - jyjy) -
-                c12 * ((gx[3] * gx[3] + gy[3] * gy[3]) - (gx[4] * gx[4] + gy[4] * gy[4]));
-        kc.m78 = -3.0f * (jxjx + jyjy);
-        kc.e = cr * ((hx[0] * hx[3] + hy[0] * hy[3]) - (hx[1] * hx[2] + hy[1] * hy[2]));
-      }
-      if constexpr (EDDY == 2) kc.w = (hx[1] - hy[0]) * ir;
+      const NbTerms kc =
+          nb_terms<EDDY, KIN>(&mac[sm][0][0], &mac[s0][0][0], &mac[sp][0][0], kKinCols, tx + 1, c12);
       float f[9], g[10];
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = cur[i];
@@ -937,6 +580,214 @@ __global__ __launch_bounds__(kKinThreads) void k_step_nb(
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kNPop; ++q) cur[q] = nxt[q];
+  }
+}
+
+// ------------------------ two steps per pass with lattice gradients
+// dst = (C S)^2 src for the closures that need the neighbours' moments
+// (kinetic, cross-helicity).  The second update at a site needs the first
+// update's output two sites out (its own gather reaches one site, the
+// gradients of the gathered moments one more), and the first update needs the
+// input three sites out for its moments and four for their gathers.  A block
+// owns a tile of kNb2Cols columns and a strip of `rows` output rows and walks
+// upward; pass t, with a = y0 - 3 + t:
+//   1. gathers row a from HBM (columns x0 - 3 .. x0 + wt + 2) and writes its
+//      moments to ring m1 (3 rows);
+//   2. first update of row a - 1 (columns x0 - 2 .. x0 + wt + 1), with the
+//      gradients of rows a - 2 .. a of m1; the planes moving along x go to the
+//      neighbouring columns through one LDS row per plane (y1), the others
+//      stay in the thread's registers;
+//   3. second gather of row a - 2 (columns x0 - 1 .. x0 + wt): each thread
+//      reads the y1 values it needs right after the barrier that publishes
+//      them and carries them on in registers (c_y = 0 planes one pass, c_y = +1
+//      two), as the three-step kernel does; their moments go to ring m2;
+//   4. second update of row a - 3 (the tile's own columns), with the
+//      gradients of rows a - 4 .. a - 2 of m2, stored.
+// Three barriers per pass, between the stages.  A fifth wave owns the six
+// halo columns.  The first update's output passes through the storage codec,
+// so the result equals two k_step_nb launches bit for bit.  MID: also store
+// the intermediate state (each block the rows and columns it owns).  HBM
+// bytes per site for two steps: one read and one write of the lattice, plus
+// halo re-reads of 6 / rows of the rows and 6 / kNb2Cols of the columns.
+constexpr int kNb2Cols = 256;
+constexpr int kNb2Threads = kNb2Cols + 64;
+
+template <int ST, int EDDY, bool KIN, bool MID>
+__global__ __launch_bounds__(kNb2Threads) void k_step_nb2(
+    const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
+    typename Codec<ST>::T* __restrict__ mid, Geom geo, Rates rt, float c12, int tiles_x,
+    int rows, bool xcd_map) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  constexpr int NF = KIN ? 5 : 3;        // staged fields: rho - 1, j (, B)
+  constexpr int W = kNb2Cols;
+  __shared__ float m1[3][NF][W + 6];     // LDS column lc + 3
+  __shared__ T y1[kT3Rows][W + 4];       // LDS column lc + 2
+  __shared__ float m2[3][NF][W + 2];     // LDS column lc + 1
+  const int nx = geo.nx, ny = geo.ny;
+  const long long P = geo.plane;
+  int tile, strip;
+  if (xcd_map) {   // whole strips per XCD, as in k_step2
+    const int k = int(blockIdx.x) >> 3;
+    strip = (int(blockIdx.x) & 7) + 8 * (k / tiles_x);
+    tile = k % tiles_x;
+  } else {
+    tile = int(blockIdx.x) % tiles_x;
+    strip = int(blockIdx.x) / tiles_x;
+  }
+  const int x0 = tile * W, y0 = strip * rows;
+  const int wt = min(W, nx - x0), h = min(rows, ny - y0);
+  // the thread's column: its own (threads 0 .. W - 1) or a halo column
+  // (lanes 0 .. 5 of the fifth wave: x0 - 3 .. x0 - 1, x0 + wt .. x0 + wt + 2)
+  const int tid = int(threadIdx.x);
+  int lc = tid;
+  bool has = tid < wt;
+  if (tid >= W) {
+    const int k = tid - W;
+    has = k < 6;
+    lc = k < 3 ? k - 3 : wt + (k - 3);
+  }
+  const bool up2 = has && lc >= -2 && lc <= wt + 1;   // takes the first update
+  const bool up3 = has && lc >= -1 && lc <= wt;       // takes the second gather
+  const bool up4 = has && lc >= 0 && lc < wt;         // takes the second update
+  // y1 column read for the second gather: lc + 2 - c_x (a fixed in-bounds
+  // column for the threads that take no second gather)
+  const int c3 = up3 ? lc + 2 : 2;
+  int xc = (x0 + lc) % nx;
+  if (xc < 0) xc += nx;
+  const int xl = xc == 0 ? nx - 1 : xc - 1;
+  const int xr = xc == nx - 1 ? 0 : xc + 1;
+
+  float p1c[kNPop], p2c[kNPop];        // gathers of the previous pass (rows a - 1, a - 3)
+  float z1c[3], z1u1[3], z1u2[3];      // y1, planes with c_x = 0, by c_y and pass
+  float x1c[6], x1u1[2], x1u2[2];      // y1, planes with c_x != 0, taken from lc - c_x
+#pragma unroll
+  for (int q = 0; q < kNPop; ++q) p1c[q] = p2c[q] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) z1c[k] = z1u1[k] = z1u2[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) x1c[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) x1u1[k] = x1u2[k] = 0.0f;
+  for (int t = 0; t < h + 6; ++t) {
+    const int s0 = t % 3;                         // ring slot of this pass
+    const int s1 = s0 == 0 ? 2 : s0 - 1;          // (t - 1) mod 3
+    const int s2 = s1 == 0 ? 2 : s1 - 1;          // (t - 2) mod 3
+    // 1. gather row a = y0 - 3 + t and stage its moments
+    float p1n[kNPop];
+    if (has) {
+      // rows y0 - 3 .. y0 + h + 2: more than one period on a lattice two rows high
+      int a = (y0 - 3 + t) % ny;
+      if (a < 0) a += ny;
+      unsigned row[3];
+      t2_rows(a, geo, row);
+      float v[kNPop][1];
+      gather_row<ST, 1>(src, P, xc, xl, xr, row, v);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) p1n[q] = v[q][0];
+      float m[5];
+      site_moments(p1n, m);
+#pragma unroll
+      for (int k = 0; k < NF; ++k) m1[s0][k][lc + 3] = m[k];
+    }
+    __syncthreads();
+    // 2. first update of row a - 1 (from pass 2 on)
+    float n2c[3], n2u[3], n2d[3];
+    const bool do2 = up2 && t >= 2;
+    if (do2) {
+      const NbTerms kc =
+          nb_terms<EDDY, KIN>(&m1[s2][0][0], &m1[s1][0][0], &m1[s0][0][0], W + 6, lc + 3, c12);
+      float f[9], g[10];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = p1c[i];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) g[k] = p1c[9 + k];
+      collide<EDDY, KIN>(f, g, rt, kc);
+      float v[kNPop];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) v[i] = f[i];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) v[9 + k] = g[k];
+      const int r1 = y0 - 4 + t;                  // row a - 1
+      if (MID && lc >= 0 && lc < wt && r1 >= y0 && r1 < y0 + h) {
+        const unsigned od = unsigned(r1) * geo.pitch + unsigned(xc);
+#pragma unroll
+        for (int q = 0; q < kNPop; ++q) st_plane_nt<T>(mid + q * P, od, C::enc(v[q]));
+      }
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const T e = C::enc(v[q]);
+        const int k = kT2Reg[q];
+        if (kT2Group[q] >= 0)
+          y1[t3_row(q)][lc + 2] = e;
+        else if (kPlaneCy[q] == 0)
+          n2c[k] = C::dec(e);
+        else if (kPlaneCy[q] == 1)
+          n2u[k] = C::dec(e);
+        else
+          n2d[k] = C::dec(e);
+      }
+    }
+    __syncthreads();
+    // 3. second gather of row a - 2 (from pass 4 on); the y1 row of this pass
+    // is read in every pass, before the next one overwrites it
+    float p2n[kNPop];
+    const bool do3 = up3 && t >= 4;
+    {
+      float e[kT3Rows];
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q)
+        if (kT2Group[q] >= 0) e[t3_row(q)] = C::dec(y1[t3_row(q)][c3 - kPlaneCx[q]]);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) {
+        const int g = kT2Group[q], i = kT2Index[q], k = kT2Reg[q];
+        if (g >= 0)
+          p2n[q] = g == 0 ? x1u2[i] : (g == 1 ? x1c[i] : e[t3_row(q)]);
+        else
+          p2n[q] = kPlaneCy[q] == 0 ? z1c[k] : (kPlaneCy[q] == 1 ? z1u2[k] : n2d[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        x1u2[i] = x1u1[i];
+        x1u1[i] = e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) x1c[i] = e[2 + i];
+      if (do3) {
+        float m[5];
+        site_moments(p2n, m);
+#pragma unroll
+        for (int k = 0; k < NF; ++k) m2[s0][k][lc + 1] = m[k];
+      }
+    }
+    __syncthreads();
+    // 4. second update of row a - 3 (from pass 6 on), stored
+    if (up4 && t >= 6) {
+      const NbTerms kc =
+          nb_terms<EDDY, KIN>(&m2[s2][0][0], &m2[s1][0][0], &m2[s0][0][0], W + 2, lc + 1, c12);
+      float f[9], g[10];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = p2c[i];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) g[k] = p2c[9 + k];
+      collide<EDDY, KIN>(f, g, rt, kc);
+      const unsigned od = unsigned(y0 - 6 + t) * geo.pitch + unsigned(xc);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st_plane_nt<T>(dst + i * P, od, C::enc(f[i]));
+#pragma unroll
+      for (int k = 0; k < 10; ++k) st_plane_nt<T>(dst + (9 + k) * P, od, C::enc(g[k]));
+    }
+#pragma unroll
+    for (int q = 0; q < kNPop; ++q) {
+      p1c[q] = has ? p1n[q] : 0.0f;
+      p2c[q] = do3 ? p2n[q] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      z1u2[k] = z1u1[k];
+      z1u1[k] = do2 ? n2u[k] : 0.0f;
+      z1c[k] = do2 ? n2c[k] : 0.0f;
+    }
   }
 }
 
@@ -1531,6 +1382,65 @@ hipError_t launch_step_nb_s(int eddy, bool kin, const void* src, void* dst, cons
   else
     return hipErrorInvalidValue;   // no neighbour terms: the plain step applies
   return hipGetLastError();
+}
+
+// Strip height of the two-step kernel with lattice gradients (halo overhead
+// 6 / rows): as for the three-step kernel, about 512 blocks up to 128-row
+// strips, 32-row strips beyond.
+static int step_nb2_rows(const Geom& g) {
+  const long long tiles_x = (g.nx + kNb2Cols - 1) / kNb2Cols;
+  const long long rows = tiles_x * g.ny / 512;
+  return int(rows < 8 ? 8 : (rows > 128 ? 32 : rows));
+}
+
+template <int ST, int EDDY, bool KIN>
+void launch_step_nb2_t(const void* src, void* dst, void* mid, const Geom& g, const Rates& r,
+                       float c12, hipStream_t s) {
+  using T = typename Codec<ST>::T;
+  const int rows = step_nb2_rows(g);
+  const int tiles_x = (g.nx + kNb2Cols - 1) / kNb2Cols;
+  const int strips = (g.ny + rows - 1) / rows;
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kNb2Threads);
+  const bool xcd_map = strips % 8 == 0;
+  auto* a = static_cast<const T*>(src);
+  auto* b = static_cast<T*>(dst);
+  auto* m = static_cast<T*>(mid);
+  if (m)
+    hipLaunchKernelGGL((k_step_nb2<ST, EDDY, KIN, true>), grid, block, 0, s, a, b, m, g, r, c12,
+                       tiles_x, rows, xcd_map);
+  else
+    hipLaunchKernelGGL((k_step_nb2<ST, EDDY, KIN, false>), grid, block, 0, s, a, b, m, g, r, c12,
+                       tiles_x, rows, xcd_map);
+}
+
+template <int ST>
+hipError_t launch_step_nb2_s(int eddy, bool kin, const void* src, void* dst, void* mid,
+                             const Geom& g, const Rates& r, float c12, hipStream_t s) {
+  if (kin && eddy == 0)
+    launch_step_nb2_t<ST, 0, true>(src, dst, mid, g, r, c12, s);
+  else if (kin && eddy == 1)
+    launch_step_nb2_t<ST, 1, true>(src, dst, mid, g, r, c12, s);
+  else if (kin && eddy == 2)
+    launch_step_nb2_t<ST, 2, true>(src, dst, mid, g, r, c12, s);
+  else if (!kin && eddy == 2)
+    launch_step_nb2_t<ST, 2, false>(src, dst, mid, g, r, c12, s);
+  else
+    return hipErrorInvalidValue;   // no neighbour terms: the plain kernels apply
+  return hipGetLastError();
+}
+
+hipError_t launch_step_nb2(int storage, int eddy, bool kin, const void* src, void* dst,
+                           void* mid, const Geom& g, const Rates& r, double delta,
+                           hipStream_t s) {
+  const float c12 = float(delta * delta / 12.0);
+  if (storage == LBMHD_FP32)
+    return launch_step_nb2_s<LBMHD_FP32>(eddy, kin, src, dst, mid, g, r, c12, s);
+  return launch_step_nb2_s<LBMHD_FP16>(eddy, kin, src, dst, mid, g, r, c12, s);
+}
+
+bool step_nb2_pays(const Geom& g) {
+  const long long tiles_x = (g.nx + kNb2Cols - 1) / kNb2Cols;
+  return tiles_x * ((g.ny + 7) / 8) >= 512;
 }
 
 hipError_t launch_step_nb(int storage, int eddy, bool kin, const void* src, void* dst,

@@ -33,12 +33,13 @@ class LBMHDConfig:
     storage: "fp32" or "fp16" (deviation from the rest state, FP16 scaled by 2^10).
     inplace: one lattice updated in place (AA pattern) instead of two; not with
     the closures that read neighbours (les = 2, 3, 4, 6).
-    steps_per_pass: with two lattices and les = 0 or 1, step() can advance
-    several steps per pass over the lattice with the intermediate states kept
-    on chip, equal to single steps bit for bit in both storages.  0 (default):
-    three per pass with FP32 storage and two with FP16 where the lattice is
-    large enough for it to pay; 3: three with FP32, two with FP16; 2: two;
-    1: one.
+    steps_per_pass: with two lattices, step() can advance several steps per
+    pass over the lattice with the intermediate states kept on chip, equal to
+    single steps bit for bit in both storages.  les = 0 or 1: 0 (default)
+    takes three per pass with FP32 storage and two with FP16 where the lattice
+    is large enough for it to pay; 3: three with FP32, two with FP16; 2: two.
+    les = 2, 3, 4, 6: 0 takes two with FP32 storage and les = 2, 3 or 4 where
+    the lattice is large enough, 2 and 3 two.  1: one.
     """
     nx: int
     ny: int
@@ -143,6 +144,18 @@ class Lattice:
         self._check(self._L.lbmhd_step_store(self._h, _ptr(src),
                                              _ptr(store) if n else ctypes.c_void_p(0),
                                              stride, int(n)), "lbmhd_step_store")
+
+    def step_store_pairs(self, src: torch.Tensor, store: torch.Tensor, npairs: int):
+        """npairs pairs of steps from encoded lattice src, one pass each; state
+        2k (k = 1..npairs) goes to row k - 1 of store (odd states are not
+        kept).  The current state is untouched."""
+        stride = self._store_stride(store, npairs)
+        if src.numel() < self.lattice_bytes:
+            raise ValueError("state buffer too small")
+        self._check(self._L.lbmhd_step_store_pairs(self._h, _ptr(src),
+                                                   _ptr(store) if npairs else ctypes.c_void_p(0),
+                                                   stride, int(npairs)),
+                    "lbmhd_step_store_pairs")
 
     def _store_stride(self, store: torch.Tensor, n: int) -> int:
         if n == 0:
@@ -287,6 +300,25 @@ class Lattice:
         sp = _ptr(store) if n > 1 else ctypes.c_void_p(0)
         self._check(self._L.lbmhd_adj_sweep(self._h, _ptr(src), sp, stride, int(n), _ptr(lam),
                                             _ptr(tmp), _ptr(acc)), "lbmhd_adj_sweep")
+
+    def adj_step2(self, state_t: torch.Tensor, lam_next: torch.Tensor, lam_prev: torch.Tensor,
+                  acc: torch.Tensor):
+        """Two reverse steps from state x_t alone (x_{t+1} recomputed on the
+        device): lam_prev = lam_t from lam_next = lam_{t+2}."""
+        self._check(self._L.lbmhd_adj_step2(self._h, _ptr(state_t), _ptr(lam_next),
+                                            _ptr(lam_prev), _ptr(acc)), "lbmhd_adj_step2")
+
+    def adj_sweep_pairs(self, src: torch.Tensor, store: torch.Tensor | None, n: int,
+                        lam: torch.Tensor, tmp: torch.Tensor, acc: torch.Tensor):
+        """Reverse sweep over n steps from every other state (the layout of
+        step_store_pairs): x_0 = src, x_t = row t / 2 - 1 of store for the even
+        t <= n - 1; lam holds lam_n on entry and lam_0 on return."""
+        rows = (n - 1) // 2
+        stride = self._store_stride(store, rows) if rows > 0 else self.lattice_bytes
+        sp = _ptr(store) if rows > 0 else ctypes.c_void_p(0)
+        self._check(self._L.lbmhd_adj_sweep_pairs(self._h, _ptr(src), sp, stride, int(n),
+                                                  _ptr(lam), _ptr(tmp), _ptr(acc)),
+                    "lbmhd_adj_sweep_pairs")
 
     def adj_acc_total(self, acc: torch.Tensor) -> tuple[float, float]:
         """(sum lam . dx/dC_Sv, sum lam . dx/dC_Sb) accumulated in acc."""

@@ -4,13 +4,27 @@ import pytest
 from paper_1607_08675_amd.adjoint import choose_interval, states_needed
 
 
-def brute_min_interval(nsteps, fit):
-    """Smallest k whose peak buffer count fits, by direct count of what the
-    sweep holds: ceil(n / k) checkpoints, the final state and k - 1 segment
-    buffers, or all n + 1 states at k = 1."""
+def held(nsteps, k, pairs):
+    """Buffers the sweep holds, counted directly: ceil(n / k) checkpoints,
+    the final state and the segment states the reverse steps read (all of
+    1 .. k - 1, or with paired reverse steps the even ones), or at k = 1 every
+    state the sweep reads and the final one."""
+    if k == 1:
+        if pairs and nsteps > 1:
+            return len([0] + list(range(2, nsteps, 2))) + 1
+        return nsteps + 1
+    seg = len(range(2, k, 2)) if pairs else k - 1
+    return len(range(0, nsteps, k)) + 1 + seg
+
+
+def brute_min_interval(nsteps, fit, pairs=False):
+    """The smallest interval that fits; with pairs an odd one > 1 rounded up
+    to the next even one, which holds no more."""
     for k in range(1, nsteps + 1):
-        held = nsteps + 1 if k == 1 else len(range(0, nsteps, k)) + 1 + (k - 1)
-        if held <= fit:
+        if held(nsteps, k, pairs) <= fit:
+            if pairs and k > 1 and k % 2:
+                assert held(nsteps, k + 1, pairs) <= held(nsteps, k, pairs)
+                return k + 1
             return k
     return None
 
@@ -20,16 +34,28 @@ def test_everything_fits_means_no_recompute():
     assert choose_interval(2000, 80 << 20, 2001 * (80 << 20)) == 1
 
 
-def test_matches_brute_force_over_budgets():
-    for n in (1, 2, 7, 50, 101, 400):
+@pytest.mark.parametrize("pairs", [False, True])
+def test_matches_brute_force_over_budgets(pairs):
+    for n in (1, 2, 3, 7, 50, 101, 400):
         for fit in range(2, n + 3):
-            want = brute_min_interval(n, fit)
+            want = brute_min_interval(n, fit, pairs)
             if want is None:
                 with pytest.raises(MemoryError):
-                    choose_interval(n, 1000, fit * 1000)
+                    choose_interval(n, 1000, fit * 1000, pairs)
             else:
-                assert choose_interval(n, 1000, fit * 1000) == want, (n, fit)
-                assert states_needed(n, want) <= fit
+                assert choose_interval(n, 1000, fit * 1000, pairs) == want, (n, fit)
+                assert states_needed(n, want, pairs) <= fit
+
+
+def test_paired_sweep_keeps_half_the_states():
+    """2000 steps: every other state and the final one (1001 buffers) when
+    every state the paired sweep reads is kept; with room for 157 states the
+    smallest interval that fits is 13 (154 checkpoints, the final state, six
+    segment states), taken as 14 (143 checkpoints, the same six)."""
+    assert states_needed(2000, 1, True) == 1001
+    assert states_needed(2000, 13, True) == 154 + 1 + 6
+    assert choose_interval(2000, 1, 161, True) == 14
+    assert states_needed(2000, 14, True) == 143 + 1 + 6
 
 
 def test_interval_near_square_root_when_memory_is_short():

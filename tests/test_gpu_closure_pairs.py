@@ -1,0 +1,158 @@
+"""Two steps per pass for the closures that read the neighbours' moments
+(kinetic closure, les = 2 and 3; cross-helicity closure, les = 4 and 6)
+against single steps and against the oracle (GPU).
+
+The second update at a site needs the first update's output two sites out
+and the input four sites out.  The pass keeps the intermediate state on chip
+in the storage encoding and evaluates the gradient terms and the collision
+with the same functions as the single step, so n steps taken in pairs equal n
+single steps bit for bit, in FP32 and in FP16 storage.  The cases cover full
+and ragged 256-column tiles and strips, lattices two and three sites wide or
+high (the three halo columns and rows on each side wrap onto the tile itself),
+the XCD-grouped block order (a multiple of 8 strips, the last one ragged), the
+4096^2 lattice, odd step counts (a single step after the pairs) and the pass
+that also stores the intermediate state (the adjoint's trajectory).  The
+oracle comparison repeats the closures' forward parity bounds on the paired
+path.
+"""
+import numpy as np
+import pytest
+import torch
+
+from lbmhd_inputs import decaying_turbulence, orszag_tang, random_planes
+from state_words import stored_words
+from test_oracle_precision import fp16_storage
+
+pytestmark = pytest.mark.gpu
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+W19 = np.concatenate([W9, np.zeros(10)])
+CLOSURE = {2: dict(delta=1.3), 3: dict(delta=1.3, cs=0.15, cs_b=0.1),
+           4: dict(delta=1.3, cs=0.15), 6: dict(delta=1.3, cs=0.15)}
+
+
+@pytest.fixture(scope="module")
+def lb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_08675_amd import lattice
+    return lattice
+
+
+def random_state(nx, ny, seed, famp=0.02, gamp=0.01):
+    """Populations around rest with perturbations of relative size famp (f)
+    and absolute size gamp (g): about half the sites in backscatter."""
+    scale = np.concatenate([W9 * famp, np.full(10, gamp)])
+    return random_planes(19, nx, ny, seed, W19, scale)
+
+
+def config(lb, nx, ny, les, storage, spp):
+    return lb.LBMHDConfig(nx=nx, ny=ny, storage=storage, les=les, nu=1e-3, eta=2e-3, s5=1.2,
+                          s7=1.5, s8=0.8, steps_per_pass=spp, **CLOSURE[les])
+
+
+def same(a, b):
+    assert torch.equal(a, b), int((a != b).sum())
+
+
+# (600, 60) and (1030, 124): several tiles, 8 and 16 strips of 8 rows with a
+# ragged last one, so the blocks take the XCD-grouped order
+SIZES = [(256, 64), (300, 70), (2, 2), (3, 5), (5, 3), (2, 9), (513, 9), (258, 17),
+         (600, 60), (1030, 124), (77, 41)]
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("les", [2, 3, 4, 6])
+@pytest.mark.parametrize("nx,ny", SIZES)
+def test_pairs_equal_single_steps(lb, nx, ny, les, storage):
+    print(f"\npairs les={les} {storage} {nx}x{ny}", flush=True)
+    x0 = random_state(nx, ny, seed=nx * 1000 + ny + les)
+    out = []
+    for spp in (1, 2):
+        L = lb.Lattice(config(lb, nx, ny, les, storage, spp))
+        assert L.steps_per_pass == spp
+        L.set_populations(x0).step(5)
+        assert L.step_count == 5
+        out.append(stored_words(L))
+    same(out[0], out[1])
+
+
+@pytest.mark.parametrize("les,storage,spp", [(2, "fp32", 0), (3, "fp32", 0), (4, "fp32", 0),
+                                             (6, "fp32", 2), (4, "fp16", 2), (3, "fp16", 2)])
+def test_pairs_large_lattice(lb, les, storage, spp):
+    """4096^2 Orszag-Tang at nu = eta = 1e-5 against single steps over 6
+    steps: pairs as the automatic choice takes them (FP32, one closure) and as
+    steps_per_pass = 2 asks for them."""
+    n = 4096
+    print(f"\npairs 4096^2 les={les} {storage}", flush=True)
+    f = orszag_tang(n, n)
+    out = []
+    for s in (1, spp):
+        cfg = lb.LBMHDConfig(nx=n, ny=n, storage=storage, les=les, nu=1e-5, eta=1e-5,
+                             steps_per_pass=s, **CLOSURE[les])
+        L = lb.Lattice(cfg)
+        assert L.steps_per_pass == (1 if s == 1 else 2)
+        L.init_fields(*f).step(6)
+        out.append(stored_words(L).clone())
+        del L
+        torch.cuda.empty_cache()
+    same(out[0], out[1])
+
+
+@pytest.mark.parametrize("les,storage,nx,ny", [(2, "fp32", 300, 70), (6, "fp32", 2, 2),
+                                               (4, "fp32", 600, 60), (3, "fp16", 258, 17),
+                                               (6, "fp16", 77, 41)])
+def test_stored_trajectory_equals_single_steps(lb, les, storage, nx, ny):
+    """lbmhd_step_store in pairs stores both states of each pair; every
+    stored state equals the single-step one, and the current state is
+    untouched."""
+    print(f"\nstore les={les} {storage} {nx}x{ny}", flush=True)
+    x0 = random_state(nx, ny, seed=7 + nx + les)
+    out = []
+    for spp in (1, 2):
+        L = lb.Lattice(config(lb, nx, ny, les, storage, spp))
+        L.set_populations(x0)
+        before = stored_words(L).clone()
+        store = torch.zeros(5, L.lattice_bytes, dtype=torch.uint8, device="cuda")
+        L.step_store(L.save_state(), store, 5)
+        same(stored_words(L), before)
+        out.append([stored_words(L, store[i]).clone() for i in range(5)])
+    for a, b in zip(*out):
+        same(a, b)
+
+
+@pytest.mark.parametrize("les", [2, 3, 4, 6])
+@pytest.mark.parametrize("storage,nx,ny", [("fp32", 300, 70), ("fp16", 600, 34)])
+def test_pairs_match_oracle(lb, orc, les, storage, nx, ny):
+    """12 steps in pairs from decaying turbulence against the FP64 oracle:
+    relative L2 of u and B within 1e-5 (FP32); with FP16 storage within 1.25
+    times the departure of the oracle run whose state is rounded to the FP16
+    storage after every step (that rounding alone accounts for it: 1.2e-3 to
+    1.6e-3 in u_y here).  A GPU step streams, then collides, and its state
+    is the post-collision one, so after n steps it holds
+    C (S C)^(n-1) S x0, where the oracle's run gives (S C)^n x0; the two
+    differ by the first collision of the initial equilibrium, which the
+    kinetic closure's filtered equilibria do not leave unchanged."""
+    steps = 12
+    fields = decaying_turbulence(nx, ny, u_rms=0.05, b_rms=0.05)
+    cfg = config(lb, nx, ny, les, storage, 2)
+    L = lb.Lattice(cfg)
+    L.init_fields(*fields).step(steps)
+    got = {k: v.cpu().numpy() for k, v in L.macro().items()}
+    op = orc.Params(nx, ny, nu=cfg.nu, eta=cfg.eta, s5=cfg.s5, s6=cfg.s5, s7=cfg.s7, s8=cfg.s8,
+                    les=les, cs=cfg.cs, csb=cfg.cs_b, delta=cfg.delta)
+    x0 = orc.init(op, *fields)
+    want = orc.macro(op, orc.collide(op, orc.run(op, orc.stream(op, x0), steps - 1)))
+    emu = None
+    if storage == "fp16":
+        q = fp16_storage(x0)
+        for _ in range(steps):
+            q = fp16_storage(orc.collide(op, orc.stream(op, q)))
+        emu = orc.macro(op, q)
+    for k in ("ux", "uy", "bx", "by"):
+        err = np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k])
+        if emu is None:
+            assert err < 1e-5, (k, err)
+        else:
+            dep = np.linalg.norm(emu[k] - want[k]) / np.linalg.norm(want[k])
+            assert err < 1.25 * dep, (k, err, dep)

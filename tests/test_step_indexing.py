@@ -39,6 +39,20 @@ def block_origin(b, tiles, strips, rows, width):
     return tile * width, strip * rows
 
 
+def cmod(a, n):
+    """C's remainder (the sign of the dividend), as the kernels compute it."""
+    return -((-a) % n) if a < 0 else a % n
+
+
+def gather_rows(r, ny):
+    """t2_rows: the row r wrapped once and its two neighbours; all must lie
+    in the lattice."""
+    r = r + ny if r < 0 else (r - ny if r >= ny else r)
+    rows = ((r + 1) if r < ny - 1 else 0, r, (r - 1) if r > 0 else ny - 1)
+    assert all(0 <= v < ny for v in rows), (r, ny)
+    return rows
+
+
 def ring_row(q, t, slots):
     g = GROUP[q]
     base = {0: 0, 1: 2 * slots[0], 2: 2 * slots[0] + 6 * slots[1]}[g]
@@ -60,6 +74,7 @@ def two_step(nx, ny, V, fp16):
         wt, h = min(W, nx - x0), min(rows, ny - y0)
         lds, reg = {}, {}
         for t in range(h + 2):
+            gather_rows(y0 - 1 + t, ny)
             r = (y0 - 1 + t) % ny
             sites = []
             for tid in range(256):
@@ -136,6 +151,8 @@ def three_step(nx, ny):
         for t in range(h + 2 * H):
             for s in range(3):
                 r = y0 - H + t - s
+                if s == 0:
+                    gather_rows(r, ny)
                 if s > 0:
                     # every pass, each thread of the update's columns takes the
                     # c_x != 0 planes of the row just published at lc - c_x
@@ -180,6 +197,133 @@ def three_step(nx, ny):
     assert len(mids[0]) == len(mids[1]) == nx * ny
 
 
+def two_step_neighbours(nx, ny):
+    """k_step_nb2: 256 threads plus a fifth wave for the six halo columns;
+    pass t gathers row a = y0 - 3 + t (moments to ring m1), takes the first
+    update of row a - 1 (gradients from m1, planes moving along x to one LDS
+    row each), the second gather of row a - 2 (moments to ring m2) and the
+    second update of row a - 3 (gradients from m2); three barriers per pass.
+    Checks every moment read (site and pass), every population of both
+    gathers, LDS bounds, single writes, and the trajectory-storing variant's
+    intermediate sites."""
+    W = 256
+    tiles = (nx + W - 1) // W
+    rows = tiles * ny // 512
+    rows = 8 if rows < 8 else (32 if rows > 128 else rows)
+    strips = (ny + rows - 1) // rows
+    written, mids = set(), set()
+    for b in range(tiles * strips):
+        x0, y0 = block_origin(b, tiles, strips, rows, W)
+        wt, h = min(W, nx - x0), min(rows, ny - y0)
+        cols = []
+        for tid in range(W + 64):
+            if tid < W:
+                cols.append((tid, tid < wt))
+            else:
+                k = tid - W
+                cols.append(((k - 3 if k < 3 else wt + k - 3) if k < 6 else 0, k < 6))
+        m1, m2, y1 = {}, {}, {}
+        p1c, p2c = {}, {}            # tid -> site whose gather the thread holds from the last pass
+        zc, zu1, zu2 = {}, {}, {}    # tid -> {q: site} of the c_x = 0 first-update planes
+        xc1, xu1, xu2 = {}, {}, {}   # tid -> {q: site} of the carried c_x != 0 planes
+        for t in range(h + 6):
+            a = y0 - 3 + t
+            aw = cmod(a, ny)
+            gather_rows(aw + ny if aw < 0 else aw, ny)
+            s0, s1, s2 = t % 3, (t - 1) % 3, (t - 2) % 3
+            site = {}
+            # 1. gather row a, moments to m1 at column lc + 3
+            cells = set()
+            p1n = {}
+            for tid, (lc, has) in enumerate(cols):
+                if not has:
+                    continue
+                xc = (x0 + lc) % nx
+                site[tid] = xc
+                key = (s0, lc + 3)
+                assert 0 <= key[1] < W + 6 and key not in cells
+                cells.add(key)
+                m1[key] = ((xc, a % ny), t)
+                p1n[tid] = (xc, a % ny)
+            # 2. first update of row a - 1
+            cells, n2 = set(), {}
+            for tid, (lc, has) in enumerate(cols):
+                if not (has and -2 <= lc <= wt + 1 and t >= 2):
+                    continue
+                xc = site[tid]
+                r = a - 1
+                for dy, sl in ((-1, s2), (0, s1), (1, s0)):
+                    for dx in (-1, 0, 1):
+                        c = lc + 3 + dx
+                        assert 0 <= c < W + 6
+                        assert m1[(sl, c)] == (((xc + dx) % nx, (r + dy) % ny), t + dy - 1)
+                assert p1c[tid] == (xc, r % ny)
+                if 0 <= lc < wt and y0 <= r < y0 + h:
+                    assert (xc, r) not in mids
+                    mids.add((xc, r))
+                n2[tid] = {}
+                for q in range(19):
+                    if GROUP[q] >= 0:
+                        key = (t3_row(q), lc + 2)
+                        assert 0 <= key[1] < W + 4 and key not in cells
+                        cells.add(key)
+                        y1[key] = (q, xc, r % ny, t)
+                    else:
+                        n2[tid][q] = (xc, r % ny)
+            # 3. second gather of row a - 2: every thread takes the y1 values of
+            # this pass at lc + 2 - c_x (threads without the gather at 2 - c_x)
+            cells, p2n = set(), {}
+            for tid, (lc, has) in enumerate(cols):
+                up3 = has and -1 <= lc <= wt
+                c3 = lc + 2 if up3 else 2
+                e = {}
+                for q in range(19):
+                    if GROUP[q] >= 0:
+                        col = c3 - CX[q]
+                        assert 0 <= col < W + 4
+                        e[q] = y1.get((t3_row(q), col))
+                if up3 and t >= 4:
+                    xc, r = site[tid], a - 2
+                    for q in range(19):
+                        want = ((xc - CX[q]) % nx, (r - CY[q]) % ny)
+                        if GROUP[q] >= 0:
+                            got = {1: xu2, 0: xc1, -1: {tid: e}}[CY[q]][tid][q]
+                            assert got is not None and got[0] == q and got[1:3] == want
+                            assert got[3] == t - REG_DELAY[CY[q]]
+                        else:
+                            got = {0: zc, 1: zu2, -1: n2}[CY[q]][tid][q]
+                            assert got == want
+                    key = (s0, lc + 1)
+                    assert 0 <= key[1] < W + 2 and key not in cells
+                    cells.add(key)
+                    m2[key] = ((xc, r % ny), t)
+                    p2n[tid] = (xc, r % ny)
+                xu2[tid] = {q: v for q, v in xu1.get(tid, {}).items()}
+                xu1[tid] = {q: v for q, v in e.items() if CY[q] == 1}
+                xc1[tid] = {q: v for q, v in e.items() if CY[q] == 0}
+            # 4. second update of row a - 3, stored
+            for tid, (lc, has) in enumerate(cols):
+                if not (has and 0 <= lc < wt and t >= 6):
+                    continue
+                xc, r = site[tid], a - 3
+                for dy, sl in ((-1, s2), (0, s1), (1, s0)):
+                    for dx in (-1, 0, 1):
+                        c = lc + 1 + dx
+                        assert 0 <= c < W + 2
+                        assert m2[(sl, c)] == (((xc + dx) % nx, (r + dy) % ny), t + dy - 1)
+                assert p2c[tid] == (xc, r % ny)
+                assert y0 <= r < y0 + h and (xc, r) not in written
+                written.add((xc, r))
+            for tid, (lc, has) in enumerate(cols):
+                p1c[tid] = p1n.get(tid)
+                p2c[tid] = p2n.get(tid)
+                zu2[tid] = zu1.get(tid, {})
+                zu1[tid] = {q: v for q, v in n2.get(tid, {}).items() if CY[q] == 1}
+                zc[tid] = {q: v for q, v in n2.get(tid, {}).items() if CY[q] == 0}
+    assert len(written) == nx * ny
+    assert len(mids) == nx * ny
+
+
 SIZES = [(256, 64), (300, 70), (2, 2), (3, 5), (513, 9), (600, 60), (77, 41), (4, 600)]
 
 
@@ -201,6 +345,11 @@ def test_two_step_fp16_odd_index_model(nx, ny):
 @pytest.mark.parametrize("nx,ny", SIZES + [(5, 3)])
 def test_three_step_index_model(nx, ny):
     three_step(nx, ny)
+
+
+@pytest.mark.parametrize("nx,ny", SIZES + [(5, 3), (258, 17), (2, 3)])
+def test_two_step_neighbour_closures_index_model(nx, ny):
+    two_step_neighbours(nx, ny)
 
 
 @pytest.mark.parametrize("tiles,strips", [(1, 8), (3, 8), (16, 32), (5, 64), (32, 64)])
