@@ -132,10 +132,9 @@ typedef struct {
                              triples with FP32 (pairs with FP16); 2 always
                              takes pairs.  Closures that read the neighbours'
                              moments (les = 2, 3, 4, 6): 0 takes pairs with
-                             FP32 storage and les = 2, 3 or 4 from 512 tiles
-                             of 8 rows by 256 columns on (else single steps),
-                             2 and 3 always take pairs.  1 takes single
-                             steps.  A
+                             FP32 storage from 512 tiles of 8 rows by 256
+                             columns on (else single steps), 2 and 3 always
+                             take pairs.  1 takes single steps.  A
                              remainder goes in pairs (a remainder of one takes
                              the last triple along as two pairs), so a single
                              step runs only when one is left.  Other values

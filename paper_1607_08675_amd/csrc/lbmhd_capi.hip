@@ -68,17 +68,16 @@ hipError_t launch_two_steps(const lbmhd_t* h, const void* src, void* dst, void* 
 // Steps that one kernel pass of lbmhd_step covers: 3 (FP32 only), 2 or 1.
 // Automatic: where the multi-step kernels fill the chip, triples for FP32
 // (measured faster than pairs from 1024^2 to 8192^2) and pairs for FP16; the
-// closures that read the neighbours' moments take pairs with FP32 storage and
-// one of the two closures (at 4096^2, 1.6x single steps for the kinetic
-// closure, 1.4x for the cross-helicity one; with FP16 storage, and with both
-// closures together, pairs measured slower than single steps).
+// closures that read the neighbours' moments take pairs with FP32 storage (at
+// 4096^2, 1.9x single steps for the kinetic closure, 1.65x for the
+// cross-helicity one, 1.15x for both together; with FP16 storage pairs
+// measured no faster than single steps).
 int pass_steps(const lbmhd_t* h) {
   const int spp = h->p.steps_per_pass;
   if (h->p.inplace || spp == 1) return 1;
   if (reads_neighbours(h)) {
     if (spp >= 2) return 2;
-    const bool both = (h->p.les & 2) && eddy_of(h) == 2;
-    return h->p.storage == LBMHD_FP32 && !both && lbk::step_nb2_pays(h->geo) ? 2 : 1;
+    return h->p.storage == LBMHD_FP32 && lbk::step_nb2_pays(h->geo) ? 2 : 1;
   }
   const bool fp32 = h->p.storage == LBMHD_FP32;
   if (spp == 3) return fp32 ? 3 : 2;

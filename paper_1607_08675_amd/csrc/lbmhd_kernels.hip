@@ -612,8 +612,12 @@ __global__ __launch_bounds__(kKinThreads) void k_step_nb(
 constexpr int kNb2Cols = 256;
 constexpr int kNb2Threads = kNb2Cols + 64;
 
+// Compiled for at least four waves per SIMD (at most 128 VGPRs): with the
+// compiler's own choice the pass measured 1.2x slower for the kinetic and the
+// cross-helicity closure and 1.5x slower for both together (135 VGPRs), at
+// 4096^2, with bit-identical results.
 template <int ST, int EDDY, bool KIN, bool MID>
-__global__ __launch_bounds__(kNb2Threads) void k_step_nb2(
+__global__ __launch_bounds__(kNb2Threads) __attribute__((amdgpu_waves_per_eu(4))) void k_step_nb2(
     const typename Codec<ST>::T* __restrict__ src, typename Codec<ST>::T* __restrict__ dst,
     typename Codec<ST>::T* __restrict__ mid, Geom geo, Rates rt, float c12, int tiles_x,
     int rows, bool xcd_map) {

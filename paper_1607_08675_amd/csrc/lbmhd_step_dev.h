@@ -155,15 +155,19 @@ struct NbTerms {
 // nears 3/2 the clip nears the cubic's double root at sqrt(p / 3), where
 // Newton converges only linearly.  Six steps land within 1e-6 of the root
 // up to p = 5/4 (measured: 8.8e-4 at p = 1.4), and lbmhd_create refuses the
-// closure beyond.
+// closure beyond.  The steps stop early once a step has left d unchanged in
+// every lane of the wavefront: the step is a fixed map of d, so every later
+// step would leave it unchanged too, and the result is that of six steps.
 __device__ __forceinline__ float cubic_root_sq(float p, float sp, float q) {
 #pragma clang fp contract(off)
   float d = q > 0.0f ? fminf(q * (0.5f * frcp(p)), cbrtf(q)) : 0.0f;
-#pragma unroll
   for (int i = 0; i < 6; ++i) {
     const float h = fmaf(d, fmaf(d, 3.0f * sp + d, 2.0f * p), -q);
     const float hp = fmaf(d, fmaf(3.0f, d, 6.0f * sp), 2.0f * p);
-    d = fmaf(-h, frcp(hp), d);
+    const float dn = fmaf(-h, frcp(hp), d);
+    const bool fixed = dn == d;
+    d = dn;
+    if (__all(fixed)) break;
   }
   return fmaf(d, 2.0f * sp + d, p);
 }

@@ -38,8 +38,8 @@ class LBMHDConfig:
     single steps bit for bit in both storages.  les = 0 or 1: 0 (default)
     takes three per pass with FP32 storage and two with FP16 where the lattice
     is large enough for it to pay; 3: three with FP32, two with FP16; 2: two.
-    les = 2, 3, 4, 6: 0 takes two with FP32 storage and les = 2, 3 or 4 where
-    the lattice is large enough, 2 and 3 two.  1: one.
+    les = 2, 3, 4, 6: 0 takes two with FP32 storage where the lattice is large
+    enough, 2 and 3 two.  1: one.
     """
     nx: int
     ny: int
