@@ -62,6 +62,19 @@ typedef struct {
   int32_t storage;        /* LBMHD_FP32: deviations f - w (g as is) in FP32;
                              LBMHD_FP16: half(2^10 (f - w)), round to nearest
                              even (the 2D encodings); arithmetic in FP32 */
+  int32_t mrt;            /* 0: single relaxation f* = f - (f - f^eq) / tau;
+                             1: moment-space collision (Sec. 3) in the
+                             tensor-product basis p_r(c_x, c_y) q_k(c_z) of
+                             the paper's nine D2Q9 rows (eq. FluidTMatrix)
+                             and q = 1, c_z, 3 c_z^2 - 1: the z sums (k = 0)
+                             relax with the paper's 2D rates (shear 1/tau,
+                             s5 for rows 5 and 6, s7, s8), so fields
+                             invariant along z follow the 2D model exactly;
+                             the shears xz, yz take 1/tau, the z normal
+                             stress szz, every other moment varying along c_z
+                             sg.  The basis singles out z. */
+  double s5, s7, s8;      /* rates in (0, 2) of the 2D rows 5 and 6, 7, 8 */
+  double sg, szz;         /* rates in (0, 2) (mrt = 1; ignored otherwise) */
 } lbmhd3_params;
 
 typedef struct {

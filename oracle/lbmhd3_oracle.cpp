@@ -24,6 +24,19 @@
 //     g* = g - (g - g^eq) / tau_m: the paper's moment-space collision gives the
 //     BGK update of Sec. 1.2 when every rate equals 1/tau, and no 3D moment
 //     basis is given;
+//   * or (mrt = 1) a moment-space collision for f (Sec. 3): the moments are
+//     the products p_r(c_x, c_y) q_k(c_z) of the paper's nine D2Q9 rows
+//     (eq. FluidTMatrix) with q_0 = 1, q_1 = c_z, q_2 = 3 c_z^2 - 1, the
+//     tensor-product basis of D3Q27 = D2Q9 x D1Q3; f* = f - T^-1 S T (f - f^eq).
+//     Rates: the k = 0 block (the z sums) takes the paper's 2D rates (shear
+//     1/tau for rows 3, 4, s5 for rows 5, 6, s7, s8), so for fields invariant
+//     along z the z sums follow the paper's 2D update exactly at any rates;
+//     the shears xz, yz (k = 1, rows 1, 2) take 1/tau, the z normal stress
+//     (k = 2, row 0) szz, every other moment that varies along c_z the ghost
+//     rate sg; rows 0 (k = 0, 1) are conserved.  With every rate 1/tau this
+//     is the BGK update.  The basis singles out z: the update is covariant
+//     under the cube's rotations only when the rates of rotated moments agree
+//     (for instance all 1/tau);
 //   * Smagorinsky closure per site exactly as in 2D: with Pi' the traceless
 //     part of Pi^neq = sum_i c_i c_i (f_i - f^eq_i) and Q = sqrt(2 Pi':Pi'),
 //     |S| = 3 Q / (2 rho tau) and tau = (tau0 + sqrt(tau0^2 + 18 C_Sv Delta^2 Q
@@ -37,6 +50,7 @@
 // adjacent after the rest velocity); planes 27..32 the x component of g for
 // the six vectors of C6, 33..38 the y component, 39..44 the z component.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -71,7 +85,72 @@ struct P3 {
   double nu, eta;
   int les;
   double cs, csb, delta;
+  int mrt;
+  double s5, s7, s8, sg, szz;
 };
+
+// Row r of the paper's D2Q9 moment transform (eq. FluidTMatrix) as a
+// polynomial in (c_x, c_y), and the three D1Q3 rows in c_z.
+double prow(int r, double cx, double cy) {
+  const double x2 = cx * cx, y2 = cy * cy;
+  switch (r) {
+    case 0: return 1.0;
+    case 1: return cx;
+    case 2: return cy;
+    case 3: return cx * cy;
+    case 4: return x2 - y2;
+    case 5: return 3.0 * cx * y2 - 2.0 * cx;
+    case 6: return 3.0 * cy * x2 - 2.0 * cy;
+    case 7: return 4.0 - 9.0 * (x2 + y2 - 2.0 * x2 * y2);
+    default: return 4.0 - 4.0 * (x2 + y2) + 3.0 * x2 * y2;
+  }
+}
+double qrow(int k, double cz) { return k == 0 ? 1.0 : (k == 1 ? cz : 3.0 * cz * cz - 1.0); }
+
+// T (27 x 27, row 3 r + k = p_r q_k) and its inverse by Gauss-Jordan
+// elimination with partial pivoting, computed once.
+struct Basis27 {
+  double T[27][27], Ti[27][27];
+  Basis27() {
+    double A[27][54];
+    for (int m = 0; m < 27; ++m)
+      for (int i = 0; i < 27; ++i) {
+        T[m][i] = prow(m / 3, C27[i][0], C27[i][1]) * qrow(m % 3, C27[i][2]);
+        A[m][i] = T[m][i];
+        A[m][27 + i] = m == i ? 1.0 : 0.0;
+      }
+    for (int c = 0; c < 27; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < 27; ++r)
+        if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+      for (int j = 0; j < 54; ++j) std::swap(A[c][j], A[piv][j]);
+      const double d = A[c][c];
+      for (int j = 0; j < 54; ++j) A[c][j] /= d;
+      for (int r = 0; r < 27; ++r)
+        if (r != c) {
+          const double f = A[r][c];
+          for (int j = 0; j < 54; ++j) A[r][j] -= f * A[c][j];
+        }
+    }
+    for (int i = 0; i < 27; ++i)
+      for (int m = 0; m < 27; ++m) Ti[i][m] = A[i][27 + m];
+  }
+};
+const Basis27& basis27() {
+  static const Basis27 b;
+  return b;
+}
+
+// Rate of moment m = 3 r + k (see the header): sv = 1/tau.
+double rate27(const P3& p, int m, double sv) {
+  const int r = m / 3, k = m % 3;
+  if (k == 0) {
+    const double s2d[9] = {0.0, 0.0, 0.0, sv, sv, p.s5, p.s5, p.s7, p.s8};
+    return s2d[r];
+  }
+  if (k == 1) return r == 0 ? 0.0 : (r <= 2 ? sv : p.sg);
+  return r == 0 ? p.szz : p.sg;
+}
 
 void equilibrium(double rho, const double u[3], const double B[3], double feq[27],
                  double geq[18]) {
@@ -143,15 +222,33 @@ void collide_site(const P3& p, double f[27], double g[18], double* tau_out, doub
   }
   if (tau_out) *tau_out = tau;
   if (taum_out) *taum_out = taum;
-  for (int i = 0; i < 27; ++i) f[i] -= (f[i] - feq[i]) / tau;
+  if (p.mrt) {
+    const Basis27& b = basis27();
+    double rel[27];
+    for (int m = 0; m < 27; ++m) {
+      double nm = 0.0;
+      for (int i = 0; i < 27; ++i) nm += b.T[m][i] * (f[i] - feq[i]);
+      rel[m] = rate27(p, m, 1.0 / tau) * nm;
+    }
+    for (int i = 0; i < 27; ++i) {
+      double df = 0.0;
+      for (int m = 0; m < 27; ++m) df += b.Ti[i][m] * rel[m];
+      f[i] -= df;
+    }
+  } else {
+    for (int i = 0; i < 27; ++i) f[i] -= (f[i] - feq[i]) / tau;
+  }
   for (int q = 0; q < 18; ++q) g[q] -= (g[q] - geq[q]) / taum;
 }
 
 inline int64_t wrap(int64_t a, int64_t n) { return ((a % n) + n) % n; }
 
 bool valid(const P3* p) {
+  auto rate = [](double s) { return s > 0.0 && s < 2.0; };
   return p && p->nx >= 1 && p->ny >= 1 && p->nz >= 1 && p->nu > 0.0 && p->eta > 0.0 &&
-         (p->les == 0 || p->les == 1);
+         (p->les == 0 || p->les == 1) && (p->mrt == 0 || p->mrt == 1) &&
+         (p->mrt == 0 || (rate(p->s5) && rate(p->s7) && rate(p->s8) && rate(p->sg) &&
+                          rate(p->szz)));
 }
 
 int64_t sites(const P3& p) { return int64_t(p.nx) * p.ny * p.nz; }
@@ -206,6 +303,9 @@ typedef struct {
   int32_t les;          // 0: fixed rates; 1: Smagorinsky-MHD closure
   double cs, csb;       // closure constants C_Sv and C_Sb
   double delta;         // filter width
+  int32_t mrt;          // 0: single relaxation; 1: moment-space collision for f
+  double s5, s7, s8;    // rates of the paper's 2D rows 5 and 6, 7, 8 (k = 0)
+  double sg, szz;       // the other moments that vary along c_z; the z normal stress
 } orc3_params;
 
 int orc3_num_threads(void) {
@@ -234,7 +334,8 @@ void orc3_equilibrium(double rho, const double u[3], const double B[3], double f
 }
 
 static P3 unpack(const orc3_params* q) {
-  return P3{q->nx, q->ny, q->nz, q->nu, q->eta, q->les, q->cs, q->csb, q->delta};
+  return P3{q->nx, q->ny, q->nz, q->nu, q->eta, q->les, q->cs, q->csb, q->delta,
+            q->mrt, q->s5, q->s7, q->s8, q->sg, q->szz};
 }
 
 int orc3_init(const orc3_params* q, const double* rho, const double* ux, const double* uy,

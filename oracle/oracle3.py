@@ -36,14 +36,19 @@ def build(force: bool = False) -> str:
 class _P(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("les", ctypes.c_int32),
-                ("cs", ctypes.c_double), ("csb", ctypes.c_double), ("delta", ctypes.c_double)]
+                ("cs", ctypes.c_double), ("csb", ctypes.c_double), ("delta", ctypes.c_double),
+                ("mrt", ctypes.c_int32), ("s5", ctypes.c_double), ("s7", ctypes.c_double),
+                ("s8", ctypes.c_double), ("sg", ctypes.c_double), ("szz", ctypes.c_double)]
 
 
 @dataclass
 class Params:
     """Lattice size, nu, eta (tau0 = 3 nu + 1/2, tau_m0 = 3 eta + 1/2), les
     (0 or 1: Smagorinsky-MHD closure), closure constants cs (C_Sv) and csb
-    (C_Sb, None for cs) and the filter width delta."""
+    (C_Sb, None for cs) and the filter width delta.  mrt = 1: moment-space
+    collision for f with the rates s5 (2D rows 5, 6), s7, s8, sg (the other
+    moments varying along c_z) and szz (the z normal stress); the shears
+    take 1/tau."""
     nx: int
     ny: int
     nz: int
@@ -53,10 +58,17 @@ class Params:
     cs: float = 0.1
     delta: float = 1.0
     csb: float | None = None
+    mrt: int = 0
+    s5: float = 1.0
+    s7: float = 1.0
+    s8: float = 1.0
+    sg: float = 1.0
+    szz: float = 1.0
 
     def c(self) -> _P:
         return _P(self.nx, self.ny, self.nz, self.nu, self.eta, int(self.les), self.cs,
-                  self.cs if self.csb is None else self.csb, self.delta)
+                  self.cs if self.csb is None else self.csb, self.delta, int(self.mrt),
+                  self.s5, self.s7, self.s8, self.sg, self.szz)
 
 
 _lib = None

@@ -63,7 +63,9 @@ class Params3(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("les", ctypes.c_int32),
         ("cs", ctypes.c_double), ("cs_b", ctypes.c_double), ("delta", ctypes.c_double),
-        ("storage", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("mrt", ctypes.c_int32),
+        ("s5", ctypes.c_double), ("s7", ctypes.c_double), ("s8", ctypes.c_double),
+        ("sg", ctypes.c_double), ("szz", ctypes.c_double),
     ]
 
 

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "lbmhd3.h"
 
@@ -61,7 +62,95 @@ struct Rates3 {
   float itau0, itaum0;    // fixed-rate case
   float tau0, tau0sq, taum0, taum0sq;
   float cf, cm;           // 18 C_Sv Delta^2, 36 C_Sb Delta^2
+  float s5, s7, s8, sg, szz;   // moment-space collision rates
 };
+
+// The paper's D2Q9 velocity order (rows of eq. FluidTMatrix act on it) and
+// 180 times the inverse of its nine rows: column r maps a moment back to the
+// nine populations.
+__device__ constexpr int kX2[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kY2[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr float kT2inv180[9][9] = {
+    {20, 0, 0, 0, 0, 0, 0, 4, 36},       {20, 30, 0, 0, 45, -30, 0, -5, 0},
+    {20, 0, 30, 0, -45, 0, -30, -5, 0},  {20, -30, 0, 0, 45, 30, 0, -5, 0},
+    {20, 0, -30, 0, -45, 0, 30, -5, 0},  {20, 30, 30, 45, 0, 15, 15, 4, -9},
+    {20, -30, 30, -45, 0, -15, 15, 4, -9}, {20, -30, -30, 45, 0, -15, -15, 4, -9},
+    {20, 30, -30, -45, 0, 15, -15, 4, -9}};
+
+// Row r of the paper's D2Q9 transform at velocity (cx, cy) (compile time).
+__host__ __device__ constexpr float prow2(int r, int cx, int cy) {
+  return r == 0   ? 1.0f
+         : r == 1 ? float(cx)
+         : r == 2 ? float(cy)
+         : r == 3 ? float(cx * cy)
+         : r == 4 ? float(cx * cx - cy * cy)
+         : r == 5 ? float(3 * cx * cy * cy - 2 * cx)
+         : r == 6 ? float(3 * cy * cx * cx - 2 * cy)
+         : r == 7 ? float(4 - 9 * (cx * cx + cy * cy - 2 * cx * cx * cy * cy))
+                  : float(4 - 4 * (cx * cx + cy * cy) + 3 * cx * cx * cy * cy);
+}
+
+// f* = f - T^-1 S T (f - f^eq) in the tensor-product basis p_r q_k (see
+// lbmhd3_params): nq = f - f^eq in, the amount to subtract from f out.
+// T = T2 (x) T1 factorises: the c_z transform (q = 1, c_z, 3 c_z^2 - 1) of
+// each of the nine (c_x, c_y) columns, the paper's nine rows on each of the
+// three results, the rates, and back (T1^-1: w_z q_k / |q_k|^2 with
+// |q|^2 = 1, 1/3, 2 under the D1Q3 weights).
+__device__ __forceinline__ void mrt_relax(float (&nq)[kQ], float sv, const Rates3& r) {
+  float a[3][9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) a[0][j] = a[1][j] = a[2][j] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+      if (kCx[i] == kX2[j] && kCy[i] == kY2[j]) {
+        a[0][j] += nq[i];
+        if (kCz[i]) {
+          a[1][j] += float(kCz[i]) * nq[i];
+          a[2][j] += 2.0f * nq[i];
+        } else {
+          a[2][j] -= nq[i];
+        }
+      }
+  }
+  float b[3][9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float rel[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      float mom = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 9; ++j)
+        if (prow2(m, kX2[j], kY2[j]) != 0.0f) mom += prow2(m, kX2[j], kY2[j]) * a[k][j];
+      float s;
+      if (k == 0)
+        s = m < 3 ? 0.0f : (m < 5 ? sv : (m < 7 ? r.s5 : (m == 7 ? r.s7 : r.s8)));
+      else if (k == 1)
+        s = m == 0 ? 0.0f : (m < 3 ? sv : r.sg);
+      else
+        s = m == 0 ? r.szz : r.sg;
+      rel[m] = (1.0f / 180.0f) * (s * mom);
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int m = 0; m < 9; ++m)
+        if (kT2inv180[j][m] != 0.0f) acc += kT2inv180[j][m] * rel[m];
+      b[k][j] = acc;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+      if (kCx[i] == kX2[j] && kCy[i] == kY2[j])
+        nq[i] = kCz[i] == 0 ? (2.0f / 3.0f) * b[0][j] - (1.0f / 3.0f) * b[2][j]
+                            : (1.0f / 6.0f) * (b[0][j] + b[2][j]) + float(kCz[i]) * 0.5f * b[1][j];
+  }
+}
 
 // Storage codecs: FP32 deviations, or FP16 deviations scaled by 2^10 (the
 // scaling is exact; the conversion to half rounds to nearest even).  The
@@ -97,7 +186,7 @@ __device__ __forceinline__ void st_nt(T* __restrict__ base, unsigned off, T v) {
 
 // One collision at one site.  d[27] = f - w (deviations), g[18] (x, y, z
 // components of the six vectors) in, post-collision values out.
-template <bool LES>
+template <bool LES, bool MRT>
 __device__ __forceinline__ void collide3(float (&d)[kQ], float (&g)[18], const Rates3& r) {
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
   float pxx = 0.0f, pyy = 0.0f, pzz = 0.0f, pxy = 0.0f, pxz = 0.0f, pyz = 0.0f;
@@ -187,8 +276,17 @@ __device__ __forceinline__ void collide3(float (&d)[kQ], float (&g)[18], const R
   deq[4] -= ry;
   deq[5] += rz;
   deq[6] -= rz;
+  if (MRT) {
+    float nq[kQ];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) d[i] -= itau * (d[i] - deq[i]);
+    for (int i = 0; i < kQ; ++i) nq[i] = d[i] - deq[i];
+    mrt_relax(nq, itau, r);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) d[i] -= nq[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) d[i] -= itau * (d[i] - deq[i]);
+  }
   // g^eq_kb = (B_b + 3 (C_k.u B_b - C_k.B u_b)) / 6 for C_k = +-e_a:
   // +-(u_a B_b - B_a u_b) / 2 around B_b / 6.  The +-z pair takes the
   // remainder (B_b - 4 (B_b / 6)) / 2 so that sum_k g^eq = B holds in FP32
@@ -209,7 +307,7 @@ __device__ __forceinline__ void collide3(float (&d)[kQ], float (&g)[18], const R
 
 // Thread t of block b updates site x = (b mod tiles_x) * 256 + t of row
 // (y, z), b / tiles_x = z * ny + y.
-template <int ST, bool LES>
+template <int ST, bool LES, bool MRT>
 __global__ __launch_bounds__(kThreads) void k_step3(const typename Codec3<ST>::T* __restrict__ src,
                                                     typename Codec3<ST>::T* __restrict__ dst,
                                                     Geom3 g, Rates3 r, int tiles_x) {
@@ -233,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_step3(const typename Codec3<ST>::T
   for (int i = 0; i < kQ; ++i) d[i] = v[i];
 #pragma unroll
   for (int k = 0; k < 18; ++k) gg[k] = v[kQ + k];
-  collide3<LES>(d, gg, r);
+  collide3<LES, MRT>(d, gg, r);
   const unsigned o = (unsigned(z) * unsigned(g.ny) + unsigned(y)) * g.pitch + unsigned(x);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) st_nt(dst + i * g.plane, o, C::enc(d[i]));
@@ -486,6 +584,11 @@ int lbmhd3_create(const lbmhd3_params* p, lbmhd3_t** out) {
     return LBMHD_ERR_INVALID_ARG;
   if (p->les != 0 && p->les != 1) return LBMHD_ERR_INVALID_ARG;
   if (p->storage != LBMHD_FP32 && p->storage != LBMHD_FP16) return LBMHD_ERR_INVALID_ARG;
+  if (p->mrt != 0 && p->mrt != 1) return LBMHD_ERR_INVALID_ARG;
+  if (p->mrt) {
+    for (double s : {p->s5, p->s7, p->s8, p->sg, p->szz})
+      if (!(s > 0.0 && s < 2.0)) return LBMHD_ERR_INVALID_ARG;
+  }
   const size_t esize = p->storage == LBMHD_FP32 ? 4 : 2;
   if (!(p->cs >= 0.0) || !(p->cs_b >= 0.0) || !std::isfinite(p->cs) || !std::isfinite(p->cs_b) ||
       !(p->delta > 0.0) || !std::isfinite(p->delta))
@@ -505,7 +608,8 @@ int lbmhd3_create(const lbmhd3_params* p, lbmhd3_t** out) {
   const double tau0 = 3.0 * p->nu + 0.5, taum0 = 3.0 * p->eta + 0.5, d2 = p->delta * p->delta;
   h->rates = lbk3::Rates3{float(1.0 / tau0), float(1.0 / taum0), float(tau0), float(tau0 * tau0),
                           float(taum0), float(taum0 * taum0), float(18.0 * p->cs * d2),
-                          float(36.0 * p->cs_b * d2)};
+                          float(36.0 * p->cs_b * d2), float(p->s5), float(p->s7),
+                          float(p->s8), float(p->sg), float(p->szz)};
   h->lattice_bytes = size_t(lbk3::kNPop) * size_t(g.plane) * esize;
   h->workspace_bytes =
       (ws_doubles3((long long)p->nx * p->ny * p->nz) * sizeof(double) + kAlign3 - 1) / kAlign3 *
@@ -580,25 +684,26 @@ int lbmhd3_step(lbmhd3_t* h, int64_t nsteps) {
   for (int64_t t = 0; t < nsteps; ++t) {
     const void* src = h->lat[h->cur];
     void* dst = h->lat[1 - h->cur];
-    if (h->p.storage == LBMHD_FP32) {
-      auto* a = static_cast<const float*>(src);
-      auto* b = static_cast<float*>(dst);
-      if (les)
-        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP32, true>), grid, dim3(lbk3::kThreads), 0,
-                           h->stream, a, b, h->geo, h->rates, tiles_x);
-      else
-        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP32, false>), grid, dim3(lbk3::kThreads), 0,
-                           h->stream, a, b, h->geo, h->rates, tiles_x);
-    } else {
-      auto* a = static_cast<const _Float16*>(src);
-      auto* b = static_cast<_Float16*>(dst);
-      if (les)
-        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP16, true>), grid, dim3(lbk3::kThreads), 0,
-                           h->stream, a, b, h->geo, h->rates, tiles_x);
-      else
-        hipLaunchKernelGGL((lbk3::k_step3<LBMHD_FP16, false>), grid, dim3(lbk3::kThreads), 0,
-                           h->stream, a, b, h->geo, h->rates, tiles_x);
-    }
+    auto go = [&](auto st_tag, auto les_tag, auto mrt_tag) {
+      constexpr int ST = decltype(st_tag)::value;
+      using T = typename lbk3::Codec3<ST>::T;
+      hipLaunchKernelGGL((lbk3::k_step3<ST, decltype(les_tag)::value, decltype(mrt_tag)::value>),
+                         grid, dim3(lbk3::kThreads), 0, h->stream, static_cast<const T*>(src),
+                         static_cast<T*>(dst), h->geo, h->rates, tiles_x);
+    };
+    using F32 = std::integral_constant<int, LBMHD_FP32>;
+    using F16 = std::integral_constant<int, LBMHD_FP16>;
+    using Y = std::true_type;
+    using N = std::false_type;
+    const bool fp32 = h->p.storage == LBMHD_FP32, mrt = h->p.mrt != 0;
+    if (fp32 && les && mrt) go(F32{}, Y{}, Y{});
+    else if (fp32 && les) go(F32{}, Y{}, N{});
+    else if (fp32 && mrt) go(F32{}, N{}, Y{});
+    else if (fp32) go(F32{}, N{}, N{});
+    else if (les && mrt) go(F16{}, Y{}, Y{});
+    else if (les) go(F16{}, Y{}, N{});
+    else if (mrt) go(F16{}, N{}, Y{});
+    else go(F16{}, N{}, N{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail3(h, e, "step launch");
     h->cur = 1 - h->cur;

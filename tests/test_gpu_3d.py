@@ -39,8 +39,14 @@ def o3():
 def make(lb3, o3, nx, ny, nz, **kw):
     cfg = lb3.LBMHD3Config(nx=nx, ny=ny, nz=nz, **kw)
     p = o3.Params(nx, ny, nz, nu=cfg.nu, eta=cfg.eta, les=cfg.les, cs=cfg.cs, delta=cfg.delta,
-                  csb=cfg.cs_b)
+                  csb=cfg.cs_b, mrt=cfg.mrt, s5=cfg.s5, s7=cfg.s7, s8=cfg.s8, sg=cfg.sg,
+                  szz=cfg.szz)
     return lb3.Lattice3(cfg), p
+
+
+# unequal moment-space rates, none of them 1/tau (the oracle pins their
+# meaning: exact reduction to the paper's 2D update along z)
+MRT = dict(mrt=1, s5=1.3, s7=0.7, s8=1.6, sg=1.1, szz=0.9)
 
 
 def random_state(o3, p, seed, amp=2e-3):
@@ -69,6 +75,61 @@ def test_one_step(lb3, o3, nx, ny, nz, les):
     L.set_populations(x0).step(1)
     err = np.abs(L.populations().cpu().numpy() - after(o3, p, x0, 1)).max()
     assert err < 5e-7, err
+
+
+@pytest.mark.parametrize("les", [0, 1])
+@pytest.mark.parametrize("nx,ny,nz", [(8, 8, 8), (37, 5, 3), (300, 4, 2), (2, 2, 2), (16, 3, 1),
+                                      (513, 2, 3)])
+def test_one_step_moment_collision(lb3, o3, nx, ny, nz, les):
+    """The moment-space collision at unequal rates, one step, FP32: within
+    5e-7 of the oracle, as the single-relaxation step."""
+    print(f"\n3D MRT one step les={les} {nx}x{ny}x{nz}", flush=True)
+    L, p = make(lb3, o3, nx, ny, nz, nu=0.01, eta=0.02, les=les, cs=0.15, cs_b=0.1, delta=1.3,
+                **MRT)
+    x0 = random_state(o3, p, nx * 100 + ny * 10 + nz + 7)
+    L.set_populations(x0).step(1)
+    err = np.abs(L.populations().cpu().numpy() - after(o3, p, x0, 1)).max()
+    assert err < 5e-7, err
+    # and it is not the single-relaxation step
+    p0 = o3.Params(nx, ny, nz, nu=0.01, eta=0.02, les=les, cs=0.15, csb=0.1, delta=1.3)
+    assert np.abs(after(o3, p0, x0, 1) - after(o3, p, x0, 1)).max() > 1e-5
+
+
+def test_ten_steps_moment_collision(lb3, o3):
+    L, p = make(lb3, o3, 20, 12, 6, nu=0.005, eta=0.01, les=1, cs=0.1, **MRT)
+    x0 = random_state(o3, p, 17)
+    L.set_populations(x0).step(10)
+    err = np.abs(L.populations().cpu().numpy() - after(o3, p, x0, 10)).max()
+    assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(8, 8, 8), (37, 5, 3), (2, 2, 2)])
+def test_one_step_moment_collision_fp16(lb3, o3, nx, ny, nz):
+    """FP16 storage with the moment-space collision: one step within one
+    half-precision rounding of the oracle's step from the stored state."""
+    L, p = make(lb3, o3, nx, ny, nz, nu=0.01, eta=0.02, les=1, cs=0.15, cs_b=0.1, delta=1.3,
+                storage="fp16", **MRT)
+    x0 = fp16_representable(o3, random_state(o3, p, nx * 100 + ny * 10 + nz + 3))
+    L.set_populations(x0).step(1)
+    got = L.populations().cpu().numpy()
+    want = after(o3, p, x0, 1)
+    dev = np.abs(want - weights45(o3))
+    assert np.all(np.abs(got - want) <= dev * 2.0 ** -11 + 1e-6)
+
+
+def test_vortex_moment_collision(lb3, o3):
+    """24^3 vortex, 100 steps with the moment-space collision at unequal rates
+    and the closure: relative L2 of u and B within 1e-5 of the oracle."""
+    n, steps = 24, 100
+    f = orszag_tang_3d(n, n, n)
+    L, p = make(lb3, o3, n, n, n, nu=0.01, eta=0.01, les=1, cs=0.1, **MRT)
+    L.init_fields(*f).step(steps)
+    g = {k: v.cpu().numpy() for k, v in L.macro().items()}
+    o = o3.macro(p, o3.run(p, o3.init(p, *f), steps))
+    for keys in (("ux", "uy", "uz"), ("bx", "by", "bz")):
+        num = np.sqrt(sum(np.sum((g[k] - o[k]) ** 2) for k in keys))
+        den = np.sqrt(sum(np.sum(o[k] ** 2) for k in keys))
+        assert num / den < 1e-5, (keys, num / den)
 
 
 def test_closure_matters(lb3, o3):

@@ -131,6 +131,78 @@ def test_reduces_to_the_paper_2d_update(o3, orc, axis):
         np.testing.assert_allclose(_project(st3, c, C, axis), st2, atol=2e-15)
 
 
+@pytest.mark.parametrize("rates", [(1.3, 0.7, 1.6, 1.1, 0.9), (0.6, 1.8, 0.5, 1.9, 1.4)])
+def test_moment_collision_reduces_to_the_paper_2d_mrt(o3, orc, rates):
+    """The moment-space collision (mrt = 1) with unequal rates: for fields
+    independent of z, with no velocity or field along z, the 3D update summed
+    over c_z is the paper's 2D update with the same s5 = s6, s7, s8 (shear
+    1/tau0), step by step, to rounding, whatever the rates sg and szz of the
+    moments that vary along c_z.  The two sets differ from each other and
+    from 1/tau0 = 1.79 in every rate, so a 3D rate table that mixed the z
+    sums with those moments, or a 2D row taken wrong, shows here."""
+    c, w, C, W = o3.lattice()
+    n0, n1, nu, eta = 12, 10, 0.02, 0.03
+    s5, s7, s8, sg, szz = rates
+    rho, ux, uy, bx, by = random_fields(n0, n1, 7, u_amp=0.05, b_amp=0.05)
+    zero = np.zeros_like(ux)
+    def lift(a):
+        return np.broadcast_to(np.asarray(a, dtype=np.float64)[None], (2, n1, n0)).copy()
+    p3 = o3.Params(n0, n1, 2, nu=nu, eta=eta, les=0, mrt=1, s5=s5, s7=s7, s8=s8, sg=sg,
+                   szz=szz)
+    st3 = o3.init(p3, *[lift(a) for a in (rho, ux, uy, zero, bx, by, zero)])
+    p2 = orc.Params(n0, n1, nu=nu, eta=eta, s5=s5, s6=s5, s7=s7, s8=s8, les=0)
+    st2 = orc.init(p2, rho, ux, uy, bx, by)
+    # a non-equilibrium start: the same perturbation of every z layer, even
+    # in c_z (u_z and B_z stay zero), none on the g_z planes
+    rng = np.random.default_rng(3)
+    dz = 1e-3 * rng.standard_normal((45, 1, n1, n0)) * np.concatenate(
+        [w, np.full(18, 0.2)])[:, None, None, None]
+    mirror = [next(j for j in range(27) if list(c[j]) == [c[i][0], c[i][1], -c[i][2]])
+              for i in range(27)]
+    mirror += [27 + 6 * (q // 6) + next(j for j in range(6) if list(C[j]) == [
+        C[q % 6][0], C[q % 6][1], -C[q % 6][2]]) for q in range(18)]
+    dz = 0.5 * (dz + dz[mirror])
+    dz[39:45] = 0.0
+    st3 = st3 + dz
+    st2 = st2 + _project(dz * np.ones((1, 2, 1, 1)), c, C, 2)
+    np.testing.assert_allclose(_project(st3, c, C, 2), st2, atol=1e-15)
+    for _ in range(3):
+        st3, st2 = o3.run(p3, st3, 4), orc.run(p2, st2, 4)
+        np.testing.assert_allclose(_project(st3, c, C, 2), st2, atol=2e-15)
+    # the 3D update is not the BGK one at these rates
+    pb = o3.Params(n0, n1, 2, nu=nu, eta=eta, les=0)
+    assert np.abs(o3.run(pb, st3, 1) - o3.run(p3, st3, 1)).max() > 1e-6
+
+
+def test_moment_collision_with_every_rate_one_over_tau_is_bgk(o3):
+    """mrt = 1 with every rate 1/tau (per site, with the closure) is the
+    single-relaxation update: T^-1 S T = I / tau."""
+    p = o3.Params(5, 4, 3, nu=0.02, eta=0.01, les=1, cs=0.2, csb=0.15)
+    rng = np.random.default_rng(4)
+    f = [1 + 0.01 * rng.standard_normal((3, 4, 5))] + [0.05 * rng.standard_normal((3, 4, 5))
+                                                       for _ in range(6)]
+    st = o3.init(p, *f) + 1e-3 * rng.standard_normal((45, 3, 4, 5))
+    s0 = 1 / (3 * p.nu + 0.5)
+    pm = o3.Params(5, 4, 3, nu=0.02, eta=0.01, les=0, mrt=1, s5=s0, s7=s0, s8=s0, sg=s0, szz=s0)
+    p0 = o3.Params(5, 4, 3, nu=0.02, eta=0.01, les=0)
+    np.testing.assert_allclose(o3.collide(pm, st), o3.collide(p0, st), atol=1e-16)
+
+
+def test_moment_collision_conserves_and_keeps_equilibria(o3):
+    p = o3.Params(6, 5, 4, nu=0.02, eta=0.01, les=1, cs=0.2, csb=0.15, mrt=1, s5=1.3,
+                  s7=0.7, s8=1.6, sg=1.1, szz=0.9)
+    rng = np.random.default_rng(1)
+    f = [1 + 0.01 * rng.standard_normal((4, 5, 6))] + [0.05 * rng.standard_normal((4, 5, 6))
+                                                       for _ in range(6)]
+    st = o3.init(p, *f) + 1e-3 * rng.standard_normal((45, 4, 5, 6))
+    d0, d1 = o3.diag(p, st), o3.diag(p, o3.run(p, st, 10))
+    assert abs(d1["mass"] - d0["mass"]) < 1e-14 * d0["mass"]
+    for k in ("mom_x", "mom_y", "mom_z", "flux_x", "flux_y", "flux_z"):
+        assert abs(d1[k] - d0[k]) < 1e-14, k
+    eq = o3.init(p, *f)
+    np.testing.assert_allclose(o3.collide(p, eq), eq, atol=1e-16)
+
+
 def test_conservation_and_fixed_point(o3):
     p = o3.Params(6, 5, 4, nu=0.02, eta=0.01, les=1, cs=0.2, csb=0.15)
     rng = np.random.default_rng(1)
@@ -161,6 +233,22 @@ def test_transport_coefficients_along_z(o3):
     z = np.arange(n)[:, None, None] * np.ones((1, 2, 2))
     zero = np.zeros_like(z)
     p = o3.Params(2, 2, n, nu=0.02, eta=0.04, les=0)
+    r = _decay(o3, p, (1.0, 1e-4 * np.sin(k * z), zero, zero, zero, zero, zero), "ux", k, z)
+    assert abs(r / (p.nu * k * k) - 1) < 2e-3, r / (p.nu * k * k)
+    r = _decay(o3, p, (1.0, zero, zero, zero, zero, 1e-4 * np.sin(k * z), zero), "by", k, z)
+    assert abs(r / (p.eta * k * k) - 1) < 2e-3, r / (p.eta * k * k)
+
+
+def test_moment_collision_transport_along_z(o3):
+    """With the moment-space collision at unequal rates the shears xz and yz
+    still relax at 1/tau: u_x = U sin(k z) decays at nu k^2 and B_y = B0
+    sin(k z) at eta k^2, as with single relaxation."""
+    n = 64
+    k = 2 * np.pi / n
+    z = np.arange(n)[:, None, None] * np.ones((1, 2, 2))
+    zero = np.zeros_like(z)
+    p = o3.Params(2, 2, n, nu=0.02, eta=0.04, les=0, mrt=1, s5=1.3, s7=0.7, s8=1.6, sg=1.1,
+                  szz=0.9)
     r = _decay(o3, p, (1.0, 1e-4 * np.sin(k * z), zero, zero, zero, zero, zero), "ux", k, z)
     assert abs(r / (p.nu * k * k) - 1) < 2e-3, r / (p.nu * k * k)
     r = _decay(o3, p, (1.0, zero, zero, zero, zero, 1e-4 * np.sin(k * z), zero), "by", k, z)
