@@ -44,11 +44,19 @@ def choose_interval(nsteps: int, state_bytes: int, budget_bytes: int,
     every state and makes the backward sweep recompute nothing).  With pairs an
     odd interval k > 1 becomes k + 1: that holds no more buffers (the same
     (k - 1) // 2 segment states, fewer checkpoints) and takes every reverse
-    step in a pair, where k leaves one single step per segment."""
+    step in a pair, where k leaves one single step per segment.  An even
+    interval that is not a multiple of 4 then becomes the next multiple of 4
+    where that still fits: a segment's sweep is then an even number of paired
+    launches, so it ends in lam without a copy of the adjoint lattice."""
     fit = budget_bytes // max(state_bytes, 1)
     for k in range(1, max(nsteps, 1) + 1):
         if states_needed(nsteps, k, pairs) <= fit:
-            return k + 1 if pairs and k > 1 and k % 2 else k
+            if not pairs or k == 1:
+                return k
+            k += k % 2
+            if k % 4 and states_needed(nsteps, k + 2, pairs) <= fit:
+                k += 2
+            return k
     raise MemoryError("not even one checkpoint segment fits the memory budget")
 
 

@@ -19,12 +19,17 @@ def held(nsteps, k, pairs):
 
 def brute_min_interval(nsteps, fit, pairs=False):
     """The smallest interval that fits; with pairs an odd one > 1 rounded up
-    to the next even one, which holds no more."""
+    to the next even one, which holds no more, and that to the next multiple
+    of 4 where it still fits."""
     for k in range(1, nsteps + 1):
         if held(nsteps, k, pairs) <= fit:
-            if pairs and k > 1 and k % 2:
+            if not pairs or k == 1:
+                return k
+            if k % 2:
                 assert held(nsteps, k + 1, pairs) <= held(nsteps, k, pairs)
-                return k + 1
+                k += 1
+            if k % 4 and held(nsteps, k + 2, pairs) <= fit:
+                k += 2
             return k
     return None
 
@@ -49,13 +54,18 @@ def test_matches_brute_force_over_budgets(pairs):
 
 def test_paired_sweep_keeps_half_the_states():
     """2000 steps: every other state and the final one (1001 buffers) when
-    every state the paired sweep reads is kept; with room for 157 states the
+    every state the paired sweep reads is kept; with room for 161 states the
     smallest interval that fits is 13 (154 checkpoints, the final state, six
-    segment states), taken as 14 (143 checkpoints, the same six)."""
+    segment states), taken as 14 (143 checkpoints, the same six) and then as
+    16 (125 checkpoints, seven segment states), whose segments sweep in eight
+    paired launches."""
     assert states_needed(2000, 1, True) == 1001
     assert states_needed(2000, 13, True) == 154 + 1 + 6
-    assert choose_interval(2000, 1, 161, True) == 14
     assert states_needed(2000, 14, True) == 143 + 1 + 6
+    assert choose_interval(2000, 1, 161, True) == 16
+    assert states_needed(2000, 16, True) == 125 + 1 + 7
+    # no room for the multiple of 4: stays at the even interval
+    assert choose_interval(17, 1, 6, True) == 6 and states_needed(17, 8, True) > 6
 
 
 def test_interval_near_square_root_when_memory_is_short():
