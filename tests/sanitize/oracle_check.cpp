@@ -23,6 +23,8 @@ typedef struct {
   double nu, eta;
   int32_t les;
   double cs, csb, delta;
+  int32_t mrt;
+  double s5, s7, s8, sg, szz;
 } orc3_params;
 
 void orc_lattice(double*, double*, double*, double*, double*, double*);
@@ -133,8 +135,8 @@ static void check2(int nx, int ny, int les) {
   CHECK(std::isfinite(J) && std::isfinite(dJ[0]) && std::isfinite(dJ[1]));
 }
 
-static void check3(int nx, int ny, int nz, int les) {
-  orc3_params p{nx, ny, nz, 0.02, 0.03, les, 0.1, 0.05, 1.0};
+static void check3(int nx, int ny, int nz, int les, int mrt) {
+  orc3_params p{nx, ny, nz, 0.02, 0.03, les, 0.1, 0.05, 1.0, mrt, 1.3, 0.7, 1.6, 1.1, 0.9};
   const size_t n = size_t(nx) * ny * nz;
   std::vector<double> f[7];
   for (auto& a : f) a.assign(n, 0.0);
@@ -189,7 +191,8 @@ int main() {
     for (int les : {0, 1, 2, 3, 4, 6}) check2(sz[0], sz[1], les);
   const int sizes3[][3] = {{2, 2, 2}, {3, 4, 5}, {5, 2, 3}};
   for (auto& sz : sizes3)
-    for (int les : {0, 1}) check3(sz[0], sz[1], sz[2], les);
+    for (int les : {0, 1})
+      for (int mrt : {0, 1}) check3(sz[0], sz[1], sz[2], les, mrt);
   if (failures) {
     std::printf("%d failures\n", failures);
     return 1;

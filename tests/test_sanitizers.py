@@ -2,7 +2,8 @@
 and UndefinedBehaviorSanitizer (CPU only).
 
 tests/sanitize/oracle_check.cpp drives every oracle entry point on small and
-ragged lattices (2x2 up to 7x4, 3D down to 2x2x2, every closure); the build
+ragged lattices (2x2 up to 7x4, 3D down to 2x2x2, every closure, the 3D
+moment-space collision as well as single relaxation); the build
 links the oracle sources with g++ -fsanitize=address,undefined.
 tests/sanitize/capi_check.cpp drives the host paths of the library
 (validation, sizes, calls refused before bind, error strings); the HIP
