@@ -191,6 +191,20 @@ int lbmhd_destroy(lbmhd_t* h);
 int lbmhd_sizes(const lbmhd_t* h, size_t* lattice, size_t* workspace, size_t* adj_lattice,
                 size_t* adj_acc);
 
+/* Layout of an encoded lattice and of an adjoint lattice, in elements (FP32
+ * or FP16 as `storage` selects for a state, FP32 for an adjoint lattice):
+ * population q of site (x, y) is element q * plane + y * pitch + x of a
+ * state, and q * adj_plane + y * adj_pitch + x of an adjoint lattice.  Rows
+ * are padded to whole 256-byte blocks, and successive planes are spaced by
+ * their ny rows plus a gap of 768 bytes, so that the 19 populations of a site
+ * are not a large power of two apart (the kernels moving a row of every
+ * plane at once run faster); the row padding and the gaps are never read or
+ * written.  lattice = 19 * plane * element size, adj_lattice = 19 *
+ * adj_plane * 4.  Any output pointer may be NULL.  Errors:
+ * LBMHD_ERR_INVALID_ARG (h NULL). */
+int lbmhd_layout(const lbmhd_t* h, int64_t* pitch, int64_t* plane, int64_t* adj_pitch,
+                 int64_t* adj_plane);
+
 /* Attach caller-owned device buffers and the HIP stream (a hipStream_t, or
  * NULL for the null stream).  lat_a and lat_b must each hold `lattice`
  * bytes and workspace `workspace` bytes (lbmhd_sizes), 256-byte aligned, and

@@ -36,7 +36,8 @@
  * post-collision population at the current step (the step gathers from the
  * neighbours, then collides).  The lattice holds the encoded deviations f - w
  * and g (FP32, or FP16 scaled by 2^10, as `storage` selects) in 45 planes of
- * [z][y][row pitch padded to 256 bytes].
+ * [z][y][row pitch padded to 256 bytes], successive planes spaced by their
+ * rows plus a gap of 768 bytes (never read or written).
  */
 #ifndef LBMHD3_H
 #define LBMHD3_H

@@ -27,7 +27,7 @@ LBMHD_FP16 = 1
 # Every function declared in include/lbmhd.h, in declaration order.
 EXPORTS = (
     "lbmhd_strerror", "lbmhd_last_error", "lbmhd_create", "lbmhd_destroy", "lbmhd_sizes",
-    "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_steps_per_pass",
+    "lbmhd_layout", "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_steps_per_pass",
     "lbmhd_step_between", "lbmhd_step_store", "lbmhd_step_store_pairs",
     "lbmhd_macro",
     "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_get_populations",
@@ -118,6 +118,7 @@ def lib():
             "lbmhd_create": [P(Params), P(vp)],
             "lbmhd_destroy": [vp],
             "lbmhd_sizes": [vp, P(sz), P(sz), P(sz), P(sz)],
+            "lbmhd_layout": [vp, P(i64), P(i64), P(i64), P(i64)],
             "lbmhd_bind": [vp, vp, sz, vp, sz, vp, sz, vp],
             "lbmhd_init_fields": [vp] * 6,
             "lbmhd_step": [vp, i64],

@@ -598,7 +598,9 @@ int lbmhd3_create(const lbmhd3_params* p, lbmhd3_t** out) {
   g.ny = p->ny;
   g.nz = p->nz;
   g.pitch = unsigned((size_t(p->nx) * esize + kAlign3 - 1) / kAlign3 * kAlign3 / esize);
-  g.plane = (long long)g.pitch * p->ny * p->nz;
+  // planes spaced by their rows plus a gap of three 256-byte blocks, as in 2D
+  // (at 256^3 FP32 they would otherwise lie 2^26 bytes apart)
+  g.plane = (long long)g.pitch * p->ny * p->nz + (long long)(768 / esize);
   // in-plane byte offsets are 32-bit in the step kernel
   if ((unsigned long long)g.plane * esize >= (1ull << 32)) return LBMHD_ERR_INVALID_ARG;
   lbmhd3_t* h = new (std::nothrow) lbmhd3;

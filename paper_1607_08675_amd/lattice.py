@@ -87,6 +87,10 @@ class Lattice:
         C.check(L.lbmhd_sizes(h, *[ctypes.byref(s) for s in sizes]), "lbmhd_sizes", h)
         (self.lattice_bytes, self.workspace_bytes,
          self.adj_lattice_bytes, self.adj_acc_bytes) = (s.value for s in sizes)
+        lay = [ctypes.c_int64() for _ in range(4)]
+        C.check(L.lbmhd_layout(h, *[ctypes.byref(v) for v in lay]), "lbmhd_layout", h)
+        # elements: population q of site (x, y) at q * plane + y * pitch + x
+        self.pitch, self.plane, self.adj_pitch, self.adj_plane = (v.value for v in lay)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._a = torch.empty(self.lattice_bytes, dtype=torch.uint8, device=self.device)
         self._b = (None if cfg.inplace else
@@ -336,7 +340,16 @@ class Lattice:
         return tuple(outs)
 
     def adj_view(self, lam: torch.Tensor) -> torch.Tensor:
-        """(19, ny, nx) view of an adjoint buffer (drops the row padding).  Entries
-        are in streamed position: plane i at site x + c_i holds dJ/dx_i(x)."""
-        pitch = (self.adj_lattice_bytes // 4) // (19 * self.cfg.ny)
-        return lam.view(19, self.cfg.ny, pitch)[:, :, : self.cfg.nx]
+        """(19, ny, nx) view of an adjoint buffer (drops the row padding and the
+        gaps between planes).  Entries are in streamed position: plane i at site
+        x + c_i holds dJ/dx_i(x)."""
+        return lam.as_strided((19, self.cfg.ny, self.cfg.nx), (self.adj_plane, self.adj_pitch, 1))
+
+    def state_view(self, state: torch.Tensor | None = None) -> torch.Tensor:
+        """(19, ny, nx) view of the stored elements of an encoded lattice (default:
+        the current state, returned to the natural layout): float32 for FP32
+        storage, float16 (deviation x 2^10) for FP16."""
+        st = self.save_state() if state is None else state
+        dt = torch.float32 if self.cfg.storage == "fp32" else torch.float16
+        return st[: self.lattice_bytes].view(dt).as_strided(
+            (19, self.cfg.ny, self.cfg.nx), (self.plane, self.pitch, 1))

@@ -91,8 +91,14 @@ def test_sizes_and_layout(capi):
         assert L.lbmhd_sizes(h, *[ctypes.byref(x) for x in s]) == 0
         lat, ws, adj, acc = (x.value for x in s)
         pitch = -(-100 * esize // 256) * 256 // esize   # rows padded to 256 bytes
-        assert lat == 19 * 36 * pitch * esize
-        assert adj == 19 * 36 * 128 * 4
+        plane = 36 * pitch + 768 // esize                # and a 768-byte gap between planes
+        assert lat == 19 * plane * esize
+        assert adj == 19 * (36 * 128 + 192) * 4
+        lay = [ctypes.c_int64() for _ in range(4)]
+        assert L.lbmhd_layout(h, *[ctypes.byref(x) for x in lay]) == 0
+        assert [x.value for x in lay] == [pitch, plane, 128, 36 * 128 + 192]
+        assert L.lbmhd_layout(h, None, None, None, None) == 0
+        assert L.lbmhd_layout(None, None, None, None, None) == capi.LBMHD_ERR_INVALID_ARG
         assert ws >= 16 * 8 and ws % 256 == 0   # reduction partials and results only
         assert acc % 256 == 0 and acc >= 2 * 8 * 36   # two slot arrays, >= 1 block per row
         assert L.lbmhd_destroy(h) == 0
@@ -191,7 +197,7 @@ def test_3d_sizes_and_unbound_calls(capi):
     assert L.lbmhd3_create(ctypes.byref(_params3(capi, nx=100, ny=6, nz=5)), ctypes.byref(h)) == 0
     lat, ws = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.lbmhd3_sizes(h, ctypes.byref(lat), ctypes.byref(ws)) == 0
-    assert lat.value == 45 * 5 * 6 * 128 * 4      # rows padded to 256 bytes
+    assert lat.value == 45 * (5 * 6 * 128 + 192) * 4   # rows padded to 256 bytes, 768-byte gaps
     assert ws.value >= 7 * 100 * 6 * 5 * 8 and ws.value % 256 == 0
     assert L.lbmhd3_step(h, 1) == capi.LBMHD_ERR_NOT_BOUND
     assert b"bind" in L.lbmhd3_last_error(h)
@@ -199,7 +205,7 @@ def test_3d_sizes_and_unbound_calls(capi):
     p16 = _params3(capi, nx=100, ny=6, nz=5, storage=capi.LBMHD_FP16)
     assert L.lbmhd3_create(ctypes.byref(p16), ctypes.byref(h)) == 0
     assert L.lbmhd3_sizes(h, ctypes.byref(lat), None) == 0
-    assert lat.value == 45 * 5 * 6 * 128 * 2      # 128 halves = 256 bytes per row
+    assert lat.value == 45 * (5 * 6 * 128 + 384) * 2   # 128 halves = 256 bytes per row
     assert L.lbmhd3_destroy(h) == 0
     # a plane of 2^14 x 2^14 x 4 sites takes 4 GiB in FP32 (refused: in-plane
     # byte offsets are 32-bit) and 2 GiB in FP16 (accepted)

@@ -64,7 +64,7 @@ def test_largest_lattice(lb, orc, storage, inplace, tol):
     cfg = lb.LBMHDConfig(nx=NX, ny=NY, nu=1e-5, eta=1e-5, les=1, cs=0.1, storage=storage,
                          inplace=inplace)
     L = lb.Lattice(cfg)
-    assert (L.lattice_bytes // esize // 19) * 4 < 2 ** 32
+    assert L.pitch * NY * 4 < 2 ** 32 and L.lattice_bytes == 19 * L.plane * esize
     dev = L.device
     x = torch.arange(NX, device=dev, dtype=torch.float64) * (2 * math.pi / NX)
     y = torch.arange(NY, device=dev, dtype=torch.float64) * (2 * math.pi / NY)
@@ -83,8 +83,7 @@ def test_largest_lattice(lb, orc, storage, inplace, tol):
     d = L.diag()                      # also returns an in-place lattice to its natural layout
     assert d["nonfinite"] == 0 and abs(d["mass"] - n) <= 1e-6 * n
     cur = L.current_state()
-    plane = L.lattice_bytes // esize // 19
-    pitch = plane // NY
+    plane, pitch = L.plane, L.pitch
     raw = cur.view(torch.float32 if storage == "fp32" else torch.float16)
     rng = np.random.default_rng(7)
     sites = [(0, 0), (NX - 1, NY - 1), (0, NY - 1), (NX - 1, 0), (NX // 2, NY // 2), (NX - 1, 5)]
