@@ -77,6 +77,13 @@ int main() {
       CHECK(lbmhd_sizes(h, &lat, &ws, &adj, &acc) == LBMHD_OK);
       CHECK(lat > 0 && ws > 0 && adj > 0 && acc > 0);
       CHECK(lbmhd_sizes(h, nullptr, nullptr, nullptr, nullptr) == LBMHD_OK);
+      int64_t pitch = 0, plane = 0, apitch = 0, aplane = 0;
+      CHECK(lbmhd_layout(h, &pitch, &plane, &apitch, &aplane) == LBMHD_OK);
+      CHECK(pitch >= p.nx && plane >= pitch * p.ny && apitch >= p.nx && aplane >= apitch * p.ny);
+      CHECK(lat == size_t(19 * plane) * (p.storage == LBMHD_FP32 ? 4 : 2));
+      CHECK(adj == size_t(19 * aplane) * 4);
+      CHECK(lbmhd_layout(h, nullptr, nullptr, nullptr, nullptr) == LBMHD_OK);
+      CHECK(lbmhd_layout(nullptr, &pitch, nullptr, nullptr, nullptr) == LBMHD_ERR_INVALID_ARG);
       CHECK(lbmhd_step(h, 1) == LBMHD_ERR_NOT_BOUND);
       CHECK(std::strlen(lbmhd_last_error(h)) > 0);
       lbmhd_diag_t d;
