@@ -795,7 +795,7 @@ def main():
                 "J": radj["run_4096"]["J"], "dJ_dcsv": radj["run_4096"]["dJ_dcsv"],
             },
             "kinetic_closure_adj_ms_4096": round(radj["adj_kin_ms_4096"], 5),
-            "kinetic_closure_adj_gbs_4096": round(460 * 4096 * 4096 / (radj["adj_kin_ms_4096"] * 1e-3) / 1e9, 1),
+            "kinetic_closure_adj_gbs_4096": round(228 * 4096 * 4096 / (radj["adj_kin_ms_4096"] * 1e-3) / 1e9, 1),
             "kinetic_closure_adj_over_forward_4096": round(radj["adj_kin_ms_4096"] / radj["fwd_kin_ms_4096"], 3),
         }
     if rfit:

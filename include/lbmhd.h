@@ -183,8 +183,8 @@ int lbmhd_destroy(lbmhd_t* h);
 
 /* Byte sizes the caller must allocate in device memory:
  *   lattice    -- one encoded population lattice (two are bound, one in place);
- *   workspace  -- scratch used by diagnostics, energy and reductions, and
- *                 with the kinetic closure by the adjoint step;
+ *   workspace  -- scratch used by diagnostics, energy and reductions (block
+ *                 partials and results, the same at any lattice size);
  *   adj_lattice -- one FP32 adjoint lattice (lambda), for the adjoint calls;
  *   adj_acc    -- the FP64 accumulator array of lbmhd_adj_step.
  * Any output pointer may be NULL. */
@@ -351,9 +351,9 @@ int lbmhd_adj_seed_mismatch(lbmhd_t* h, const void* state, const double* ux_t,
                             double scale, float* lam);
 
 /* The adjoint calls below cover les = 0, 1, 2 and 3.  With the kinetic
- * closure (les = 2, 3) the step is taken in two passes: the equilibrium
- * terms depend on the neighbours' moments, whose adjoints go back through
- * the transposed gradient stencil (scratch planes in the workspace).  With
+ * closure (les = 2, 3) the equilibrium terms depend on the neighbours'
+ * moments, whose adjoints go back through the transposed gradient stencil;
+ * one pass over strips of rows keeps those adjoints on chip.  With
  * the cross-helicity closure (les = 4, 6) lbmhd_adj_step and lbmhd_adj_sweep
  * return LBMHD_ERR_UNSUPPORTED. */
 

@@ -455,18 +455,14 @@ __global__ void k_adj_fields(const float* __restrict__ lam, const double* __rest
 // The kinetic closure's equilibrium terms depend on the gradients of
 // rho - 1, j, B over the eight neighbours (isotropic D2Q9 difference
 // d_a X = 3 sum_i w_i c_ia X(x + c_i)) and on the site's own moments, all of
-// the gathered pre-collision state.  The reverse step therefore takes two
-// passes.  Pass A, per site: recompute the forward terms, apply the transposed
-// collision Jacobian with those terms held fixed, carry the adjoints of the
-// terms back to the site's own moments (added to its populations in lam_prev)
-// and to the ten gradient components (written to scratch planes).  Pass B,
-// per site: add the transposed stencil of the neighbours' gradient adjoints
-// to the site's moment adjoints and map them onto its populations.  Pass A
-// walks strips of rows with a rolling 3-row LDS buffer of moments, as the
-// forward step does.
-constexpr int kAdjKinThreads = 512;
-constexpr int kAdjKinRows = 16;
-constexpr int kAdjKinCols = kAdjKinThreads + 2;
+// the gathered pre-collision state.  The reverse step has two parts per site.
+// Part A: recompute the forward terms, apply the transposed collision
+// Jacobian with those terms held fixed, and carry the adjoints of the terms
+// back to the site's own moments (added to its populations) and to the ten
+// gradient components.  Part B: add the transposed stencil of the
+// neighbours' gradient adjoints to the site's moment adjoints and map them
+// onto its populations.  One kernel walks strips of rows and takes both
+// (k_adj_kin below).
 
 // The closure's terms from the gradients gx, gy and the site's moments v of
 // (rho - 1, j_x, j_y, B_x, B_y); c12 = Delta^2 / 12.  Same operations as the
@@ -555,34 +551,55 @@ __device__ __forceinline__ void add_moment_adjoints(const float (&m)[5], float (
   }
 }
 
-// Pass A.  Block: kAdjKinThreads columns x a strip of kAdjKinRows rows.
-// gb: ten planes (adjoint layout) for d/d(d_x X), then d/d(d_y X), X = rho - 1,
-// j_x, j_y, B_x, B_y.  nslots: the stride between the two slot arrays of acc.
+// Both parts in one walk.  A block owns a tile of kT3Cols columns and a strip
+// of `rows` rows: pass t gathers row y0 + t (its moments go to a 3-row LDS
+// ring with two halo columns on each side), applies part A to row
+// a = y0 - 1 + t on the tile's columns and one halo column on each side (the
+// ten gradient adjoints go to a second 3-row LDS ring), and part B to row
+// a - 1, whose part-A adjoint the thread carried from the last pass in
+// registers; lam_prev is written once.  The fifth wave owns the halo columns
+// (lanes 0 .. 3: x0 - 2, x0 - 1, x0 + wt, x0 + wt + 1; part A on the inner
+// two).  Two barriers per pass.  HBM bytes per site: the state gather, the
+// lam_next gather and the lam_prev store, plus four halo rows of gathers and
+// two of part A per strip.  The closure-constant derivatives are summed per
+// block over the sites it owns (slots b and nslots + b of acc).
 template <int ST, bool LES>
-__global__ __launch_bounds__(kAdjKinThreads) void k_adj_kin_a(
+__global__ __launch_bounds__(kT3Threads) void k_adj_kin(
     const typename Dec<ST>::T* __restrict__ st, const float* __restrict__ lam_next,
-    float* __restrict__ lam_prev, float* __restrict__ gb, double* __restrict__ acc, Geom geo,
-    Geom ga, Rates rt, AdjConsts ac, float c12, int tiles_x, int nslots) {
+    float* __restrict__ lam_prev, double* __restrict__ acc, Geom geo, Geom ga, Rates rt,
+    AdjConsts ac, float c12, int tiles_x, int rows, int nslots) {
   using D = Dec<ST>;
-  __shared__ float mac[3][5][kAdjKinCols];
-  const int tx = int(threadIdx.x);
-  const int xt = (int(blockIdx.x) % tiles_x) * kAdjKinThreads;
-  const int y0 = (int(blockIdx.x) / tiles_x) * kAdjKinRows;
-  const int y1 = min(y0 + kAdjKinRows, geo.ny);
-  const int x = xt + tx;
-  const bool active = x < geo.nx;
-  const int xc = x % geo.nx;
-  const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1) : (xt + kAdjKinThreads) % geo.nx;
-  const int ch = tx == 0 ? 0 : kAdjKinCols - 1;
+  __shared__ float mac[3][5][kT3Cols + 4];    // moments: column lc + 2
+  __shared__ float gbr[3][10][kT3Cols + 2];   // gradient adjoints: column lc + 1
+  const int nx = geo.nx, ny = geo.ny;
   const long long P = geo.plane, PA = ga.plane;
-  // gathered pre-collision populations of site (xx, yy): x_n(. - c_q)
-  auto gather = [&](int xx, int yy, float (&p)[19]) {
-    yy = yy < 0 ? yy + geo.ny : (yy >= geo.ny ? yy - geo.ny : yy);
-    const int xm = xx == 0 ? geo.nx - 1 : xx - 1, xp = xx == geo.nx - 1 ? 0 : xx + 1;
-    const int ym = yy == 0 ? geo.ny - 1 : yy - 1, yp = yy == geo.ny - 1 ? 0 : yy + 1;
+  const int tile = int(blockIdx.x) % tiles_x, strip = int(blockIdx.x) / tiles_x;
+  const int x0 = tile * kT3Cols, y0 = strip * rows;
+  const int wt = min(kT3Cols, nx - x0), h = min(rows, ny - y0);
+  const int tid = int(threadIdx.x);
+  // the thread's column lc: its own (threads 0 .. kT3Cols - 1) or a halo one
+  int lc = tid;
+  bool hasm = tid < wt;   // gathers the column's populations and moments
+  if (tid >= kT3Cols) {
+    const int k = tid - kT3Cols;
+    hasm = k < 4;
+    lc = k == 0 ? -2 : (k == 1 ? -1 : (k == 2 ? wt : wt + 1));
+  }
+  const bool hasa = hasm && lc >= -1 && lc <= wt;   // part A
+  const bool own = hasm && lc >= 0 && lc < wt;      // part B and lam_prev
+  const int mc = lc + 2, gc = lc + 1;
+  int x = (x0 + lc) % nx;
+  if (x < 0) x += nx;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  // gathered pre-collision populations of row yy (any integer, periodic) at
+  // this thread's column: x_n(. - c_q)
+  auto gather = [&](int yy, float (&p)[19]) {
+    yy %= ny;
+    if (yy < 0) yy += ny;
+    const int ym = yy == 0 ? ny - 1 : yy - 1, yp = yy == ny - 1 ? 0 : yy + 1;
     const unsigned r0 = unsigned(yy) * geo.pitch, rm = unsigned(ym) * geo.pitch,
                    rp = unsigned(yp) * geo.pitch;
-    const unsigned o[9] = {r0 + xx, r0 + xm, rm + xx, r0 + xp, rp + xx,
+    const unsigned o[9] = {r0 + x, r0 + xm, rm + x, r0 + xp, rp + x,
                            rm + xm, rm + xp, rp + xp, rp + xm};
 #pragma unroll
     for (int i = 0; i < 9; ++i) p[i] = D::dec(ld_elem(st + i * P, o[i]));
@@ -592,32 +609,38 @@ __global__ __launch_bounds__(kAdjKinThreads) void k_adj_kin_a(
       p[14 + k] = D::dec(ld_elem(st + (14 + k) * P, o[k]));
     }
   };
-  auto moments = [&](const float (&p)[19], int slot, int col) {
-    mac[slot][0][col] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])) + p[8];
-    mac[slot][1][col] = (p[1] - p[3]) + (p[5] - p[7]) - (p[6] - p[8]);
-    mac[slot][2][col] = (p[2] - p[4]) + (p[5] - p[7]) + (p[6] - p[8]);
-    mac[slot][3][col] = (p[9] + p[10]) + (p[11] + p[12]) + p[13];
-    mac[slot][4][col] = (p[14] + p[15]) + (p[16] + p[17]) + p[18];
-  };
-  auto stage = [&](int yy, int slot, float (&p)[19]) {
-    gather(xc, yy, p);
-    moments(p, slot, tx + 1);
-    if (tx < 2) {
-      float q[19];
-      gather(xh, yy, q);
-      moments(q, slot, ch);
-    }
+  auto moments = [&](const float (&p)[19], int slot) {
+    mac[slot][0][mc] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])) + p[8];
+    mac[slot][1][mc] = (p[1] - p[3]) + (p[5] - p[7]) - (p[6] - p[8]);
+    mac[slot][2][mc] = (p[2] - p[4]) + (p[5] - p[7]) + (p[6] - p[8]);
+    mac[slot][3][mc] = (p[9] + p[10]) + (p[11] + p[12]) + p[13];
+    mac[slot][4][mc] = (p[14] + p[15]) + (p[16] + p[17]) + p[18];
   };
   CsGrad dcs{0.0f, 0.0f};
   float cur[19], nxt[19];
-  stage(y0 - 1, 0, nxt);
-  stage(y0, 1, cur);
-  for (int y = y0; y < y1; ++y) {
-    const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
-    stage(y + 1, sp, nxt);
+  float clf[9], clg[10];   // part-A adjoint of the last pass's row (own columns)
+#pragma unroll
+  for (int i = 0; i < 9; ++i) clf[i] = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 10; ++q) clg[q] = 0.0f;
+  if (hasm) {
+    gather(y0 - 2, nxt);
+    moments(nxt, 0);
+    gather(y0 - 1, cur);
+    moments(cur, 1);
+  }
+  for (int t = 0; t < h + 2; ++t) {
+    const int a = y0 - 1 + t;
+    const int sm = t % 3, s0 = (t + 1) % 3, sp = (t + 2) % 3;
+    if (hasm) {
+      gather(a + 1, nxt);
+      moments(nxt, sp);
+    }
     __syncthreads();
-    if (active) {
-      const int c = tx + 1;
+    // part A at row a
+    float lf[9], lg[10];
+    if (hasa) {
+      const int c = mc;
       float gx[5], gy[5], v[5];
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
@@ -631,13 +654,14 @@ __global__ __launch_bounds__(kAdjKinThreads) void k_adj_kin_a(
       }
       const KinTerms kc = kin_terms(gx, gy, v, c12);
       // lam_{n+1} of this site's populations, kept at x + c_i
-      const int xm = x == 0 ? geo.nx - 1 : x - 1, xp = x == geo.nx - 1 ? 0 : x + 1;
-      const int ym = y == 0 ? geo.ny - 1 : y - 1, yp = y == geo.ny - 1 ? 0 : y + 1;
-      const unsigned a0 = unsigned(y) * ga.pitch, am = unsigned(ym) * ga.pitch,
+      int ya = a % ny;
+      if (ya < 0) ya += ny;
+      const int ym = ya == 0 ? ny - 1 : ya - 1, yp = ya == ny - 1 ? 0 : ya + 1;
+      const unsigned a0 = unsigned(ya) * ga.pitch, am = unsigned(ym) * ga.pitch,
                      ap = unsigned(yp) * ga.pitch;
       const unsigned on[9] = {a0 + x, a0 + xp, ap + x, a0 + xm, am + x,
                               ap + xp, ap + xm, am + xm, am + xp};
-      float lf[9], lg[10], f[9], g[10];
+      float f[9], g[10];
 #pragma unroll
       for (int i = 0; i < 9; ++i) lf[i] = ld_elem(lam_next + i * PA, on[i]);
 #pragma unroll
@@ -651,81 +675,73 @@ __global__ __launch_bounds__(kAdjKinThreads) void k_adj_kin_a(
       for (int q = 0; q < 10; ++q) g[q] = cur[9 + q];
       KinTerms kcb;
       const CsGrad d = collide_adjoint<LES, true>(f, g, lf, lg, rt, ac, kc, &kcb);
-      dcs.v += d.v;
-      dcs.b += d.b;
+      if (own && t >= 1 && t <= h) {
+        dcs.v += d.v;
+        dcs.b += d.b;
+      }
       float gxb[5], gyb[5], vb[5];
       kin_terms_adjoint(gx, gy, v, c12, kcb, gxb, gyb, vb);
       add_moment_adjoints(vb, lf, lg);
-      const unsigned oc = a0 + x;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) st_plane_nt(lam_prev + i * PA, oc, lf[i]);
-#pragma unroll
-      for (int q = 0; q < 10; ++q) st_plane_nt(lam_prev + (9 + q) * PA, oc, lg[q]);
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
-        st_plane_nt(gb + k * PA, oc, gxb[k]);
-        st_plane_nt(gb + (5 + k) * PA, oc, gyb[k]);
+        gbr[sm][k][gc] = gxb[k];
+        gbr[sm][5 + k][gc] = gyb[k];
       }
     }
     __syncthreads();
+    // part B at row a - 1: rows a - 2, a - 1, a of the gradient adjoints are
+    // in the slots of passes t - 2, t - 1, t
+    if (own && t >= 2) {
+      const int rm = (t - 2) % 3, r0 = (t - 1) % 3, rp = t % 3;
+      const int c = gc;
+      float eta[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        // d/d(d_x X_k) in plane k, d/d(d_y X_k) in plane 5 + k
+        eta[k] = (1.0f / 3.0f) * ((gbr[r0][k][c - 1] - gbr[r0][k][c + 1]) +
+                                  (gbr[rm][5 + k][c] - gbr[rp][5 + k][c])) +
+                 (1.0f / 12.0f) * ((gbr[rm][k][c - 1] + gbr[rm][5 + k][c - 1]) +
+                                   (gbr[rm][5 + k][c + 1] - gbr[rm][k][c + 1]) +
+                                   (gbr[rp][k][c - 1] - gbr[rp][5 + k][c - 1]) -
+                                   (gbr[rp][k][c + 1] + gbr[rp][5 + k][c + 1]));
+      }
+      add_moment_adjoints(eta, clf, clg);
+      int yb = (a - 1) % ny;
+      if (yb < 0) yb += ny;
+      const unsigned oc = unsigned(yb) * ga.pitch + unsigned(x);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) st_plane_nt(lam_prev + i * PA, oc, clf[i]);
+#pragma unroll
+      for (int q = 0; q < 10; ++q) st_plane_nt(lam_prev + (9 + q) * PA, oc, clg[q]);
+    }
+    if (own) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) clf[i] = lf[i];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) clg[q] = lg[q];
+    }
 #pragma unroll
     for (int q = 0; q < 19; ++q) cur[q] = nxt[q];
   }
   if (LES) {
     // the block's sums into acc[b] (C_Sv) and acc[nslots + b] (C_Sb), reduced
     // in the (now idle) moment buffer
-    float* red = &mac[0][0][0];
-    static_assert(3 * 5 * kAdjKinCols >= 2 * kAdjKinThreads, "moment buffer too small");
-    red[tx] = dcs.v;
-    red[kAdjKinThreads + tx] = dcs.b;
     __syncthreads();
-    if (tx == 0) {
+    float* red = &mac[0][0][0];
+    static_assert(3 * 5 * (kT3Cols + 4) >= 2 * kT3Threads, "moment buffer too small");
+    red[tid] = dcs.v;
+    red[kT3Threads + tid] = dcs.b;
+    __syncthreads();
+    if (tid == 0) {
       double sv = 0.0, sb = 0.0;
-      for (int t = 0; t < kAdjKinThreads; ++t) {
-        sv += double(red[t]);
-        sb += double(red[kAdjKinThreads + t]);
+      for (int i = 0; i < kT3Threads; ++i) {
+        sv += double(red[i]);
+        sb += double(red[kT3Threads + i]);
       }
       acc[blockIdx.x] += sv;
       acc[nslots + blockIdx.x] += sb;
     }
   }
-}
-
-// Pass B.  One thread per site: the transposed gradient stencil over the
-// neighbours' gradient adjoints, added to the site's moment adjoints.
-__global__ __launch_bounds__(256) void k_adj_kin_b(const float* __restrict__ gb,
-                                                   float* __restrict__ lam, Geom ga, int tiles_x) {
-  const int x = (int(blockIdx.x) % tiles_x) * 256 + int(threadIdx.x);
-  const int y = int(blockIdx.x) / tiles_x;
-  if (x >= ga.nx) return;
-  const int xm = x == 0 ? ga.nx - 1 : x - 1, xp = x == ga.nx - 1 ? 0 : x + 1;
-  const unsigned r0 = unsigned(y) * ga.pitch,
-                 rm = unsigned(y == 0 ? ga.ny - 1 : y - 1) * ga.pitch,
-                 rp = unsigned(y == ga.ny - 1 ? 0 : y + 1) * ga.pitch;
-  const long long PA = ga.plane;
-  float eta[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const float* bx = gb + k * PA;
-    const float* by = gb + (5 + k) * PA;
-    eta[k] = (1.0f / 3.0f) * ((ld_elem(bx, r0 + xm) - ld_elem(bx, r0 + xp)) +
-                              (ld_elem(by, rm + x) - ld_elem(by, rp + x))) +
-             (1.0f / 12.0f) * ((ld_elem(bx, rm + xm) + ld_elem(by, rm + xm)) +
-                               (ld_elem(by, rm + xp) - ld_elem(bx, rm + xp)) +
-                               (ld_elem(bx, rp + xm) - ld_elem(by, rp + xm)) -
-                               (ld_elem(bx, rp + xp) + ld_elem(by, rp + xp)));
-  }
-  const unsigned oc = r0 + x;
-  float lf[9], lg[10];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) lf[i] = ld_elem(lam + i * PA, oc);
-#pragma unroll
-  for (int q = 0; q < 10; ++q) lg[q] = ld_elem(lam + (9 + q) * PA, oc);
-  add_moment_adjoints(eta, lf, lg);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) st_plane_nt(lam + i * PA, oc, lf[i]);
-#pragma unroll
-  for (int q = 0; q < 10; ++q) st_plane_nt(lam + (9 + q) * PA, oc, lg[q]);
 }
 
 // ------------------------------------------- two reverse steps in one pass
@@ -1076,35 +1092,40 @@ bool adj_step2_pays(const Geom& g) {
   return tiles_x * ((g.ny + 7) / 8) >= 512;
 }
 
+// Strip height of the kinetic reverse step: about 512 blocks (two per CU; two
+// halo rows of part A and four of gathers per strip), 8 to 256 rows.  At 4096^2
+// (128-row strips) that took 1.31 ms per step, against 1.60 with 384 blocks,
+// 1.65 with 768 or 1536 and 2.16 with 256.
+static int adj_kin_rows(const Geom& g) {
+  const long long tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
+  const long long rows = (tiles_x * g.ny + 511) / 512;
+  return int(rows < 8 ? 8 : (rows > 256 ? 256 : rows));
+}
+
 hipError_t launch_adj_step_kin(int storage, bool les, const void* state, const float* lam_next,
-                               float* lam_prev, float* gb, double* acc, const Geom& g,
-                               const Geom& ga, const Rates& r, double delta2, hipStream_t s) {
-  const int tiles_x = (g.nx + kAdjKinThreads - 1) / kAdjKinThreads;
-  const int strips = (g.ny + kAdjKinRows - 1) / kAdjKinRows;
-  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kAdjKinThreads);
+                               float* lam_prev, double* acc, const Geom& g, const Geom& ga,
+                               const Rates& r, double delta2, hipStream_t s) {
+  const int tiles_x = (g.nx + kT3Cols - 1) / kT3Cols;
+  const int rows = adj_kin_rows(g);
+  const int strips = (g.ny + rows - 1) / rows;
+  const dim3 grid(unsigned(tiles_x) * unsigned(strips)), block(kT3Threads);
   const AdjConsts ac{float(18.0 * delta2), float(36.0 * delta2)};
   const float c12 = float(delta2 / 12.0);
   const int nslots = adj_step_blocks(g);
-  if (storage == LBMHD_FP32) {
-    auto* st = static_cast<const float*>(state);
+  auto go = [&](auto fp32) {
+    constexpr int ST = decltype(fp32)::value ? LBMHD_FP32 : LBMHD_FP16;
+    auto* st = static_cast<const typename Dec<ST>::T*>(state);
     if (les)
-      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP32, true>), grid, block, 0, s, st, lam_next,
-                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
+      hipLaunchKernelGGL((k_adj_kin<ST, true>), grid, block, 0, s, st, lam_next, lam_prev, acc,
+                         g, ga, r, ac, c12, tiles_x, rows, nslots);
     else
-      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP32, false>), grid, block, 0, s, st, lam_next,
-                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
-  } else {
-    auto* st = static_cast<const _Float16*>(state);
-    if (les)
-      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP16, true>), grid, block, 0, s, st, lam_next,
-                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
-    else
-      hipLaunchKernelGGL((k_adj_kin_a<LBMHD_FP16, false>), grid, block, 0, s, st, lam_next,
-                         lam_prev, gb, acc, g, ga, r, ac, c12, tiles_x, nslots);
-  }
-  const int tb = (ga.nx + 255) / 256;
-  hipLaunchKernelGGL(k_adj_kin_b, dim3(unsigned(tb) * unsigned(ga.ny)), dim3(256), 0, s, gb,
-                     lam_prev, ga, tb);
+      hipLaunchKernelGGL((k_adj_kin<ST, false>), grid, block, 0, s, st, lam_next, lam_prev, acc,
+                         g, ga, r, ac, c12, tiles_x, rows, nslots);
+  };
+  if (storage == LBMHD_FP32)
+    go(std::true_type{});
+  else
+    go(std::false_type{});
   return hipGetLastError();
 }
 

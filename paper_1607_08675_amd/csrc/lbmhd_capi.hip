@@ -118,14 +118,9 @@ bool rate_ok(double s) { return s > 0.0 && s < 2.0; }
 
 // Workspace (doubles): per-block partials of the reductions, then 32 result
 // slots ([0, 16) diagnostics, [16] the C_Sv sum, [17] the mismatch, [18] the
-// C_Sb sum); with the kinetic closure, ten FP32 planes in the adjoint layout
-// follow (the reverse step's gradient adjoints).
+// C_Sb sum).
 size_t workspace_doubles() { return size_t(lbk::kDiagBlocks) * lbk::kDiagSlots + 32; }
 double* ws_out(lbmhd_t* h) { return h->ws + size_t(lbk::kDiagBlocks) * lbk::kDiagSlots; }
-float* ws_kin(lbmhd_t* h) {
-  return reinterpret_cast<float*>(reinterpret_cast<char*>(h->ws) +
-                                  round_up(workspace_doubles() * sizeof(double), kAlign));
-}
 
 int need_bound(lbmhd_t* h) {
   if (!h) return LBMHD_ERR_INVALID_ARG;
@@ -171,8 +166,8 @@ hipError_t adj_one(lbmhd_t* h, const void* x, const float* from, float* to, doub
   const double d2 = h->p.delta * h->p.delta;
   const bool smag = (h->p.les & 1) != 0;
   if (h->p.les & 2)
-    return lbk::launch_adj_step_kin(h->p.storage, smag, x, from, to, ws_kin(h), acc, h->geo,
-                                    h->geoa, h->rates, d2, h->stream);
+    return lbk::launch_adj_step_kin(h->p.storage, smag, x, from, to, acc, h->geo, h->geoa,
+                                    h->rates, d2, h->stream);
   return lbk::launch_adj_step(h->p.storage, smag, x, from, to, acc, h->geo, h->geoa, h->rates,
                               d2, h->stream);
 }
@@ -387,7 +382,6 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
   h->lattice_bytes = size_t(lbk::kNPop) * size_t(g.plane) * esize;
   h->adj_lattice_bytes = size_t(lbk::kNPop) * size_t(ga.plane) * 4;
   h->workspace_bytes = round_up(workspace_doubles() * sizeof(double), kAlign);
-  if (p->les & 2) h->workspace_bytes += round_up(10 * size_t(ga.plane) * 4, kAlign);
   h->adj_acc_bytes = round_up(2 * size_t(lbk::adj_step_blocks(g)) * sizeof(double), kAlign);
   *out = h;
   return LBMHD_OK;

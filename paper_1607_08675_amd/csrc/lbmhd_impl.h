@@ -139,11 +139,11 @@ hipError_t launch_adj_step2(int storage, bool les_fwd, bool les, const void* sta
 // Whether launch_adj_step2 fills the chip on this lattice.
 bool adj_step2_pays(const Geom& g);
 // The same reverse step for the kinetic closure (les = 2, or 3 with the
-// Smagorinsky-MHD closure): two passes, gb = ten scratch planes in the
-// adjoint layout.
+// Smagorinsky-MHD closure): one walk over strips of rows, the gradient
+// adjoints of the neighbours kept on chip.
 hipError_t launch_adj_step_kin(int storage, bool les, const void* state, const float* lam_next,
-                               float* lam_prev, float* gb, double* acc, const Geom& g,
-                               const Geom& ga, const Rates& r, double delta2, hipStream_t s);
+                               float* lam_prev, double* acc, const Geom& g, const Geom& ga,
+                               const Rates& r, double delta2, hipStream_t s);
 hipError_t launch_sum(const double* in, long long n, double* out_dev, hipStream_t s);
 hipError_t launch_adj_fields(const float* lam0, const double* rho0, const double* ux0,
                              const double* uy0, const double* bx0, const double* by0,
