@@ -557,7 +557,8 @@ __device__ __forceinline__ void add_moment_adjoints(const float (&m)[5], float (
 // a = y0 - 1 + t on the tile's columns and one halo column on each side (the
 // ten gradient adjoints go to a second 3-row LDS ring), and part B to row
 // a - 1, whose part-A adjoint the thread carried from the last pass in
-// registers; lam_prev is written once.  The fifth wave owns the halo columns
+// registers; lam_prev is written once (with FP32 states the gather of pass
+// t + 1 is issued during pass t).  The fifth wave owns the halo columns
 // (lanes 0 .. 3: x0 - 2, x0 - 1, x0 + wt, x0 + wt + 1; part A on the inner
 // two).  Two barriers per pass.  HBM bytes per site: the state gather, the
 // lam_next gather and the lam_prev store, plus four halo rows of gathers and
@@ -617,7 +618,12 @@ __global__ __launch_bounds__(kT3Threads) void k_adj_kin(
     mac[slot][4][mc] = (p[14] + p[15]) + (p[16] + p[17]) + p[18];
   };
   CsGrad dcs{0.0f, 0.0f};
-  float cur[19], nxt[19];
+  // With FP32 states the next pass's gather is issued right after the first
+  // barrier and flies during parts A and B (1.03 / 1.18 ms per step at 4096^2
+  // with les = 2 / 3, against 1.31 / 1.30 gathering at the start of each
+  // pass); with FP16 states that ran slower (1.50 against 1.19 ms).
+  constexpr bool kPf = ST == LBMHD_FP32;
+  float cur[19], nxt[19], nx2[19];
   float clf[9], clg[10];   // part-A adjoint of the last pass's row (own columns)
 #pragma unroll
   for (int i = 0; i < 9; ++i) clf[i] = 0.0f;
@@ -628,15 +634,17 @@ __global__ __launch_bounds__(kT3Threads) void k_adj_kin(
     moments(nxt, 0);
     gather(y0 - 1, cur);
     moments(cur, 1);
+    if (kPf) gather(y0, nxt);
   }
   for (int t = 0; t < h + 2; ++t) {
     const int a = y0 - 1 + t;
     const int sm = t % 3, s0 = (t + 1) % 3, sp = (t + 2) % 3;
     if (hasm) {
-      gather(a + 1, nxt);
+      if (!kPf) gather(a + 1, nxt);
       moments(nxt, sp);
     }
     __syncthreads();
+    if (kPf && hasm && t + 1 < h + 2) gather(a + 2, nx2);
     // part A at row a
     float lf[9], lg[10];
     if (hasa) {
@@ -721,7 +729,10 @@ __global__ __launch_bounds__(kT3Threads) void k_adj_kin(
       for (int q = 0; q < 10; ++q) clg[q] = lg[q];
     }
 #pragma unroll
-    for (int q = 0; q < 19; ++q) cur[q] = nxt[q];
+    for (int q = 0; q < 19; ++q) {
+      cur[q] = nxt[q];
+      if (kPf) nxt[q] = nx2[q];
+    }
   }
   if (LES) {
     // the block's sums into acc[b] (C_Sv) and acc[nslots + b] (C_Sb), reduced
