@@ -9,9 +9,10 @@ writes the row padding or the gaps: both bound lattices, the stored
 trajectories and the adjoint buffers are filled with a sentinel byte first,
 then every kind of pass runs (one, two and three steps per pass, in place,
 the closures that read the neighbours, the stored trajectories, single and
-paired reverse steps), and every byte outside the stored elements must still
-hold the sentinel.  Lattices 300 x 70 (FP32 rows padded from 1200 to 1280
-bytes) and 100 x 36 (FP16: 200 to 256 bytes).
+paired reverse steps, the kinetic closure's reverse step), and every byte
+outside the stored elements must still hold the sentinel.  Lattices 300 x 70
+(FP32 rows padded from 1200 to 1280 bytes) and 100 x 36 (FP16: 200 to 256
+bytes).
 """
 import numpy as np
 import pytest
@@ -70,11 +71,11 @@ def test_layout_places_every_population(lb):
 
 @pytest.mark.parametrize("storage,nx,ny", [("fp32", 300, 70), ("fp16", 100, 36)])
 @pytest.mark.parametrize("kind", ["single", "pairs", "triples", "inplace", "kinetic",
-                                  "cross-helicity", "store", "adjoint"])
+                                  "cross-helicity", "store", "adjoint", "kinetic-adjoint"])
 def test_no_kernel_writes_padding_or_gaps(lb, storage, nx, ny, kind):
     print(f"\nlayout {kind} {storage} {nx}x{ny}", flush=True)
     esize = 4 if storage == "fp32" else 2
-    les = {"kinetic": 2, "cross-helicity": 4}.get(kind, 1)
+    les = {"kinetic": 2, "cross-helicity": 4, "kinetic-adjoint": 3}.get(kind, 1)
     spp = {"single": 1, "pairs": 2, "triples": 3}.get(kind, 0)
     if kind in ("kinetic", "cross-helicity"):
         spp = 2
@@ -93,7 +94,7 @@ def test_no_kernel_writes_padding_or_gaps(lb, storage, nx, ny, kind):
         half = torch.full((2, L.lattice_bytes), SENTINEL, dtype=torch.uint8, device="cuda")
         L.step_store_pairs(L.save_state(), half, 2)
         extra = [store[i] for i in range(5)] + [half[i] for i in range(2)]
-    elif kind == "adjoint":
+    elif kind in ("adjoint", "kinetic-adjoint"):
         amask = element_mask(L.adj_lattice_bytes, L.adj_plane, L.adj_pitch, nx, ny, 4)
         x0 = L.save_state()
         lam = [L.new_adj_buffer() for _ in range(3)]
@@ -102,7 +103,10 @@ def test_no_kernel_writes_padding_or_gaps(lb, storage, nx, ny, kind):
         acc = L.new_adj_acc()
         L.adj_seed_energy(x0, lam[0])
         L.adj_step(x0, lam[0], lam[1], acc)
-        L.adj_step2(x0, lam[1], lam[2], acc)
+        if kind == "adjoint":
+            L.adj_step2(x0, lam[1], lam[2], acc)
+        else:
+            L.adj_step(x0, lam[1], lam[2], acc)
         torch.cuda.synchronize()
         for t in lam:
             ok, bad = untouched(t.view(torch.uint8), amask)
