@@ -5,7 +5,9 @@ Headline (``value``): site updates per second (MLUPS) of the FP32
 stream-collide update on a 4096 x 4096 periodic Orszag-Tang vortex
 (nu = eta = 1e-5, Smagorinsky-MHD closure with C_S = 0.1), inputs resident in
 HBM, K timed steps with the FP64 diagnostics reduction run every 100 steps
-inside the timed region.  Steps go three per pass over the lattice (the
+inside the timed region (one lbmhd_run call: each diagnostics pass overlaps
+the next kernel pass, and the host waits once, at the end, for all results).
+Steps go three per pass over the lattice (the
 intermediate states stay on chip; the results equal single steps bit for
 bit), so the dominant kernel moves 152 B per site per launch for three
 updates; the single-step kernel is timed beside it.  The same JSON line also reports the FP16-storage
@@ -102,23 +104,28 @@ def valu_roofline(key, ms_per_launch):
 
 
 def timed_steps(torch, lat, steps, diag_every):
-    """Run `steps` steps (diagnostics every diag_every) between two events on the
+    """Run `steps` steps with the FP64 diagnostics after every diag_every of
+    them (one lbmhd_run call: each diagnostics pass overlaps the next kernel
+    pass, and the host waits once, at the end) between two events on the
     lattice's stream; returns milliseconds."""
     s = lat.stream
+    dev = torch.empty(16 * max(1, steps // diag_every), dtype=torch.float64, device="cuda")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(s)
-    done = 0
-    while done < steps:
-        k = min(diag_every, steps - done) if diag_every else steps - done
-        lat.step(k)
-        done += k
-        if diag_every and done % diag_every == 0:
-            lat.diag()
+    lat.run(steps, diag_every, dev)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
+
+
+def warm_up(lat, steps):
+    """Untimed steps through lbmhd_run with at least one diagnostics pass, so
+    that the library's diagnostics stream has run before the timed call (its
+    first dispatch costs a few milliseconds once)."""
+    if steps > 0:
+        lat.run(steps, min(100, steps))
 
 
 def burst_ms_per_step(torch, lat, steps):
@@ -152,7 +159,7 @@ def fp32_leg(torch, args):
     torch.cuda.empty_cache()
     lat = Lattice(cfg)
     lat.init_fields(*fields)
-    lat.step(args.warmup)
+    warm_up(lat, args.warmup)
     torch.cuda.synchronize()
     log(f"fp32 4096^2: warmup {args.warmup} done, timing {args.steps} steps")
     t0 = time.perf_counter()
@@ -269,7 +276,8 @@ def fp16_leg(torch, args):
         m = lat.macro()
         snaps[st] = torch.stack([m["ux"], m["uy"], m["bx"], m["by"]])
         del m
-        lat.init_fields(*fields).step(args.warmup)
+        lat.init_fields(*fields)
+        warm_up(lat, args.warmup)
         torch.cuda.synchronize()
         log(f"{st} 8192^2: timing {args.fp16_steps} steps")
         ms = timed_steps(torch, lat, args.fp16_steps, 100)

@@ -134,10 +134,10 @@ typedef struct {
                              moments (les = 2, 3, 4, 6): 0 takes pairs with
                              FP32 storage from 512 tiles of 8 rows by 256
                              columns on (else single steps), 2 and 3 always
-                             take pairs.  1 takes single steps.  A
-                             remainder goes in pairs (a remainder of one takes
-                             the last triple along as two pairs), so a single
-                             step runs only when one is left.  Other values
+                             take pairs.  1 takes single steps.  After the
+                             triples a remainder of two steps is one pair and
+                             of one a single step; after pairs a single step
+                             runs only when one is left.  Other values
                              are rejected.  The
                              result is bit for bit that of single steps, in
                              FP32 and FP16 storage (every kernel rounds the
@@ -290,6 +290,34 @@ int lbmhd_mismatch(lbmhd_t* h, const void* state, const double* ux_t, const doub
  * Synchronises the bound stream.  Returns LBMHD_ERR_NONFINITE (with *out
  * filled) when any population is NaN or Inf. */
 int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out);
+
+/* nsteps >= 0 steps of the update (Sec. 3), as lbmhd_step, with the
+ * diagnostics of lbmhd_diag taken after steps every, 2 every, ... (those
+ * <= nsteps) and no wait on the host between them.  With two bound lattices
+ * each diagnostics pass runs on a second stream of the handle (one HIP stream
+ * and two events, created at the first such call, no device memory): it
+ * starts after the bound stream's work so far and overlaps the next kernel
+ * pass, which only reads that state; a pass that would overwrite a state still
+ * being read waits for it on the bound stream.  An in-place lattice takes its
+ * diagnostics on the bound stream.  The reductions' block partials use the
+ * bound workspace.
+ *   dev   -- device memory, 8-byte aligned, of at least nout * 16 doubles,
+ *            overlapping no bound buffer; diagnostics k is left in doubles
+ *            16k .. 16k + 12 in the order mass, mom_x, mom_y, flux_x,
+ *            flux_y, e_kin, e_mag, cross_helicity, enstrophy, current_sq,
+ *            nonfinite, max_abs_divB, max_u, the rest unspecified;
+ *   out   -- host array of nout >= nsteps / every results, with step set.
+ * Results equal those of lbmhd_diag at the same steps bit for bit (the same
+ * kernels and reduction order).  When at least one diagnostics pass is taken,
+ * the call synchronises the bound stream once, at the end, and returns
+ * LBMHD_ERR_NONFINITE (every result filled) when any pass found NaN or Inf
+ * populations; with every = 0 or nsteps < every it is lbmhd_step (dev and out
+ * unused, asynchronous).  Errors: LBMHD_ERR_INVALID_ARG for negative nsteps or
+ * every, NULL or undersized dev / out, or dev unaligned or overlapping a bound
+ * buffer; LBMHD_ERR_NOT_BOUND, LBMHD_ERR_HIP.  Calls on one handle from
+ * several threads race. */
+int lbmhd_run(lbmhd_t* h, int64_t nsteps, int64_t every, double* dev, lbmhd_diag_t* out,
+              int64_t nout);
 
 /* Decode the current state to plain populations (device, 19*nx*ny float64):
  * f_i = w_i + deviation.  Asynchronous. */

@@ -30,7 +30,7 @@ EXPORTS = (
     "lbmhd_layout", "lbmhd_bind", "lbmhd_init_fields", "lbmhd_step", "lbmhd_steps_per_pass",
     "lbmhd_step_between", "lbmhd_step_store", "lbmhd_step_store_pairs",
     "lbmhd_macro",
-    "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_get_populations",
+    "lbmhd_macro_box", "lbmhd_mismatch", "lbmhd_diag", "lbmhd_run", "lbmhd_get_populations",
     "lbmhd_set_populations", "lbmhd_save_state", "lbmhd_load_state", "lbmhd_get_step",
     "lbmhd_current_state",
     "lbmhd_energy", "lbmhd_adj_seed_energy", "lbmhd_adj_seed_mismatch", "lbmhd_adj_step",
@@ -129,6 +129,7 @@ def lib():
             "lbmhd_mismatch": [vp] * 6 + [P(ctypes.c_double)],
             "lbmhd_adj_seed_mismatch": [vp] * 6 + [ctypes.c_double, vp],
             "lbmhd_diag": [vp, P(Diag)],
+            "lbmhd_run": [vp, i64, i64, vp, P(Diag), i64],
             "lbmhd_diag_noalloc": [vp, P(Diag)],
             "lbmhd_get_populations": [vp, vp],
             "lbmhd_set_populations": [vp, vp, i64],

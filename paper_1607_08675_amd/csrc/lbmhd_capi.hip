@@ -12,6 +12,7 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "lbmhd_impl.h"
 
@@ -28,6 +29,12 @@ struct lbmhd {
   int cur = 0;  // index of the lattice holding the current state
   bool reversed = false;  // in-place mode: the lattice is in the reversed layout
   int64_t step = 0;
+  // lbmhd_run: the stream its diagnostics passes run on, the events that
+  // order them against the bound stream, and which bound lattices a pass
+  // enqueued there may still be reading
+  hipStream_t side = nullptr;
+  hipEvent_t ev_state = nullptr, ev_diag = nullptr;
+  bool reading[2] = {false, false};
   std::string err;
 };
 
@@ -388,6 +395,12 @@ int lbmhd_create(const lbmhd_params* p, lbmhd_t** out) {
 }
 
 int lbmhd_destroy(lbmhd_t* h) {
+  if (h && h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h && h->ev_state) (void)hipEventDestroy(h->ev_state);
+  if (h && h->ev_diag) (void)hipEventDestroy(h->ev_diag);
   delete h;
   return LBMHD_OK;
 }
@@ -461,6 +474,16 @@ int lbmhd_steps_per_pass(const lbmhd_t* h, int32_t* out) {
   return LBMHD_OK;
 }
 
+// Before a pass writes bound lattice i: if a diagnostics pass of lbmhd_run
+// may still read it, the bound stream waits for the last one enqueued (the
+// side stream runs them in order, so that covers every earlier one too).
+int before_write(lbmhd_t* h, int i) {
+  if (!h->reading[i]) return LBMHD_OK;
+  h->reading[0] = h->reading[1] = false;
+  hipError_t e = hipStreamWaitEvent(h->stream, h->ev_diag, 0);
+  return e == hipSuccess ? LBMHD_OK : hip_fail(h, e, "diagnostics wait");
+}
+
 int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   if (int rc = need_bound(h)) return rc;
   if (nsteps < 0) return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count");
@@ -468,10 +491,11 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   int64_t t = 0;
   const int ps = pass_steps(h);
   if (ps == 3) {
-    // a remainder of one step goes with the last triple as two pairs
-    int64_t triples = nsteps / 3;
-    if (nsteps % 3 == 1 && triples > 0) --triples;
-    for (; t < 3 * triples; t += 3) {
+    // a remainder of two steps is one pair, of one step a single step: a
+    // triple and a single step took 5-8% less time than two pairs from 2048^2
+    // to 8192^2 on MI355X (as long at 1024^2)
+    for (; t + 3 <= nsteps; t += 3) {
+      if (int rc = before_write(h, 1 - h->cur)) return rc;
       hipError_t e = lbk::launch_step_t3(les, h->lat[h->cur], h->lat[1 - h->cur], nullptr,
                                          nullptr, h->geo, h->rates, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "step launch");
@@ -481,6 +505,7 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
   }
   if (ps >= 2) {
     for (; t + 2 <= nsteps; t += 2) {
+      if (int rc = before_write(h, 1 - h->cur)) return rc;
       hipError_t e = launch_two_steps(h, h->lat[h->cur], h->lat[1 - h->cur], nullptr);
       if (e != hipSuccess) return hip_fail(h, e, "step launch");
       h->cur = 1 - h->cur;
@@ -488,6 +513,7 @@ int lbmhd_step(lbmhd_t* h, int64_t nsteps) {
     }
   }
   for (; t < nsteps; ++t) {
+    if (int rc = before_write(h, h->p.inplace ? 0 : 1 - h->cur)) return rc;
     hipError_t e;
     if (h->p.inplace) {
       e = lbk::launch_step_aa(h->p.storage, les, h->reversed ? 1 : 0, h->lat[0], h->geo,
@@ -655,6 +681,83 @@ int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out) {
   if (int rc = current(h, &st)) return rc;
   if (int rc = run_diag(h, st, v)) return rc;
   return fill_diag(h, v, out);
+}
+
+// The diagnostics of the state just reached, enqueued without waiting on the
+// host: results to dev (16 doubles).  With two lattices the pass runs on the
+// side stream after the bound stream's work so far, and the lattice it reads
+// is marked so that the next pass that writes it waits for it; an in-place
+// lattice (whose next pass rewrites it) is read on the bound stream.
+int enqueue_diag(lbmhd_t* h, double* dev) {
+  const void* st = nullptr;
+  if (int rc = current(h, &st)) return rc;
+  hipError_t e;
+  if (h->p.inplace) {
+    e = lbk::launch_diag(h->p.storage, st, h->ws, dev, h->geo, h->stream);
+    return e == hipSuccess ? LBMHD_OK : hip_fail(h, e, "diagnostics launch");
+  }
+  if ((e = hipEventRecord(h->ev_state, h->stream)) != hipSuccess ||
+      (e = hipStreamWaitEvent(h->side, h->ev_state, 0)) != hipSuccess)
+    return hip_fail(h, e, "diagnostics ordering");
+  if ((e = lbk::launch_diag(h->p.storage, st, h->ws, dev, h->geo, h->side)) != hipSuccess)
+    return hip_fail(h, e, "diagnostics launch");
+  if ((e = hipEventRecord(h->ev_diag, h->side)) != hipSuccess)
+    return hip_fail(h, e, "diagnostics ordering");
+  h->reading[h->cur] = true;
+  return LBMHD_OK;
+}
+
+int lbmhd_run(lbmhd_t* h, int64_t nsteps, int64_t every, double* dev, lbmhd_diag_t* out,
+              int64_t nout) {
+  if (int rc = need_bound(h)) return rc;
+  if (nsteps < 0 || every < 0)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "negative step count or interval");
+  if (every == 0 || nsteps < every) return lbmhd_step(h, nsteps);
+  const int64_t nd = nsteps / every;
+  if (!dev || !out || nout < nd)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "diagnostics buffers missing or too small");
+  const size_t dev_bytes = size_t(nd) * lbk::kDiagSlots * sizeof(double);
+  if (reinterpret_cast<uintptr_t>(dev) % alignof(double) != 0)
+    return fail(h, LBMHD_ERR_INVALID_ARG, "unaligned diagnostics buffer");
+  for (const void* b : {(const void*)h->lat[0], (const void*)h->lat[1]})
+    if (b && overlap(dev, dev_bytes, b, h->lattice_bytes))
+      return fail(h, LBMHD_ERR_INVALID_ARG, "diagnostics buffer overlaps a bound lattice");
+  if (overlap(dev, dev_bytes, h->ws, h->workspace_bytes))
+    return fail(h, LBMHD_ERR_INVALID_ARG, "diagnostics buffer overlaps the workspace");
+  if (!h->p.inplace && !h->side) {
+    hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_state, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_diag, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(h, e, "diagnostics stream");
+  }
+  std::vector<int64_t> at(size_t(nd), 0);
+  int rc = LBMHD_OK;
+  for (int64_t k = 0; k < nd && rc == LBMHD_OK; ++k) {
+    rc = lbmhd_step(h, every);
+    at[size_t(k)] = h->step;
+    if (rc == LBMHD_OK) rc = enqueue_diag(h, dev + k * lbk::kDiagSlots);
+  }
+  if (rc == LBMHD_OK) rc = lbmhd_step(h, nsteps - nd * every);
+  // later work on the bound stream (and the copy below) follows every pass
+  if (h->reading[0] || h->reading[1]) {
+    h->reading[0] = h->reading[1] = false;
+    hipError_t e = hipStreamWaitEvent(h->stream, h->ev_diag, 0);
+    if (e != hipSuccess && rc == LBMHD_OK) rc = hip_fail(h, e, "diagnostics wait");
+  }
+  if (rc != LBMHD_OK) return rc;
+  std::vector<double> v(size_t(nd) * lbk::kDiagSlots);
+  hipError_t e = hipMemcpyAsync(v.data(), dev, dev_bytes, hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "diagnostics copy");
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
+    return hip_fail(h, e, "diagnostics synchronise");
+  const int64_t now = h->step;
+  for (int64_t k = 0; k < nd; ++k) {
+    h->step = at[size_t(k)];
+    const int r = fill_diag(h, v.data() + k * lbk::kDiagSlots, out + k);
+    if (r != LBMHD_OK && rc == LBMHD_OK) rc = r;
+  }
+  h->step = now;
+  return rc;
 }
 
 int lbmhd_diag_noalloc(lbmhd_t* h, lbmhd_diag_t* out) {

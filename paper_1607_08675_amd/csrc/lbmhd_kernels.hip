@@ -1159,7 +1159,7 @@ __device__ void block_reduce(double (&v)[kNRed], double* __restrict__ out) {
     }
     __syncthreads();
   }
-  if (t < kNRed) out[t] = sh[t][0];
+  if (t < kNRed) out[t] = t == kMaxU ? sqrt(sh[t][0]) : sh[t][0];
 }
 
 // One pass over the lattice: a block of kDiagThreads threads owns as many
@@ -1171,7 +1171,10 @@ __device__ void block_reduce(double (&v)[kNRed], double* __restrict__ out) {
 // maxima of the site's own fields and the centred differences
 // d_x a = (a(x + 1) - a(x - 1)) / 2 of div B, w = d_x u_y - d_y u_x and
 // j = d_x B_y - d_y B_x.  A site with a non-finite population has rho = NaN.
-// Each block writes one partial (sums, maxima) to part[blockIdx.x].
+// Each block writes one partial (sums, maxima) to part[blockIdx.x], with the
+// largest |u|^2 in the slot of max |u|: the final fold takes its square root
+// (a correctly rounded square root is monotone, so the root of the largest
+// square is the largest root).
 constexpr int kDiagThreads = 256;
 constexpr int kDiagRows = 64;   // 8-11% faster than 16 rows (fewer halo rows)
 
@@ -1270,7 +1273,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag(const typename Codec<ST>:
         v[kSumJ2] += 0.5 * jz * jz;
         v[kSumBad] += isfinite(r) ? 0.0 : 1.0;
         v[kMaxDiv] = fmax(v[kMaxDiv], fabs(div));
-        v[kMaxU] = fmax(v[kMaxU], sqrt(ux * ux + uy * uy));
+        v[kMaxU] = fmax(v[kMaxU], ux * ux + uy * uy);   // |u|^2: rooted in the fold
       }
       __syncthreads();
     }

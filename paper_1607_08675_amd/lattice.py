@@ -200,6 +200,26 @@ class Lattice:
             self._check(rc, "lbmhd_diag")
         return d.as_dict()
 
+    def run(self, n: int, every: int, dev: torch.Tensor = None,
+            raise_nonfinite: bool = False) -> list:
+        """n steps with the diagnostics of diag() after steps every, 2 every, ...
+        (lbmhd_run: no host wait between them, one at the end); returns their
+        dicts.  dev: optional device float64 buffer of at least 16 n // every
+        elements for the results (allocated here when not given)."""
+        nd = n // every if every > 0 else 0
+        if nd == 0:
+            self.step(n)
+            return []
+        if dev is None:
+            dev = torch.empty(16 * nd, dtype=torch.float64, device=self.device)
+        elif dev.dtype != torch.float64 or dev.numel() < 16 * nd or not dev.is_contiguous():
+            raise ValueError("dev must be a contiguous float64 tensor of 16 n // every elements")
+        out = (C.Diag * nd)()
+        rc = self._L.lbmhd_run(self._h, int(n), int(every), _ptr(dev), out, nd)
+        if rc != C.LBMHD_ERR_NONFINITE or raise_nonfinite:
+            self._check(rc, "lbmhd_run")
+        return [d.as_dict() for d in out]
+
     def diag_noalloc(self, raise_nonfinite: bool = False) -> dict:
         """diag() through lbmhd_diag_noalloc: the reductions' scratch is the
         library's static device array, not the bound workspace."""
@@ -259,8 +279,8 @@ class Lattice:
     @property
     def steps_per_pass(self) -> int:
         """Steps one kernel pass covers in step(): 3 (FP32 triples), 2 or 1.
-        With 3, a remainder of two steps is one pair, and a remainder of one
-        step takes the last triple along as two pairs."""
+        With 3, a remainder of two steps is one pair and of one step a
+        single step."""
         v = ctypes.c_int32()
         self._check(self._L.lbmhd_steps_per_pass(self._h, ctypes.byref(v)),
                     "lbmhd_steps_per_pass")

@@ -148,6 +148,7 @@ def test_calls_before_bind_are_refused(capi):
     assert b"bind" in L.lbmhd_last_error(h)
     d = capi.Diag()
     assert L.lbmhd_diag(h, ctypes.byref(d)) == capi.LBMHD_ERR_NOT_BOUND
+    assert L.lbmhd_run(h, 10, 5, None, ctypes.byref(d), 2) == capi.LBMHD_ERR_NOT_BOUND
     assert L.lbmhd_bind(h, None, 0, None, 0, None, 0, None) == capi.LBMHD_ERR_INVALID_ARG
     step = ctypes.c_int64(-1)
     assert L.lbmhd_get_step(h, ctypes.byref(step)) == 0 and step.value == 0

@@ -149,10 +149,9 @@ T3_CASES = [(256, 64), (300, 70), (2, 2), (3, 5), (513, 9), (600, 60), (5, 3), (
 @pytest.mark.parametrize("les", [0, 1])
 @pytest.mark.parametrize("n", [3, 4, 5, 7])
 def test_three_steps_per_pass_equal_single_steps(lb, nx, ny, les, n):
-    """Three steps per pass (FP32): triples, the remainder in pairs (a
-    remainder of one takes the last triple along as two pairs), bit for bit
-    equal to single steps; full and ragged tiles and strips, halos wrapping
-    onto tiny lattices."""
+    """Three steps per pass (FP32): triples, then a remainder of two as one
+    pair and of one as a single step, bit for bit equal to single steps; full
+    and ragged tiles and strips, halos wrapping onto tiny lattices."""
     fields = random_fields(nx, ny, 23 + nx + ny)
     out = []
     for spp in (1, 3):
