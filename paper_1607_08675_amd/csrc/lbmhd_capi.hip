@@ -699,12 +699,12 @@ int enqueue_diag(lbmhd_t* h, double* dev) {
   if ((e = hipEventRecord(h->ev_state, h->stream)) != hipSuccess ||
       (e = hipStreamWaitEvent(h->side, h->ev_state, 0)) != hipSuccess)
     return hip_fail(h, e, "diagnostics ordering");
-  if ((e = lbk::launch_diag(h->p.storage, st, h->ws, dev, h->geo, h->side)) != hipSuccess)
-    return hip_fail(h, e, "diagnostics launch");
+  // whatever of the pass got enqueued, later writes of the lattice wait for it
+  const hipError_t el = lbk::launch_diag(h->p.storage, st, h->ws, dev, h->geo, h->side);
   if ((e = hipEventRecord(h->ev_diag, h->side)) != hipSuccess)
     return hip_fail(h, e, "diagnostics ordering");
   h->reading[h->cur] = true;
-  return LBMHD_OK;
+  return el == hipSuccess ? LBMHD_OK : hip_fail(h, el, "diagnostics launch");
 }
 
 int lbmhd_run(lbmhd_t* h, int64_t nsteps, int64_t every, double* dev, lbmhd_diag_t* out,
