@@ -298,7 +298,10 @@ int lbmhd_diag(lbmhd_t* h, lbmhd_diag_t* out);
  * and two events, created at the first such call, no device memory): it
  * starts after the bound stream's work so far and overlaps the next kernel
  * pass, which only reads that state; a pass that would overwrite a state still
- * being read waits for it on the bound stream.  An in-place lattice takes its
+ * being read waits for it on the bound stream.  Where lbmhd_step would end an
+ * interval with a single step (FP32 storage, les = 0 or 1: e.g. intervals of
+ * 3k + 1 steps taken in triples), that step and the diagnostics of its result
+ * are one pass on the bound stream instead.  An in-place lattice takes its
  * diagnostics on the bound stream.  The reductions' block partials use the
  * bound workspace.
  *   dev   -- device memory, 8-byte aligned, of at least nout * 16 doubles,

@@ -724,7 +724,13 @@ int lbmhd_run(lbmhd_t* h, int64_t nsteps, int64_t every, double* dev, lbmhd_diag
       return fail(h, LBMHD_ERR_INVALID_ARG, "diagnostics buffer overlaps a bound lattice");
   if (overlap(dev, dev_bytes, h->ws, h->workspace_bytes))
     return fail(h, LBMHD_ERR_INVALID_ARG, "diagnostics buffer overlaps the workspace");
-  if (!h->p.inplace && !h->side) {
+  // an interval that lbmhd_step ends with a single step (FP32 storage, a
+  // closure without neighbour terms) takes that step and the diagnostics of
+  // its result in one pass on the bound stream
+  const int ps = pass_steps(h);
+  const bool fuse = !h->p.inplace && h->p.storage == LBMHD_FP32 && !reads_neighbours(h) &&
+                    (ps == 1 || every % ps == 1);
+  if (!h->p.inplace && !fuse && !h->side) {
     hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_state, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_diag, hipEventDisableTiming);
@@ -733,9 +739,27 @@ int lbmhd_run(lbmhd_t* h, int64_t nsteps, int64_t every, double* dev, lbmhd_diag
   std::vector<int64_t> at(size_t(nd), 0);
   int rc = LBMHD_OK;
   for (int64_t k = 0; k < nd && rc == LBMHD_OK; ++k) {
-    rc = lbmhd_step(h, every);
+    if (fuse) {
+      rc = lbmhd_step(h, every - 1);
+      // the pass writes the workspace partials and the other lattice
+      if (rc == LBMHD_OK) rc = before_write(h, 0);
+      if (rc == LBMHD_OK) rc = before_write(h, 1);
+      if (rc == LBMHD_OK) {
+        hipError_t e = lbk::launch_step_diag(eddy_of(h) == 1, h->lat[h->cur], h->lat[1 - h->cur],
+                                             h->ws, dev + k * lbk::kDiagSlots, h->geo, h->rates,
+                                             h->stream);
+        if (e != hipSuccess) {
+          rc = hip_fail(h, e, "step and diagnostics launch");
+        } else {
+          h->cur = 1 - h->cur;
+          ++h->step;
+        }
+      }
+    } else {
+      rc = lbmhd_step(h, every);
+      if (rc == LBMHD_OK) rc = enqueue_diag(h, dev + k * lbk::kDiagSlots);
+    }
     at[size_t(k)] = h->step;
-    if (rc == LBMHD_OK) rc = enqueue_diag(h, dev + k * lbk::kDiagSlots);
   }
   if (rc == LBMHD_OK) rc = lbmhd_step(h, nsteps - nd * every);
   // later work on the bound stream (and the copy below) follows every pass

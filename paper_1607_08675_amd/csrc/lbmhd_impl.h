@@ -103,6 +103,10 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // kDiagBlocks x kDiagSlots doubles at part) folded into out_dev[0 .. 12].
 hipError_t launch_diag(int storage, const void* lat, double* part, double* out_dev,
                        const Geom& g, hipStream_t s);
+// One step src -> dst of FP32 storage (the plain or the Smagorinsky-MHD
+// update) fused with the diagnostics of dst, results as launch_diag's.
+hipError_t launch_step_diag(bool les, const void* src, void* dst, double* part, double* out_dev,
+                            const Geom& g, const Rates& r, hipStream_t s);
 // Number of block partials launch_diag writes for this lattice (<= kDiagBlocks).
 int diag_partials(const Geom& g);
 

@@ -1178,108 +1178,80 @@ __device__ void block_reduce(double (&v)[kNRed], double* __restrict__ out) {
 constexpr int kDiagThreads = 256;
 constexpr int kDiagRows = 64;   // 8-11% faster than 16 rows (fewer halo rows)
 
-template <int ST>
-__global__ __launch_bounds__(kDiagThreads) void k_diag(const typename Codec<ST>::T* __restrict__ lat,
-                                                       double* __restrict__ part, Geom geo,
-                                                       int tiles_x, int units) {
-  using C = Codec<ST>;
-  using T = typename C::T;
-  constexpr int NC = kDiagThreads + 2;
-  __shared__ double mac[3][5][NC];
-  const int tx = int(threadIdx.x);
-  double v[kNRed];
+constexpr int kDiagNC = kDiagThreads + 2;
+typedef double DiagRing[3][5][kDiagNC];   // rho, ux, uy, Bx, By of three rows
+
+// The moments of one site from its stored populations (deviations f - w in
+// the storage order, decoded by C) into column col of ring slot `slot`: rho
+// (NaN when a population is not finite), u = j / rho and B.  Contraction is
+// off here and in the two functions below, so that every kernel inlining
+// them forms the diagnostics identically.
+template <class C>
+__device__ __forceinline__ void diag_moments(const typename C::T (&p)[kNPop], DiagRing& mac,
+                                             int slot, int col) {
+#pragma clang fp contract(off)
+  bool ok = true;
+  double dr = 0.0, jx = 0.0, jy = 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll
-  for (int q = 0; q < kNRed; ++q) v[q] = 0.0;
-  for (int u = int(blockIdx.x); u < units; u += int(gridDim.x)) {
-    const int xt = (u % tiles_x) * kDiagThreads;
-    const int y0 = (u / tiles_x) * kDiagRows;
-    const int y1 = min(y0 + kDiagRows, geo.ny);
-    const int x = xt + tx;
-    const bool active = x < geo.nx;
-    const int xc = x % geo.nx;   // past the last column: its periodic images
-    const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1) : (xt + kDiagThreads) % geo.nx;
-    const int ch = tx == 0 ? 0 : NC - 1;
-    T raw[kNPop], rawh[kNPop];
-    auto load = [&](int xx, int yy, T (&p)[kNPop]) {
-      const unsigned o = unsigned(yy) * geo.pitch + unsigned(xx);
-#pragma unroll
-      for (int q = 0; q < kNPop; ++q) p[q] = ld_plane<T>(lat + q * geo.plane, o);
-    };
-    auto issue = [&](int yy) {
-      yy = yy < 0 ? yy + geo.ny : (yy >= geo.ny ? yy - geo.ny : yy);
-      load(xc, yy, raw);
-      if (tx < 2) load(xh, yy, rawh);
-    };
-    auto moments = [&](const T (&p)[kNPop], int slot, int col) {
-      bool ok = true;
-      double dr = 0.0, jx = 0.0, jy = 0.0, b0 = 0.0, b1 = 0.0;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const float f = C::dec(p[i]);
-        ok = ok && isfinite(f);
-        dr += double(f);
-        jx += kCx[i] * double(f);
-        jy += kCy[i] * double(f);
-      }
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const float gx = C::dec(p[9 + k]), gy = C::dec(p[14 + k]);
-        ok = ok && isfinite(gx) && isfinite(gy);
-        b0 += double(gx);
-        b1 += double(gy);
-      }
-      const double r = 1.0 + dr;
-      const double ir = 1.0 / r;
-      mac[slot][0][col] = ok ? r : __builtin_nan("");
-      mac[slot][1][col] = jx * ir;
-      mac[slot][2][col] = jy * ir;
-      mac[slot][3][col] = b0;
-      mac[slot][4][col] = b1;
-    };
-    auto commit = [&](int slot) {
-      moments(raw, slot, tx + 1);
-      if (tx < 2) moments(rawh, slot, ch);
-    };
-    issue(y0 - 1);
-    commit(0);
-    issue(y0);
-    commit(1);
-    issue(y0 + 1);
-    for (int y = y0; y < y1; ++y) {
-      const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
-      commit(sp);
-      if (y + 2 <= y1) issue(y + 2);
-      __syncthreads();
-      if (active) {
-        const int c = tx + 1;
-        const double r = mac[s0][0][c], ux = mac[s0][1][c], uy = mac[s0][2][c];
-        const double b0 = mac[s0][3][c], b1 = mac[s0][4][c];
-        const double jx = r * ux, jy = r * uy;
-        v[kSumMass] += r;
-        v[kSumMx] += jx;
-        v[kSumMy] += jy;
-        v[kSumBx] += b0;
-        v[kSumBy] += b1;
-        v[kSumEk] += 0.5 * (jx * ux + jy * uy);   // |j|^2 / (2 rho)
-        v[kSumEm] += 0.5 * (b0 * b0 + b1 * b1);
-        v[kSumHc] += ux * b0 + uy * b1;
-        const double div = 0.5 * (mac[s0][3][c + 1] - mac[s0][3][c - 1]) +
-                           0.5 * (mac[sp][4][c] - mac[sm][4][c]);
-        const double om = 0.5 * (mac[s0][2][c + 1] - mac[s0][2][c - 1]) -
-                          0.5 * (mac[sp][1][c] - mac[sm][1][c]);
-        const double jz = 0.5 * (mac[s0][4][c + 1] - mac[s0][4][c - 1]) -
-                          0.5 * (mac[sp][3][c] - mac[sm][3][c]);
-        v[kSumOm] += 0.5 * om * om;
-        v[kSumJ2] += 0.5 * jz * jz;
-        v[kSumBad] += isfinite(r) ? 0.0 : 1.0;
-        v[kMaxDiv] = fmax(v[kMaxDiv], fabs(div));
-        v[kMaxU] = fmax(v[kMaxU], ux * ux + uy * uy);   // |u|^2: rooted in the fold
-      }
-      __syncthreads();
-    }
+  for (int i = 0; i < 9; ++i) {
+    const float f = C::dec(p[i]);
+    ok = ok && isfinite(f);
+    dr += double(f);
+    jx += kCx[i] * double(f);
+    jy += kCy[i] * double(f);
   }
-  // block reduction in the (now idle) row buffer
-  static_assert(3 * 5 * NC >= kNRed * kDiagThreads, "row buffer too small to reduce in");
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const float gx = C::dec(p[9 + k]), gy = C::dec(p[14 + k]);
+    ok = ok && isfinite(gx) && isfinite(gy);
+    b0 += double(gx);
+    b1 += double(gy);
+  }
+  const double r = 1.0 + dr;
+  const double ir = 1.0 / r;
+  mac[slot][0][col] = ok ? r : __builtin_nan("");
+  mac[slot][1][col] = jx * ir;
+  mac[slot][2][col] = jy * ir;
+  mac[slot][3][col] = b0;
+  mac[slot][4][col] = b1;
+}
+
+// Adds the site in ring column c of the middle row (slot s0; sm below, sp
+// above) to the thread's sums and maxima.
+__device__ __forceinline__ void diag_accumulate(double (&v)[kNRed], const DiagRing& mac, int sm,
+                                                int s0, int sp, int c) {
+#pragma clang fp contract(off)
+  const double r = mac[s0][0][c], ux = mac[s0][1][c], uy = mac[s0][2][c];
+  const double b0 = mac[s0][3][c], b1 = mac[s0][4][c];
+  const double jx = r * ux, jy = r * uy;
+  v[kSumMass] += r;
+  v[kSumMx] += jx;
+  v[kSumMy] += jy;
+  v[kSumBx] += b0;
+  v[kSumBy] += b1;
+  v[kSumEk] += 0.5 * (jx * ux + jy * uy);   // |j|^2 / (2 rho)
+  v[kSumEm] += 0.5 * (b0 * b0 + b1 * b1);
+  v[kSumHc] += ux * b0 + uy * b1;
+  const double div = 0.5 * (mac[s0][3][c + 1] - mac[s0][3][c - 1]) +
+                     0.5 * (mac[sp][4][c] - mac[sm][4][c]);
+  const double om = 0.5 * (mac[s0][2][c + 1] - mac[s0][2][c - 1]) -
+                    0.5 * (mac[sp][1][c] - mac[sm][1][c]);
+  const double jz = 0.5 * (mac[s0][4][c + 1] - mac[s0][4][c - 1]) -
+                    0.5 * (mac[sp][3][c] - mac[sm][3][c]);
+  v[kSumOm] += 0.5 * om * om;
+  v[kSumJ2] += 0.5 * jz * jz;
+  v[kSumBad] += isfinite(r) ? 0.0 : 1.0;
+  v[kMaxDiv] = fmax(v[kMaxDiv], fabs(div));
+  v[kMaxU] = fmax(v[kMaxU], ux * ux + uy * uy);   // |u|^2: rooted in the fold
+}
+
+// The block's sums and maxima into part[blockIdx.x], reduced in the (idle)
+// ring.
+__device__ __forceinline__ void diag_partial(const double (&v)[kNRed], DiagRing& mac,
+                                             double* __restrict__ part) {
+#pragma clang fp contract(off)
+  static_assert(3 * 5 * kDiagNC >= kNRed * kDiagThreads, "ring too small to reduce in");
+  const int tx = int(threadIdx.x);
   double* red = &mac[0][0][0];
 #pragma unroll
   for (int q = 0; q < kNRed; ++q) red[q * kDiagThreads + tx] = v[q];
@@ -1295,6 +1267,129 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag(const typename Codec<ST>:
     __syncthreads();
   }
   if (tx < kNRed) part[(long long)blockIdx.x * kDiagSlots + tx] = red[tx * kDiagThreads];
+}
+
+template <int ST>
+__global__ __launch_bounds__(kDiagThreads) void k_diag(const typename Codec<ST>::T* __restrict__ lat,
+                                                       double* __restrict__ part, Geom geo,
+                                                       int tiles_x, int units) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  __shared__ DiagRing mac;
+  const int tx = int(threadIdx.x);
+  double v[kNRed];
+#pragma unroll
+  for (int q = 0; q < kNRed; ++q) v[q] = 0.0;
+  for (int u = int(blockIdx.x); u < units; u += int(gridDim.x)) {
+    const int xt = (u % tiles_x) * kDiagThreads;
+    const int y0 = (u / tiles_x) * kDiagRows;
+    const int y1 = min(y0 + kDiagRows, geo.ny);
+    const int x = xt + tx;
+    const bool active = x < geo.nx;
+    const int xc = x % geo.nx;   // past the last column: its periodic images
+    const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1) : (xt + kDiagThreads) % geo.nx;
+    const int ch = tx == 0 ? 0 : kDiagNC - 1;
+    T raw[kNPop], rawh[kNPop];
+    auto load = [&](int xx, int yy, T (&p)[kNPop]) {
+      const unsigned o = unsigned(yy) * geo.pitch + unsigned(xx);
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) p[q] = ld_plane<T>(lat + q * geo.plane, o);
+    };
+    auto issue = [&](int yy) {
+      yy = yy < 0 ? yy + geo.ny : (yy >= geo.ny ? yy - geo.ny : yy);
+      load(xc, yy, raw);
+      if (tx < 2) load(xh, yy, rawh);
+    };
+    auto commit = [&](int slot) {
+      diag_moments<C>(raw, mac, slot, tx + 1);
+      if (tx < 2) diag_moments<C>(rawh, mac, slot, ch);
+    };
+    issue(y0 - 1);
+    commit(0);
+    issue(y0);
+    commit(1);
+    issue(y0 + 1);
+    for (int y = y0; y < y1; ++y) {
+      const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
+      commit(sp);
+      if (y + 2 <= y1) issue(y + 2);
+      __syncthreads();
+      if (active) diag_accumulate(v, mac, sm, s0, sp, tx + 1);
+      __syncthreads();
+    }
+  }
+  diag_partial(v, mac, part);
+}
+
+// One step src -> dst (as k_step, FP32 storage) fused with the diagnostics
+// of dst (as k_diag): the same tiles, strips, units and accumulation order, so
+// the partials equal those of k_diag on the stored result bit for bit.  Each
+// block computes the new state of its strip's rows and of the row above and
+// below (not stored), on its tile's columns and one halo column on each side
+// (threads 0 and 1, not stored), gathering the next row while it accumulates
+// the current one; only the strip's own rows and columns are written.
+template <bool LES>
+__global__ __launch_bounds__(kDiagThreads) void k_step_diag(const float* __restrict__ src,
+                                                            float* __restrict__ dst,
+                                                            double* __restrict__ part, Geom geo,
+                                                            Rates rt, int tiles_x, int units) {
+  __shared__ DiagRing mac;
+  const int tx = int(threadIdx.x);
+  const long long P = geo.plane;
+  double v[kNRed];
+#pragma unroll
+  for (int q = 0; q < kNRed; ++q) v[q] = 0.0;
+  for (int u = int(blockIdx.x); u < units; u += int(gridDim.x)) {
+    const int xt = (u % tiles_x) * kDiagThreads;
+    const int y0 = (u / tiles_x) * kDiagRows;
+    const int y1 = min(y0 + kDiagRows, geo.ny);
+    const int x = xt + tx;
+    const bool active = x < geo.nx;
+    const int xc = x % geo.nx;   // past the last column: its periodic images
+    const int xh = tx == 0 ? (xt == 0 ? geo.nx - 1 : xt - 1) : (xt + kDiagThreads) % geo.nx;
+    const int ch = tx == 0 ? 0 : kDiagNC - 1;
+    const int xcl = xc == 0 ? geo.nx - 1 : xc - 1, xcr = xc == geo.nx - 1 ? 0 : xc + 1;
+    const int xhl = xh == 0 ? geo.nx - 1 : xh - 1, xhr = xh == geo.nx - 1 ? 0 : xh + 1;
+    float f[kNPop][1], fh[kNPop][1];   // the gathered row in flight
+    auto gather = [&](int r) {
+      unsigned row[3];
+      t2_rows(r, geo, row);
+      gather_row<LBMHD_FP32, 1>(src, P, xc, xcl, xcr, row, f);
+      if (tx < 2) gather_row<LBMHD_FP32, 1>(src, P, xh, xhl, xhr, row, fh);
+    };
+    auto moments = [&](const float (&w)[kNPop][1], int slot, int col) {
+      float e[kNPop];   // FP32 storage: the values stored are the collided ones
+#pragma unroll
+      for (int q = 0; q < kNPop; ++q) e[q] = w[q][0];
+      diag_moments<Codec<LBMHD_FP32>>(e, mac, slot, col);
+    };
+    // collide the gathered row r, store it if it is one of the strip's rows,
+    // and put its moments into ring slot `slot`
+    auto finish = [&](int r, int slot) {
+      collide_sites<1, LES, false>(f, rt);
+      if (active && r >= y0 && r < y1)
+        store_row<LBMHD_FP32, 1>(dst, P, unsigned(r) * geo.pitch + unsigned(x), f);
+      moments(f, slot, tx + 1);
+      if (tx < 2) {
+        collide_sites<1, LES, false>(fh, rt);
+        moments(fh, slot, ch);
+      }
+    };
+    gather(y0 - 1);
+    finish(y0 - 1, 0);
+    gather(y0);
+    finish(y0, 1);
+    gather(y0 + 1);
+    for (int y = y0; y < y1; ++y) {
+      const int sm = (y - y0) % 3, s0 = (y - y0 + 1) % 3, sp = (y - y0 + 2) % 3;
+      finish(y + 1, sp);
+      if (y + 2 <= y1) gather(y + 2);
+      __syncthreads();
+      if (active) diag_accumulate(v, mac, sm, s0, sp, tx + 1);
+      __syncthreads();
+    }
+  }
+  diag_partial(v, mac, part);
 }
 
 // Pass 3: one block folds the partials.
@@ -1661,6 +1756,23 @@ hipError_t launch_diag(int storage, const void* lat, double* part, double* out_d
   else
     hipLaunchKernelGGL(k_diag<LBMHD_FP16>, dim3(nparts), dim3(kDiagThreads), 0, s,
                        static_cast<const _Float16*>(lat), part, g, tiles_x, int(units));
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_diag(bool les, const void* src, void* dst, double* part, double* out_dev,
+                            const Geom& g, const Rates& r, hipStream_t s) {
+  const int tiles_x = (g.nx + kDiagThreads - 1) / kDiagThreads;
+  const long long units = (long long)tiles_x * ((g.ny + kDiagRows - 1) / kDiagRows);
+  const int nparts = diag_partials(g);
+  auto* a = static_cast<const float*>(src);
+  auto* b = static_cast<float*>(dst);
+  if (les)
+    hipLaunchKernelGGL(k_step_diag<true>, dim3(nparts), dim3(kDiagThreads), 0, s, a, b, part, g, r,
+                       tiles_x, int(units));
+  else
+    hipLaunchKernelGGL(k_step_diag<false>, dim3(nparts), dim3(kDiagThreads), 0, s, a, b, part, g,
+                       r, tiles_x, int(units));
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out_dev);
   return hipGetLastError();
 }

@@ -9,8 +9,11 @@ same reduction order, the step counts, and the final state bit for bit.  An
 interval of one or three steps makes every pass write the lattice that a
 diagnostics pass enqueued one or two passes earlier reads, so a missing wait
 would show as a differing result at 1024^2, where the passes take tens of
-microseconds.  Also: the in-place lattice, FP16 storage, the kinetic closure, the
-non-finite count, and the argument checks (made before anything is enqueued).
+microseconds.  Intervals that end in a single step of FP32 storage take that
+step and its diagnostics in one fused pass, also equal bit for bit (the headline
+lattice, the plain update, ragged and tiny lattices, every step).  Also: the
+in-place lattice, FP16 storage, the kinetic closure, the non-finite count, and
+the argument checks (made before anything is enqueued).
 """
 import ctypes
 
@@ -33,11 +36,13 @@ def lb():
 
 
 def pair(lb, n, **kw):
-    """Two lattices of the same configuration, both at the Orszag-Tang state."""
-    cfg = lb.LBMHDConfig(nx=n, ny=n, nu=1e-4, eta=1e-4, les=kw.pop("les", 1), cs=0.1,
+    """Two lattices of the same configuration (n x n, or nx x ny for n a
+    pair), both at the Orszag-Tang state."""
+    nx, ny = n if isinstance(n, tuple) else (n, n)
+    cfg = lb.LBMHDConfig(nx=nx, ny=ny, nu=1e-4, eta=1e-4, les=kw.pop("les", 1), cs=0.1,
                          delta=1.0, **kw)
     a, b = lb.Lattice(cfg), lb.Lattice(cfg)
-    f = orszag_tang(n, n)
+    f = orszag_tang(nx, ny)
     a.init_fields(*f)
     b.init_fields(*f)
     return a, b
@@ -65,13 +70,20 @@ CASES = [
     ("kinetic pairs", 256, dict(storage="fp32", steps_per_pass=2, les=2), 30, 6),
     ("in place", 256, dict(storage="fp32", inplace=True), 33, 5),
     ("overlap every pass", 1024, dict(storage="fp32", steps_per_pass=3), 60, 3),
-    ("overlap single steps", 1024, dict(storage="fp32", steps_per_pass=3), 12, 1),
+    ("overlap single steps", 1024, dict(storage="fp16", steps_per_pass=2), 12, 1),
+    # intervals that end in a single step of FP32 storage: that step and the
+    # diagnostics in one pass (k_step_diag)
+    ("fused headline chunks", 4096, dict(storage="fp32", steps_per_pass=3), 200, 100),
+    ("fused plain", 256, dict(storage="fp32", steps_per_pass=3, les=0), 22, 4),
+    ("fused ragged", (300, 70), dict(storage="fp32", steps_per_pass=3), 15, 7),
+    ("fused tiny", (5, 3), dict(storage="fp32", steps_per_pass=1), 9, 3),
+    ("fused every step", 1024, dict(storage="fp32", steps_per_pass=3), 12, 1),
 ]
 
 
 @pytest.mark.parametrize("name,n,kw,steps,every", CASES, ids=[c[0] for c in CASES])
 def test_run_equals_steps_then_diag(lb, name, n, kw, steps, every):
-    print(f"\nrun {name} {n}^2 steps={steps} every={every}", flush=True)
+    print(f"\nrun {name} {n} steps={steps} every={every}", flush=True)
     a, b = pair(lb, n, **kw)
     got = a.run(steps, every)
     want = plain(b, steps, every)
