@@ -88,6 +88,8 @@ int main() {
       CHECK(std::strlen(lbmhd_last_error(h)) > 0);
       lbmhd_diag_t d;
       CHECK(lbmhd_diag(h, &d) == LBMHD_ERR_NOT_BOUND);
+      CHECK(lbmhd_run(h, 10, 5, nullptr, &d, 2) == LBMHD_ERR_NOT_BOUND);
+      CHECK(lbmhd_run(h, -1, 5, nullptr, nullptr, 0) == LBMHD_ERR_NOT_BOUND);
       CHECK(lbmhd_bind(h, nullptr, 0, nullptr, 0, nullptr, 0, nullptr) == LBMHD_ERR_INVALID_ARG);
       int64_t step = -1;
       CHECK(lbmhd_get_step(h, &step) == LBMHD_OK && step == 0);
